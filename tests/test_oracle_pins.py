@@ -1,0 +1,362 @@
+"""Pins of the oracle against facts that do not come from the oracle itself.
+
+Each test names what fixes the expected value: a published reference output,
+exact rational arithmetic, a library routine (scipy connected components),
+brute-force reachability / enumeration on tiny graphs, the exact IC cascade
+spread, or a closed form.  A plausible slip in the oracle (a dropped term, a
+flipped comparison, a wrong index or tie rule) fails at least one of them.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import connected_components
+
+import oracle
+from paper_2311_07554_amd import inputs
+from tests import brute
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+M64 = (1 << 64) - 1
+
+
+# ---------------------------------------------------------------- hash / thresholds
+
+def _golden_streams():
+    rows = []
+    with open(os.path.join(GOLDEN, "splitmix64_reference.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            parts = line.split()
+            rows.append((int(parts[0]), [int(x, 16) for x in parts[1:]]))
+    return rows
+
+
+@pytest.mark.parametrize("state,outs", _golden_streams())
+def test_mix64_reproduces_published_splitmix64(state, outs):
+    s = state
+    for want in outs:
+        s = (s + brute.PHI) & M64
+        assert oracle.mix64(s) == want
+        assert brute.mix64_int(s) == want  # the numpy transcription used by other pins
+
+
+def test_edge_hash_spec_vectors():
+    # Frozen before any implementation: h(u,v,r,seed) = mix64(((min<<32)|max) ^ K(seed, r)),
+    # K(seed, r) = mix64(seed * phi + r), evaluated by hand from the published mixer.
+    vec = [((0, 1, 0, 1), 0x9E0160293A33AAF7), ((1, 0, 0, 1), 0x9E0160293A33AAF7),
+           ((3, 7, 5, 1), 0x76AD6B051034D182), ((999, 0, 63, 1), 0xC63F261867D006FB),
+           ((123456, 654321, 255, 42), 0xBB7968C30C90476D)]
+    for (u, v, r, seed), h in vec:
+        a, b = min(u, v), max(u, v)
+        assert oracle.mix64(((a << 32) | b) ^ oracle.key(seed, r)) == h
+        # live iff h < T: a threshold just above / at h decides it
+        assert oracle.live(u, v, r, seed, h + 1) and not oracle.live(u, v, r, seed, h)
+
+
+def test_threshold_is_exact_floor_of_p_times_2_64():
+    rng = np.random.default_rng(7)
+    ps = list(rng.random(2000)) + [0.05, 0.02, 0.1, 0.01, 0.001, 5e-324, 1e-300, 0.5,
+                                   math.nextafter(1.0, 0.0)]
+    for p in ps:
+        assert oracle.threshold(p) == int(Fraction(float(p)) * (1 << 64)), p
+    assert oracle.threshold(0.0) == 0 and oracle.threshold(-0.5) == 0
+    assert oracle.threshold(1.0) == M64 and oracle.threshold(3.0) == M64
+    # values quoted with the workload definitions
+    assert oracle.threshold(0.05) == 0x0CCCCCCCCCCCCD00
+    assert oracle.threshold(0.02) == 0x051EB851EB851EC0
+
+
+def test_live_fraction_calibrated():
+    # binomial 5-sigma band around p over 200k (edge, sketch) pairs
+    rng = np.random.default_rng(3)
+    u = rng.integers(0, 1 << 20, 20000)
+    v = rng.integers(0, 1 << 20, 20000)
+    keys = (np.minimum(u, v).astype(np.uint64) << np.uint64(32)) | np.maximum(u, v).astype(np.uint64)
+    for p in (0.5, 0.05, 0.001):
+        T = oracle.threshold(p)
+        live = sum(int(brute.live_mask(keys, r, 11, T).sum()) for r in range(10))
+        N = keys.size * 10
+        assert abs(live - N * p) <= 5 * math.sqrt(N * p * (1 - p)) + 1
+    # spot-check the numpy transcription against the oracle's own live test
+    T = oracle.threshold(0.3)
+    mask = brute.live_mask(keys[:200], 4, 9, T)
+    for i in range(200):
+        assert bool(mask[i]) == oracle.live(int(u[i]), int(v[i]), 4, 9, T)
+
+
+def test_trivalency_classes():
+    rng = np.random.default_rng(5)
+    cnt = {oracle.threshold(0.1): 0, oracle.threshold(0.01): 0, oracle.threshold(0.001): 0}
+    for _ in range(3000):
+        a, b = (int(x) for x in rng.integers(0, 1 << 30, 2))
+        if a == b:
+            continue
+        T = oracle.edge_threshold(1, 0.0, a, b)
+        assert T in cnt
+        assert T == oracle.edge_threshold(1, 0.7, b, a)  # symmetric, ignores p
+        cnt[T] += 1
+    tot = sum(cnt.values())
+    for c in cnt.values():
+        assert abs(c - tot / 3) <= 5 * math.sqrt(tot * (1 / 3) * (2 / 3))
+    # class = mix64(key ^ mix64(SALT_TRIV)) mod 3, checked with the numpy transcription
+    key = (12 << 32) | 345
+    cls = int(brute.mix64_np(np.array([key ^ brute.key_int(0, oracle.SALT_TRIV)], dtype=np.uint64))[0]) % 3
+    assert oracle.edge_threshold(1, 0.0, 345, 12) == oracle.threshold((0.1, 0.01, 0.001)[cls])
+
+
+# ---------------------------------------------------------------- sketches (labels, sizes)
+
+def _edge_keys(g):
+    rows = np.repeat(np.arange(g.n, dtype=np.uint64), np.diff(g.offsets.astype(np.int64)))
+    cols = g.cols.astype(np.uint64)
+    sel = rows < cols
+    return (rows[sel] << np.uint64(32)) | cols[sel]
+
+
+def _scipy_labels(n, keys, live):
+    k = keys[live]
+    u = (k >> np.uint64(32)).astype(np.int64)
+    v = (k & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    A = sp.coo_matrix((np.ones(u.size), (u, v)), shape=(n, n))
+    ncc, comp = connected_components(A, directed=False)
+    mins = np.full(ncc, n, dtype=np.int64)
+    np.minimum.at(mins, comp, np.arange(n))
+    sizes = np.bincount(comp, minlength=ncc)
+    return mins[comp].astype(np.uint32), sizes[comp].astype(np.uint32), ncc
+
+
+@pytest.mark.parametrize("which", ["er", "rmat"])
+def test_sketch_labels_match_library_connected_components(which):
+    if which == "er":
+        g, kind, p = inputs.er_graph(1000, 5000, seed=1), 0, 0.05
+    else:
+        g, kind, p = inputs.rmat_graph(12, 16 << 12, seed=9), 1, 0.0
+    keys = _edge_keys(g)
+    if kind == 0:
+        T = np.full(keys.size, oracle.threshold(p), dtype=np.uint64)
+    else:
+        cls = brute.mix64_np(keys ^ np.uint64(brute.key_int(0, oracle.SALT_TRIV))) % np.uint64(3)
+        tri = np.array([oracle.threshold(x) for x in (0.1, 0.01, 0.001)], dtype=np.uint64)
+        T = tri[cls.astype(np.int64)]
+    for r in (0, 1, 17, 63):
+        K = np.uint64(brute.key_int(1, r))
+        live = brute.mix64_np(keys ^ K) < T
+        want_l, want_s, ncc = _scipy_labels(g.n, keys, live)
+        lab, siz = oracle.sketch(g, kind, p, 1, r)
+        assert np.array_equal(lab, want_l)
+        assert np.array_equal(siz, want_s)
+        # invariant: component sizes over the roots sum to n
+        roots = lab == np.arange(g.n)
+        assert int(siz[roots].sum()) == g.n and int(roots.sum()) == ncc
+
+
+def _tiny_graphs():
+    rng = np.random.default_rng(2024)
+    out = []
+    for t in range(6):
+        n = int(rng.integers(4, 13))
+        pairs = {(int(a), int(b)) for a, b in rng.integers(0, n, (int(rng.integers(n, 2 * n + 3)), 2)) if a != b}
+        out.append(inputs.csr_from_pairs(n, pairs))
+    return out
+
+
+def _live_edges(g, kind, p, seed, r):
+    res = []
+    for u in range(g.n):
+        for j in range(int(g.offsets[u]), int(g.offsets[u + 1])):
+            w = int(g.cols[j])
+            if u < w:
+                # the live test spelled out from the published mixer, not the oracle
+                T = oracle.threshold(p) if kind == 0 else None
+                if kind == 1:
+                    cls = brute.mix64_int(((u << 32) | w) ^ brute.key_int(0, oracle.SALT_TRIV)) % 3
+                    T = oracle.threshold((0.1, 0.01, 0.001)[cls])
+                if T == M64 or brute.mix64_int(((u << 32) | w) ^ brute.key_int(seed, r)) < T:
+                    res.append((u, w))
+    return res
+
+
+@pytest.mark.parametrize("gi", range(6))
+def test_sketch_labels_match_transitive_closure(gi):
+    g = _tiny_graphs()[gi]
+    for r in range(8):
+        edges = _live_edges(g, 0, 0.45, 3, r)
+        lab_b, siz_b, _ = brute.closure_labels(g.n, edges)
+        lab, siz = oracle.sketch(g, 0, 0.45, 3, r)
+        assert np.array_equal(lab, lab_b) and np.array_equal(siz, siz_b)
+
+
+# ---------------------------------------------------------------- greedy
+
+@pytest.mark.parametrize("gi", range(6))
+def test_greedy_matches_brute_force_and_bounds(gi):
+    g = _tiny_graphs()[gi]
+    R, p, seed = 6, 0.4, 5
+    k = min(3, g.n)
+    worlds = [brute.closure_labels(g.n, _live_edges(g, 0, p, seed, r))[2] for r in range(R)]
+    lab, siz = oracle.sketches(g, 0, p, seed, R)
+    seeds, gains = oracle.greedy(lab, siz, k)
+    bs, bg = brute.brute_greedy(worlds, g.n, k)
+    assert list(seeds) == bs and list(gains) == bg
+    # gains non-increasing (submodularity), total = f(S_k) <= R*n
+    assert all(gains[i] >= gains[i + 1] for i in range(k - 1))
+    fk = sum(brute.spread_in_world(A, list(map(int, seeds))) for A in worlds)
+    assert int(gains.sum()) == fk <= R * g.n
+    # (1 - 1/e) guarantee of greedy against the exhaustive optimum
+    assert fk >= (1 - 1 / math.e) * brute.best_k_subset(worlds, g.n, k) - 1e-9
+
+
+def test_greedy_on_all_worlds_equals_exact_ic_spread():
+    # With the sketch set = every live-edge world of a tiny graph at p = 1/2, the
+    # coverage f(S) equals 2^m * sigma(S), sigma from the IC cascade definition.
+    n = 6
+    edges = [(0, 1), (1, 2), (2, 0), (2, 3), (3, 4), (4, 5), (1, 5)]
+    m = len(edges)
+    labs, sizs = [], []
+    for mask in range(1 << m):
+        live = [e for i, e in enumerate(edges) if mask >> i & 1]
+        l, s, _ = brute.closure_labels(n, live)
+        labs.append(l)
+        sizs.append(s)
+    lab, siz = np.array(labs), np.array(sizs)
+    k = 3
+    seeds, gains = oracle.greedy(lab, siz, k)
+    S = []
+    prev = Fraction(0)
+    for i in range(k):
+        sig = {v: brute.exact_ic_spread(n, edges, Fraction(1, 2), S + [v]) for v in range(n) if v not in S}
+        best = max(sig.values())
+        want = min(v for v in sig if sig[v] == best)
+        assert seeds[i] == want
+        assert Fraction(int(gains[i]), 1 << m) == best - prev
+        S.append(want)
+        prev = best
+
+
+def test_closed_form_p0_and_cliques():
+    # p = 0: every CC is a singleton, so seeds are 0..k-1 with gain R each
+    g = inputs.er_graph(200, 600, seed=4)
+    lab, siz = oracle.sketches(g, 0, 0.0, 1, 8)
+    seeds, gains = oracle.greedy(lab, siz, 5)
+    assert list(seeds) == [0, 1, 2, 3, 4] and list(gains) == [8] * 5
+    # p = 1 on disjoint cliques: components in decreasing size (ties -> smaller min id),
+    # the seed is the component's smallest id, gain R*|C|; then zero gains, smallest unused ids
+    comps = [[7, 8, 9], [0, 1], [2, 3, 4, 5, 6], [10, 11, 12], [13]]
+    pairs = [(a, b) for c in comps for i, a in enumerate(c) for b in c[i + 1:]]
+    g = inputs.csr_from_pairs(14, pairs)
+    R = 4
+    lab, siz = oracle.sketches(g, 0, 1.0, 9, R)
+    seeds, gains = oracle.greedy(lab, siz, 8)
+    assert list(seeds) == [2, 7, 10, 0, 13, 1, 3, 4]
+    assert list(gains) == [5 * R, 3 * R, 3 * R, 2 * R, 1 * R, 0, 0, 0]
+
+
+def test_celf_equals_plain_greedy():
+    g = inputs.rmat_graph(11, 16 << 11, seed=3)
+    lab, siz = oracle.sketches(g, 1, 0.0, 2, 16)
+    s1, g1 = oracle.greedy(lab, siz, 12)
+    s2, g2, ev = oracle.celf(lab, siz, 12)
+    assert np.array_equal(s1, s2) and np.array_equal(g1, g2)
+    assert ev.min() >= 1
+
+
+# ---------------------------------------------------------------- CompactSketch
+
+def test_centers_are_hashed_bernoulli():
+    n, seed = 20000, 3
+    for alpha in (0.1, 0.5):
+        c = oracle.centers(n, seed, alpha)
+        assert np.all(np.diff(c.astype(np.int64)) > 0)
+        K = brute.key_int(seed, oracle.SALT_CENTER)
+        want = np.nonzero(brute.mix64_np(np.arange(n, dtype=np.uint64) ^ np.uint64(K))
+                          < np.uint64(oracle.threshold(alpha)))[0]
+        assert np.array_equal(c, want)
+        assert abs(c.size - n * alpha) <= 5 * math.sqrt(n * alpha * (1 - alpha))
+    assert np.array_equal(oracle.centers(50, 1, 1.0), np.arange(50))
+    assert oracle.centers(50, 1, 0.0).size == 0
+
+
+@pytest.mark.parametrize("gi", range(6))
+def test_compact_triple_matches_definition(gi):
+    g = _tiny_graphs()[gi]
+    cents = oracle.centers(g.n, 5, 0.5)
+    for r in range(5):
+        edges = _live_edges(g, 0, 0.45, 5, r)
+        _, _, A = brute.closure_labels(g.n, edges)
+        lab, siz = oracle.sketch(g, 0, 0.45, 5, r)
+        lc, sc = oracle.compact(lab, siz, cents)
+        for i, c in enumerate(cents):
+            j = min(jj for jj, cc in enumerate(cents) if A[c, cc])
+            assert lc[i] == j
+            assert sc[i] == (int(A[c].sum()) if j == i else 0)
+
+
+@pytest.mark.parametrize("alpha", [0.05, 0.3, 1.0])
+def test_compact_greedy_equals_full_greedy(alpha):
+    # alpha-equivalence (Sec. 3): the GetCenter route reaches the full-label result
+    g = inputs.rmat_graph(9, 8 << 9, seed=6)
+    R, k, seed = 12, 8, 4
+    lab, siz = oracle.sketches(g, 1, 0.0, seed, R)
+    s_full, g_full = oracle.greedy(lab, siz, k)
+    cents = oracle.centers(g.n, seed, alpha)
+    lc, sc = oracle.compact_all(lab, siz, cents)
+    s_c, g_c, _ = oracle.compact_greedy(g, 1, 0.0, seed, cents, lc, sc, k)
+    assert np.array_equal(s_full, s_c) and np.array_equal(g_full, g_c)
+
+
+def test_getcenter_cases_and_visit_bound():
+    g = inputs.er_graph(3000, 9000, seed=8)
+    p, seed, alpha = 0.3, 2, 0.1
+    R = 4
+    lab, siz = oracle.sketches(g, 0, p, seed, R)
+    cents = oracle.centers(g.n, seed, alpha)
+    lc, sc = oracle.compact_all(lab, siz, cents)
+    in_s = np.zeros(g.n, dtype=np.uint8)
+    tot_vis, calls = 0, 0
+    for r in range(R):
+        for v in range(0, g.n, 7):
+            d, l, vis = oracle.getcenter(g, 0, p, seed, r, cents, lc[r], sc[r], in_s, v)
+            assert d == siz[r, v]               # no seeds yet: influence = CC size
+            has_center = bool(np.any(lab[r, cents] == lab[r, v]))
+            assert (l != oracle.NONE) == has_center
+            tot_vis += vis
+            calls += 1
+    # Theorem 3.1: expected visits per call <= min(1/alpha, T); allow sampling slack
+    assert tot_vis / calls <= 1.5 / alpha
+    # a seed in a center-less CC zeroes the gain of every vertex of that CC
+    r = 0
+    nocenter = [v for v in range(g.n) if siz[r, v] > 1 and not np.any(lab[r, cents] == lab[r, v])]
+    if nocenter:
+        v = nocenter[0]
+        other = [w for w in range(g.n) if lab[r, w] == lab[r, v] and w != v][0]
+        in_s[other] = 1
+        d, l, _ = oracle.getcenter(g, 0, p, seed, r, cents, lc[r], sc[r], in_s, v)
+        assert d == 0 and l == oracle.NONE
+
+
+# ---------------------------------------------------------------- inputs
+
+def test_generators_are_deterministic_and_simple():
+    a = inputs.rmat_keys(12, 4000, 0.57, 0.19, 0.19, 5)
+    b = inputs.rmat_keys(12, 4000, 0.57, 0.19, 0.19, 5)
+    assert np.array_equal(a, b) and a.size == 4000
+    assert np.all(np.diff(a.astype(np.int64)) > 0)
+    g = inputs.csr_from_keys(1 << 12, a)
+    off = g.offsets.astype(np.int64)
+    rows = np.repeat(np.arange(g.n), np.diff(off))
+    assert np.all(rows != g.cols)
+    fwd = set(zip(rows.tolist(), g.cols.tolist()))
+    assert all((v, u) in fwd for (u, v) in fwd)
+    for u in range(g.n):
+        seg = g.cols[off[u]:off[u + 1]]
+        assert np.all(np.diff(seg.astype(np.int64)) > 0)
+    c = inputs.chunglu_keys(5000, 12.0, 2.2, 9)
+    assert 0 < c.size <= 30000
+    e = inputs.er_keys(1000, 5000, 1)
+    assert e.size == 5000
