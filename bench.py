@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark of the sketch-based greedy influence-maximization hot path on one MI355X.
+
+Workload (default): R-MAT scale 20 (2^20 vertices, 2^24 undirected pairs,
+a=0.57 b=c=0.19), trivalency IC probabilities, R = 256 sketches, k = 100 seeds.
+One step = the whole path twice on the resident graph: full labels (alpha = 1)
+and CompactSketch (alpha = 0.1), each = build R sketches + select k seeds.
+
+Prints one JSON line.  value = sampled edges per second over the step
+(2 * R * m_und sampled edges / step time); the breakdown gives the sketch-only
+sampled-edge rate, seeds/s of selection, and the per-kernel roofline of the
+dominant kernel measured with HIP events on the library's stream.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sampled edges/s for Sketch; seeds/s for k-seed select; HBM GB/s vs peak"
+HBM_PEAK_GBS = 8000.0
+# Integer VALU ceiling of the live-edge hash: 256 CUs x 64 lanes x 2.4 GHz full-rate
+# 32-bit lane-ops, and one hash costs 20 full-rate + 6 quarter-rate VALU
+# instructions (44 issue slots) in the sampling loop.
+VALU_LANE_OPS = 256 * 64 * 2.4e9
+SLOTS_PER_HASH = 44.0
+HASH_PEAK_G = VALU_LANE_OPS / SLOTS_PER_HASH / 1e9
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--R", type=int, default=256)
+    ap.add_argument("--k", type=int, default=100)
+    ap.add_argument("--alpha", type=float, default=0.1, help="CompactSketch alpha of the second query")
+    ap.add_argument("--modes", default="full,compact")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sketches", type=int, default=16)
+    return ap.parse_args()
+
+
+def cpu_baseline(g, kind, p, R, k, seed, nsk):
+    """The oracle as it stands (single thread) on nsk of the R sketches plus the plain
+    greedy over them; scaled linearly in R to the full query."""
+    import oracle
+    t0 = time.perf_counter()
+    lab, siz = oracle.sketches(g, kind, p, seed, nsk, threads=1)
+    t1 = time.perf_counter()
+    oracle.greedy(lab, siz, k)
+    t2 = time.perf_counter()
+    scale = R / nsk
+    t_query = (t1 - t0) * scale + (t2 - t1) * scale
+    return {
+        "value": R * g.m_und / t_query,
+        "unit": "sampled edges/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{nsk} of {R} sketches (BFS labelling) + plain greedy k={k} over them, "
+                  f"{t2 - t0:.1f} s measured, times scaled x{scale:g} to R={R}",
+        "sketch_edges_per_s": nsk * g.m_und / (t1 - t0),
+        "greedy_s_measured": t2 - t1,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2311_07554_amd import inputs, pacim
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    torch.cuda.set_device(0)
+    t = time.perf_counter()
+    w = inputs.rmat20(R=args.R, k=args.k, scale=args.scale)
+    q = w.queries[0]
+    g = q.graph
+    print(f"[bench] graph {g.name}: n={g.n} m_und={g.m_und} generated in {time.perf_counter() - t:.1f}s",
+          file=sys.stderr, flush=True)
+    modes = [m for m in args.modes.split(",") if m]
+    alphas = {"full": 1.0, "compact": args.alpha}
+
+    stream = torch.cuda.Stream()
+    ctx = pacim.Context(0, stream)
+    gr = ctx.graph(g.n, torch.from_numpy(g.offsets.view(np.int64)).cuda(),
+                   torch.from_numpy(g.cols.view(np.int32)).cuda())
+    torch.cuda.synchronize()
+
+    def one_step(record):
+        per = {}
+        for m in modes:
+            sk = gr.sketches(q.prob_kind, q.p, q.R, q.seed, alphas[m])
+            s, gn = sk.select(q.k)
+            st = sk.stats()
+            sk.close()
+            if record is not None:
+                record.setdefault(m, []).append((st["build_ms"], st["select_ms"], st["evaluations"],
+                                                 st["sketches_per_pass"]))
+            per[m] = (s, gn)
+        return per
+
+    for i in range(args.warmup):
+        one_step(None)
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    ctx.profiling(True)
+    rec = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        res = one_step(rec)
+        print(f"[bench] step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+
+    kern = {}
+    for name in ("sample_hook", "compress", "emit", "select"):
+        n_l, ms = ctx.kernel_time(name)
+        kern[name] = {"launches": n_l, "avg_ms": (ms / n_l) if n_l else None, "total_ms": ms}
+    ctx.profiling(False)
+
+    R, m_und, n = q.R, g.m_und, g.n
+    breakdown = {}
+    for m, rows in rec.items():
+        b = np.array([r[0] for r in rows])
+        s = np.array([r[1] for r in rows])
+        breakdown[m] = {
+            "alpha": alphas[m],
+            "sketch_ms": float(b.mean()),
+            "select_ms": float(s.mean()),
+            "sampled_edges_per_s_sketch": R * m_und / (b.mean() / 1e3),
+            "seeds_per_s_select": q.k / (s.mean() / 1e3),
+            "evaluations": int(rows[-1][2]),
+            "sketches_per_pass": int(rows[-1][3]),
+        }
+    # dominant kernel: the sampling + hooking pass over the edge list
+    hk = kern["sample_hook"]
+    B = breakdown[modes[0]]["sketches_per_pass"]
+    hashes_per_launch = m_und * B  # one launch samples B sketches of every edge
+    roofline = None
+    if hk["avg_ms"]:
+        achieved = hashes_per_launch / (hk["avg_ms"] / 1e3) / 1e9
+        roofline = {"bound": "alu", "kernel": "k_sample_hook", "achieved": achieved, "peak": HASH_PEAK_G,
+                    "unit": "Ghash/s", "frac": achieved / HASH_PEAK_G, "traffic": None,
+                    "per_launch_hashes": hashes_per_launch, "avg_launch_ms": hk["avg_ms"]}
+
+    out = {
+        "metric": METRIC,
+        "value": len(modes) * R * m_und / (ms_step / 1e3),
+        "unit": "sampled edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"rmat{args.scale}_trivalency_R{R}_k{q.k}_" + "+".join(modes),
+                   "n": n, "m_und": m_und, "R": R, "k": q.k, "alpha_compact": args.alpha,
+                   "prob": "trivalency {0.1,0.01,0.001}", "parallelism": "single GPU"},
+        "breakdown": breakdown,
+        "kernels": kern,
+        "roofline": roofline,
+        "seeds_head": [int(x) for x in res[modes[0]][0][:5]],
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle on a bounded sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(g, q.prob_kind, q.p, R, q.k, q.seed, args.cpu_sketches)
+    gr.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

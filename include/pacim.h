@@ -1,0 +1,164 @@
+/*
+ * pacim.h -- C-ABI of the MI355X (gfx950) sketch-based influence-maximization
+ * library: the hot path of PaC-IM (Wang, Ding, Gu, Sun, "Fast and
+ * Space-Efficient Parallel Algorithms for Influence Maximization", PVLDB 17(3),
+ * 2023) under the Independent Cascade (IC) model on undirected graphs.
+ *
+ * The library computes, for a graph G, an edge-probability model, R sketches
+ * and k, the greedy seed sequence s_1..s_k and integer gains g_1..g_k with
+ *     f(S) = sum_{r<R} | union_{s in S} CC_r(s) |,
+ *     s_i = argmax_{v not in S_{i-1}} f(S_{i-1} + v) - f(S_{i-1})   (smallest id on ties),
+ *     g_i = f(S_i) - f(S_{i-1}),
+ * where CC_r(v) is v's connected component in the r-th sampled graph G'_r
+ * (Sec. 2, sketch-based algorithms and memoization; Algorithm 1).  Dividing by R
+ * gives the paper's spread estimate; the library keeps the exact integers.
+ *
+ * Conventions for every call:
+ *   - Every function returns im_status.  On error nothing the caller passed as
+ *     an output is written, and im_last_error(ctx) describes the failure.
+ *   - No exceptions and no C++ types cross this boundary.
+ *   - Host buffers are owned by the caller and only read/written during the call.
+ *   - Handles (im_ctx, im_graph, im_sketches, im_server) are owned by the
+ *     library; free them with the matching *_free / *_destroy call.
+ *   - An im_ctx is not thread-safe: use one per host thread (the server API
+ *     handles concurrent requests itself).
+ *   - Work is issued on the context's HIP stream; calls that return host
+ *     results synchronise that stream before returning.
+ *
+ * Sampling (Sec. 3, function Sample; "fusion" of Sec. 2): edge {u,v} is live in
+ * sketch r iff  mix64(((min<<32)|max) ^ K(seed, r)) < T(p_e), where mix64 is the
+ * SplitMix64 output function, K(seed, x) = mix64(seed*0x9E3779B97F4A7C15 + x)
+ * and T(p) = floor(p * 2^64) for 0 <= p < 1 (every edge live for p >= 1).
+ * Sampled graphs are never stored.
+ */
+#ifndef PACIM_H
+#define PACIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IM_OK = 0,
+    IM_EINVAL = 1,    /* an argument is out of range or a graph is malformed   */
+    IM_ENOMEM = 2,    /* device memory (or the context's HBM cap) is exhausted */
+    IM_EDEVICE = 3,   /* a HIP call failed                                     */
+    IM_EBUSY = 4,     /* the request can never fit the server's memory budget  */
+    IM_EINTERNAL = 5  /* an internal consistency check failed                  */
+} im_status;
+
+typedef struct im_ctx im_ctx;
+typedef struct im_graph im_graph;
+typedef struct im_sketches im_sketches;
+
+/* Edge-probability models (Sec. 6 and its appendix use constant p per graph). */
+typedef enum {
+    IM_PROB_UNIFORM = 0,     /* p_e = p for every edge                                    */
+    IM_PROB_TRIVALENCY = 1   /* p_e in {0.1, 0.01, 0.001}, chosen by
+                                mix64(((min<<32)|max) ^ K(0, 0xC000000000000002)) mod 3;
+                                a property of the edge, independent of the sampling seed */
+} im_prob_kind;
+
+typedef struct {
+    int32_t kind;  /* im_prob_kind */
+    double p;      /* used by IM_PROB_UNIFORM; must lie in [0, 1] */
+} im_prob;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Creates a context on HIP device `device`.  hip_stream: a hipStream_t to issue
+ * work on, or NULL for a library-owned stream (default priority).  hbm_cap: the
+ * most device memory (bytes) this context may hold at once, 0 for no cap beyond
+ * the device's.  Errors: EINVAL (bad device), EDEVICE. */
+im_status im_ctx_create(int device, void *hip_stream, size_t hbm_cap, im_ctx **out);
+im_status im_ctx_destroy(im_ctx *ctx);
+/* Text of the last error on ctx ("" if none).  Valid until the next call on ctx. */
+const char *im_last_error(const im_ctx *ctx);
+/* Bytes of device memory the context currently holds. */
+im_status im_ctx_memory(const im_ctx *ctx, size_t *used, size_t *cap);
+/* Turns per-kernel HIP-event timing on (1) or off (0); see im_kernel_time. */
+im_status im_ctx_set_profiling(im_ctx *ctx, int on);
+/* Accumulated launches and milliseconds of one kernel family since profiling was
+ * turned on: "sample_hook", "compress", "emit", "marginal", "select_round", ...
+ * Unknown names give count 0. */
+im_status im_kernel_time(im_ctx *ctx, const char *name, uint64_t *launches, double *ms);
+
+/* ---- graph ---------------------------------------------------------------- */
+
+/* Uploads a simple undirected graph given as a symmetric CSR: offsets[n+1]
+ * (uint64, offsets[0] = 0, non-decreasing, offsets[n] = m_dir) and cols[m_dir]
+ * (uint32 neighbour ids).  Every undirected edge {u,v} appears as v in u's row
+ * and u in v's row, exactly once each (Sec. 6: |E| counts these directed
+ * entries).  device_ptrs = 1 if offsets/cols are device pointers, 0 for host.
+ * The library copies the graph into memory it owns.
+ * Errors: EINVAL if n == 0, offsets are not monotone, a column is >= n, a row
+ * holds a self-loop or a duplicate, or the CSR is not symmetric; ENOMEM. */
+im_status im_graph_upload(im_ctx *ctx, uint32_t n, uint64_t m_dir, const uint64_t *offsets,
+                          const uint32_t *cols, int device_ptrs, im_graph **out);
+im_status im_graph_free(im_graph *g);
+
+/* ---- sketches (Sec. 3: Sketch(r), the sketch triple <r, label, size>) ------ */
+
+/* Builds R sketches of G under model `prob` with sampling seed `seed`.
+ * alpha = 1: full labels -- for every vertex v and sketch r the CC label
+ *            (smallest vertex id in CC_r(v)) and, at the label's own entry, the
+ *            CC size (the InfuserMG-style memoization the paper extends).
+ * 0 < alpha < 1: CompactSketch (Sec. 3) -- vertex v is a center iff
+ *            mix64(v ^ K(seed, 0xC000000000000001)) < T(alpha); centers are
+ *            ranked by id; per sketch only label_c[i] (smallest center rank in
+ *            c_i's CC) and size_c[i] (CC size if label_c[i] = i, else 0) are kept,
+ *            and Marginal uses the GetCenter BFS.
+ * The initial gains Marginal(empty, v) = sum_r |CC_r(v)| are computed while the
+ * components are built.  Requires R >= 1 and ceil(log2(R*n+2)) + ceil(log2 n) <= 64.
+ * Errors: EINVAL (bad R, alpha outside (0,1], bad prob), ENOMEM, EDEVICE. */
+im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob prob, uint32_t R, uint64_t seed,
+                            double alpha, im_sketches **out);
+im_status im_sketches_free(im_sketches *s);
+
+/* Selects the next k seeds (Algorithm 1's loop: NextSeed by a parallel lazy
+ * greedy over a winning tree -- Sec. 4, Algorithm 5 -- then MarkSeed), continuing
+ * from the seeds the handle already holds, so k1 then k2 equals k1 + k2 at once.
+ * seeds_out[k], gains_out[k]: caller-owned host arrays.  Errors: EINVAL if
+ * k > n - (seeds already chosen); EINTERNAL. */
+im_status im_select_seeds_from(im_ctx *ctx, im_sketches *s, uint32_t k, uint32_t *seeds_out,
+                               uint64_t *gains_out);
+
+/* One shot with full labels: build R sketches, select k seeds, free.
+ * Same errors as im_build_sketches and im_select_seeds_from. */
+im_status im_select_seeds(im_ctx *ctx, const im_graph *g, im_prob prob, uint32_t R, uint32_t k,
+                          uint64_t seed, uint32_t *seeds_out, uint64_t *gains_out);
+
+/* ---- inspection (tests, measurement) -------------------------------------- */
+
+/* Sketch r as it was built (MarkSeed's zeroing not applied):
+ * full labels: labels[n] = CC label of every vertex, sizes[n] = CC size of every vertex;
+ * CompactSketch: labels[rho] = label_c, sizes[rho] = size_c (see im_centers for rho).
+ * Caller-owned host arrays.  Errors: EINVAL if r >= R. */
+im_status im_sketches_dump(im_ctx *ctx, const im_sketches *s, uint32_t r, uint32_t *labels, uint32_t *sizes);
+/* Centers of a CompactSketch (all vertices for alpha = 1): *rho gets their
+ * number; centers (may be NULL) receives them in increasing id order. */
+im_status im_centers(im_ctx *ctx, const im_sketches *s, uint32_t *centers, uint32_t *rho);
+/* Initial gains Marginal(empty, v) for every vertex: gains[n], host. */
+im_status im_initial_gains(im_ctx *ctx, const im_sketches *s, uint64_t *gains);
+/* Counters of the handle: seeds chosen so far, total and per-call re-evaluations
+ * performed by NextSeed, and the sketch build's byte/time figures. */
+typedef struct {
+    uint32_t seeds_chosen;
+    uint32_t rho;
+    uint64_t evaluations;        /* vertex re-evaluations by NextSeed, all rounds  */
+    uint64_t bfs_overflow;       /* GetCenter searches that left the on-chip queue */
+    double build_ms;             /* last im_build_sketches, device time            */
+    double select_ms;            /* device time of all im_select_seeds_from calls  */
+    uint32_t sketches_per_pass;  /* sketches sampled per pass over the edge list  */
+    uint64_t sketch_bytes;       /* device bytes held by the sketch arrays         */
+} im_sketch_stats;
+im_status im_sketches_stats(const im_sketches *s, im_sketch_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PACIM_H */

@@ -1,0 +1,273 @@
+// CompactSketch evaluation (Sec. 3): Marginal(S, v) = sum_r delta_r with
+// <delta_r, l> = GetCenter(Phi_r, v, S), and MarkSeed zeroing size_c[r][l].
+//
+// GetCenter is a BFS from v over the live edges of sketch r that stops at the
+// first center it reaches (delta = size_c[label_c[center]], the CC's size or 0
+// once a seed covered it); if the CC holds no center the BFS exhausts it and
+// delta = |CC|, or 0 if a seed was met.  Theorem 3.1 bounds the expected number
+// of vertices visited by min(1/alpha, T).
+//
+// GPU form: one wave per (vertex, sketch) search.  The wave takes one queued
+// vertex at a time and scans its adjacency 64 neighbours per step, one lane per
+// neighbour (hash test, center test, ballot); newly reached vertices are
+// deduplicated in an LDS hash set and appended to an LDS queue with one ballot.
+// A search that would outgrow the LDS queue is handed, whole, to a slower
+// global-memory version (bitmap + queue of n entries per slot), so the result is
+// exact for every component size.
+#pragma once
+
+#include "common.h"
+#include "select_kernels.h"
+
+namespace pacim {
+
+constexpr uint32_t kQCap = 512;    // LDS queue entries per wave
+constexpr uint32_t kHCap = 1024;   // LDS hash-set slots per wave (2 x queue)
+constexpr uint32_t kBfsBlock = 256;
+constexpr uint32_t kBfsWaves = kBfsBlock / kWave;
+
+struct GraphDev {
+    const uint64_t *off;
+    const uint32_t *cols;
+};
+
+struct CompactDev {
+    const uint32_t *center_rank;   // [n], rank or kNone
+    const uint32_t *label_c;       // [R][rho]
+    uint32_t *size_c;              // [R][rho]
+    uint32_t rho;
+};
+
+struct BfsOut {
+    uint64_t delta;
+    uint32_t label;   // label_c of the reached center, or kNone
+    bool overflow;
+};
+
+__device__ __forceinline__ uint32_t hs_slot(uint32_t w) { return (w * 0x9E3779B1u) >> (32 - 10); }
+static_assert(kHCap == 1024, "hs_slot assumes 2^10 slots");
+
+__device__ __forceinline__ BfsOut center_hit(const CompactDev &cd, uint32_t r, uint32_t rank) {
+    const size_t row = (size_t)r * cd.rho;
+    const uint32_t l = cd.label_c[row + rank];
+    return BfsOut{cd.size_c[row + l], l, false};
+}
+
+// GetCenter with the queue and visited set in LDS (q: kQCap, hs: kHCap words).
+__device__ BfsOut getcenter_lds(const GraphDev &g, const ProbDev &pm, uint64_t kr, const CompactDev &cd,
+                                uint32_t r, const uint8_t *__restrict__ in_s, uint32_t v, uint32_t *q,
+                                uint32_t *hs) {
+    const uint32_t lane = lane_id();
+    const uint32_t cr0 = cd.center_rank[v];
+    if (cr0 != kNone) return center_hit(cd, r, cr0);
+    for (uint32_t i = lane; i < kHCap; i += kWave) hs[i] = kNone;
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+        q[0] = v;
+        hs[hs_slot(v)] = v;
+    }
+    __builtin_amdgcn_wave_barrier();
+    uint32_t head = 0, tail = 1, found = kNone;
+    bool met = in_s[v] != 0;
+    while (head < tail && found == kNone) {
+        const uint32_t u = q[head];
+        ++head;
+        const uint64_t o1 = g.off[u + 1];
+        for (uint64_t base = g.off[u]; base < o1; base += kWave) {
+            const uint64_t j = base + lane;
+            bool live = false;
+            uint32_t w = 0;
+            if (j < o1) {
+                w = g.cols[j];
+                const uint64_t x = edge_word(u, w);
+                live = is_live(x, kr, edge_threshold(pm, x));
+            }
+            const uint32_t wr = live ? cd.center_rank[w] : kNone;
+            const uint64_t cm = __ballot(wr != kNone);
+            if (cm) {
+                found = __shfl(wr, (int)__builtin_ctzll(cm));
+                break;
+            }
+            bool ins = false;
+            if (live) {
+                uint32_t h = hs_slot(w);
+                for (;;) {
+                    const uint32_t old = atomicCAS(&hs[h], kNone, w);
+                    if (old == kNone) { ins = true; break; }
+                    if (old == w) break;
+                    h = (h + 1) & (kHCap - 1);
+                }
+            }
+            const uint64_t im = __ballot(ins);
+            const uint32_t ni = (uint32_t)__popcll(im);
+            if (tail + ni > kQCap) return BfsOut{0, kNone, true};
+            if (ins) q[tail + (uint32_t)__popcll(im & ((1ull << lane) - 1ull))] = w;
+            if (__ballot(ins && in_s[w] != 0)) met = true;
+            tail += ni;
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if (found != kNone) return center_hit(cd, r, found);
+    return BfsOut{met ? 0ull : (uint64_t)tail, kNone, false};
+}
+
+// The same search with an n-entry queue and an n-bit visited bitmap in global
+// memory (one slot per wave); clears its bitmap bits before returning.
+__device__ BfsOut getcenter_global(const GraphDev &g, const ProbDev &pm, uint64_t kr, const CompactDev &cd,
+                                   uint32_t r, const uint8_t *__restrict__ in_s, uint32_t v, uint32_t *gq,
+                                   uint32_t *gvis) {
+    const uint32_t lane = lane_id();
+    const uint32_t cr0 = cd.center_rank[v];
+    if (cr0 != kNone) return center_hit(cd, r, cr0);
+    if (lane == 0) {
+        gq[0] = v;
+        atomicOr(&gvis[v >> 5], 1u << (v & 31));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    uint32_t head = 0, tail = 1, found = kNone;
+    bool met = in_s[v] != 0;
+    while (head < tail && found == kNone) {
+        const uint32_t u = __hip_atomic_load(&gq[head], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        ++head;
+        const uint64_t o1 = g.off[u + 1];
+        for (uint64_t base = g.off[u]; base < o1; base += kWave) {
+            const uint64_t j = base + lane;
+            bool live = false;
+            uint32_t w = 0;
+            if (j < o1) {
+                w = g.cols[j];
+                const uint64_t x = edge_word(u, w);
+                live = is_live(x, kr, edge_threshold(pm, x));
+            }
+            const uint32_t wr = live ? cd.center_rank[w] : kNone;
+            const uint64_t cm = __ballot(wr != kNone);
+            if (cm) {
+                found = __shfl(wr, (int)__builtin_ctzll(cm));
+                break;
+            }
+            bool ins = false;
+            if (live) {
+                const uint32_t bit = 1u << (w & 31);
+                ins = (atomicOr(&gvis[w >> 5], bit) & bit) == 0;
+            }
+            const uint64_t im = __ballot(ins);
+            if (ins) gq[tail + (uint32_t)__popcll(im & ((1ull << lane) - 1ull))] = w;
+            if (__ballot(ins && in_s[w] != 0)) met = true;
+            tail += (uint32_t)__popcll(im);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    for (uint32_t i = lane; i < tail; i += kWave) {
+        const uint32_t w = __hip_atomic_load(&gq[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        atomicAnd(&gvis[w >> 5], ~(1u << (w & 31)));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    if (found != kNone) return center_hit(cd, r, found);
+    return BfsOut{met ? 0ull : (uint64_t)tail, kNone, false};
+}
+
+__device__ __forceinline__ void push_overflow(SelState *st, uint2 *ov, uint32_t ov_cap, uint32_t a, uint32_t r) {
+    const uint32_t slot = atomicAdd(&st->ov_cnt, 1u);
+    if (slot < ov_cap) ov[slot] = make_uint2(a, r);
+    else st->err = 2;
+}
+
+// eval(l) on CompactSketch, part 1: one wave per (listed vertex, sketch), sketch-major.
+__global__ void __launch_bounds__(kBfsBlock) k_eval_compact_bfs(uint32_t l, SelState *__restrict__ st,
+                                                                const uint32_t *__restrict__ evl,
+                                                                unsigned long long *__restrict__ partial,
+                                                                GraphDev g, ProbDev pm, const uint64_t *__restrict__ K,
+                                                                uint32_t R, CompactDev cd,
+                                                                const uint8_t *__restrict__ in_s,
+                                                                uint2 *__restrict__ ov, uint32_t ov_cap) {
+    __shared__ uint32_t lds[kBfsWaves][kQCap + kHCap];
+    uint32_t *q = lds[threadIdx.x / kWave];
+    uint32_t *hs = q + kQCap;
+    const uint32_t ne = st->ev_cnt[l];
+    const uint64_t total = (uint64_t)ne * R;
+    for (uint64_t task = wave_index(); task < total; task += wave_count()) {
+        const uint32_t r = (uint32_t)(task / ne), e = (uint32_t)(task % ne);
+        const uint32_t v = evl[e];
+        const BfsOut o = getcenter_lds(g, pm, K[r], cd, r, in_s, v, q, hs);
+        if (lane_id() == 0) {
+            if (o.overflow) push_overflow(st, ov, ov_cap, e, r);
+            else if (o.delta) atomicAdd(&partial[e], (unsigned long long)o.delta);
+        }
+    }
+}
+
+// Global-memory searches for the tasks that overflowed.  mode 0: add delta to
+// partial[e]; mode 1 (MarkSeed of st->last_seed): zero size_c[r][label].
+__global__ void __launch_bounds__(64) k_overflow_bfs(int mode, SelState *__restrict__ st,
+                                                     const uint32_t *__restrict__ evl,
+                                                     unsigned long long *__restrict__ partial, GraphDev g,
+                                                     ProbDev pm, const uint64_t *__restrict__ K, CompactDev cd,
+                                                     const uint8_t *__restrict__ in_s,
+                                                     const uint2 *__restrict__ ov, uint32_t ov_cap,
+                                                     uint32_t *__restrict__ slot_q, uint32_t *__restrict__ slot_vis,
+                                                     uint32_t n) {
+    const uint32_t cnt = min(st->ov_cnt, ov_cap);
+    uint32_t *gq = slot_q + (size_t)blockIdx.x * n;
+    uint32_t *gvis = slot_vis + (size_t)blockIdx.x * ((n + 31) / 32);
+    for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+        const uint2 t = ov[i];
+        const uint32_t r = t.y;
+        const uint32_t v = (mode == 0) ? evl[t.x] : st->last_seed;
+        const BfsOut o = getcenter_global(g, pm, K[r], cd, r, in_s, v, gq, gvis);
+        if (lane_id() == 0) {
+            if (mode == 0) {
+                if (o.delta) atomicAdd(&partial[t.x], (unsigned long long)o.delta);
+            } else if (o.label != kNone) {
+                cd.size_c[(size_t)r * cd.rho + o.label] = 0;
+            }
+        }
+    }
+}
+
+// eval(l) on CompactSketch, part 2: keys from the summed deltas, Delta* update.
+__global__ void __launch_bounds__(256) k_eval_compact_finalize(uint32_t l, SelState *__restrict__ st,
+                                                               const uint32_t *__restrict__ evl,
+                                                               const unsigned long long *__restrict__ partial,
+                                                               uint32_t kb, const uint8_t *__restrict__ in_s,
+                                                               uint64_t *__restrict__ key) {
+    const uint32_t ne = st->ev_cnt[l];
+    uint64_t best = 0;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x) {
+        const uint32_t v = evl[e];
+        const uint64_t nk = in_s[v] ? 0ull : pack_key(partial[e], v, kb);
+        key[v] = nk;
+        best = nk > best ? nk : best;
+    }
+    best = wave_max_u64(best);
+    if (lane_id() == 0 && best) atomicMax(&st->delta, (unsigned long long)best);
+}
+
+// Resets the overflow list after its tasks ran (one thread).
+__global__ void k_overflow_reset(SelState *__restrict__ st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->overflow += st->ov_cnt;
+        st->ov_cnt = 0;
+    }
+}
+
+// MarkSeed on CompactSketch: one wave per sketch, GetCenter from the new seed.
+__global__ void __launch_bounds__(kBfsBlock) k_markseed_compact(SelState *__restrict__ st, GraphDev g, ProbDev pm,
+                                                                const uint64_t *__restrict__ K, uint32_t R,
+                                                                CompactDev cd, const uint8_t *__restrict__ in_s,
+                                                                uint2 *__restrict__ ov, uint32_t ov_cap) {
+    __shared__ uint32_t lds[kBfsWaves][kQCap + kHCap];
+    uint32_t *q = lds[threadIdx.x / kWave];
+    uint32_t *hs = q + kQCap;
+    const uint32_t s = st->last_seed;
+    for (uint32_t r = wave_index(); r < R; r += wave_count()) {
+        const BfsOut o = getcenter_lds(g, pm, K[r], cd, r, in_s, s, q, hs);
+        if (lane_id() == 0) {
+            if (o.overflow) push_overflow(st, ov, ov_cap, s, r);
+            else if (o.label != kNone) cd.size_c[(size_t)r * cd.rho + o.label] = 0;
+        }
+    }
+}
+
+}  // namespace pacim

@@ -1,0 +1,804 @@
+// Host runtime and C-ABI of the MI355X influence-maximization library.
+// Declarations, argument meaning and error behaviour: include/pacim.h.
+//
+// Device memory layout (all library-owned, one hipMalloc per array):
+//   graph     offsets u64[n+1], cols u32[m_dir] (symmetric CSR, for GetCenter),
+//             edges uint2[m_und] (u < v, for the sampling pass)
+//   full      E uint2[n][R]: (CC label, CC size if v is the label else 0);
+//             R consecutive entries per vertex so one evaluation reads 8R bytes
+//             in one contiguous run, and the size lookup of a singleton CC is the
+//             entry itself
+//   compact   center_rank u32[n], centers u32[rho], label_c u32[R][rho], size_c u32[R][rho]
+//   selection key u64[n], in_s u8[n], gain0 u64[n], tree ids u32[~n/63],
+//             frontier u32[~n/63], eval list u32[n], partial sums u64[n]
+//   scratch   parent/cnt(/minc) u32[B][n] for B sketches per pass, freed after the build
+#include "pacim.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "compact_kernels.h"
+#include "select_kernels.h"
+#include "sketch_kernels.h"
+
+using namespace pacim;
+
+namespace {
+
+struct KTimer {
+    uint64_t launches = 0;
+    double ms = 0.0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+};
+
+}  // namespace
+
+struct im_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t cap = 0;
+    size_t used = 0;
+    std::string err;
+    bool profiling = false;
+    std::map<std::string, KTimer> timers;
+    std::vector<hipEvent_t> spare_events;
+};
+
+struct im_graph {
+    im_ctx *ctx = nullptr;
+    uint32_t n = 0;
+    uint64_t m_dir = 0, m_und = 0;
+    uint64_t *off = nullptr;
+    uint32_t *cols = nullptr;
+    uint2 *edges = nullptr;
+};
+
+struct im_sketches {
+    im_ctx *ctx = nullptr;
+    const im_graph *g = nullptr;
+    uint32_t n = 0, R = 0;
+    uint64_t seed = 0;
+    double alpha = 1.0;
+    bool compact = false;
+    ProbDev pm{};
+    uint32_t kb = 1;
+    uint32_t rho = 0;
+    uint32_t B = 1;
+    // arrays
+    uint64_t *K = nullptr;
+    uint2 *E = nullptr;
+    uint32_t *center_rank = nullptr, *centers = nullptr, *label_c = nullptr, *size_c = nullptr;
+    uint32_t *size_c0 = nullptr;  // size_c as built (dump); only kept for small sketches
+    uint64_t *gain0 = nullptr, *key = nullptr;
+    uint8_t *in_s = nullptr;
+    TreeDesc td{};
+    uint32_t *ids = nullptr, *fr = nullptr, *evl = nullptr;
+    unsigned long long *partial = nullptr;
+    SelState *st = nullptr;
+    uint32_t *seeds_d = nullptr;
+    unsigned long long *gains_d = nullptr;
+    uint2 *ov = nullptr;
+    uint32_t ov_cap = 0;
+    uint32_t *slot_q = nullptr, *slot_vis = nullptr;
+    uint32_t slots = 0;
+    // bookkeeping
+    std::vector<std::pair<void *, size_t>> allocs;
+    uint32_t chosen = 0;
+    double build_ms = 0.0, select_ms = 0.0;
+    uint64_t bytes = 0;
+};
+
+// ---------------------------------------------------------------- helpers
+namespace {
+
+im_status fail(im_ctx *ctx, im_status s, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return s;
+}
+
+#define HIP_TRY(ctx, call)                                                                 \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail((ctx), IM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+im_status dev_alloc(im_ctx *ctx, size_t bytes, void **p) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 8;
+    if (ctx->cap && ctx->used + bytes > ctx->cap)
+        return fail(ctx, IM_ENOMEM, "allocation of " + std::to_string(bytes) + " bytes exceeds the context HBM cap");
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, IM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    ctx->used += bytes;
+    return IM_OK;
+}
+
+void dev_free(im_ctx *ctx, void *p, size_t bytes) {
+    if (!p) return;
+    if (bytes == 0) bytes = 8;
+    (void)hipFree(p);
+    ctx->used -= std::min(ctx->used, bytes);
+}
+
+template <typename T>
+im_status sk_alloc(im_sketches *s, size_t count, T **p) {
+    void *q = nullptr;
+    size_t bytes = count * sizeof(T);
+    im_status st = dev_alloc(s->ctx, bytes, &q);
+    if (st != IM_OK) return st;
+    s->allocs.push_back({q, bytes ? bytes : 8});
+    s->bytes += bytes;
+    *p = static_cast<T *>(q);
+    return IM_OK;
+}
+
+uint64_t threshold_of(double p) {
+    if (!(p > 0.0)) return 0;
+    if (p >= 1.0) return kAllLive;
+    return (uint64_t)std::ldexp(p, 64);
+}
+
+uint32_t bit_length(uint64_t x) {
+    uint32_t b = 0;
+    while (x) { ++b; x >>= 1; }
+    return b;
+}
+
+hipEvent_t take_event(im_ctx *ctx) {
+    if (!ctx->spare_events.empty()) {
+        hipEvent_t e = ctx->spare_events.back();
+        ctx->spare_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets a launch with HIP events on the context stream when profiling is on.
+struct Prof {
+    im_ctx *ctx;
+    const char *name;
+    hipEvent_t a = nullptr;
+    Prof(im_ctx *c, const char *nm) : ctx(c), name(nm) {
+        if (ctx->profiling) {
+            a = take_event(ctx);
+            if (a) (void)hipEventRecord(a, ctx->stream);
+        }
+    }
+    ~Prof() {
+        if (a) {
+            hipEvent_t b = take_event(ctx);
+            if (b) {
+                (void)hipEventRecord(b, ctx->stream);
+                ctx->timers[name].pending.push_back({a, b});
+            }
+        }
+    }
+};
+
+void drain_timers(im_ctx *ctx) {
+    for (auto &kv : ctx->timers) {
+        KTimer &t = kv.second;
+        for (auto &pr : t.pending) {
+            (void)hipEventSynchronize(pr.second);
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) t.ms += ms;
+            ++t.launches;
+            ctx->spare_events.push_back(pr.first);
+            ctx->spare_events.push_back(pr.second);
+        }
+        t.pending.clear();
+    }
+}
+
+unsigned grid_for(uint64_t items, unsigned block, unsigned cap) {
+    uint64_t g = (items + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+unsigned wave_grid(uint64_t waves, unsigned cap_waves) {
+    uint64_t w = std::min<uint64_t>(std::max<uint64_t>(waves, 1), cap_waves);
+    return (unsigned)((w + 3) / 4);  // 4 waves per 256-thread block
+}
+
+// LSD radix sort of uint64 keys (4 x 16-bit digits).
+void radix_sort_u64(std::vector<uint64_t> &a) {
+    std::vector<uint64_t> tmp(a.size());
+    std::vector<size_t> cnt(65536);
+    for (int pass = 0; pass < 4; ++pass) {
+        const int sh = pass * 16;
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (uint64_t x : a) cnt[(x >> sh) & 0xFFFF]++;
+        size_t s = 0;
+        for (auto &c : cnt) { size_t t = c; c = s; s += t; }
+        for (uint64_t x : a) tmp[cnt[(x >> sh) & 0xFFFF]++] = x;
+        a.swap(tmp);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- context
+extern "C" im_status im_ctx_create(int device, void *hip_stream, size_t hbm_cap, im_ctx **out) {
+    if (!out) return IM_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return IM_EDEVICE;
+    if (device < 0 || device >= ndev) return IM_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return IM_EDEVICE;
+    im_ctx *ctx = new (std::nothrow) im_ctx();
+    if (!ctx) return IM_ENOMEM;
+    ctx->device = device;
+    ctx->cap = hbm_cap;
+    if (hip_stream) {
+        ctx->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx;
+            return IM_EDEVICE;
+        }
+        ctx->own_stream = true;
+    }
+    *out = ctx;
+    return IM_OK;
+}
+
+extern "C" im_status im_ctx_destroy(im_ctx *ctx) {
+    if (!ctx) return IM_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    drain_timers(ctx);
+    for (hipEvent_t e : ctx->spare_events) (void)hipEventDestroy(e);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return IM_OK;
+}
+
+extern "C" const char *im_last_error(const im_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+extern "C" im_status im_ctx_memory(const im_ctx *ctx, size_t *used, size_t *cap) {
+    if (!ctx) return IM_EINVAL;
+    if (used) *used = ctx->used;
+    if (cap) *cap = ctx->cap;
+    return IM_OK;
+}
+
+extern "C" im_status im_ctx_set_profiling(im_ctx *ctx, int on) {
+    if (!ctx) return IM_EINVAL;
+    (void)hipStreamSynchronize(ctx->stream);
+    drain_timers(ctx);
+    if (on && !ctx->profiling) ctx->timers.clear();
+    ctx->profiling = on != 0;
+    return IM_OK;
+}
+
+extern "C" im_status im_kernel_time(im_ctx *ctx, const char *name, uint64_t *launches, double *ms) {
+    if (!ctx || !name) return IM_EINVAL;
+    (void)hipStreamSynchronize(ctx->stream);
+    drain_timers(ctx);
+    auto it = ctx->timers.find(name);
+    if (launches) *launches = it == ctx->timers.end() ? 0 : it->second.launches;
+    if (ms) *ms = it == ctx->timers.end() ? 0.0 : it->second.ms;
+    return IM_OK;
+}
+
+// ---------------------------------------------------------------- graph
+extern "C" im_status im_graph_upload(im_ctx *ctx, uint32_t n, uint64_t m_dir, const uint64_t *offsets,
+                                     const uint32_t *cols, int device_ptrs, im_graph **out) {
+    if (!ctx || !out) return IM_EINVAL;
+    *out = nullptr;
+    if (n == 0) return fail(ctx, IM_EINVAL, "n must be positive");
+    if (!offsets || (m_dir && !cols)) return fail(ctx, IM_EINVAL, "null CSR array");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    std::vector<uint64_t> off;
+    std::vector<uint32_t> col;
+    if (device_ptrs) {
+        off.resize((size_t)n + 1);
+        col.resize(m_dir);
+        HIP_TRY(ctx, hipMemcpy(off.data(), offsets, off.size() * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        if (m_dir) HIP_TRY(ctx, hipMemcpy(col.data(), cols, m_dir * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    } else {
+        off.assign(offsets, offsets + (size_t)n + 1);
+        col.assign(cols, cols + m_dir);
+    }
+    if (off[0] != 0 || off[n] != m_dir) return fail(ctx, IM_EINVAL, "offsets[0] must be 0 and offsets[n] = m_dir");
+    std::vector<uint32_t> mark(n, kNone);
+    std::vector<uint64_t> lo, hi;
+    lo.reserve(m_dir / 2);
+    hi.reserve(m_dir / 2);
+    for (uint32_t u = 0; u < n; ++u) {
+        if (off[u + 1] < off[u]) return fail(ctx, IM_EINVAL, "offsets are not monotone");
+        for (uint64_t j = off[u]; j < off[u + 1]; ++j) {
+            const uint32_t w = col[j];
+            if (w >= n) return fail(ctx, IM_EINVAL, "column id out of range");
+            if (w == u) return fail(ctx, IM_EINVAL, "self-loop at vertex " + std::to_string(u));
+            if (mark[w] == u) return fail(ctx, IM_EINVAL, "duplicate edge in row " + std::to_string(u));
+            mark[w] = u;
+            if (u < w) lo.push_back(((uint64_t)u << 32) | w);
+            else hi.push_back(((uint64_t)w << 32) | u);
+        }
+    }
+    if (lo.size() != hi.size()) return fail(ctx, IM_EINVAL, "CSR is not symmetric");
+    radix_sort_u64(lo);
+    radix_sort_u64(hi);
+    if (lo != hi) return fail(ctx, IM_EINVAL, "CSR is not symmetric");
+    hi.clear();
+    hi.shrink_to_fit();
+    const uint64_t m_und = lo.size();
+    std::vector<uint2> edges(m_und);
+    for (uint64_t i = 0; i < m_und; ++i) edges[i] = make_uint2((uint32_t)(lo[i] >> 32), (uint32_t)lo[i]);
+    lo.clear();
+    lo.shrink_to_fit();
+
+    im_graph *g = new (std::nothrow) im_graph();
+    if (!g) return fail(ctx, IM_ENOMEM, "host allocation");
+    g->ctx = ctx;
+    g->n = n;
+    g->m_dir = m_dir;
+    g->m_und = m_und;
+    im_status s;
+    if ((s = dev_alloc(ctx, ((size_t)n + 1) * 8, (void **)&g->off)) != IM_OK ||
+        (s = dev_alloc(ctx, m_dir * 4, (void **)&g->cols)) != IM_OK ||
+        (s = dev_alloc(ctx, m_und * 8, (void **)&g->edges)) != IM_OK) {
+        im_graph_free(g);
+        return s;
+    }
+    hipError_t e1 = hipMemcpy(g->off, off.data(), ((size_t)n + 1) * 8, hipMemcpyHostToDevice);
+    hipError_t e2 = m_dir ? hipMemcpy(g->cols, col.data(), m_dir * 4, hipMemcpyHostToDevice) : hipSuccess;
+    hipError_t e3 = m_und ? hipMemcpy(g->edges, edges.data(), m_und * 8, hipMemcpyHostToDevice) : hipSuccess;
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        im_graph_free(g);
+        return fail(ctx, IM_EDEVICE, "graph upload copy failed");
+    }
+    *out = g;
+    return IM_OK;
+}
+
+extern "C" im_status im_graph_free(im_graph *g) {
+    if (!g) return IM_EINVAL;
+    im_ctx *ctx = g->ctx;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    dev_free(ctx, g->off, ((size_t)g->n + 1) * 8);
+    dev_free(ctx, g->cols, g->m_dir * 4);
+    dev_free(ctx, g->edges, g->m_und * 8);
+    delete g;
+    return IM_OK;
+}
+
+// ---------------------------------------------------------------- sketches
+namespace {
+
+size_t g_scratch_budget() {
+    const char *e = getenv("PACIM_SCRATCH_MB");
+    size_t mb = e ? (size_t)strtoull(e, nullptr, 10) : 768;
+    return std::max<size_t>(mb, 1) << 20;
+}
+
+uint32_t g_batch_override() {
+    const char *e = getenv("PACIM_SKETCHES_PER_PASS");
+    return e ? (uint32_t)strtoul(e, nullptr, 10) : 0;
+}
+
+TreeDesc make_tree(uint32_t n) {
+    TreeDesc td{};
+    std::vector<uint32_t> sizes;  // internal levels from the deepest up
+    uint64_t cur = n;
+    do {
+        cur = (cur + kFan - 1) / kFan;
+        sizes.push_back((uint32_t)cur);
+    } while (cur > 1);
+    td.D = (uint32_t)sizes.size();
+    uint64_t off = 0;
+    for (uint32_t l = 0; l < td.D; ++l) {
+        td.lvl_n[l] = sizes[td.D - 1 - l];
+        td.lvl_off[l] = off;
+        off += td.lvl_n[l];
+    }
+    td.lvl_n[td.D] = n;
+    return td;
+}
+
+uint64_t tree_nodes(const TreeDesc &td) {
+    uint64_t t = 0;
+    for (uint32_t l = 0; l < td.D; ++l) t += td.lvl_n[l];
+    return t;
+}
+
+void free_sketches(im_sketches *s) {
+    for (auto &pr : s->allocs) dev_free(s->ctx, pr.first, pr.second);
+    s->allocs.clear();
+}
+
+}  // namespace
+
+extern "C" im_status im_sketches_free(im_sketches *s) {
+    if (!s) return IM_EINVAL;
+    (void)hipSetDevice(s->ctx->device);
+    (void)hipStreamSynchronize(s->ctx->stream);
+    free_sketches(s);
+    delete s;
+    return IM_OK;
+}
+
+extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob prob, uint32_t R, uint64_t seed,
+                                       double alpha, im_sketches **out) {
+    if (!ctx || !g || !out) return IM_EINVAL;
+    *out = nullptr;
+    if (R == 0) return fail(ctx, IM_EINVAL, "R must be >= 1");
+    if (!(alpha > 0.0) || alpha > 1.0) return fail(ctx, IM_EINVAL, "alpha must lie in (0, 1]");
+    if (prob.kind != IM_PROB_UNIFORM && prob.kind != IM_PROB_TRIVALENCY)
+        return fail(ctx, IM_EINVAL, "unknown probability model");
+    if (prob.kind == IM_PROB_UNIFORM && !(prob.p >= 0.0 && prob.p <= 1.0))
+        return fail(ctx, IM_EINVAL, "p must lie in [0, 1]");
+    const uint32_t n = g->n;
+    const uint32_t kb = std::max<uint32_t>(1, bit_length((uint64_t)n - 1));
+    if (kb + bit_length((uint64_t)R * n + 1) > 64) return fail(ctx, IM_EINVAL, "R*n too large for 64-bit keys");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+
+    im_sketches *s = new (std::nothrow) im_sketches();
+    if (!s) return fail(ctx, IM_ENOMEM, "host allocation");
+    s->ctx = ctx;
+    s->g = g;
+    s->n = n;
+    s->R = R;
+    s->seed = seed;
+    s->alpha = alpha;
+    s->compact = alpha < 1.0;
+    s->kb = kb;
+    s->pm.kind = prob.kind;
+    if (prob.kind == IM_PROB_UNIFORM) {
+        s->pm.t0 = threshold_of(prob.p);
+    } else {
+        s->pm.t0 = threshold_of(0.1);
+        s->pm.t1 = threshold_of(0.01);
+        s->pm.t2 = threshold_of(0.001);
+    }
+    hipStream_t st = ctx->stream;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
+        delete s;
+        return fail(ctx, IM_EDEVICE, "hipEventCreate failed");
+    }
+    uint32_t *parent = nullptr, *cnt = nullptr, *minc = nullptr;
+    size_t scratch_bytes = 0;
+    auto bail = [&](im_status code) {
+        if (parent) dev_free(ctx, parent, scratch_bytes);
+        (void)hipEventDestroy(t0);
+        (void)hipEventDestroy(t1);
+        free_sketches(s);
+        delete s;
+        return code;
+    };
+#define SK_TRY(expr)                      \
+    do {                                  \
+        im_status e_ = (expr);            \
+        if (e_ != IM_OK) return bail(e_); \
+    } while (0)
+#define SK_HIP(call)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess) {                                                                \
+            fail(ctx, IM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));          \
+            return bail(IM_EDEVICE);                                                           \
+        }                                                                                      \
+    } while (0)
+
+    SK_HIP(hipEventRecord(t0, st));
+    // trivalency class key K(0, SALT_TRIV) and the per-sketch keys, on the device
+    SK_TRY(sk_alloc(s, (size_t)R + 1, &s->K));
+    k_sketch_keys<<<grid_for(R, 256, 1u << 20), 256, 0, st>>>(seed, R, s->K);
+    k_salt_key<<<1, 64, 0, st>>>(0, kSaltTriv, s->K + R);  // K(0, SALT_TRIV) for the trivalency class
+    SK_HIP(hipGetLastError());
+
+    // centers (CompactSketch)
+    if (s->compact) {
+        const uint32_t nch = (n + kCenterChunk - 1) / kCenterChunk;
+        uint32_t *chunk = nullptr, *rho_d = nullptr;
+        SK_TRY(sk_alloc(s, nch, &chunk));
+        SK_TRY(sk_alloc(s, 1, &rho_d));
+        SK_TRY(sk_alloc(s, n, &s->center_rank));
+        const uint64_t Ta = threshold_of(alpha);
+        k_center_count<<<nch, 256, 0, st>>>(n, seed, Ta, chunk);
+        k_center_scan<<<1, 1024, 0, st>>>(nch, chunk, rho_d);
+        uint32_t rho = 0;
+        SK_HIP(hipMemcpyAsync(&rho, rho_d, 4, hipMemcpyDeviceToHost, st));
+        SK_HIP(hipStreamSynchronize(st));
+        s->rho = rho;
+        SK_TRY(sk_alloc(s, std::max<uint32_t>(rho, 1), &s->centers));
+        k_center_write<<<nch, 256, 0, st>>>(n, seed, Ta, chunk, s->center_rank, s->centers);
+        SK_TRY(sk_alloc(s, (size_t)R * std::max<uint32_t>(rho, 1), &s->label_c));
+        SK_TRY(sk_alloc(s, (size_t)R * std::max<uint32_t>(rho, 1), &s->size_c));
+    } else {
+        s->rho = n;
+        SK_TRY(sk_alloc(s, (size_t)n * R, &s->E));
+    }
+    SK_TRY(sk_alloc(s, n, &s->gain0));
+    SK_HIP(hipMemsetAsync(s->gain0, 0, (size_t)n * 8, st));
+
+    // sketches per pass over the edge list
+    const size_t per_sketch = (size_t)n * 4 * (s->compact ? 3 : 2);
+    uint32_t B = (uint32_t)std::min<size_t>({(size_t)R, (size_t)64, std::max<size_t>(1, g_scratch_budget() / per_sketch)});
+    if (uint32_t ov = g_batch_override()) B = std::min<uint32_t>({ov, R, 64u});
+    s->B = B;
+    scratch_bytes = per_sketch * B;
+    SK_TRY(dev_alloc(ctx, scratch_bytes, (void **)&parent));
+    cnt = parent + (size_t)B * n;
+    minc = s->compact ? cnt + (size_t)B * n : nullptr;
+
+    ProbDev pm = s->pm;
+    {
+        // the trivalency key is read back once (8 bytes) so it can travel by value
+        SK_HIP(hipMemcpyAsync(&pm.ktriv, s->K + R, 8, hipMemcpyDeviceToHost, st));
+        SK_HIP(hipStreamSynchronize(st));
+        s->pm.ktriv = pm.ktriv;
+    }
+    const unsigned hook_grid = grid_for(g->m_und, 256, 256 * 16);
+    for (uint32_t r0 = 0; r0 < R; r0 += B) {
+        const uint32_t b = std::min(B, R - r0);
+        dim3 gi((n + 255) / 256, b);
+        k_batch_init<<<gi, 256, 0, st>>>(parent, cnt, minc, n);
+        {
+            Prof p(ctx, "sample_hook");
+            if (pm.kind == 0)
+                k_sample_hook<0><<<hook_grid, 256, 0, st>>>(g->edges, g->m_und, s->K + r0, b, pm, parent, n);
+            else
+                k_sample_hook<1><<<hook_grid, 256, 0, st>>>(g->edges, g->m_und, s->K + r0, b, pm, parent, n);
+        }
+        {
+            Prof p(ctx, "compress");
+            k_compress<<<gi, 256, 0, st>>>(parent, cnt, n, s->compact ? s->center_rank : nullptr, minc);
+        }
+        if (s->compact) {
+            Prof p(ctx, "emit");
+            dim3 ge((std::max<uint32_t>(s->rho, 1) + 255) / 256, b);
+            if (s->rho) k_emit_compact<<<ge, 256, 0, st>>>(parent, cnt, minc, s->centers, s->rho, n, r0, s->label_c, s->size_c);
+            k_gain0<<<(n + 255) / 256, 256, 0, st>>>(parent, cnt, n, b, s->gain0);
+        } else {
+            Prof p(ctx, "emit");
+            k_emit_full<<<(n + kEmitTile - 1) / kEmitTile, 256, 0, st>>>(parent, cnt, n, b, R, r0, s->E, s->gain0);
+        }
+        SK_HIP(hipGetLastError());
+    }
+
+    // selection state
+    s->td = make_tree(n);
+    const uint64_t tn = tree_nodes(s->td);
+    SK_TRY(sk_alloc(s, n, &s->key));
+    SK_TRY(sk_alloc(s, n, &s->in_s));
+    SK_TRY(sk_alloc(s, tn, &s->ids));
+    SK_TRY(sk_alloc(s, tn, &s->fr));
+    SK_TRY(sk_alloc(s, n, &s->evl));
+    SK_TRY(sk_alloc(s, 1, &s->st));
+    SK_TRY(sk_alloc(s, n, &s->seeds_d));
+    SK_TRY(sk_alloc(s, n, &s->gains_d));
+    SK_HIP(hipMemsetAsync(s->in_s, 0, n, st));
+    SK_HIP(hipMemsetAsync(s->st, 0, sizeof(SelState), st));
+    if (s->compact) {
+        SK_TRY(sk_alloc(s, n, &s->partial));
+        s->ov_cap = 1u << 22;
+        SK_TRY(sk_alloc(s, s->ov_cap, &s->ov));
+        const size_t per_slot = (size_t)n * 4 + (size_t)((n + 31) / 32) * 4;
+        s->slots = (uint32_t)std::max<size_t>(1, std::min<size_t>(64, (size_t)(256u << 20) / per_slot));
+        SK_TRY(sk_alloc(s, (size_t)s->slots * n, &s->slot_q));
+        SK_TRY(sk_alloc(s, (size_t)s->slots * ((n + 31) / 32), &s->slot_vis));
+        SK_HIP(hipMemsetAsync(s->slot_vis, 0, (size_t)s->slots * ((n + 31) / 32) * 4, st));
+    }
+    k_keys_from_gain0<<<(n + 255) / 256, 256, 0, st>>>(s->gain0, n, kb, s->key);
+    for (int l = (int)s->td.D - 1; l >= 0; --l)
+        k_tree_build_level<<<wave_grid(s->td.lvl_n[l], 8192), 256, 0, st>>>(s->td, (uint32_t)l, s->ids, s->key);
+    SK_HIP(hipGetLastError());
+    SK_HIP(hipEventRecord(t1, st));
+    SK_HIP(hipEventSynchronize(t1));
+    dev_free(ctx, parent, scratch_bytes);
+    parent = nullptr;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, t0, t1);
+    s->build_ms = ms;
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    *out = s;
+    return IM_OK;
+#undef SK_TRY
+#undef SK_HIP
+}
+
+// ---------------------------------------------------------------- selection
+namespace {
+
+im_status enqueue_round(im_sketches *s) {
+    im_ctx *ctx = s->ctx;
+    hipStream_t st = ctx->stream;
+    const TreeDesc &td = s->td;
+    GraphDev gd{s->g->off, s->g->cols};
+    CompactDev cd{s->center_rank, s->label_c, s->size_c, s->rho};
+    auto eval = [&](uint32_t l) {
+        uint64_t cap = (l == 0) ? 1 : std::min<uint64_t>((uint64_t)s->n, (uint64_t)td.lvl_n[l - 1] * kFan);
+        if (!s->compact) {
+            k_eval_full<<<wave_grid(cap, 8192), 256, 0, st>>>(l, s->st, s->evl, s->E, s->R, s->kb, s->in_s, s->key);
+        } else {
+            k_eval_compact_bfs<<<wave_grid(cap * s->R, 16384), kBfsBlock, 0, st>>>(
+                l, s->st, s->evl, s->partial, gd, s->pm, s->K, s->R, cd, s->in_s, s->ov, s->ov_cap);
+            k_overflow_bfs<<<s->slots, 64, 0, st>>>(0, s->st, s->evl, s->partial, gd, s->pm, s->K, cd, s->in_s,
+                                                    s->ov, s->ov_cap, s->slot_q, s->slot_vis, s->n);
+            k_eval_compact_finalize<<<grid_for(cap, 256, 4096), 256, 0, st>>>(l, s->st, s->evl, s->partial, s->kb,
+                                                                           s->in_s, s->key);
+            k_overflow_reset<<<1, 64, 0, st>>>(s->st);
+        }
+    };
+    k_round_begin<<<1, 64, 0, st>>>(td, s->st, s->ids, s->fr, s->evl, s->partial);
+    eval(0);
+    for (uint32_t l = 0; l < td.D; ++l) {
+        k_check<<<wave_grid(td.lvl_n[l], 8192), 256, 0, st>>>(td, l, s->st, s->ids, s->key, s->fr, s->evl, s->partial);
+        eval(l + 1);
+    }
+    for (int l = (int)td.D - 1; l >= 0; --l)
+        k_relink<<<wave_grid(td.lvl_n[l], 8192), 256, 0, st>>>(td, (uint32_t)l, s->st, s->ids, s->key, s->fr);
+    k_round_end<<<1, 64, 0, st>>>(td, s->st, s->ids, s->key, s->in_s, s->kb, s->seeds_d, s->gains_d,
+                                  s->compact ? nullptr : s->E, s->R);
+    if (s->compact) {
+        k_markseed_compact<<<wave_grid(s->R, 4096), kBfsBlock, 0, st>>>(s->st, gd, s->pm, s->K, s->R, cd, s->in_s,
+                                                                         s->ov, s->ov_cap);
+        k_overflow_bfs<<<s->slots, 64, 0, st>>>(1, s->st, s->evl, s->partial, gd, s->pm, s->K, cd, s->in_s, s->ov,
+                                                s->ov_cap, s->slot_q, s->slot_vis, s->n);
+        k_overflow_reset<<<1, 64, 0, st>>>(s->st);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ctx, IM_EDEVICE, std::string("select launch: ") + hipGetErrorString(e));
+    return IM_OK;
+}
+
+}  // namespace
+
+extern "C" im_status im_select_seeds_from(im_ctx *ctx, im_sketches *s, uint32_t k, uint32_t *seeds_out,
+                                          uint64_t *gains_out) {
+    if (!ctx || !s || s->ctx != ctx) return IM_EINVAL;
+    if (k && (!seeds_out || !gains_out)) return fail(ctx, IM_EINVAL, "null output array");
+    if ((uint64_t)k + s->chosen > s->n) return fail(ctx, IM_EINVAL, "k exceeds the number of unselected vertices");
+    if (k == 0) return IM_OK;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    hipEvent_t t0, t1;
+    HIP_TRY(ctx, hipEventCreate(&t0));
+    HIP_TRY(ctx, hipEventCreate(&t1));
+    (void)hipEventRecord(t0, st);
+    im_status rc = IM_OK;
+    {
+        Prof p(ctx, "select");
+        for (uint32_t i = 0; i < k && rc == IM_OK; ++i) rc = enqueue_round(s);
+    }
+    (void)hipEventRecord(t1, st);
+    std::vector<uint32_t> seeds(k);
+    std::vector<unsigned long long> gains(k);
+    SelState hst{};
+    if (rc == IM_OK) {
+        hipError_t e1 = hipMemcpyAsync(seeds.data(), s->seeds_d + s->chosen, (size_t)k * 4, hipMemcpyDeviceToHost, st);
+        hipError_t e2 = hipMemcpyAsync(gains.data(), s->gains_d + s->chosen, (size_t)k * 8, hipMemcpyDeviceToHost, st);
+        hipError_t e3 = hipMemcpyAsync(&hst, s->st, sizeof(SelState), hipMemcpyDeviceToHost, st);
+        hipError_t e4 = hipStreamSynchronize(st);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess)
+            rc = fail(ctx, IM_EDEVICE, std::string("select: ") + hipGetErrorString(e4 != hipSuccess ? e4 : e1));
+    }
+    float ms = 0.f;
+    if (rc == IM_OK && hipEventElapsedTime(&ms, t0, t1) == hipSuccess) s->select_ms += ms;
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (rc != IM_OK) return rc;
+    if (hst.err) return fail(ctx, IM_EINTERNAL, "selection consistency check failed (code " + std::to_string(hst.err) + ")");
+    if (hst.round != s->chosen + k) return fail(ctx, IM_EINTERNAL, "round counter mismatch");
+    for (uint32_t i = 0; i < k; ++i) {
+        seeds_out[i] = seeds[i];
+        gains_out[i] = gains[i];
+    }
+    s->chosen += k;
+    return IM_OK;
+}
+
+extern "C" im_status im_select_seeds(im_ctx *ctx, const im_graph *g, im_prob prob, uint32_t R, uint32_t k,
+                                     uint64_t seed, uint32_t *seeds_out, uint64_t *gains_out) {
+    if (!ctx || !g) return IM_EINVAL;
+    if (k > g->n) return fail(ctx, IM_EINVAL, "k exceeds n");
+    im_sketches *s = nullptr;
+    im_status rc = im_build_sketches(ctx, g, prob, R, seed, 1.0, &s);
+    if (rc != IM_OK) return rc;
+    rc = im_select_seeds_from(ctx, s, k, seeds_out, gains_out);
+    im_sketches_free(s);
+    return rc;
+}
+
+// ---------------------------------------------------------------- inspection
+namespace {
+
+__global__ void k_dump_full(const uint2 *__restrict__ E, uint32_t n, uint32_t R, uint32_t r,
+                            uint32_t *__restrict__ lab, uint32_t *__restrict__ siz) {
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const uint2 e = E[(size_t)v * R + r];
+    lab[v] = e.x;
+    siz[v] = E[(size_t)e.x * R + r].y;
+}
+
+}  // namespace
+
+extern "C" im_status im_sketches_dump(im_ctx *ctx, const im_sketches *s, uint32_t r, uint32_t *labels,
+                                      uint32_t *sizes) {
+    if (!ctx || !s || !labels || !sizes) return IM_EINVAL;
+    if (r >= s->R) return fail(ctx, IM_EINVAL, "sketch index out of range");
+    if (s->chosen) return fail(ctx, IM_EINVAL, "dump is only available before seeds are selected");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    if (!s->compact) {
+        uint32_t *tmp = nullptr;
+        im_status a = dev_alloc(ctx, (size_t)s->n * 8, (void **)&tmp);
+        if (a != IM_OK) return a;
+        k_dump_full<<<(s->n + 255) / 256, 256, 0, st>>>(s->E, s->n, s->R, r, tmp, tmp + s->n);
+        hipError_t e1 = hipMemcpyAsync(labels, tmp, (size_t)s->n * 4, hipMemcpyDeviceToHost, st);
+        hipError_t e2 = hipMemcpyAsync(sizes, tmp + s->n, (size_t)s->n * 4, hipMemcpyDeviceToHost, st);
+        hipError_t e3 = hipStreamSynchronize(st);
+        dev_free(ctx, tmp, (size_t)s->n * 8);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return fail(ctx, IM_EDEVICE, "dump copy failed");
+        return IM_OK;
+    }
+    if (s->rho) {
+        HIP_TRY(ctx, hipMemcpyAsync(labels, s->label_c + (size_t)r * s->rho, (size_t)s->rho * 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(ctx, hipMemcpyAsync(sizes, s->size_c + (size_t)r * s->rho, (size_t)s->rho * 4, hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    return IM_OK;
+}
+
+extern "C" im_status im_centers(im_ctx *ctx, const im_sketches *s, uint32_t *centers, uint32_t *rho) {
+    if (!ctx || !s || !rho) return IM_EINVAL;
+    *rho = s->rho;
+    if (!centers) return IM_OK;
+    if (!s->compact) {
+        for (uint32_t v = 0; v < s->n; ++v) centers[v] = v;
+        return IM_OK;
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (s->rho) HIP_TRY(ctx, hipMemcpyAsync(centers, s->centers, (size_t)s->rho * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return IM_OK;
+}
+
+extern "C" im_status im_initial_gains(im_ctx *ctx, const im_sketches *s, uint64_t *gains) {
+    if (!ctx || !s || !gains) return IM_EINVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipMemcpyAsync(gains, s->gain0, (size_t)s->n * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return IM_OK;
+}
+
+extern "C" im_status im_sketches_stats(const im_sketches *s, im_sketch_stats *out) {
+    if (!s || !out) return IM_EINVAL;
+    SelState hst{};
+    (void)hipSetDevice(s->ctx->device);
+    if (hipMemcpy(&hst, s->st, sizeof(SelState), hipMemcpyDeviceToHost) != hipSuccess) return IM_EDEVICE;
+    out->seeds_chosen = s->chosen;
+    out->rho = s->rho;
+    out->evaluations = hst.evals;
+    out->bfs_overflow = hst.overflow;
+    out->build_ms = s->build_ms;
+    out->select_ms = s->select_ms;
+    out->sketches_per_pass = s->B;
+    out->sketch_bytes = s->bytes;
+    return IM_OK;
+}

@@ -1,0 +1,225 @@
+// Seed selection (Algorithm 1, step 2): NextSeed over a winning tree
+// (Sec. 4, Algorithm 5), Marginal (Sec. 3) on full labels or on CompactSketch
+// via GetCenter, and MarkSeed.
+//
+// The winning tree here has fan-out 64 instead of 2: a node is one wave and its
+// children are the wave's lanes, so the depth is ceil(log64 n) (4 for 2^20
+// vertices) and relinking a node is one wave-wide argmax.  Leaves are the
+// vertices themselves (leaf j is vertex j); internal level l holds ids[l][t],
+// the child with the largest key.  Algorithm 5's rules carry over unchanged:
+//   - a node is stale iff its id differs from its parent's (the root always is);
+//   - a stale node whose key is below Delta* (the best fresh key of the round)
+//     is pruned with its whole subtree;
+//   - a stale node at or above Delta* is re-evaluated and Delta* raised by an
+//     atomic max (WriteMax);
+//   - every non-pruned internal node is explored, then relinked to the child
+//     with the largest key.
+// The recursion of Algorithm 5 is run level by level: check(l) decides the
+// children of the level-l frontier, eval(l+1) re-evaluates the ones that need
+// it, and after the deepest level the frontiers are relinked bottom-up.  Keys
+// are unique ((gain+1) << kb | (2^kb-1-v)), so the argmax at the root is the
+// unique largest gain with the smallest id, the plain greedy's choice
+// (Theorem 4.4).
+#pragma once
+
+#include "common.h"
+
+namespace pacim {
+
+struct TreeDesc {
+    uint32_t D;                      // internal levels 0..D-1; level D = the n leaves
+    uint32_t lvl_n[kMaxLevels + 1];  // nodes per level
+    uint64_t lvl_off[kMaxLevels];    // offset of level l in ids / frontier buffers
+};
+
+struct SelState {
+    unsigned long long delta;        // Delta*: best fresh key this round
+    unsigned long long evals;        // re-evaluations over all rounds
+    unsigned long long overflow;     // GetCenter searches sent to the global-memory path
+    uint32_t fr_cnt[kMaxLevels + 1];
+    uint32_t ev_cnt[kMaxLevels + 1];
+    uint32_t ov_cnt;                 // overflow tasks pending in the current step
+    uint32_t round;                  // seeds chosen so far
+    uint32_t last_seed;
+    uint32_t err;
+};
+
+// ---- Marginal on full labels ------------------------------------------------
+// E[v][r] = (label, size-at-label).  Uncovered size of v in sketch r is the
+// size field of the label's own entry, zeroed by MarkSeed.
+__device__ __forceinline__ uint64_t marginal_full(const uint2 *__restrict__ E, uint32_t R, uint32_t v) {
+    const uint2 *row = E + (size_t)v * R;
+    uint64_t s = 0;
+    for (uint32_t r = lane_id(); r < R; r += kWave) {
+        const uint2 e = row[r];
+        s += (e.x == v) ? e.y : E[(size_t)e.x * R + r].y;
+    }
+    return wave_sum_u64(s);
+}
+
+// ---- tree build (initial keys from Marginal(empty, v)) ------------------------
+__global__ void k_keys_from_gain0(const uint64_t *__restrict__ gain0, uint32_t n, uint32_t kb,
+                                  uint64_t *__restrict__ key) {
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) key[v] = pack_key(gain0[v], v, kb);
+}
+
+// argmax over the children of node t of level l (wave-wide); returns the winner id
+// in every lane.  sub_child/sub_id/sub_key let the caller substitute one child's
+// freshly written id and key.
+__device__ __forceinline__ uint32_t relink_node(const TreeDesc &td, const uint32_t *__restrict__ ids,
+                                                const uint64_t *__restrict__ key, uint32_t l, uint32_t t,
+                                                uint32_t sub_child, uint32_t sub_id, uint64_t sub_key,
+                                                bool use_sub) {
+    const uint32_t lane = lane_id();
+    const uint32_t c = t * kFan + lane;
+    const bool valid = c < td.lvl_n[l + 1];
+    uint32_t cid = 0;
+    uint64_t ck = 0;
+    if (valid) {
+        cid = (l + 1 == td.D) ? c : ids[td.lvl_off[l + 1] + c];
+        ck = key[cid];
+        if (use_sub && c == sub_child) { cid = sub_id; ck = sub_key; }
+    }
+    const uint64_t best = wave_max_u64(valid ? ck : 0ull);
+    const uint64_t win = __ballot(valid && ck == best);
+    const uint32_t wl = (uint32_t)__builtin_ctzll(win);
+    return __shfl(cid, wl);
+}
+
+__global__ void __launch_bounds__(256) k_tree_build_level(TreeDesc td, uint32_t l, uint32_t *__restrict__ ids,
+                                                          const uint64_t *__restrict__ key) {
+    for (uint32_t t = wave_index(); t < td.lvl_n[l]; t += wave_count()) {
+        const uint32_t w = relink_node(td, ids, key, l, t, 0, 0, 0, false);
+        if (lane_id() == 0) ids[td.lvl_off[l] + t] = w;
+    }
+}
+
+// ---- one round ---------------------------------------------------------------
+// round_begin: the root is always stale; it is the one level-0 evaluation.
+__global__ void k_round_begin(TreeDesc td, SelState *__restrict__ st, const uint32_t *__restrict__ ids,
+                              uint32_t *__restrict__ fr, uint32_t *__restrict__ evl,
+                              unsigned long long *__restrict__ partial) {
+    if (threadIdx.x == 0) {
+        st->delta = 0;
+        for (int l = 0; l <= kMaxLevels; ++l) { st->fr_cnt[l] = 0; st->ev_cnt[l] = 0; }
+        st->ov_cnt = 0;
+        st->fr_cnt[0] = 1;
+        fr[td.lvl_off[0]] = 0;
+        st->ev_cnt[0] = 1;
+        evl[0] = ids[td.lvl_off[0]];
+        if (partial) partial[0] = 0;
+    }
+}
+
+// check(l): one wave per frontier node t of level l, one lane per child.
+__global__ void __launch_bounds__(256) k_check(TreeDesc td, uint32_t l, SelState *__restrict__ st,
+                                               const uint32_t *__restrict__ ids, const uint64_t *__restrict__ key,
+                                               uint32_t *__restrict__ fr, uint32_t *__restrict__ evl,
+                                               unsigned long long *__restrict__ partial) {
+    const uint32_t nf = st->fr_cnt[l];
+    const uint64_t delta = __hip_atomic_load(&st->delta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool leaf_children = (l + 1 == td.D);
+    for (uint32_t i = wave_index(); i < nf; i += wave_count()) {
+        const uint32_t t = fr[td.lvl_off[l] + i];
+        const uint32_t pid = ids[td.lvl_off[l] + t];
+        const uint32_t c = t * kFan + lane_id();
+        const bool valid = c < td.lvl_n[l + 1];
+        uint32_t cid = 0;
+        bool stale = false, need_eval = false;
+        if (valid) {
+            cid = leaf_children ? c : ids[td.lvl_off[l + 1] + c];
+            stale = cid != pid;
+            need_eval = stale && key[cid] >= delta;
+        }
+        const bool explore = valid && !leaf_children && (!stale || need_eval);
+        uint32_t tot;
+        const uint32_t ep = wave_append(&st->ev_cnt[l + 1], need_eval, &tot);
+        if (need_eval) {
+            evl[ep] = cid;
+            if (partial) partial[ep] = 0;
+        }
+        const uint32_t fp = wave_append(&st->fr_cnt[l + 1], explore, &tot);
+        if (explore) fr[td.lvl_off[l + 1] + fp] = c;
+    }
+}
+
+// eval(l) on full labels: one wave per listed vertex.
+__global__ void __launch_bounds__(256) k_eval_full(uint32_t l, SelState *__restrict__ st,
+                                                   const uint32_t *__restrict__ evl, const uint2 *__restrict__ E,
+                                                   uint32_t R, uint32_t kb, const uint8_t *__restrict__ in_s,
+                                                   uint64_t *__restrict__ key) {
+    const uint32_t ne = st->ev_cnt[l];
+    uint64_t best = 0;
+    for (uint32_t i = wave_index(); i < ne; i += wave_count()) {
+        const uint32_t v = evl[i];
+        const uint64_t g = marginal_full(E, R, v);
+        const uint64_t nk = in_s[v] ? 0ull : pack_key(g, v, kb);
+        if (lane_id() == 0) key[v] = nk;
+        best = nk > best ? nk : best;
+    }
+    if (lane_id() == 0 && best) atomicMax(&st->delta, (unsigned long long)best);
+}
+
+// relink(l): one wave per frontier node of level l (children already final).
+__global__ void __launch_bounds__(256) k_relink(TreeDesc td, uint32_t l, const SelState *__restrict__ st,
+                                                uint32_t *__restrict__ ids, const uint64_t *__restrict__ key,
+                                                const uint32_t *__restrict__ fr) {
+    const uint32_t nf = st->fr_cnt[l];
+    for (uint32_t i = wave_index(); i < nf; i += wave_count()) {
+        const uint32_t t = fr[td.lvl_off[l] + i];
+        const uint32_t w = relink_node(td, ids, key, l, t, 0, 0, 0, false);
+        if (lane_id() == 0) ids[td.lvl_off[l] + t] = w;
+    }
+}
+
+// round_end (one wave): record the root as the seed, remove it (key 0) and
+// relink its leaf-to-root path so the next round starts from the best stale
+// key; with full labels also MarkSeed: zero the size at the seed's label in
+// every sketch.
+__global__ void __launch_bounds__(64) k_round_end(TreeDesc td, SelState *__restrict__ st, uint32_t *__restrict__ ids,
+                                                  uint64_t *__restrict__ key, uint8_t *__restrict__ in_s,
+                                                  uint32_t kb, uint32_t *__restrict__ seeds_out,
+                                                  unsigned long long *__restrict__ gains_out,
+                                                  uint2 *__restrict__ E, uint32_t R) {
+    const uint32_t lane = lane_id();
+    const uint32_t s = ids[td.lvl_off[0]];
+    const uint64_t ks = key[s];
+    const uint32_t round = st->round;
+    const uint32_t evs = [&] {
+        uint32_t t = 0;
+        for (int l = 0; l <= kMaxLevels; ++l) t += st->ev_cnt[l];
+        return t;
+    }();
+    if (lane == 0) {
+        if (ks == 0 || in_s[s]) st->err = 1;
+        seeds_out[round] = s;
+        gains_out[round] = key_gain(ks, kb);
+        in_s[s] = 1;
+        key[s] = 0;
+        st->last_seed = s;
+        st->evals += evs;
+    }
+    // relink the path of leaf s, bottom-up, using the values this wave just wrote
+    uint32_t child = s, child_id = s;
+    uint64_t child_key = 0;
+    for (int l = (int)td.D - 1; l >= 0; --l) {
+        const uint32_t t = child >> kFanLog;
+        const uint32_t w = relink_node(td, ids, key, (uint32_t)l, t, child, child_id, child_key, true);
+        const uint64_t wk = (w == s) ? 0ull : key[w];
+        if (lane == 0) ids[td.lvl_off[l] + t] = w;
+        child = t;
+        child_id = w;
+        child_key = wk;
+    }
+    if (E) {
+        const uint2 *row = E + (size_t)s * R;
+        for (uint32_t r = lane; r < R; r += kWave) {
+            const uint32_t lab = row[r].x;
+            E[(size_t)lab * R + r].y = 0;
+        }
+    }
+    if (lane == 0) st->round = round + 1;
+}
+
+}  // namespace pacim

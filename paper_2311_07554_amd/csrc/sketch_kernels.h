@@ -1,0 +1,273 @@
+// Sketch construction (Sec. 3, Sketch(r); Algorithm 1, step 1) for a batch of
+// B sketches per pass over the edge list.
+//
+//   k_sketch_keys     K(seed, r) for every sketch
+//   k_batch_init      parent[b][v] = v, cnt = 0, minc = none
+//   k_sample_hook     one thread per undirected edge: B live tests (Sample(e, r),
+//                     fused: sampled graphs are never stored), then union by
+//                     hooking the larger root under the smaller one
+//   k_compress        every vertex points at its root (= smallest id of its CC);
+//                     non-root members counted at the root; centers' smallest
+//                     rank recorded at the root (CompactSketch)
+//   k_emit_full       (label, size) per (v, r) into E[n][R] and the initial gains
+//   k_emit_compact    CompactSketch triple label_c / size_c [R][rho]
+//   k_gain0           initial gains when only the compact triple is kept
+//   k_center_*        hashed Bernoulli(alpha) centers, ranked by id
+#pragma once
+
+#include "common.h"
+
+namespace pacim {
+
+__global__ void k_sketch_keys(uint64_t seed, uint32_t R, uint64_t *__restrict__ K) {
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < R) K[r] = sketch_key(seed, r);
+}
+
+__global__ void k_salt_key(uint64_t seed, uint64_t salt, uint64_t *__restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *out = sketch_key(seed, salt);
+}
+
+__global__ void k_batch_init(uint32_t *__restrict__ parent, uint32_t *__restrict__ cnt, uint32_t *__restrict__ minc,
+                             uint32_t n) {
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t at = (size_t)blockIdx.y * n + v;
+    if (v < n) {
+        parent[at] = v;
+        cnt[at] = 0;
+        if (minc) minc[at] = kNone;
+    }
+}
+
+// Relaxed loads of the union-find forest.  A value read here may be older than
+// the newest one (another XCD's L2, this CU's L1), but parent pointers only ever
+// move to smaller ids that stay ancestors, so an old value is still an ancestor.
+__device__ __forceinline__ uint32_t uf_load(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ uint32_t uf_find(uint32_t *P, uint32_t x) {
+    for (;;) {
+        uint32_t p = uf_load(P + x);
+        if (p == x) return x;
+        uint32_t gp = uf_load(P + p);
+        if (gp == p) return p;
+        // path halving; any ancestor is a valid parent
+        __hip_atomic_store(P + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x = gp;
+    }
+}
+
+// Union by hooking the larger root under the smaller, so the last root of every
+// component is its smallest vertex id whatever the schedule.  A failed CAS
+// returns the root's fresh parent, strictly smaller, so a+b strictly decreases
+// on every retry: the loop ends even when uf_find read old values.
+__device__ __forceinline__ void uf_unite(uint32_t *P, uint32_t a, uint32_t b) {
+    for (;;) {
+        a = uf_find(P, a);
+        b = uf_find(P, b);
+        if (a == b) return;
+        if (a < b) { uint32_t t = a; a = b; b = t; }
+        uint32_t expected = a;
+        if (__hip_atomic_compare_exchange_strong(P + a, &expected, b, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return;
+        a = expected;
+    }
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(256) k_sample_hook(const uint2 *__restrict__ edges, uint64_t m,
+                                                     const uint64_t *__restrict__ K, uint32_t B, ProbDev pm,
+                                                     uint32_t *__restrict__ parent, uint32_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
+        const uint2 uv = edges[e];
+        const uint64_t x = ((uint64_t)uv.x << 32) | uv.y;
+        uint64_t T;
+        if (KIND == 0) {
+            T = pm.t0;
+        } else {
+            const uint64_t c = mix64(x ^ pm.ktriv) % 3u;
+            T = c == 0 ? pm.t0 : (c == 1 ? pm.t1 : pm.t2);
+        }
+        uint64_t live = 0;
+        if (T == kAllLive) {
+            live = B >= 64 ? ~0ull : ((1ull << B) - 1ull);
+        } else {
+            for (uint32_t b = 0; b < B; ++b) live |= (uint64_t)(mix64(x ^ K[b]) < T) << b;
+        }
+        while (live) {
+            const uint32_t b = (uint32_t)__builtin_ctzll(live);
+            live &= live - 1ull;
+            uf_unite(parent + (size_t)b * n, uv.x, uv.y);
+        }
+    }
+}
+
+// grid: (ceil(n/256), B)
+__global__ void __launch_bounds__(256) k_compress(uint32_t *__restrict__ parent, uint32_t *__restrict__ cnt,
+                                                  uint32_t n, const uint32_t *__restrict__ center_rank,
+                                                  uint32_t *__restrict__ minc) {
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const size_t base = (size_t)blockIdx.y * n;
+    uint32_t *P = parent + base;
+    uint32_t r = v, p = P[v];
+    while (p != r) { r = p; p = P[r]; }
+    if (r != v) {
+        P[v] = r;
+        atomicAdd(cnt + base + r, 1u);
+    }
+    if (center_rank) {
+        const uint32_t cr = center_rank[v];
+        if (cr != kNone) atomicMin(minc + base + r, cr);
+    }
+}
+
+// One block of 256 threads per tile of 64 vertices; B <= 64.  The (label, size)
+// entries of the tile are staged in LDS so that each E row segment
+// E[v][r0 .. r0+B) is written by consecutive lanes.
+constexpr int kEmitTile = 64;
+__global__ void __launch_bounds__(256) k_emit_full(const uint32_t *__restrict__ parent,
+                                                   const uint32_t *__restrict__ cnt, uint32_t n, uint32_t B,
+                                                   uint32_t R, uint32_t r0, uint2 *__restrict__ E,
+                                                   uint64_t *__restrict__ gain0) {
+    __shared__ uint2 tile[kEmitTile][65];
+    __shared__ uint32_t gsz[kEmitTile][65];
+    const uint32_t v0 = blockIdx.x * kEmitTile;
+    for (uint32_t idx = threadIdx.x; idx < kEmitTile * B; idx += blockDim.x) {
+        const uint32_t b = idx / kEmitTile, vi = idx % kEmitTile, v = v0 + vi;
+        if (v < n) {
+            const size_t base = (size_t)b * n;
+            const uint32_t root = parent[base + v];
+            const uint32_t s = 1u + cnt[base + root];
+            tile[vi][b] = make_uint2(root, root == v ? s : 0u);
+            gsz[vi][b] = s;
+        }
+    }
+    __syncthreads();
+    for (uint32_t idx = threadIdx.x; idx < kEmitTile * B; idx += blockDim.x) {
+        const uint32_t vi = idx / B, b = idx % B, v = v0 + vi;
+        if (v < n) E[(size_t)v * R + r0 + b] = tile[vi][b];
+    }
+    if (threadIdx.x < kEmitTile) {
+        const uint32_t v = v0 + threadIdx.x;
+        if (v < n) {
+            uint64_t s = 0;
+            for (uint32_t b = 0; b < B; ++b) s += gsz[threadIdx.x][b];
+            gain0[v] += s;
+        }
+    }
+}
+
+// grid: (ceil(rho/256), B)
+__global__ void __launch_bounds__(256) k_emit_compact(const uint32_t *__restrict__ parent,
+                                                      const uint32_t *__restrict__ cnt,
+                                                      const uint32_t *__restrict__ minc,
+                                                      const uint32_t *__restrict__ centers, uint32_t rho,
+                                                      uint32_t n, uint32_t r0, uint32_t *__restrict__ label_c,
+                                                      uint32_t *__restrict__ size_c) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rho) return;
+    const uint32_t b = blockIdx.y;
+    const size_t base = (size_t)b * n;
+    const uint32_t v = centers[i];
+    const uint32_t root = parent[base + v];
+    const uint32_t l = minc[base + root];
+    const size_t at = (size_t)(r0 + b) * rho + i;
+    label_c[at] = l;
+    size_c[at] = (l == i) ? 1u + cnt[base + root] : 0u;
+}
+
+__global__ void __launch_bounds__(256) k_gain0(const uint32_t *__restrict__ parent, const uint32_t *__restrict__ cnt,
+                                               uint32_t n, uint32_t B, uint64_t *__restrict__ gain0) {
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    uint64_t s = 0;
+    for (uint32_t b = 0; b < B; ++b) {
+        const size_t base = (size_t)b * n;
+        s += 1u + cnt[base + parent[base + v]];
+    }
+    gain0[v] += s;
+}
+
+// ---- centers: flag, per-chunk counts, scan, ranks --------------------------
+constexpr uint32_t kCenterChunk = 1024;  // vertices per block (256 threads x 4)
+
+__device__ __forceinline__ bool center_flag(uint32_t v, uint64_t kc, uint64_t Ta) {
+    return Ta == kAllLive || mix64((uint64_t)v ^ kc) < Ta;
+}
+
+__global__ void __launch_bounds__(256) k_center_count(uint32_t n, uint64_t seed, uint64_t Ta,
+                                                      uint32_t *__restrict__ chunk_cnt) {
+    __shared__ uint32_t s;
+    if (threadIdx.x == 0) s = 0;
+    __syncthreads();
+    const uint64_t kc = sketch_key(seed, kSaltCenter);
+    uint32_t c = 0;
+    for (uint32_t j = 0; j < 4; ++j) {
+        const uint32_t v = blockIdx.x * kCenterChunk + j * 256 + threadIdx.x;
+        if (v < n && center_flag(v, kc, Ta)) ++c;
+    }
+    atomicAdd(&s, c);
+    __syncthreads();
+    if (threadIdx.x == 0) chunk_cnt[blockIdx.x] = s;
+}
+
+// single block: exclusive scan of chunk counts in place, total into *rho
+__global__ void __launch_bounds__(1024) k_center_scan(uint32_t nchunks, uint32_t *__restrict__ chunk_cnt,
+                                                      uint32_t *__restrict__ rho) {
+    __shared__ uint32_t part[1024];
+    const uint32_t per = (nchunks + 1023) / 1024;
+    const uint32_t lo = threadIdx.x * per, hi = min(nchunks, lo + per);
+    uint32_t s = 0;
+    for (uint32_t i = lo; i < hi; ++i) s += chunk_cnt[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+        uint32_t t = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += t;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - s;
+    for (uint32_t i = lo; i < hi; ++i) {
+        const uint32_t c = chunk_cnt[i];
+        chunk_cnt[i] = run;
+        run += c;
+    }
+    if (threadIdx.x == 1023) *rho = part[1023];
+}
+
+__global__ void __launch_bounds__(256) k_center_write(uint32_t n, uint64_t seed, uint64_t Ta,
+                                                      const uint32_t *__restrict__ chunk_off,
+                                                      uint32_t *__restrict__ center_rank,
+                                                      uint32_t *__restrict__ centers) {
+    __shared__ uint32_t flags[kCenterChunk];
+    __shared__ uint32_t pre[kCenterChunk];
+    const uint64_t kc = sketch_key(seed, kSaltCenter);
+    for (uint32_t j = 0; j < 4; ++j) {
+        const uint32_t i = j * 256 + threadIdx.x, v = blockIdx.x * kCenterChunk + i;
+        flags[i] = (v < n && center_flag(v, kc, Ta)) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {  // serial scan of 1024 flags: negligible next to the hash
+        uint32_t run = chunk_off[blockIdx.x];
+        for (uint32_t i = 0; i < kCenterChunk; ++i) { pre[i] = run; run += flags[i]; }
+    }
+    __syncthreads();
+    for (uint32_t j = 0; j < 4; ++j) {
+        const uint32_t i = j * 256 + threadIdx.x, v = blockIdx.x * kCenterChunk + i;
+        if (v < n) {
+            if (flags[i]) {
+                center_rank[v] = pre[i];
+                centers[pre[i]] = v;
+            } else {
+                center_rank[v] = kNone;
+            }
+        }
+    }
+}
+
+}  // namespace pacim

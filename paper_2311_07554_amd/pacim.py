@@ -1,0 +1,307 @@
+"""Thin ctypes binding of ``libpacim.so`` (the C-ABI declared in include/pacim.h).
+
+Argument marshalling only: every step of the influence-maximization path runs in
+the library's HIP kernels.  The module-level ``im_*`` functions mirror the C
+entry points one to one; ``Context``, ``Graph`` and ``Sketches`` wrap them with
+numpy / torch arguments.  torch, when given, only supplies device memory and the
+HIP stream.
+
+The binding refuses to work without the compiled library: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpacim.so")
+
+IM_OK, IM_EINVAL, IM_ENOMEM, IM_EDEVICE, IM_EBUSY, IM_EINTERNAL = range(6)
+IM_PROB_UNIFORM, IM_PROB_TRIVALENCY = 0, 1
+_STATUS = {0: "IM_OK", 1: "IM_EINVAL", 2: "IM_ENOMEM", 3: "IM_EDEVICE", 4: "IM_EBUSY", 5: "IM_EINTERNAL"}
+
+
+class ImError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class im_prob(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("p", ctypes.c_double)]
+
+
+class im_sketch_stats(ctypes.Structure):
+    _fields_ = [("seeds_chosen", ctypes.c_uint32), ("rho", ctypes.c_uint32), ("evaluations", ctypes.c_uint64),
+                ("bfs_overflow", ctypes.c_uint64), ("build_ms", ctypes.c_double), ("select_ms", ctypes.c_double),
+                ("sketches_per_pass", ctypes.c_uint32), ("sketch_bytes", ctypes.c_uint64)]
+
+
+_vp = ctypes.c_void_p
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+# name -> (restype, argtypes); the names and order follow include/pacim.h
+_SIGS = {
+    "im_ctx_create": (ctypes.c_int, [ctypes.c_int, _vp, ctypes.c_size_t, ctypes.POINTER(_vp)]),
+    "im_ctx_destroy": (ctypes.c_int, [_vp]),
+    "im_last_error": (ctypes.c_char_p, [_vp]),
+    "im_ctx_memory": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+    "im_ctx_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "im_kernel_time": (ctypes.c_int, [_vp, ctypes.c_char_p, _u64p, ctypes.POINTER(ctypes.c_double)]),
+    "im_graph_upload": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_uint64, _vp, _vp, ctypes.c_int,
+                                       ctypes.POINTER(_vp)]),
+    "im_graph_free": (ctypes.c_int, [_vp]),
+    "im_build_sketches": (ctypes.c_int, [_vp, _vp, im_prob, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double,
+                                         ctypes.POINTER(_vp)]),
+    "im_sketches_free": (ctypes.c_int, [_vp]),
+    "im_select_seeds_from": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _u32p, _u64p]),
+    "im_select_seeds": (ctypes.c_int, [_vp, _vp, im_prob, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                                       _u32p, _u64p]),
+    "im_sketches_dump": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _u32p, _u32p]),
+    "im_centers": (ctypes.c_int, [_vp, _vp, _u32p, _u32p]),
+    "im_initial_gains": (ctypes.c_int, [_vp, _vp, _u64p]),
+    "im_sketches_stats": (ctypes.c_int, [_vp, ctypes.POINTER(im_sketch_stats)]),
+}
+
+_lib = None
+
+
+def load():
+    """The compiled library; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} -- run __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def exported_symbols():
+    lib = load()
+    return [n for n in _SIGS if hasattr(lib, n)]
+
+
+def _u32(a):
+    return a.ctypes.data_as(_u32p)
+
+
+def _u64(a):
+    return a.ctypes.data_as(_u64p)
+
+
+# ---- module-level mirrors of the C entry points --------------------------------
+
+def im_ctx_create(device: int = 0, hip_stream: int | None = None, hbm_cap: int = 0) -> int:
+    h = _vp()
+    rc = load().im_ctx_create(device, hip_stream, hbm_cap, ctypes.byref(h))
+    if rc != IM_OK:
+        raise ImError(rc, "im_ctx_create failed (no usable HIP device?)")
+    return h.value
+
+
+def im_last_error(ctx) -> str:
+    s = load().im_last_error(ctx)
+    return s.decode() if s else ""
+
+
+def _check(ctx, rc):
+    if rc != IM_OK:
+        raise ImError(rc, im_last_error(ctx))
+
+
+def im_ctx_destroy(ctx):
+    _check(ctx, load().im_ctx_destroy(ctx))
+
+
+def im_ctx_memory(ctx):
+    used, cap = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(ctx, load().im_ctx_memory(ctx, ctypes.byref(used), ctypes.byref(cap)))
+    return used.value, cap.value
+
+
+def im_ctx_set_profiling(ctx, on: bool):
+    _check(ctx, load().im_ctx_set_profiling(ctx, int(bool(on))))
+
+
+def im_kernel_time(ctx, name: str):
+    n, ms = ctypes.c_uint64(), ctypes.c_double()
+    _check(ctx, load().im_kernel_time(ctx, name.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+def im_graph_upload(ctx, n: int, offsets, cols) -> int:
+    """offsets/cols: numpy arrays (host) or torch tensors (device or host)."""
+    dev = 0
+    if hasattr(offsets, "data_ptr"):
+        dev = int(offsets.is_cuda)
+        po, pc = offsets.data_ptr(), cols.data_ptr()
+        m_dir = int(cols.numel())
+        keep = (offsets, cols)
+    else:
+        offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+        cols = np.ascontiguousarray(cols, dtype=np.uint32)
+        po, pc = offsets.ctypes.data, cols.ctypes.data
+        m_dir = int(cols.size)
+        keep = (offsets, cols)
+    h = _vp()
+    _check(ctx, load().im_graph_upload(ctx, n, m_dir, po, pc if m_dir else None, dev, ctypes.byref(h)))
+    del keep
+    return h.value
+
+
+def im_graph_free(g):
+    rc = load().im_graph_free(g)
+    if rc != IM_OK:
+        raise ImError(rc, "im_graph_free")
+
+
+def _prob(kind: int, p: float):
+    return im_prob(int(kind), float(p))
+
+
+def im_build_sketches(ctx, g, kind: int, p: float, R: int, seed: int, alpha: float = 1.0) -> int:
+    h = _vp()
+    _check(ctx, load().im_build_sketches(ctx, g, _prob(kind, p), R, seed & ((1 << 64) - 1), float(alpha),
+                                         ctypes.byref(h)))
+    return h.value
+
+
+def im_sketches_free(s):
+    rc = load().im_sketches_free(s)
+    if rc != IM_OK:
+        raise ImError(rc, "im_sketches_free")
+
+
+def im_select_seeds_from(ctx, s, k: int):
+    seeds = np.empty(max(k, 1), dtype=np.uint32)
+    gains = np.empty(max(k, 1), dtype=np.uint64)
+    _check(ctx, load().im_select_seeds_from(ctx, s, k, _u32(seeds), _u64(gains)))
+    return seeds[:k], gains[:k]
+
+
+def im_select_seeds(ctx, g, kind: int, p: float, R: int, k: int, seed: int):
+    seeds = np.empty(max(k, 1), dtype=np.uint32)
+    gains = np.empty(max(k, 1), dtype=np.uint64)
+    _check(ctx, load().im_select_seeds(ctx, g, _prob(kind, p), R, k, seed & ((1 << 64) - 1), _u32(seeds),
+                                       _u64(gains)))
+    return seeds[:k], gains[:k]
+
+
+def im_centers(ctx, s):
+    rho = ctypes.c_uint32()
+    _check(ctx, load().im_centers(ctx, s, None, ctypes.byref(rho)))
+    c = np.empty(max(rho.value, 1), dtype=np.uint32)
+    _check(ctx, load().im_centers(ctx, s, _u32(c), ctypes.byref(rho)))
+    return c[: rho.value]
+
+
+def im_sketches_dump(ctx, s, r: int, count: int):
+    lab = np.empty(max(count, 1), dtype=np.uint32)
+    siz = np.empty(max(count, 1), dtype=np.uint32)
+    _check(ctx, load().im_sketches_dump(ctx, s, r, _u32(lab), _u32(siz)))
+    return lab[:count], siz[:count]
+
+
+def im_initial_gains(ctx, s, n: int):
+    g = np.empty(max(n, 1), dtype=np.uint64)
+    _check(ctx, load().im_initial_gains(ctx, s, _u64(g)))
+    return g[:n]
+
+
+def im_sketches_stats(s) -> dict:
+    st = im_sketch_stats()
+    rc = load().im_sketches_stats(s, ctypes.byref(st))
+    if rc != IM_OK:
+        raise ImError(rc, "im_sketches_stats")
+    return {f: getattr(st, f) for f, _ in im_sketch_stats._fields_}
+
+
+# ---- convenience wrappers ------------------------------------------------------
+
+class Context:
+    """An im_ctx on one device.  stream: a torch.cuda.Stream (or raw hipStream_t int) or None."""
+
+    def __init__(self, device: int = 0, stream=None, hbm_cap: int = 0):
+        raw = None
+        if stream is not None:
+            raw = getattr(stream, "cuda_stream", stream)
+        self.h = im_ctx_create(device, raw, hbm_cap)
+
+    def close(self):
+        if self.h:
+            im_ctx_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def graph(self, n, offsets, cols):
+        return Graph(self, n, offsets, cols)
+
+    def profiling(self, on=True):
+        im_ctx_set_profiling(self.h, on)
+
+    def kernel_time(self, name):
+        return im_kernel_time(self.h, name)
+
+    def memory(self):
+        return im_ctx_memory(self.h)
+
+
+class Graph:
+    def __init__(self, ctx: Context, n, offsets, cols):
+        self.ctx = ctx
+        self.n = int(n)
+        self.h = im_graph_upload(ctx.h, self.n, offsets, cols)
+
+    def close(self):
+        if self.h:
+            im_graph_free(self.h)
+            self.h = None
+
+    def sketches(self, kind, p, R, seed, alpha=1.0):
+        return Sketches(self, kind, p, R, seed, alpha)
+
+    def select_seeds(self, kind, p, R, k, seed):
+        return im_select_seeds(self.ctx.h, self.h, kind, p, R, k, seed)
+
+
+class Sketches:
+    def __init__(self, graph: Graph, kind, p, R, seed, alpha=1.0):
+        self.graph = graph
+        self.ctx = graph.ctx
+        self.R = int(R)
+        self.alpha = float(alpha)
+        self.h = im_build_sketches(self.ctx.h, graph.h, kind, p, R, seed, alpha)
+
+    def close(self):
+        if self.h:
+            im_sketches_free(self.h)
+            self.h = None
+
+    def select(self, k):
+        return im_select_seeds_from(self.ctx.h, self.h, k)
+
+    def centers(self):
+        return im_centers(self.ctx.h, self.h)
+
+    def dump(self, r):
+        count = self.graph.n if self.alpha >= 1.0 else int(self.stats()["rho"])
+        return im_sketches_dump(self.ctx.h, self.h, r, count)
+
+    def initial_gains(self):
+        return im_initial_gains(self.ctx.h, self.h, self.graph.n)
+
+    def stats(self):
+        return im_sketches_stats(self.h)
