@@ -143,6 +143,11 @@ im_status im_sketches_dump(im_ctx *ctx, const im_sketches *s, uint32_t r, uint32
 im_status im_centers(im_ctx *ctx, const im_sketches *s, uint32_t *centers, uint32_t *rho);
 /* Initial gains Marginal(empty, v) for every vertex: gains[n], host. */
 im_status im_initial_gains(im_ctx *ctx, const im_sketches *s, uint64_t *gains);
+/* Re-evaluations NextSeed performed in each of the first `count` rounds
+ * (count <= seeds chosen so far): the per-round |F_i| of Sec. 4 (the stale
+ * vertices re-evaluated before the seed is known), for comparison with CELF.
+ * Not unique: it depends on the traversal schedule. */
+im_status im_select_trace(im_ctx *ctx, const im_sketches *s, uint32_t *evals_per_round, uint32_t count);
 /* Counters of the handle: seeds chosen so far, total and per-call re-evaluations
  * performed by NextSeed, and the sketch build's byte/time figures. */
 typedef struct {
@@ -154,6 +159,9 @@ typedef struct {
     double select_ms;            /* device time of all im_select_seeds_from calls  */
     uint32_t sketches_per_pass;  /* sketches sampled per pass over the edge list  */
     uint64_t sketch_bytes;       /* device bytes held by the sketch arrays         */
+    uint32_t bulk_rounds;        /* CompactSketch rounds that evaluated every
+                                    vertex at once (after a seed that covered a
+                                    large share of every sketch)                   */
 } im_sketch_stats;
 im_status im_sketches_stats(const im_sketches *s, im_sketch_stats *out);
 

@@ -270,4 +270,60 @@ __global__ void __launch_bounds__(kBfsBlock) k_markseed_compact(SelState *__rest
     }
 }
 
+// ---- bulk round -------------------------------------------------------------
+// When the previous seed covered a large share of every sketch (a giant
+// component), nearly every stale key is invalid and the lazy search ends up
+// evaluating almost all vertices.  Such a round evaluates every unselected
+// vertex at once instead: the R sampled graphs are re-derived from their keys
+// (sketches are reproducible from r, the "fusion" of Sec. 2) with the sketch
+// kernels, and Marginal(S, v) = sum_r [CC_r(v) holds no seed] * |CC_r(v)|,
+// which is exactly what GetCenter returns (a CC's compact size is zeroed by
+// MarkSeed iff a seed lies in it).  The tree is then rebuilt from the fresh
+// keys, so its root is the plain greedy's choice.
+
+// flag[b][root of s] = 1 for every seed chosen so far (flag zeroed by k_batch_init).
+__global__ void __launch_bounds__(256) k_bulk_seed_roots(const SelState *__restrict__ st,
+                                                         const uint32_t *__restrict__ seeds,
+                                                         const uint32_t *__restrict__ parent, uint32_t n,
+                                                         uint32_t B, uint32_t *__restrict__ flag) {
+    const uint32_t ns = st->round;
+    const uint64_t total = (uint64_t)ns * B;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t b = (uint32_t)(i / ns), j = (uint32_t)(i % ns);
+        const size_t base = (size_t)b * n;
+        flag[base + parent[base + seeds[j]]] = 1u;
+    }
+}
+
+// partial[v] += sum over the batch of the uncovered CC size of v.
+__global__ void __launch_bounds__(256) k_bulk_accum(const uint32_t *__restrict__ parent,
+                                                    const uint32_t *__restrict__ cnt,
+                                                    const uint32_t *__restrict__ flag, uint32_t n, uint32_t B,
+                                                    unsigned long long *__restrict__ partial) {
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    uint64_t s = 0;
+    for (uint32_t b = 0; b < B; ++b) {
+        const size_t base = (size_t)b * n;
+        const uint32_t root = parent[base + v];
+        s += flag[base + root] ? 0u : 1u + cnt[base + root];
+    }
+    partial[v] += s;
+}
+
+// Fresh keys for every vertex; the round's evaluation count is every unselected vertex.
+__global__ void __launch_bounds__(256) k_bulk_keys(SelState *__restrict__ st,
+                                                   const unsigned long long *__restrict__ partial, uint32_t n,
+                                                   uint32_t kb, const uint8_t *__restrict__ in_s,
+                                                   uint64_t *__restrict__ key) {
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) key[v] = in_s[v] ? 0ull : pack_key(partial[v], v, kb);
+    if (v == 0) {
+        for (int l = 0; l <= kMaxLevels; ++l) { st->fr_cnt[l] = 0; st->ev_cnt[l] = 0; }
+        st->ev_cnt[0] = n - st->round;
+        st->ov_cnt = 0;
+    }
+}
+
 }  // namespace pacim

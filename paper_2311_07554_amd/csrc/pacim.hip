@@ -87,10 +87,15 @@ struct im_sketches {
     SelState *st = nullptr;
     uint32_t *seeds_d = nullptr;
     unsigned long long *gains_d = nullptr;
+    uint32_t *evals_d = nullptr;
     uint2 *ov = nullptr;
     uint32_t ov_cap = 0;
     uint32_t *slot_q = nullptr, *slot_vis = nullptr;
     uint32_t slots = 0;
+    uint32_t *bulk_scratch = nullptr;  // parent/cnt/flag [bulk_B][n], allocated at the first bulk round
+    uint32_t bulk_B = 0;
+    uint64_t last_gain = 0;            // gain of the latest seed (decides bulk rounds)
+    uint32_t bulk_rounds = 0;
     // bookkeeping
     std::vector<std::pair<void *, size_t>> allocs;
     uint32_t chosen = 0;
@@ -423,6 +428,30 @@ uint64_t tree_nodes(const TreeDesc &td) {
     return t;
 }
 
+// One pass over the edge list for b sketches (keys K[0..b)): union-find labels in
+// parent[b][n] (root = smallest id of the CC), member counts at the roots in
+// cnt, and (if center_rank) the smallest center rank of each CC in minc.
+void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const uint64_t *K, uint32_t b,
+                     uint32_t *parent, uint32_t *cnt, uint32_t *minc, uint32_t minc_init,
+                     const uint32_t *center_rank) {
+    hipStream_t st = ctx->stream;
+    const uint32_t n = g->n;
+    const unsigned hook_grid = grid_for(g->m_und, 256, 256 * 16);
+    dim3 gi((n + 255) / 256, b);
+    k_batch_init<<<gi, 256, 0, st>>>(parent, cnt, minc, n, minc_init);
+    {
+        Prof p(ctx, "sample_hook");
+        if (pm.kind == 0)
+            k_sample_hook<0><<<hook_grid, 256, 0, st>>>(g->edges, g->m_und, K, b, pm, parent, n);
+        else
+            k_sample_hook<1><<<hook_grid, 256, 0, st>>>(g->edges, g->m_und, K, b, pm, parent, n);
+    }
+    {
+        Prof p(ctx, "compress");
+        k_compress<<<gi, 256, 0, st>>>(parent, cnt, n, center_rank, minc);
+    }
+}
+
 void free_sketches(im_sketches *s) {
     for (auto &pr : s->allocs) dev_free(s->ctx, pr.first, pr.second);
     s->allocs.clear();
@@ -551,22 +580,9 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
         SK_HIP(hipStreamSynchronize(st));
         s->pm.ktriv = pm.ktriv;
     }
-    const unsigned hook_grid = grid_for(g->m_und, 256, 256 * 16);
     for (uint32_t r0 = 0; r0 < R; r0 += B) {
         const uint32_t b = std::min(B, R - r0);
-        dim3 gi((n + 255) / 256, b);
-        k_batch_init<<<gi, 256, 0, st>>>(parent, cnt, minc, n);
-        {
-            Prof p(ctx, "sample_hook");
-            if (pm.kind == 0)
-                k_sample_hook<0><<<hook_grid, 256, 0, st>>>(g->edges, g->m_und, s->K + r0, b, pm, parent, n);
-            else
-                k_sample_hook<1><<<hook_grid, 256, 0, st>>>(g->edges, g->m_und, s->K + r0, b, pm, parent, n);
-        }
-        {
-            Prof p(ctx, "compress");
-            k_compress<<<gi, 256, 0, st>>>(parent, cnt, n, s->compact ? s->center_rank : nullptr, minc);
-        }
+        enqueue_cc_pass(ctx, g, pm, s->K + r0, b, parent, cnt, minc, kNone, s->compact ? s->center_rank : nullptr);
         if (s->compact) {
             Prof p(ctx, "emit");
             dim3 ge((std::max<uint32_t>(s->rho, 1) + 255) / 256, b);
@@ -590,6 +606,7 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
     SK_TRY(sk_alloc(s, 1, &s->st));
     SK_TRY(sk_alloc(s, n, &s->seeds_d));
     SK_TRY(sk_alloc(s, n, &s->gains_d));
+    SK_TRY(sk_alloc(s, n, &s->evals_d));
     SK_HIP(hipMemsetAsync(s->in_s, 0, n, st));
     SK_HIP(hipMemsetAsync(s->st, 0, sizeof(SelState), st));
     if (s->compact) {
@@ -624,7 +641,7 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
 // ---------------------------------------------------------------- selection
 namespace {
 
-im_status enqueue_round(im_sketches *s) {
+im_status enqueue_lazy_round(im_sketches *s) {
     im_ctx *ctx = s->ctx;
     hipStream_t st = ctx->stream;
     const TreeDesc &td = s->td;
@@ -653,7 +670,7 @@ im_status enqueue_round(im_sketches *s) {
     for (int l = (int)td.D - 1; l >= 0; --l)
         k_relink<<<wave_grid(td.lvl_n[l], 8192), 256, 0, st>>>(td, (uint32_t)l, s->st, s->ids, s->key, s->fr);
     k_round_end<<<1, 64, 0, st>>>(td, s->st, s->ids, s->key, s->in_s, s->kb, s->seeds_d, s->gains_d,
-                                  s->compact ? nullptr : s->E, s->R);
+                                  s->evals_d, s->compact ? nullptr : s->E, s->R);
     if (s->compact) {
         k_markseed_compact<<<wave_grid(s->R, 4096), kBfsBlock, 0, st>>>(s->st, gd, s->pm, s->K, s->R, cd, s->in_s,
                                                                          s->ov, s->ov_cap);
@@ -664,6 +681,66 @@ im_status enqueue_round(im_sketches *s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(ctx, IM_EDEVICE, std::string("select launch: ") + hipGetErrorString(e));
     return IM_OK;
+}
+
+// A round that evaluates every unselected vertex (compact sketches): re-derive the
+// R sampled graphs' components, sum the uncovered CC sizes, rebuild the tree.
+im_status enqueue_bulk_round(im_sketches *s) {
+    im_ctx *ctx = s->ctx;
+    hipStream_t st = ctx->stream;
+    const uint32_t n = s->n;
+    if (!s->bulk_scratch) {
+        const size_t per_sketch = (size_t)n * 4 * 3;
+        uint32_t B = (uint32_t)std::min<size_t>({(size_t)s->R, (size_t)64, std::max<size_t>(1, g_scratch_budget() / per_sketch)});
+        im_status a = sk_alloc(s, per_sketch / 4 * B, &s->bulk_scratch);
+        if (a != IM_OK) return a;
+        s->bulk_B = B;
+    }
+    const uint32_t B = s->bulk_B;
+    uint32_t *parent = s->bulk_scratch, *cnt = parent + (size_t)B * n, *flag = cnt + (size_t)B * n;
+    GraphDev gd{s->g->off, s->g->cols};
+    CompactDev cd{s->center_rank, s->label_c, s->size_c, s->rho};
+    const TreeDesc &td = s->td;
+    hipError_t e0 = hipMemsetAsync(s->partial, 0, (size_t)n * 8, st);
+    if (e0 != hipSuccess) return fail(ctx, IM_EDEVICE, std::string("bulk round: ") + hipGetErrorString(e0));
+    for (uint32_t r0 = 0; r0 < s->R; r0 += B) {
+        const uint32_t b = std::min(B, s->R - r0);
+        enqueue_cc_pass(ctx, s->g, s->pm, s->K + r0, b, parent, cnt, flag, 0u, nullptr);
+        k_bulk_seed_roots<<<grid_for((uint64_t)n * b, 256, 1024), 256, 0, st>>>(s->st, s->seeds_d, parent, n, b, flag);
+        k_bulk_accum<<<(n + 255) / 256, 256, 0, st>>>(parent, cnt, flag, n, b, s->partial);
+    }
+    k_bulk_keys<<<(n + 255) / 256, 256, 0, st>>>(s->st, s->partial, n, s->kb, s->in_s, s->key);
+    for (int l = (int)td.D - 1; l >= 0; --l)
+        k_tree_build_level<<<wave_grid(td.lvl_n[l], 8192), 256, 0, st>>>(td, (uint32_t)l, s->ids, s->key);
+    k_round_end<<<1, 64, 0, st>>>(td, s->st, s->ids, s->key, s->in_s, s->kb, s->seeds_d, s->gains_d, s->evals_d,
+                                  nullptr, s->R);
+    k_markseed_compact<<<wave_grid(s->R, 4096), kBfsBlock, 0, st>>>(s->st, gd, s->pm, s->K, s->R, cd, s->in_s, s->ov,
+                                                                     s->ov_cap);
+    k_overflow_bfs<<<s->slots, 64, 0, st>>>(1, s->st, s->evl, s->partial, gd, s->pm, s->K, cd, s->in_s, s->ov,
+                                            s->ov_cap, s->slot_q, s->slot_vis, s->n);
+    k_overflow_reset<<<1, 64, 0, st>>>(s->st);
+    ++s->bulk_rounds;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ctx, IM_EDEVICE, std::string("bulk round launch: ") + hipGetErrorString(e));
+    return IM_OK;
+}
+
+// Policy for compact sketches: a round is run in bulk when the previous seed's
+// gain shows it covered at least 1/64 of the vertices per sketch on average
+// (PACIM_BULK=always|never overrides, for tests).
+int bulk_policy() {
+    const char *e = getenv("PACIM_BULK");
+    if (!e) return 0;
+    if (!strcmp(e, "always")) return 1;
+    if (!strcmp(e, "never")) return -1;
+    return 0;
+}
+
+bool want_bulk(const im_sketches *s) {
+    if (!s->compact || s->chosen == 0) return false;
+    const int pol = bulk_policy();
+    if (pol != 0) return pol > 0;
+    return s->last_gain * 64 >= (uint64_t)s->R * s->n;
 }
 
 }  // namespace
@@ -683,7 +760,26 @@ extern "C" im_status im_select_seeds_from(im_ctx *ctx, im_sketches *s, uint32_t 
     im_status rc = IM_OK;
     {
         Prof p(ctx, "select");
-        for (uint32_t i = 0; i < k && rc == IM_OK; ++i) rc = enqueue_round(s);
+        if (!s->compact) {
+            for (uint32_t i = 0; i < k && rc == IM_OK; ++i) rc = enqueue_lazy_round(s);
+        } else {
+            // compact: the gain of every seed is read back to choose the next round's kind
+            const uint32_t base = s->chosen;
+            for (uint32_t i = 0; i < k && rc == IM_OK; ++i) {
+                rc = want_bulk(s) ? enqueue_bulk_round(s) : enqueue_lazy_round(s);
+                if (rc != IM_OK) break;
+                unsigned long long g = 0;
+                hipError_t e1 = hipMemcpyAsync(&g, s->gains_d + base + i, 8, hipMemcpyDeviceToHost, st);
+                hipError_t e2 = hipStreamSynchronize(st);
+                if (e1 != hipSuccess || e2 != hipSuccess) {
+                    rc = fail(ctx, IM_EDEVICE, "select: gain read-back failed");
+                    break;
+                }
+                s->last_gain = g;
+                ++s->chosen;  // provisional, restored below
+            }
+            s->chosen = base;
+        }
     }
     (void)hipEventRecord(t1, st);
     std::vector<uint32_t> seeds(k);
@@ -787,6 +883,17 @@ extern "C" im_status im_initial_gains(im_ctx *ctx, const im_sketches *s, uint64_
     return IM_OK;
 }
 
+extern "C" im_status im_select_trace(im_ctx *ctx, const im_sketches *s, uint32_t *evals_per_round,
+                                     uint32_t count) {
+    if (!ctx || !s || (count && !evals_per_round)) return IM_EINVAL;
+    if (count > s->chosen) return fail(ctx, IM_EINVAL, "count exceeds the seeds chosen so far");
+    if (!count) return IM_OK;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipMemcpyAsync(evals_per_round, s->evals_d, (size_t)count * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return IM_OK;
+}
+
 extern "C" im_status im_sketches_stats(const im_sketches *s, im_sketch_stats *out) {
     if (!s || !out) return IM_EINVAL;
     SelState hst{};
@@ -800,5 +907,6 @@ extern "C" im_status im_sketches_stats(const im_sketches *s, im_sketch_stats *ou
     out->select_ms = s->select_ms;
     out->sketches_per_pass = s->B;
     out->sketch_bytes = s->bytes;
+    out->bulk_rounds = s->bulk_rounds;
     return IM_OK;
 }

@@ -181,7 +181,8 @@ __global__ void __launch_bounds__(64) k_round_end(TreeDesc td, SelState *__restr
                                                   uint64_t *__restrict__ key, uint8_t *__restrict__ in_s,
                                                   uint32_t kb, uint32_t *__restrict__ seeds_out,
                                                   unsigned long long *__restrict__ gains_out,
-                                                  uint2 *__restrict__ E, uint32_t R) {
+                                                  uint32_t *__restrict__ evals_out, uint2 *__restrict__ E,
+                                                  uint32_t R) {
     const uint32_t lane = lane_id();
     const uint32_t s = ids[td.lvl_off[0]];
     const uint64_t ks = key[s];
@@ -195,6 +196,7 @@ __global__ void __launch_bounds__(64) k_round_end(TreeDesc td, SelState *__restr
         if (ks == 0 || in_s[s]) st->err = 1;
         seeds_out[round] = s;
         gains_out[round] = key_gain(ks, kb);
+        evals_out[round] = evs;
         in_s[s] = 1;
         key[s] = 0;
         st->last_seed = s;

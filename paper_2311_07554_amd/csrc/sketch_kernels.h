@@ -29,13 +29,13 @@ __global__ void k_salt_key(uint64_t seed, uint64_t salt, uint64_t *__restrict__ 
 }
 
 __global__ void k_batch_init(uint32_t *__restrict__ parent, uint32_t *__restrict__ cnt, uint32_t *__restrict__ minc,
-                             uint32_t n) {
+                             uint32_t n, uint32_t minc_init) {
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     const size_t at = (size_t)blockIdx.y * n + v;
     if (v < n) {
         parent[at] = v;
         cnt[at] = 0;
-        if (minc) minc[at] = kNone;
+        if (minc) minc[at] = minc_init;
     }
 }
 
@@ -105,23 +105,45 @@ __global__ void __launch_bounds__(256) k_sample_hook(const uint2 *__restrict__ e
     }
 }
 
-// grid: (ceil(n/256), B)
+// grid: (ceil(n/256), B).  Every lane of a wave belongs to the same sketch, and
+// in social-like graphs many of them sit in the same (giant) component, so the
+// member count and the smallest center rank are combined per distinct root in
+// the wave before one atomic per root: without this, every member of a giant
+// component hits the same counter.
 __global__ void __launch_bounds__(256) k_compress(uint32_t *__restrict__ parent, uint32_t *__restrict__ cnt,
                                                   uint32_t n, const uint32_t *__restrict__ center_rank,
                                                   uint32_t *__restrict__ minc) {
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
+    const uint32_t lane = lane_id();
+    const bool valid = v < n;
     const size_t base = (size_t)blockIdx.y * n;
     uint32_t *P = parent + base;
-    uint32_t r = v, p = P[v];
-    while (p != r) { r = p; p = P[r]; }
-    if (r != v) {
-        P[v] = r;
-        atomicAdd(cnt + base + r, 1u);
+    uint32_t r = v;
+    if (valid) {
+        uint32_t p = P[v];
+        while (p != r) { r = p; p = P[r]; }
+        if (r != v) P[v] = r;
+    }
+    bool need = valid && r != v;
+    for (uint64_t m = __ballot(need); m; m = __ballot(need)) {
+        const uint32_t lr = __shfl(r, (int)__builtin_ctzll(m));
+        const bool same = need && r == lr;
+        const uint64_t sm = __ballot(same);
+        if (lane == (uint32_t)__builtin_ctzll(m)) atomicAdd(cnt + base + lr, (uint32_t)__popcll(sm));
+        if (same) need = false;
     }
     if (center_rank) {
-        const uint32_t cr = center_rank[v];
-        if (cr != kNone) atomicMin(minc + base + r, cr);
+        const uint32_t cr = valid ? center_rank[v] : kNone;
+        bool cneed = cr != kNone;
+        for (uint64_t m = __ballot(cneed); m; m = __ballot(cneed)) {
+            const uint32_t lr = __shfl(r, (int)__builtin_ctzll(m));
+            const bool same = cneed && r == lr;
+            uint32_t mn = same ? cr : kNone;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) mn = min(mn, (uint32_t)__shfl_xor(mn, off));
+            if (lane == (uint32_t)__builtin_ctzll(m)) atomicMin(minc + base + lr, mn);
+            if (same) cneed = false;
+        }
     }
 }
 

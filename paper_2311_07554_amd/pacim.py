@@ -36,7 +36,8 @@ class im_prob(ctypes.Structure):
 class im_sketch_stats(ctypes.Structure):
     _fields_ = [("seeds_chosen", ctypes.c_uint32), ("rho", ctypes.c_uint32), ("evaluations", ctypes.c_uint64),
                 ("bfs_overflow", ctypes.c_uint64), ("build_ms", ctypes.c_double), ("select_ms", ctypes.c_double),
-                ("sketches_per_pass", ctypes.c_uint32), ("sketch_bytes", ctypes.c_uint64)]
+                ("sketches_per_pass", ctypes.c_uint32), ("sketch_bytes", ctypes.c_uint64),
+                ("bulk_rounds", ctypes.c_uint32)]
 
 
 _vp = ctypes.c_void_p
@@ -64,6 +65,7 @@ _SIGS = {
     "im_centers": (ctypes.c_int, [_vp, _vp, _u32p, _u32p]),
     "im_initial_gains": (ctypes.c_int, [_vp, _vp, _u64p]),
     "im_sketches_stats": (ctypes.c_int, [_vp, ctypes.POINTER(im_sketch_stats)]),
+    "im_select_trace": (ctypes.c_int, [_vp, _vp, _u32p, ctypes.c_uint32]),
 }
 
 _lib = None
@@ -216,6 +218,12 @@ def im_initial_gains(ctx, s, n: int):
     return g[:n]
 
 
+def im_select_trace(ctx, s, count: int):
+    ev = np.empty(max(count, 1), dtype=np.uint32)
+    _check(ctx, load().im_select_trace(ctx, s, _u32(ev), count))
+    return ev[:count]
+
+
 def im_sketches_stats(s) -> dict:
     st = im_sketch_stats()
     rc = load().im_sketches_stats(s, ctypes.byref(st))
@@ -305,3 +313,6 @@ class Sketches:
 
     def stats(self):
         return im_sketches_stats(self.h)
+
+    def trace(self):
+        return im_select_trace(self.ctx.h, self.h, int(self.stats()["seeds_chosen"]))

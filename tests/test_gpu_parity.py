@@ -92,6 +92,28 @@ def test_rmat_compact_matches_oracle(ctx, alpha):
     gr.close()
 
 
+@pytest.mark.parametrize("policy", ["always", "never", "auto"])
+def test_compact_bulk_rounds_match_oracle(ctx, policy, monkeypatch):
+    # uniform p = 0.1 on R-MAT gives a giant component, so the first seed covers a
+    # large share of every sketch and "auto" switches the next round to bulk.
+    monkeypatch.setenv("PACIM_BULK", policy)
+    g = inputs.rmat_graph(12, 16 << 12, seed=31)
+    R, k, seed, alpha = 32, 25, 5, 0.1
+    _say(f"case compact bulk={policy}")
+    lab, siz = oracle.sketches(g, U, 0.1, seed, R, threads=8)
+    ws, wg = oracle.greedy(lab, siz, k)
+    s, gn, st = run_select(ctx, g, U, 0.1, R, k, seed, alpha=alpha)
+    assert np.array_equal(s, ws) and np.array_equal(gn, wg)
+    if policy == "always":
+        assert st["bulk_rounds"] == k - 1
+    elif policy == "never":
+        assert st["bulk_rounds"] == 0
+    else:
+        assert st["bulk_rounds"] >= 1
+    s2, g2, _ = run_select(ctx, g, U, 0.1, R, k, seed, alpha=alpha, chunks=[1, 3, 21])
+    assert np.array_equal(s2, ws) and np.array_equal(g2, wg)
+
+
 def test_compact_overflow_path_exact(ctx):
     # p = 1 on a long path: one component of 3000 vertices and a tiny alpha, so
     # GetCenter searches outgrow the on-chip queue and take the global-memory path.
