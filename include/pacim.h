@@ -112,7 +112,8 @@ im_status im_graph_free(im_graph *g);
  *            c_i's CC) and size_c[i] (CC size if label_c[i] = i, else 0) are kept,
  *            and Marginal uses the GetCenter BFS.
  * The initial gains Marginal(empty, v) = sum_r |CC_r(v)| are computed while the
- * components are built.  Requires R >= 1 and ceil(log2(R*n+2)) + ceil(log2 n) <= 64.
+ * components are built.  Requires R >= 1 and ceil(log2(R*n+2)) + ceil(log2 n) <= 64;
+ * CompactSketch also needs R*n < 2^40 and R < 2^24.
  * Errors: EINVAL (bad R, alpha outside (0,1], bad prob), ENOMEM, EDEVICE. */
 im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob prob, uint32_t R, uint64_t seed,
                             double alpha, im_sketches **out);
@@ -164,6 +165,16 @@ typedef struct {
                                     large share of every sketch)                   */
 } im_sketch_stats;
 im_status im_sketches_stats(const im_sketches *s, im_sketch_stats *out);
+
+/* ---- device ceilings (roofline) -------------------------------------------- */
+
+/* Measures, on the context's device, (a) the rate of live-edge hash tests the
+ * sampling loop's arithmetic reaches with no memory traffic (keys in scalar
+ * registers, 64 tests per edge word), in tests per second, and (b) the bandwidth
+ * of a streaming 16-byte-per-lane copy of 1 GiB, counting bytes read plus
+ * written, in bytes per second.  Allocates 2 GiB for the duration of the call.
+ * Errors: ENOMEM, EDEVICE. */
+im_status im_probe_device(im_ctx *ctx, double *hash_per_s, double *copy_bytes_per_s);
 
 #ifdef __cplusplus
 }

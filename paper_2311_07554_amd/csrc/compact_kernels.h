@@ -168,19 +168,38 @@ __device__ BfsOut getcenter_global(const GraphDev &g, const ProbDev &pm, uint64_
     return BfsOut{met ? 0ull : (uint64_t)tail, kNone, false};
 }
 
-__device__ __forceinline__ void push_overflow(SelState *st, uint2 *ov, uint32_t ov_cap, uint32_t a, uint32_t r) {
-    const uint32_t slot = atomicAdd(&st->ov_cnt, 1u);
+// Overflow tasks of one step go to list ovl (capacity ov_cap), counted in *ocnt.
+__device__ __forceinline__ void push_overflow(SelState *st, uint32_t *ocnt, uint2 *ov, uint32_t ov_cap, uint32_t a,
+                                              uint32_t r) {
+    const uint32_t slot = atomicAdd(ocnt, 1u);
     if (slot < ov_cap) ov[slot] = make_uint2(a, r);
     else st->err = 2;
 }
 
-// eval(l) on CompactSketch, part 1: one wave per (listed vertex, sketch), sketch-major.
+// Adds one sketch's delta to a listed vertex; the last of its R searches turns the
+// sum into the vertex's key and raises Delta*.  partial = (tasks left << 40) + sum.
+constexpr int kPartialShift = 40;
+__device__ __forceinline__ void add_delta(SelState *st, unsigned long long *partial, uint32_t e, uint64_t delta,
+                                          const uint32_t *evl, uint32_t kb, const uint8_t *in_s, uint64_t *key) {
+    const unsigned long long old = atomicAdd(&partial[e], (unsigned long long)(delta - (1ull << kPartialShift)));
+    if ((old >> kPartialShift) == 1ull) {
+        const uint64_t sum = (old & ((1ull << kPartialShift) - 1ull)) + delta;
+        const uint32_t v = evl[e];
+        const uint64_t nk = in_s[v] ? 0ull : pack_key(sum, v, kb);
+        key[v] = nk;
+        if (nk) atomicMax(&st->delta, (unsigned long long)nk);
+    }
+}
+
+// eval(l) on CompactSketch: one wave per (listed vertex, sketch), sketch-major;
+// searches that outgrow the LDS queue are listed for k_overflow_bfs.
 __global__ void __launch_bounds__(kBfsBlock) k_eval_compact_bfs(uint32_t l, SelState *__restrict__ st,
                                                                 const uint32_t *__restrict__ evl,
                                                                 unsigned long long *__restrict__ partial,
                                                                 GraphDev g, ProbDev pm, const uint64_t *__restrict__ K,
-                                                                uint32_t R, CompactDev cd,
+                                                                uint32_t R, CompactDev cd, uint32_t kb,
                                                                 const uint8_t *__restrict__ in_s,
+                                                                uint64_t *__restrict__ key,
                                                                 uint2 *__restrict__ ov, uint32_t ov_cap) {
     __shared__ uint32_t lds[kBfsWaves][kQCap + kHCap];
     uint32_t *q = lds[threadIdx.x / kWave];
@@ -192,23 +211,24 @@ __global__ void __launch_bounds__(kBfsBlock) k_eval_compact_bfs(uint32_t l, SelS
         const uint32_t v = evl[e];
         const BfsOut o = getcenter_lds(g, pm, K[r], cd, r, in_s, v, q, hs);
         if (lane_id() == 0) {
-            if (o.overflow) push_overflow(st, ov, ov_cap, e, r);
-            else if (o.delta) atomicAdd(&partial[e], (unsigned long long)o.delta);
+            if (o.overflow) push_overflow(st, &st->ov_cnt[l], ov, ov_cap, e, r);
+            else add_delta(st, partial, e, o.delta, evl, kb, in_s, key);
         }
     }
 }
 
-// Global-memory searches for the tasks that overflowed.  mode 0: add delta to
-// partial[e]; mode 1 (MarkSeed of st->last_seed): zero size_c[r][label].
-__global__ void __launch_bounds__(64) k_overflow_bfs(int mode, SelState *__restrict__ st,
+// Global-memory searches for the tasks of one step that overflowed (count in
+// st->ov_cnt[slot]).  mode 0: evaluation of level `slot` (add the delta);
+// mode 1: MarkSeed of st->last_seed (zero size_c[r][label]).
+__global__ void __launch_bounds__(64) k_overflow_bfs(int mode, uint32_t slot, SelState *__restrict__ st,
                                                      const uint32_t *__restrict__ evl,
                                                      unsigned long long *__restrict__ partial, GraphDev g,
                                                      ProbDev pm, const uint64_t *__restrict__ K, CompactDev cd,
-                                                     const uint8_t *__restrict__ in_s,
-                                                     const uint2 *__restrict__ ov, uint32_t ov_cap,
-                                                     uint32_t *__restrict__ slot_q, uint32_t *__restrict__ slot_vis,
-                                                     uint32_t n) {
-    const uint32_t cnt = min(st->ov_cnt, ov_cap);
+                                                     uint32_t kb, const uint8_t *__restrict__ in_s,
+                                                     uint64_t *__restrict__ key, const uint2 *__restrict__ ov,
+                                                     uint32_t ov_cap, uint32_t *__restrict__ slot_q,
+                                                     uint32_t *__restrict__ slot_vis, uint32_t n) {
+    const uint32_t cnt = min(st->ov_cnt[slot], ov_cap);
     uint32_t *gq = slot_q + (size_t)blockIdx.x * n;
     uint32_t *gvis = slot_vis + (size_t)blockIdx.x * ((n + 31) / 32);
     for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
@@ -217,38 +237,9 @@ __global__ void __launch_bounds__(64) k_overflow_bfs(int mode, SelState *__restr
         const uint32_t v = (mode == 0) ? evl[t.x] : st->last_seed;
         const BfsOut o = getcenter_global(g, pm, K[r], cd, r, in_s, v, gq, gvis);
         if (lane_id() == 0) {
-            if (mode == 0) {
-                if (o.delta) atomicAdd(&partial[t.x], (unsigned long long)o.delta);
-            } else if (o.label != kNone) {
-                cd.size_c[(size_t)r * cd.rho + o.label] = 0;
-            }
+            if (mode == 0) add_delta(st, partial, t.x, o.delta, evl, kb, in_s, key);
+            else if (o.label != kNone) cd.size_c[(size_t)r * cd.rho + o.label] = 0;
         }
-    }
-}
-
-// eval(l) on CompactSketch, part 2: keys from the summed deltas, Delta* update.
-__global__ void __launch_bounds__(256) k_eval_compact_finalize(uint32_t l, SelState *__restrict__ st,
-                                                               const uint32_t *__restrict__ evl,
-                                                               const unsigned long long *__restrict__ partial,
-                                                               uint32_t kb, const uint8_t *__restrict__ in_s,
-                                                               uint64_t *__restrict__ key) {
-    const uint32_t ne = st->ev_cnt[l];
-    uint64_t best = 0;
-    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x) {
-        const uint32_t v = evl[e];
-        const uint64_t nk = in_s[v] ? 0ull : pack_key(partial[e], v, kb);
-        key[v] = nk;
-        best = nk > best ? nk : best;
-    }
-    best = wave_max_u64(best);
-    if (lane_id() == 0 && best) atomicMax(&st->delta, (unsigned long long)best);
-}
-
-// Resets the overflow list after its tasks ran (one thread).
-__global__ void k_overflow_reset(SelState *__restrict__ st) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        st->overflow += st->ov_cnt;
-        st->ov_cnt = 0;
     }
 }
 
@@ -264,7 +255,7 @@ __global__ void __launch_bounds__(kBfsBlock) k_markseed_compact(SelState *__rest
     for (uint32_t r = wave_index(); r < R; r += wave_count()) {
         const BfsOut o = getcenter_lds(g, pm, K[r], cd, r, in_s, s, q, hs);
         if (lane_id() == 0) {
-            if (o.overflow) push_overflow(st, ov, ov_cap, s, r);
+            if (o.overflow) push_overflow(st, &st->ov_cnt[kMaxLevels + 1], ov, ov_cap, s, r);
             else if (o.label != kNone) cd.size_c[(size_t)r * cd.rho + o.label] = 0;
         }
     }
@@ -321,8 +312,8 @@ __global__ void __launch_bounds__(256) k_bulk_keys(SelState *__restrict__ st,
     if (v < n) key[v] = in_s[v] ? 0ull : pack_key(partial[v], v, kb);
     if (v == 0) {
         for (int l = 0; l <= kMaxLevels; ++l) { st->fr_cnt[l] = 0; st->ev_cnt[l] = 0; }
+        for (int l = 0; l < kMaxLevels + 2; ++l) st->ov_cnt[l] = 0;
         st->ev_cnt[0] = n - st->round;
-        st->ov_cnt = 0;
     }
 }
 

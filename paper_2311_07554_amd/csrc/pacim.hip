@@ -27,6 +27,7 @@
 
 #include "common.h"
 #include "compact_kernels.h"
+#include "probe_kernels.h"
 #include "select_kernels.h"
 #include "sketch_kernels.h"
 
@@ -92,8 +93,7 @@ struct im_sketches {
     uint32_t ov_cap = 0;
     uint32_t *slot_q = nullptr, *slot_vis = nullptr;
     uint32_t slots = 0;
-    uint32_t *bulk_scratch = nullptr;  // parent/cnt/flag [bulk_B][n], allocated at the first bulk round
-    uint32_t bulk_B = 0;
+    void *bulk_cs = nullptr;           // CCScratch of bulk rounds, allocated at the first one
     uint64_t last_gain = 0;            // gain of the latest seed (decides bulk rounds)
     uint32_t bulk_rounds = 0;
     // bookkeeping
@@ -428,31 +428,66 @@ uint64_t tree_nodes(const TreeDesc &td) {
     return t;
 }
 
-// One pass over the edge list for b sketches (keys K[0..b)): union-find labels in
-// parent[b][n] (root = smallest id of the CC), member counts at the roots in
-// cnt, and (if center_rank) the smallest center rank of each CC in minc.
+uint32_t key_slots(uint32_t R) { return ((R + 7u) & ~7u) + 8u; }
+
+// Scratch of the component-labelling passes: parent/cnt(/minc) for B sketches.
+struct CCScratch {
+    uint32_t B = 0;
+    uint32_t *parent = nullptr, *cnt = nullptr, *minc = nullptr;
+    void *block = nullptr;
+    size_t bytes = 0;
+};
+
+im_status cc_scratch_alloc(im_ctx *ctx, const im_graph *g, uint32_t R, bool with_minc, CCScratch *cs) {
+    const uint32_t n = g->n;
+    const size_t per_sketch = (size_t)n * 4 * (with_minc ? 3 : 2);
+    uint32_t B = (uint32_t)std::min<size_t>({(size_t)R, (size_t)64, std::max<size_t>(1, g_scratch_budget() / per_sketch)});
+    if (uint32_t ov = g_batch_override()) B = std::min<uint32_t>({ov, R, 64u});
+    cs->B = B;
+    cs->bytes = per_sketch * B;
+    im_status st = dev_alloc(ctx, cs->bytes, &cs->block);
+    if (st != IM_OK) return st;
+    cs->parent = static_cast<uint32_t *>(cs->block);
+    cs->cnt = cs->parent + (size_t)B * n;
+    cs->minc = with_minc ? cs->cnt + (size_t)B * n : nullptr;
+    return IM_OK;
+}
+
+void cc_scratch_free(im_ctx *ctx, CCScratch *cs) {
+    if (cs->block) dev_free(ctx, cs->block, cs->bytes);
+    *cs = CCScratch();
+}
+
+// One pass over the edge list for b <= cs.B sketches (keys K[0..b)): union-find
+// labels in parent[b][n] (root = smallest id of the CC), member counts at the
+// roots in cnt, and (if center_rank) the smallest center rank of each CC in minc.
 void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const uint64_t *K, uint32_t b,
-                     uint32_t *parent, uint32_t *cnt, uint32_t *minc, uint32_t minc_init,
-                     const uint32_t *center_rank) {
+                     const CCScratch &cs, uint32_t *minc, uint32_t minc_init, const uint32_t *center_rank) {
     hipStream_t st = ctx->stream;
     const uint32_t n = g->n;
     const unsigned hook_grid = grid_for(g->m_und, 256, 256 * 16);
     dim3 gi((n + 255) / 256, b);
-    k_batch_init<<<gi, 256, 0, st>>>(parent, cnt, minc, n, minc_init);
+    k_batch_init<<<gi, 256, 0, st>>>(cs.parent, cs.cnt, minc, n, minc_init);
     {
         Prof p(ctx, "sample_hook");
         if (pm.kind == 0)
-            k_sample_hook<0><<<hook_grid, 256, 0, st>>>(g->edges, g->m_und, K, b, pm, parent, n);
+            k_sample_hook<0><<<hook_grid, 256, 0, st>>>(g->edges, g->m_und, K, b, pm, cs.parent, n);
         else
-            k_sample_hook<1><<<hook_grid, 256, 0, st>>>(g->edges, g->m_und, K, b, pm, parent, n);
+            k_sample_hook<1><<<hook_grid, 256, 0, st>>>(g->edges, g->m_und, K, b, pm, cs.parent, n);
     }
     {
         Prof p(ctx, "compress");
-        k_compress<<<gi, 256, 0, st>>>(parent, cnt, n, center_rank, minc);
+        dim3 gc(std::min<unsigned>((n + 255) / 256, 64u), b);
+        k_compress<<<gc, 256, 0, st>>>(cs.parent, cs.cnt, n, center_rank, minc);
     }
 }
 
 void free_sketches(im_sketches *s) {
+    if (s->bulk_cs) {
+        cc_scratch_free(s->ctx, static_cast<CCScratch *>(s->bulk_cs));
+        delete static_cast<CCScratch *>(s->bulk_cs);
+        s->bulk_cs = nullptr;
+    }
     for (auto &pr : s->allocs) dev_free(s->ctx, pr.first, pr.second);
     s->allocs.clear();
 }
@@ -481,6 +516,8 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
     const uint32_t n = g->n;
     const uint32_t kb = std::max<uint32_t>(1, bit_length((uint64_t)n - 1));
     if (kb + bit_length((uint64_t)R * n + 1) > 64) return fail(ctx, IM_EINVAL, "R*n too large for 64-bit keys");
+    if (alpha < 1.0 && ((uint64_t)R * n >= (1ull << kPartialShift) || R >= (1u << (64 - kPartialShift))))
+        return fail(ctx, IM_EINVAL, "CompactSketch needs R*n < 2^40 and R < 2^24");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
 
     im_sketches *s = new (std::nothrow) im_sketches();
@@ -507,10 +544,9 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
         delete s;
         return fail(ctx, IM_EDEVICE, "hipEventCreate failed");
     }
-    uint32_t *parent = nullptr, *cnt = nullptr, *minc = nullptr;
-    size_t scratch_bytes = 0;
+    CCScratch cs;
     auto bail = [&](im_status code) {
-        if (parent) dev_free(ctx, parent, scratch_bytes);
+        cc_scratch_free(ctx, &cs);
         (void)hipEventDestroy(t0);
         (void)hipEventDestroy(t1);
         free_sketches(s);
@@ -532,11 +568,15 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
     } while (0)
 
     SK_HIP(hipEventRecord(t0, st));
-    // trivalency class key K(0, SALT_TRIV) and the per-sketch keys, on the device
-    SK_TRY(sk_alloc(s, (size_t)R + 1, &s->K));
-    k_sketch_keys<<<grid_for(R, 256, 1u << 20), 256, 0, st>>>(seed, R, s->K);
-    k_salt_key<<<1, 64, 0, st>>>(0, kSaltTriv, s->K + R);  // K(0, SALT_TRIV) for the trivalency class
+    // keys of sketches 0 .. Rpad-1 (the sampling kernel reads them 8 at a time), then K(0, SALT_TRIV)
+    const uint32_t Rpad = key_slots(R);
+    SK_TRY(sk_alloc(s, (size_t)Rpad + 1, &s->K));
+    k_sketch_keys<<<grid_for(Rpad, 256, 1u << 20), 256, 0, st>>>(seed, Rpad, s->K);
+    k_salt_key<<<1, 64, 0, st>>>(0, kSaltTriv, s->K + Rpad);
     SK_HIP(hipGetLastError());
+    // the trivalency key is read back once (8 bytes) so it can travel by value
+    SK_HIP(hipMemcpyAsync(&s->pm.ktriv, s->K + Rpad, 8, hipMemcpyDeviceToHost, st));
+    SK_HIP(hipStreamSynchronize(st));
 
     // centers (CompactSketch)
     if (s->compact) {
@@ -563,26 +603,14 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
     SK_TRY(sk_alloc(s, n, &s->gain0));
     SK_HIP(hipMemsetAsync(s->gain0, 0, (size_t)n * 8, st));
 
-    // sketches per pass over the edge list
-    const size_t per_sketch = (size_t)n * 4 * (s->compact ? 3 : 2);
-    uint32_t B = (uint32_t)std::min<size_t>({(size_t)R, (size_t)64, std::max<size_t>(1, g_scratch_budget() / per_sketch)});
-    if (uint32_t ov = g_batch_override()) B = std::min<uint32_t>({ov, R, 64u});
-    s->B = B;
-    scratch_bytes = per_sketch * B;
-    SK_TRY(dev_alloc(ctx, scratch_bytes, (void **)&parent));
-    cnt = parent + (size_t)B * n;
-    minc = s->compact ? cnt + (size_t)B * n : nullptr;
-
-    ProbDev pm = s->pm;
-    {
-        // the trivalency key is read back once (8 bytes) so it can travel by value
-        SK_HIP(hipMemcpyAsync(&pm.ktriv, s->K + R, 8, hipMemcpyDeviceToHost, st));
-        SK_HIP(hipStreamSynchronize(st));
-        s->pm.ktriv = pm.ktriv;
-    }
+    // component-labelling scratch: B sketches per pass over the edge list
+    SK_TRY(cc_scratch_alloc(ctx, g, R, s->compact, &cs));
+    s->B = cs.B;
+    const uint32_t B = cs.B;
+    uint32_t *parent = cs.parent, *cnt = cs.cnt, *minc = cs.minc;
     for (uint32_t r0 = 0; r0 < R; r0 += B) {
         const uint32_t b = std::min(B, R - r0);
-        enqueue_cc_pass(ctx, g, pm, s->K + r0, b, parent, cnt, minc, kNone, s->compact ? s->center_rank : nullptr);
+        enqueue_cc_pass(ctx, g, s->pm, s->K + r0, b, cs, minc, kNone, s->compact ? s->center_rank : nullptr);
         if (s->compact) {
             Prof p(ctx, "emit");
             dim3 ge((std::max<uint32_t>(s->rho, 1) + 255) / 256, b);
@@ -625,8 +653,7 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
     SK_HIP(hipGetLastError());
     SK_HIP(hipEventRecord(t1, st));
     SK_HIP(hipEventSynchronize(t1));
-    dev_free(ctx, parent, scratch_bytes);
-    parent = nullptr;
+    cc_scratch_free(ctx, &cs);
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, t0, t1);
     s->build_ms = ms;
@@ -641,43 +668,47 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
 // ---------------------------------------------------------------- selection
 namespace {
 
+// MarkSeed on CompactSketch for st->last_seed: one GetCenter per sketch.
+void enqueue_markseed_compact(im_sketches *s) {
+    hipStream_t st = s->ctx->stream;
+    GraphDev gd{s->g->off, s->g->cols};
+    CompactDev cd{s->center_rank, s->label_c, s->size_c, s->rho};
+    k_markseed_compact<<<wave_grid(s->R, 4096), kBfsBlock, 0, st>>>(s->st, gd, s->pm, s->K, s->R, cd, s->in_s, s->ov,
+                                                                     s->ov_cap);
+    k_overflow_bfs<<<s->slots, 64, 0, st>>>(1, kMaxLevels + 1, s->st, s->evl, s->partial, gd, s->pm, s->K, cd, s->kb,
+                                            s->in_s, s->key, s->ov, s->ov_cap, s->slot_q, s->slot_vis, s->n);
+}
+
 im_status enqueue_lazy_round(im_sketches *s) {
     im_ctx *ctx = s->ctx;
     hipStream_t st = ctx->stream;
     const TreeDesc &td = s->td;
     GraphDev gd{s->g->off, s->g->cols};
     CompactDev cd{s->center_rank, s->label_c, s->size_c, s->rho};
+    const unsigned long long pinit = (unsigned long long)s->R << kPartialShift;
     auto eval = [&](uint32_t l) {
         uint64_t cap = (l == 0) ? 1 : std::min<uint64_t>((uint64_t)s->n, (uint64_t)td.lvl_n[l - 1] * kFan);
         if (!s->compact) {
             k_eval_full<<<wave_grid(cap, 8192), 256, 0, st>>>(l, s->st, s->evl, s->E, s->R, s->kb, s->in_s, s->key);
         } else {
             k_eval_compact_bfs<<<wave_grid(cap * s->R, 16384), kBfsBlock, 0, st>>>(
-                l, s->st, s->evl, s->partial, gd, s->pm, s->K, s->R, cd, s->in_s, s->ov, s->ov_cap);
-            k_overflow_bfs<<<s->slots, 64, 0, st>>>(0, s->st, s->evl, s->partial, gd, s->pm, s->K, cd, s->in_s,
-                                                    s->ov, s->ov_cap, s->slot_q, s->slot_vis, s->n);
-            k_eval_compact_finalize<<<grid_for(cap, 256, 4096), 256, 0, st>>>(l, s->st, s->evl, s->partial, s->kb,
-                                                                           s->in_s, s->key);
-            k_overflow_reset<<<1, 64, 0, st>>>(s->st);
+                l, s->st, s->evl, s->partial, gd, s->pm, s->K, s->R, cd, s->kb, s->in_s, s->key, s->ov, s->ov_cap);
+            k_overflow_bfs<<<s->slots, 64, 0, st>>>(0, l, s->st, s->evl, s->partial, gd, s->pm, s->K, cd, s->kb,
+                                                    s->in_s, s->key, s->ov, s->ov_cap, s->slot_q, s->slot_vis, s->n);
         }
     };
-    k_round_begin<<<1, 64, 0, st>>>(td, s->st, s->ids, s->fr, s->evl, s->partial);
+    k_round_begin<<<1, 64, 0, st>>>(td, s->st, s->ids, s->fr, s->evl, s->partial, pinit);
     eval(0);
     for (uint32_t l = 0; l < td.D; ++l) {
-        k_check<<<wave_grid(td.lvl_n[l], 8192), 256, 0, st>>>(td, l, s->st, s->ids, s->key, s->fr, s->evl, s->partial);
+        k_check<<<wave_grid(td.lvl_n[l], 8192), 256, 0, st>>>(td, l, s->st, s->ids, s->key, s->fr, s->evl, s->partial,
+                                                                pinit);
         eval(l + 1);
     }
     for (int l = (int)td.D - 1; l >= 0; --l)
         k_relink<<<wave_grid(td.lvl_n[l], 8192), 256, 0, st>>>(td, (uint32_t)l, s->st, s->ids, s->key, s->fr);
     k_round_end<<<1, 64, 0, st>>>(td, s->st, s->ids, s->key, s->in_s, s->kb, s->seeds_d, s->gains_d,
                                   s->evals_d, s->compact ? nullptr : s->E, s->R);
-    if (s->compact) {
-        k_markseed_compact<<<wave_grid(s->R, 4096), kBfsBlock, 0, st>>>(s->st, gd, s->pm, s->K, s->R, cd, s->in_s,
-                                                                         s->ov, s->ov_cap);
-        k_overflow_bfs<<<s->slots, 64, 0, st>>>(1, s->st, s->evl, s->partial, gd, s->pm, s->K, cd, s->in_s, s->ov,
-                                                s->ov_cap, s->slot_q, s->slot_vis, s->n);
-        k_overflow_reset<<<1, 64, 0, st>>>(s->st);
-    }
+    if (s->compact) enqueue_markseed_compact(s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(ctx, IM_EDEVICE, std::string("select launch: ") + hipGetErrorString(e));
     return IM_OK;
@@ -689,23 +720,22 @@ im_status enqueue_bulk_round(im_sketches *s) {
     im_ctx *ctx = s->ctx;
     hipStream_t st = ctx->stream;
     const uint32_t n = s->n;
-    if (!s->bulk_scratch) {
-        const size_t per_sketch = (size_t)n * 4 * 3;
-        uint32_t B = (uint32_t)std::min<size_t>({(size_t)s->R, (size_t)64, std::max<size_t>(1, g_scratch_budget() / per_sketch)});
-        im_status a = sk_alloc(s, per_sketch / 4 * B, &s->bulk_scratch);
-        if (a != IM_OK) return a;
-        s->bulk_B = B;
+    if (!s->bulk_cs) {
+        CCScratch *c = new (std::nothrow) CCScratch();
+        if (!c) return fail(ctx, IM_ENOMEM, "host allocation");
+        im_status a = cc_scratch_alloc(ctx, s->g, s->R, true, c);
+        if (a != IM_OK) { delete c; return a; }
+        s->bulk_cs = c;
     }
-    const uint32_t B = s->bulk_B;
-    uint32_t *parent = s->bulk_scratch, *cnt = parent + (size_t)B * n, *flag = cnt + (size_t)B * n;
-    GraphDev gd{s->g->off, s->g->cols};
-    CompactDev cd{s->center_rank, s->label_c, s->size_c, s->rho};
+    const CCScratch &cs = *static_cast<CCScratch *>(s->bulk_cs);
+    const uint32_t B = cs.B;
+    uint32_t *parent = cs.parent, *cnt = cs.cnt, *flag = cs.minc;
     const TreeDesc &td = s->td;
     hipError_t e0 = hipMemsetAsync(s->partial, 0, (size_t)n * 8, st);
     if (e0 != hipSuccess) return fail(ctx, IM_EDEVICE, std::string("bulk round: ") + hipGetErrorString(e0));
     for (uint32_t r0 = 0; r0 < s->R; r0 += B) {
         const uint32_t b = std::min(B, s->R - r0);
-        enqueue_cc_pass(ctx, s->g, s->pm, s->K + r0, b, parent, cnt, flag, 0u, nullptr);
+        enqueue_cc_pass(ctx, s->g, s->pm, s->K + r0, b, cs, flag, 0u, nullptr);
         k_bulk_seed_roots<<<grid_for((uint64_t)n * b, 256, 1024), 256, 0, st>>>(s->st, s->seeds_d, parent, n, b, flag);
         k_bulk_accum<<<(n + 255) / 256, 256, 0, st>>>(parent, cnt, flag, n, b, s->partial);
     }
@@ -714,11 +744,7 @@ im_status enqueue_bulk_round(im_sketches *s) {
         k_tree_build_level<<<wave_grid(td.lvl_n[l], 8192), 256, 0, st>>>(td, (uint32_t)l, s->ids, s->key);
     k_round_end<<<1, 64, 0, st>>>(td, s->st, s->ids, s->key, s->in_s, s->kb, s->seeds_d, s->gains_d, s->evals_d,
                                   nullptr, s->R);
-    k_markseed_compact<<<wave_grid(s->R, 4096), kBfsBlock, 0, st>>>(s->st, gd, s->pm, s->K, s->R, cd, s->in_s, s->ov,
-                                                                     s->ov_cap);
-    k_overflow_bfs<<<s->slots, 64, 0, st>>>(1, s->st, s->evl, s->partial, gd, s->pm, s->K, cd, s->in_s, s->ov,
-                                            s->ov_cap, s->slot_q, s->slot_vis, s->n);
-    k_overflow_reset<<<1, 64, 0, st>>>(s->st);
+    enqueue_markseed_compact(s);
     ++s->bulk_rounds;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(ctx, IM_EDEVICE, std::string("bulk round launch: ") + hipGetErrorString(e));
@@ -736,11 +762,13 @@ int bulk_policy() {
     return 0;
 }
 
+bool bulk_gain(const im_sketches *s, uint64_t gain) { return gain * 64 >= (uint64_t)s->R * s->n; }
+
 bool want_bulk(const im_sketches *s) {
     if (!s->compact || s->chosen == 0) return false;
     const int pol = bulk_policy();
     if (pol != 0) return pol > 0;
-    return s->last_gain * 64 >= (uint64_t)s->R * s->n;
+    return bulk_gain(s, s->last_gain);
 }
 
 }  // namespace
@@ -763,11 +791,19 @@ extern "C" im_status im_select_seeds_from(im_ctx *ctx, im_sketches *s, uint32_t 
         if (!s->compact) {
             for (uint32_t i = 0; i < k && rc == IM_OK; ++i) rc = enqueue_lazy_round(s);
         } else {
-            // compact: the gain of every seed is read back to choose the next round's kind
+            // compact: while a bulk round is still possible, each seed's gain is read back to
+            // choose the next round's kind.  Gains never increase, so once one falls below
+            // the bulk threshold no later round can be bulk and the read-backs stop.
             const uint32_t base = s->chosen;
+            bool watch = bulk_policy() == 0 && (s->chosen == 0 || bulk_gain(s, s->last_gain));
             for (uint32_t i = 0; i < k && rc == IM_OK; ++i) {
                 rc = want_bulk(s) ? enqueue_bulk_round(s) : enqueue_lazy_round(s);
                 if (rc != IM_OK) break;
+                ++s->chosen;  // provisional, restored below
+                if (!watch) {
+                    s->last_gain = 0;
+                    continue;
+                }
                 unsigned long long g = 0;
                 hipError_t e1 = hipMemcpyAsync(&g, s->gains_d + base + i, 8, hipMemcpyDeviceToHost, st);
                 hipError_t e2 = hipStreamSynchronize(st);
@@ -776,7 +812,7 @@ extern "C" im_status im_select_seeds_from(im_ctx *ctx, im_sketches *s, uint32_t 
                     break;
                 }
                 s->last_gain = g;
-                ++s->chosen;  // provisional, restored below
+                watch = bulk_gain(s, g);
             }
             s->chosen = base;
         }
@@ -805,6 +841,7 @@ extern "C" im_status im_select_seeds_from(im_ctx *ctx, im_sketches *s, uint32_t 
         gains_out[i] = gains[i];
     }
     s->chosen += k;
+    s->last_gain = gains[k - 1];
     return IM_OK;
 }
 
@@ -908,5 +945,59 @@ extern "C" im_status im_sketches_stats(const im_sketches *s, im_sketch_stats *ou
     out->sketches_per_pass = s->B;
     out->sketch_bytes = s->bytes;
     out->bulk_rounds = s->bulk_rounds;
+    return IM_OK;
+}
+
+// ---------------------------------------------------------------- device probe
+extern "C" im_status im_probe_device(im_ctx *ctx, double *hash_per_s, double *copy_bytes_per_s) {
+    if (!ctx || !hash_per_s || !copy_bytes_per_s) return IM_EINVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const size_t bytes = (size_t)1 << 30;
+    void *a = nullptr, *b = nullptr, *k = nullptr;
+    im_status rc = dev_alloc(ctx, bytes, &a);
+    if (rc == IM_OK) rc = dev_alloc(ctx, bytes, &b);
+    if (rc == IM_OK) rc = dev_alloc(ctx, 72 * 8, &k);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == IM_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = fail(ctx, IM_EDEVICE, "hipEventCreate failed");
+    double best_hash = 0, best_copy = 0;
+    if (rc == IM_OK) {
+        k_sketch_keys<<<1, 128, 0, st>>>(1, 72, static_cast<uint64_t *>(k));
+        (void)hipMemsetAsync(a, 0x5A, bytes, st);
+        const unsigned blocks = 256 * 8, iters = 64;
+        const uint64_t T = (uint64_t)std::ldexp(0.037, 64);
+        for (int rep = 0; rep < 4; ++rep) {
+            (void)hipEventRecord(e0, st);
+            k_probe_hash<<<blocks, 256, 0, st>>>(static_cast<uint64_t *>(k), iters, T,
+                                                 static_cast<unsigned long long *>(b));
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep && ms > 0) best_hash = std::max(best_hash, (double)blocks * 256 * iters * 64 / (ms * 1e-3));
+        }
+        const uint64_t cnt = bytes / 16;
+        for (int rep = 0; rep < 4; ++rep) {
+            (void)hipEventRecord(e0, st);
+            k_probe_copy<<<256 * 16, 256, 0, st>>>(static_cast<const uint4 *>(a), static_cast<uint4 *>(b), cnt);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep && ms > 0) best_copy = std::max(best_copy, 2.0 * bytes / (ms * 1e-3));
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) rc = fail(ctx, IM_EDEVICE, std::string("probe: ") + hipGetErrorString(e));
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(st);
+    dev_free(ctx, a, bytes);
+    dev_free(ctx, b, bytes);
+    dev_free(ctx, k, 72 * 8);
+    if (rc != IM_OK) return rc;
+    *hash_per_s = best_hash;
+    *copy_bytes_per_s = best_copy;
     return IM_OK;
 }

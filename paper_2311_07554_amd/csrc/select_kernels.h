@@ -38,7 +38,8 @@ struct SelState {
     unsigned long long overflow;     // GetCenter searches sent to the global-memory path
     uint32_t fr_cnt[kMaxLevels + 1];
     uint32_t ev_cnt[kMaxLevels + 1];
-    uint32_t ov_cnt;                 // overflow tasks pending in the current step
+    uint32_t ov_cnt[kMaxLevels + 2]; // GetCenter searches left for the global-memory path:
+                                     // per evaluation level, then MarkSeed
     uint32_t round;                  // seeds chosen so far
     uint32_t last_seed;
     uint32_t err;
@@ -97,18 +98,20 @@ __global__ void __launch_bounds__(256) k_tree_build_level(TreeDesc td, uint32_t 
 
 // ---- one round ---------------------------------------------------------------
 // round_begin: the root is always stale; it is the one level-0 evaluation.
+// partial (CompactSketch only): per listed vertex, (tasks left << 40) + summed
+// deltas, started at partial_init = R << 40.
 __global__ void k_round_begin(TreeDesc td, SelState *__restrict__ st, const uint32_t *__restrict__ ids,
                               uint32_t *__restrict__ fr, uint32_t *__restrict__ evl,
-                              unsigned long long *__restrict__ partial) {
+                              unsigned long long *__restrict__ partial, unsigned long long partial_init) {
     if (threadIdx.x == 0) {
         st->delta = 0;
         for (int l = 0; l <= kMaxLevels; ++l) { st->fr_cnt[l] = 0; st->ev_cnt[l] = 0; }
-        st->ov_cnt = 0;
+        for (int l = 0; l < kMaxLevels + 2; ++l) st->ov_cnt[l] = 0;
         st->fr_cnt[0] = 1;
         fr[td.lvl_off[0]] = 0;
         st->ev_cnt[0] = 1;
         evl[0] = ids[td.lvl_off[0]];
-        if (partial) partial[0] = 0;
+        if (partial) partial[0] = partial_init;
     }
 }
 
@@ -116,7 +119,8 @@ __global__ void k_round_begin(TreeDesc td, SelState *__restrict__ st, const uint
 __global__ void __launch_bounds__(256) k_check(TreeDesc td, uint32_t l, SelState *__restrict__ st,
                                                const uint32_t *__restrict__ ids, const uint64_t *__restrict__ key,
                                                uint32_t *__restrict__ fr, uint32_t *__restrict__ evl,
-                                               unsigned long long *__restrict__ partial) {
+                                               unsigned long long *__restrict__ partial,
+                                               unsigned long long partial_init) {
     const uint32_t nf = st->fr_cnt[l];
     const uint64_t delta = __hip_atomic_load(&st->delta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const bool leaf_children = (l + 1 == td.D);
@@ -137,7 +141,7 @@ __global__ void __launch_bounds__(256) k_check(TreeDesc td, uint32_t l, SelState
         const uint32_t ep = wave_append(&st->ev_cnt[l + 1], need_eval, &tot);
         if (need_eval) {
             evl[ep] = cid;
-            if (partial) partial[ep] = 0;
+            if (partial) partial[ep] = partial_init;
         }
         const uint32_t fp = wave_append(&st->fr_cnt[l + 1], explore, &tot);
         if (explore) fr[td.lvl_off[l + 1] + fp] = c;
@@ -192,6 +196,11 @@ __global__ void __launch_bounds__(64) k_round_end(TreeDesc td, SelState *__restr
         for (int l = 0; l <= kMaxLevels; ++l) t += st->ev_cnt[l];
         return t;
     }();
+    const uint32_t ovs = [&] {
+        uint32_t t = 0;
+        for (int l = 0; l < kMaxLevels + 2; ++l) t += st->ov_cnt[l];
+        return t;
+    }();
     if (lane == 0) {
         if (ks == 0 || in_s[s]) st->err = 1;
         seeds_out[round] = s;
@@ -201,6 +210,7 @@ __global__ void __launch_bounds__(64) k_round_end(TreeDesc td, SelState *__restr
         key[s] = 0;
         st->last_seed = s;
         st->evals += evs;
+        st->overflow += ovs;
     }
     // relink the path of leaf s, bottom-up, using the values this wave just wrote
     uint32_t child = s, child_id = s;

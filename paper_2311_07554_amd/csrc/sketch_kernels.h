@@ -76,6 +76,7 @@ __device__ __forceinline__ void uf_unite(uint32_t *P, uint32_t a, uint32_t b) {
     }
 }
 
+// K must hold round_up(B, 8) keys.
 template <int KIND>
 __global__ void __launch_bounds__(256) k_sample_hook(const uint2 *__restrict__ edges, uint64_t m,
                                                      const uint64_t *__restrict__ K, uint32_t B, ProbDev pm,
@@ -95,7 +96,13 @@ __global__ void __launch_bounds__(256) k_sample_hook(const uint2 *__restrict__ e
         if (T == kAllLive) {
             live = B >= 64 ? ~0ull : ((1ull << B) - 1ull);
         } else {
-            for (uint32_t b = 0; b < B; ++b) live |= (uint64_t)(mix64(x ^ K[b]) < T) << b;
+            for (uint32_t b0 = 0; b0 < B; b0 += 8) {
+                uint32_t chunk = 0;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) chunk |= (mix64(x ^ K[b0 + j]) < T) ? (1u << j) : 0u;
+                live |= (uint64_t)chunk << b0;
+            }
+            live &= B >= 64 ? ~0ull : ((1ull << B) - 1ull);
         }
         while (live) {
             const uint32_t b = (uint32_t)__builtin_ctzll(live);
@@ -105,45 +112,67 @@ __global__ void __launch_bounds__(256) k_sample_hook(const uint2 *__restrict__ e
     }
 }
 
-// grid: (ceil(n/256), B).  Every lane of a wave belongs to the same sketch, and
-// in social-like graphs many of them sit in the same (giant) component, so the
-// member count and the smallest center rank are combined per distinct root in
-// the wave before one atomic per root: without this, every member of a giant
-// component hits the same counter.
+// grid: (G, B), block 256: the blocks of sketch blockIdx.y stride over its
+// vertices.  In social-like graphs almost every non-root vertex of a sketch lies
+// in one giant component, so per-vertex atomics on its root counter serialise.
+// Each wave therefore keeps the first root it meets as a "hot" root whose member
+// count and smallest center rank it accumulates in registers and flushes once at
+// the end; members of other roots are combined per distinct root in the wave
+// and added with one atomic per root.
 __global__ void __launch_bounds__(256) k_compress(uint32_t *__restrict__ parent, uint32_t *__restrict__ cnt,
                                                   uint32_t n, const uint32_t *__restrict__ center_rank,
                                                   uint32_t *__restrict__ minc) {
-    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t lane = lane_id();
-    const bool valid = v < n;
     const size_t base = (size_t)blockIdx.y * n;
     uint32_t *P = parent + base;
-    uint32_t r = v;
-    if (valid) {
-        uint32_t p = P[v];
-        while (p != r) { r = p; p = P[r]; }
-        if (r != v) P[v] = r;
-    }
-    bool need = valid && r != v;
-    for (uint64_t m = __ballot(need); m; m = __ballot(need)) {
-        const uint32_t lr = __shfl(r, (int)__builtin_ctzll(m));
-        const bool same = need && r == lr;
-        const uint64_t sm = __ballot(same);
-        if (lane == (uint32_t)__builtin_ctzll(m)) atomicAdd(cnt + base + lr, (uint32_t)__popcll(sm));
-        if (same) need = false;
-    }
-    if (center_rank) {
-        const uint32_t cr = valid ? center_rank[v] : kNone;
-        bool cneed = cr != kNone;
-        for (uint64_t m = __ballot(cneed); m; m = __ballot(cneed)) {
-            const uint32_t lr = __shfl(r, (int)__builtin_ctzll(m));
-            const bool same = cneed && r == lr;
-            uint32_t mn = same ? cr : kNone;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) mn = min(mn, (uint32_t)__shfl_xor(mn, off));
-            if (lane == (uint32_t)__builtin_ctzll(m)) atomicMin(minc + base + lr, mn);
-            if (same) cneed = false;
+    uint32_t hot = kNone, hot_cnt = 0, hot_min = kNone;  // wave-uniform
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t v0 = blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); v0 < n; v0 += stride) {
+        const uint32_t v = v0 + lane;
+        const bool valid = v < n;
+        uint32_t r = v;
+        if (valid) {
+            uint32_t p = P[v];
+            while (p != r) { r = p; p = P[r]; }
+            if (r != v) P[v] = r;
         }
+        bool need = valid && r != v;
+        if (hot == kNone) {
+            const uint64_t m = __ballot(need);
+            if (m) hot = __shfl(r, (int)__builtin_ctzll(m));
+        }
+        const bool in_hot = need && r == hot;
+        hot_cnt += (uint32_t)__popcll(__ballot(in_hot));
+        if (in_hot) need = false;
+        for (uint64_t m = __ballot(need); m; m = __ballot(need)) {
+            const uint32_t lr = __shfl(r, (int)__builtin_ctzll(m));
+            const bool same = need && r == lr;
+            const uint64_t sm = __ballot(same);
+            if (lane == (uint32_t)__builtin_ctzll(m)) atomicAdd(cnt + base + lr, (uint32_t)__popcll(sm));
+            if (same) need = false;
+        }
+        if (center_rank) {
+            const uint32_t cr = valid ? center_rank[v] : kNone;
+            bool cneed = cr != kNone;
+            uint32_t hm = (cneed && r == hot) ? cr : kNone;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) hm = min(hm, (uint32_t)__shfl_xor(hm, off));
+            hot_min = min(hot_min, hm);
+            if (r == hot) cneed = false;
+            for (uint64_t m = __ballot(cneed); m; m = __ballot(cneed)) {
+                const uint32_t lr = __shfl(r, (int)__builtin_ctzll(m));
+                const bool same = cneed && r == lr;
+                uint32_t mn = same ? cr : kNone;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) mn = min(mn, (uint32_t)__shfl_xor(mn, off));
+                if (lane == (uint32_t)__builtin_ctzll(m)) atomicMin(minc + base + lr, mn);
+                if (same) cneed = false;
+            }
+        }
+    }
+    if (lane == 0 && hot != kNone) {
+        if (hot_cnt) atomicAdd(cnt + base + hot, hot_cnt);
+        if (center_rank && hot_min != kNone) atomicMin(minc + base + hot, hot_min);
     }
 }
 

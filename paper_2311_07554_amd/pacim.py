@@ -66,6 +66,7 @@ _SIGS = {
     "im_initial_gains": (ctypes.c_int, [_vp, _vp, _u64p]),
     "im_sketches_stats": (ctypes.c_int, [_vp, ctypes.POINTER(im_sketch_stats)]),
     "im_select_trace": (ctypes.c_int, [_vp, _vp, _u32p, ctypes.c_uint32]),
+    "im_probe_device": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None
@@ -224,6 +225,13 @@ def im_select_trace(ctx, s, count: int):
     return ev[:count]
 
 
+def im_probe_device(ctx):
+    """(hash tests per second, copy bytes per second) measured on the device."""
+    h, c = ctypes.c_double(), ctypes.c_double()
+    _check(ctx, load().im_probe_device(ctx, ctypes.byref(h), ctypes.byref(c)))
+    return h.value, c.value
+
+
 def im_sketches_stats(s) -> dict:
     st = im_sketch_stats()
     rc = load().im_sketches_stats(s, ctypes.byref(st))
@@ -265,6 +273,9 @@ class Context:
 
     def memory(self):
         return im_ctx_memory(self.h)
+
+    def probe(self):
+        return im_probe_device(self.h)
 
 
 class Graph:
