@@ -54,7 +54,7 @@ typedef struct im_ctx im_ctx;
 typedef struct im_graph im_graph;
 typedef struct im_sketches im_sketches;
 
-/* Edge-probability models (Sec. 6 and its appendix use constant p per graph). */
+/* Edge-probability models (Sec. 5 uses a constant p per graph; Appendix A varies it). */
 typedef enum {
     IM_PROB_UNIFORM = 0,     /* p_e = p for every edge                                    */
     IM_PROB_TRIVALENCY = 1   /* p_e in {0.1, 0.01, 0.001}, chosen by
@@ -91,7 +91,7 @@ im_status im_kernel_time(im_ctx *ctx, const char *name, uint64_t *launches, doub
 /* Uploads a simple undirected graph given as a symmetric CSR: offsets[n+1]
  * (uint64, offsets[0] = 0, non-decreasing, offsets[n] = m_dir) and cols[m_dir]
  * (uint32 neighbour ids).  Every undirected edge {u,v} appears as v in u's row
- * and u in v's row, exactly once each (Sec. 6: |E| counts these directed
+ * and u in v's row, exactly once each (Sec. 5, Table 2: |E| counts these directed
  * entries).  device_ptrs = 1 if offsets/cols are device pointers, 0 for host.
  * The library copies the graph into memory it owns.
  * Errors: EINVAL if n == 0, offsets are not monotone, a column is >= n, a row

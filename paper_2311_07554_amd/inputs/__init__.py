@@ -5,7 +5,7 @@ only builds simple undirected graphs (symmetric CSR, no self-loops, no duplicate
 pairs) and the workload descriptions that go with them.  The generators are in
 ``graphgen.c`` (compiled to ``libpacim_gen.so`` next to this file).
 
-Workloads, shaped like the paper's inputs (Sec. 6: social and web graphs with
+Workloads, shaped like the paper's inputs (Sec. 5: social and web graphs with
 IC p = 0.02, R = 256 sketches, k = 100 seeds):
 
 * ``er_small``      Erdos-Renyi, n = 1,000, 5,000 pairs (avg degree 10), uniform p = 0.05,
