@@ -166,6 +166,40 @@ typedef struct {
 } im_sketch_stats;
 im_status im_sketches_stats(const im_sketches *s, im_sketch_stats *out);
 
+/* ---- batched selection ------------------------------------------------------ */
+
+/* One request: graph, probability model, R sketches (full labels), k seeds, seed. */
+typedef struct {
+    const im_graph *graph;
+    im_prob prob;
+    uint32_t R;
+    uint32_t k;
+    uint64_t seed;
+} im_query;
+
+/* Launch shapes of the batched kernels (0 = library default).  hook_block and
+ * select_block must be multiples of 64 and at most 1024.  Chosen by the
+ * project's autotuner (paper_2311_07554_amd/autotune.py). */
+typedef struct {
+    uint32_t hook_block;    /* threads per block of the sampling + hooking pass      */
+    uint32_t hook_grid;     /* blocks of the sampling + hooking pass                 */
+    uint32_t select_block;  /* threads of each selection workgroup (one per query)   */
+    uint32_t select_grid;   /* selection workgroups (taking queries from a counter)  */
+} im_batch_config;
+
+/* Answers nq independent requests together (Algorithm 1 for each, full-label
+ * sketches): all sketch builds run as flattened persistent kernels over every
+ * (query, pass, edge) and (query, sketch, vertex), and every query's selection
+ * runs in one workgroup of a persistent kernel; the five kernels are captured
+ * in one hipGraph and launched once.  Each query's seeds and gains equal what
+ * im_select_seeds returns for it alone.
+ * seeds_out[q] / gains_out[q]: caller-owned host arrays of queries[q].k entries.
+ * cfg may be NULL.  *device_ms (may be NULL) gets the graph launch's device time.
+ * Errors: EINVAL (a query's k > n, R = 0, bad prob, bad cfg), ENOMEM, EDEVICE,
+ * EINTERNAL. */
+im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_query *queries, const im_batch_config *cfg,
+                                  uint32_t *const *seeds_out, uint64_t *const *gains_out, double *device_ms);
+
 /* ---- device ceilings (roofline) -------------------------------------------- */
 
 /* Measures, on the context's device, (a) the rate of live-edge hash tests the

@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "common.h"
+#include "batch_kernels.h"
 #include "compact_kernels.h"
 #include "probe_kernels.h"
 #include "select_kernels.h"
@@ -1000,4 +1001,257 @@ extern "C" im_status im_probe_device(im_ctx *ctx, double *hash_per_s, double *co
     *hash_per_s = best_hash;
     *copy_bytes_per_s = best_copy;
     return IM_OK;
+}
+
+// ---------------------------------------------------------------- batched selection
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+im_status check_prob(im_ctx *ctx, const im_prob &prob) {
+    if (prob.kind != IM_PROB_UNIFORM && prob.kind != IM_PROB_TRIVALENCY)
+        return fail(ctx, IM_EINVAL, "unknown probability model");
+    if (prob.kind == IM_PROB_UNIFORM && !(prob.p >= 0.0 && prob.p <= 1.0))
+        return fail(ctx, IM_EINVAL, "p must lie in [0, 1]");
+    return IM_OK;
+}
+
+ProbDev prob_dev(const im_prob &prob, uint64_t ktriv) {
+    ProbDev pm{};
+    pm.kind = prob.kind;
+    if (prob.kind == IM_PROB_UNIFORM) {
+        pm.t0 = threshold_of(prob.p);
+    } else {
+        pm.t0 = threshold_of(0.1);
+        pm.t1 = threshold_of(0.01);
+        pm.t2 = threshold_of(0.001);
+    }
+    pm.ktriv = ktriv;
+    return pm;
+}
+
+uint32_t cov_slots(uint32_t R, uint32_t k) {
+    uint64_t need = 2ull * R * std::max<uint32_t>(k, 1) + 64;
+    uint32_t c = 64;
+    while (c < need) c <<= 1;
+    return c;
+}
+
+// K(0, SALT_TRIV), computed on the device once per context.
+im_status trivalency_key(im_ctx *ctx, uint64_t *out) {
+    uint64_t *d = nullptr;
+    im_status rc = dev_alloc(ctx, 8, (void **)&d);
+    if (rc != IM_OK) return rc;
+    k_salt_key<<<1, 64, 0, ctx->stream>>>(0, kSaltTriv, d);
+    hipError_t e1 = hipMemcpyAsync(out, d, 8, hipMemcpyDeviceToHost, ctx->stream);
+    hipError_t e2 = hipStreamSynchronize(ctx->stream);
+    dev_free(ctx, d, 8);
+    if (e1 != hipSuccess || e2 != hipSuccess) return fail(ctx, IM_EDEVICE, "trivalency key read-back failed");
+    return IM_OK;
+}
+
+}  // namespace
+
+extern "C" im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_query *queries,
+                                             const im_batch_config *cfg, uint32_t *const *seeds_out,
+                                             uint64_t *const *gains_out, double *device_ms) {
+    if (!ctx || (nq && (!queries || !seeds_out || !gains_out))) return IM_EINVAL;
+    if (nq == 0) return IM_OK;
+    im_batch_config c{256, 0, 1024, 0};
+    if (cfg) {
+        if (cfg->hook_block) c.hook_block = cfg->hook_block;
+        if (cfg->hook_grid) c.hook_grid = cfg->hook_grid;
+        if (cfg->select_block) c.select_block = cfg->select_block;
+        if (cfg->select_grid) c.select_grid = cfg->select_grid;
+    }
+    if (c.hook_block % 64 || c.hook_block > 1024 || c.select_block % 64 || c.select_block > 1024)
+        return fail(ctx, IM_EINVAL, "block sizes must be multiples of 64 and at most 1024");
+    for (uint32_t q = 0; q < nq; ++q) {
+        const im_query &Q = queries[q];
+        if (!Q.graph || Q.graph->ctx != ctx) return fail(ctx, IM_EINVAL, "query graph belongs to another context");
+        if (Q.R == 0) return fail(ctx, IM_EINVAL, "R must be >= 1");
+        if (Q.k > Q.graph->n) return fail(ctx, IM_EINVAL, "k exceeds n");
+        if (!seeds_out[q] || !gains_out[q]) return fail(ctx, IM_EINVAL, "null output array");
+        im_status pr = check_prob(ctx, Q.prob);
+        if (pr != IM_OK) return pr;
+        const uint32_t kb = std::max<uint32_t>(1, bit_length((uint64_t)Q.graph->n - 1));
+        if (kb + bit_length((uint64_t)Q.R * Q.graph->n + 1) > 64) return fail(ctx, IM_EINVAL, "R*n too large");
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    uint64_t ktriv = 0;
+    im_status rc = trivalency_key(ctx, &ktriv);
+    if (rc != IM_OK) return rc;
+
+    // one arena for every query's arrays
+    std::vector<BatchQuery> hq(nq);
+    std::vector<size_t> at(nq);
+    size_t total = 0;
+    auto take = [&](size_t bytes) { size_t o = total; total += align256(bytes); return o; };
+    struct Off { size_t K, E, gain0, parent, cnt, key, in_s, ids, fr, evl, cov, seeds, gains, evals; };
+    std::vector<Off> off(nq);
+    for (uint32_t q = 0; q < nq; ++q) {
+        const im_query &Q = queries[q];
+        const uint32_t n = Q.graph->n, R = Q.R, k = std::max<uint32_t>(Q.k, 1);
+        TreeDesc td = make_tree(n);
+        const uint64_t tn = tree_nodes(td);
+        Off &o = off[q];
+        o.K = take((size_t)key_slots(R) * 8);
+        o.E = take((size_t)n * R * 8);
+        o.gain0 = take((size_t)n * 8);
+        o.parent = take((size_t)n * R * 4);
+        o.cnt = take((size_t)n * R * 4);
+        o.key = take((size_t)n * 8);
+        o.in_s = take(n);
+        o.ids = take(tn * 4);
+        o.fr = take(tn * 4);
+        o.evl = take((size_t)n * 4);
+        o.cov = take((size_t)cov_slots(R, Q.k) * 8);
+        o.seeds = take((size_t)k * 4);
+        o.gains = take((size_t)k * 8);
+        o.evals = take((size_t)k * 4);
+        BatchQuery &B = hq[q];
+        B = BatchQuery{};
+        B.n = n;
+        B.R = R;
+        B.k = Q.k;
+        B.kb = std::max<uint32_t>(1, bit_length((uint64_t)n - 1));
+        B.m = Q.graph->m_und;
+        B.edges = Q.graph->edges;
+        B.pm = prob_dev(Q.prob, ktriv);
+        B.cov_mask = cov_slots(R, Q.k) - 1;
+        B.td = td;
+    }
+    const size_t desc_at = take(sizeof(BatchQuery) * nq);
+    const size_t pre_at = take(sizeof(uint64_t) * 4 * (nq + 1));
+    const size_t next_at = take(64);
+    const size_t order_at = take(sizeof(uint32_t) * nq);
+    char *arena = nullptr;
+    rc = dev_alloc(ctx, total, (void **)&arena);
+    if (rc != IM_OK) return rc;
+    std::vector<uint64_t> pre(4 * (nq + 1), 0);
+    for (uint32_t q = 0; q < nq; ++q) {
+        BatchQuery &B = hq[q];
+        const Off &o = off[q];
+        B.K = reinterpret_cast<uint64_t *>(arena + o.K);
+        B.E = reinterpret_cast<uint2 *>(arena + o.E);
+        B.gain0 = reinterpret_cast<uint64_t *>(arena + o.gain0);
+        B.parent = reinterpret_cast<uint32_t *>(arena + o.parent);
+        B.cnt = reinterpret_cast<uint32_t *>(arena + o.cnt);
+        B.key = reinterpret_cast<uint64_t *>(arena + o.key);
+        B.in_s = reinterpret_cast<uint8_t *>(arena + o.in_s);
+        B.ids = reinterpret_cast<uint32_t *>(arena + o.ids);
+        B.fr = reinterpret_cast<uint32_t *>(arena + o.fr);
+        B.evl = reinterpret_cast<uint32_t *>(arena + o.evl);
+        B.cov = reinterpret_cast<unsigned long long *>(arena + o.cov);
+        B.seeds = reinterpret_cast<uint32_t *>(arena + o.seeds);
+        B.gains = reinterpret_cast<unsigned long long *>(arena + o.gains);
+        B.evals = reinterpret_cast<uint32_t *>(arena + o.evals);
+        pre[q + 1] = pre[q] + (uint64_t)B.R * B.n;                                          // (sketch, vertex)
+        const uint64_t hook = (uint64_t)((B.R + 63) / 64) * B.m;
+        pre[(nq + 1) + q + 1] = pre[(nq + 1) + q] + ((hook + 63) & ~63ull);                 // (pass, edge), wave-padded
+        pre[2 * (nq + 1) + q + 1] = pre[2 * (nq + 1) + q] + (B.n + kEmitTile - 1) / kEmitTile;  // 64-vertex tiles
+        pre[3 * (nq + 1) + q + 1] = pre[3 * (nq + 1) + q] + B.n;                                 // vertices
+        k_sketch_keys<<<grid_for(key_slots(B.R), 256, 1u << 20), 256, 0, st>>>(queries[q].seed, key_slots(B.R),
+                                                                              const_cast<uint64_t *>(B.K));
+    }
+    BatchQuery *dq = reinterpret_cast<BatchQuery *>(arena + desc_at);
+    uint64_t *dpre = reinterpret_cast<uint64_t *>(arena + pre_at);
+    uint32_t *next_q = reinterpret_cast<uint32_t *>(arena + next_at);
+    uint32_t *dorder = reinterpret_cast<uint32_t *>(arena + order_at);
+    // selection workgroups take the queries with the most (vertex, sketch) entries first
+    std::vector<uint32_t> order(nq);
+    for (uint32_t q = 0; q < nq; ++q) order[q] = q;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        return (uint64_t)hq[a].n * hq[a].R > (uint64_t)hq[b].n * hq[b].R;
+    });
+    (void)hipMemcpyAsync(dorder, order.data(), sizeof(uint32_t) * nq, hipMemcpyHostToDevice, st);
+    hipError_t e1 = hipMemcpyAsync(dq, hq.data(), sizeof(BatchQuery) * nq, hipMemcpyHostToDevice, st);
+    hipError_t e2 = hipMemcpyAsync(dpre, pre.data(), pre.size() * 8, hipMemcpyHostToDevice, st);
+    hipError_t e3 = hipStreamSynchronize(st);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        dev_free(ctx, arena, total);
+        return fail(ctx, IM_EDEVICE, "batched setup copy failed");
+    }
+    const uint64_t tot_vn = pre[nq], tot_hook = pre[2 * nq + 1], tot_tiles = pre[3 * nq + 2];
+    const uint64_t tot_n = pre[4 * nq + 3];
+    const unsigned g_bulk = wave_grid(tot_n, 16384);
+    const unsigned g_init = grid_for(tot_vn, 256, 256 * 64);
+    const unsigned g_hook = c.hook_grid ? c.hook_grid : grid_for(tot_hook, c.hook_block, 256 * 64);
+    const unsigned g_comp = grid_for(tot_vn, 256, 256 * 32);
+    const unsigned g_emit = (unsigned)std::min<uint64_t>(std::max<uint64_t>(tot_tiles, 1), 256 * 32);
+    const unsigned g_sel = c.select_grid ? c.select_grid : std::min<uint32_t>(nq, 256);
+
+    // the five kernels, captured once and launched as one graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    rc = IM_OK;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeGlobal) != hipSuccess) {
+        rc = fail(ctx, IM_EDEVICE, "hipStreamBeginCapture failed");
+    } else {
+        k_bat_init<<<g_init, 256, 0, st>>>(dq, nq, dpre, next_q);
+        k_bat_hook<<<g_hook, c.hook_block, 0, st>>>(dq, nq, dpre + (nq + 1));
+        k_bat_compress<<<g_comp, 256, 0, st>>>(dq, nq, dpre);
+        k_bat_emit<<<g_emit, 256, 0, st>>>(dq, nq, dpre + 2 * (nq + 1));
+        // selection; before a round predicted to re-evaluate nearly every vertex a query
+        // pauses, the whole GPU evaluates its vertices, and the next launch finishes it
+        for (int phase = 0; phase < 3; ++phase) {
+            k_bat_select<<<g_sel, c.select_block, 0, st>>>(dq, nq, dorder, next_q, 0xFFFFFFFFu, phase < 2 ? 1u : 0u);
+            if (phase < 2) k_bat_bulk_eval<<<g_bulk, 256, 0, st>>>(dq, nq, dpre + 3 * (nq + 1), next_q);
+        }
+        hipError_t ec = hipStreamEndCapture(st, &graph);
+        if (ec != hipSuccess || !graph) rc = fail(ctx, IM_EDEVICE, std::string("capture: ") + hipGetErrorString(ec));
+        else if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+            rc = fail(ctx, IM_EDEVICE, "hipGraphInstantiate failed");
+    }
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    float ms = 0.f;
+    if (rc == IM_OK) {
+        (void)hipEventCreate(&t0);
+        (void)hipEventCreate(&t1);
+        (void)hipEventRecord(t0, st);
+        hipError_t el = hipGraphLaunch(exec, st);
+        (void)hipEventRecord(t1, st);
+        hipError_t es = hipStreamSynchronize(st);
+        if (el != hipSuccess || es != hipSuccess)
+            rc = fail(ctx, IM_EDEVICE, std::string("batched launch: ") + hipGetErrorString(el != hipSuccess ? el : es));
+        else (void)hipEventElapsedTime(&ms, t0, t1);
+    }
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    // results
+    if (rc == IM_OK) {
+        std::vector<BatchQuery> back(nq);
+        if (hipMemcpy(back.data(), dq, sizeof(BatchQuery) * nq, hipMemcpyDeviceToHost) != hipSuccess)
+            rc = fail(ctx, IM_EDEVICE, "batched result copy failed");
+        for (uint32_t q = 0; q < nq && rc == IM_OK; ++q) {
+            if (back[q].err || back[q].rounds_done != queries[q].k) {
+                rc = fail(ctx, IM_EINTERNAL, "batched selection consistency check failed for query " + std::to_string(q));
+                break;
+            }
+        }
+        std::vector<std::vector<unsigned long long>> gtmp(nq);
+        std::vector<std::vector<uint32_t>> stmp(nq);
+        for (uint32_t q = 0; q < nq && rc == IM_OK; ++q) {
+            const uint32_t k = queries[q].k;
+            stmp[q].resize(k);
+            gtmp[q].resize(k);
+            if (!k) continue;
+            if (hipMemcpy(stmp[q].data(), hq[q].seeds, (size_t)k * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(gtmp[q].data(), hq[q].gains, (size_t)k * 8, hipMemcpyDeviceToHost) != hipSuccess)
+                rc = fail(ctx, IM_EDEVICE, "batched result copy failed");
+        }
+        if (rc == IM_OK) {
+            for (uint32_t q = 0; q < nq; ++q)
+                for (uint32_t i = 0; i < queries[q].k; ++i) {
+                    seeds_out[q][i] = stmp[q][i];
+                    gains_out[q][i] = gtmp[q][i];
+                }
+            if (device_ms) *device_ms = ms;
+        }
+    }
+    dev_free(ctx, arena, total);
+    return rc;
 }

@@ -44,6 +44,16 @@ _vp = ctypes.c_void_p
 _u32p = ctypes.POINTER(ctypes.c_uint32)
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 
+
+class im_query(ctypes.Structure):
+    _fields_ = [("graph", _vp), ("prob", im_prob), ("R", ctypes.c_uint32), ("k", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64)]
+
+
+class im_batch_config(ctypes.Structure):
+    _fields_ = [("hook_block", ctypes.c_uint32), ("hook_grid", ctypes.c_uint32), ("select_block", ctypes.c_uint32),
+                ("select_grid", ctypes.c_uint32)]
+
 # name -> (restype, argtypes); the names and order follow include/pacim.h
 _SIGS = {
     "im_ctx_create": (ctypes.c_int, [ctypes.c_int, _vp, ctypes.c_size_t, ctypes.POINTER(_vp)]),
@@ -67,6 +77,9 @@ _SIGS = {
     "im_sketches_stats": (ctypes.c_int, [_vp, ctypes.POINTER(im_sketch_stats)]),
     "im_select_trace": (ctypes.c_int, [_vp, _vp, _u32p, ctypes.c_uint32]),
     "im_probe_device": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "im_select_seeds_batched": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.POINTER(im_query),
+                                               ctypes.POINTER(im_batch_config), ctypes.POINTER(_u32p),
+                                               ctypes.POINTER(_u64p), ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None
@@ -232,6 +245,28 @@ def im_probe_device(ctx):
     return h.value, c.value
 
 
+def im_select_seeds_batched(ctx, queries, cfg=None):
+    """queries: iterable of (graph handle, kind, p, R, k, seed).  cfg: dict with any of
+    hook_block, hook_grid, select_block, select_grid.  Returns ([(seeds, gains)], device_ms)."""
+    queries = list(queries)
+    nq = len(queries)
+    arr = (im_query * max(nq, 1))()
+    outs = []
+    for i, (g, kind, p, R, k, seed) in enumerate(queries):
+        arr[i] = im_query(g, _prob(kind, p), R, k, seed & ((1 << 64) - 1))
+        outs.append((np.empty(max(k, 1), dtype=np.uint32), np.empty(max(k, 1), dtype=np.uint64)))
+    sp = (_u32p * max(nq, 1))(*[_u32(a) for a, _ in outs])
+    gp = (_u64p * max(nq, 1))(*[_u64(b) for _, b in outs])
+    c = None
+    if cfg:
+        c = im_batch_config(int(cfg.get("hook_block", 0)), int(cfg.get("hook_grid", 0)),
+                            int(cfg.get("select_block", 0)), int(cfg.get("select_grid", 0)))
+    ms = ctypes.c_double()
+    _check(ctx, load().im_select_seeds_batched(ctx, nq, arr, ctypes.byref(c) if c else None, sp, gp,
+                                               ctypes.byref(ms)))
+    return [(a[:q[4]], b[:q[4]]) for (a, b), q in zip(outs, queries)], ms.value
+
+
 def im_sketches_stats(s) -> dict:
     st = im_sketch_stats()
     rc = load().im_sketches_stats(s, ctypes.byref(st))
@@ -276,6 +311,10 @@ class Context:
 
     def probe(self):
         return im_probe_device(self.h)
+
+    def select_batched(self, queries, cfg=None):
+        """queries: list of (Graph, kind, p, R, k, seed)."""
+        return im_select_seeds_batched(self.h, [(g.h, kd, p, R, k, sd) for (g, kd, p, R, k, sd) in queries], cfg)
 
 
 class Graph:
