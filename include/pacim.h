@@ -200,6 +200,57 @@ typedef struct {
 im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_query *queries, const im_batch_config *cfg,
                                   uint32_t *const *seeds_out, uint64_t *const *gains_out, double *device_ms);
 
+/* ---- serving ---------------------------------------------------------------- */
+
+typedef struct im_server im_server;
+
+typedef struct {
+    size_t hbm_budget;         /* bytes for query slots, build scratch and cached sketch
+                                  sets together (0: 64 GiB)                              */
+    uint32_t max_active;       /* requests selected concurrently (0: 16, at most 256)    */
+    uint32_t rounds_per_step;  /* rounds each active request advances per step (0: 16)   */
+    uint32_t max_R;            /* largest R accepted (0: 256)                            */
+    uint32_t max_k;            /* largest k accepted (0: 1000)                           */
+    uint64_t sample_seed;      /* sampling seed of every sketch set                      */
+} im_server_config;
+
+typedef struct {
+    uint64_t submitted, completed, steps, builds, cache_hits, evictions;
+    size_t bytes_in_use, peak_bytes;
+    uint32_t cached_sets;
+    double admit_ms;       /* worker time in admission (sketch-set allocation, eviction, build launch) */
+    double build_wait_ms;  /* worker time waiting with every admitted request's sketches unbuilt      */
+    double step_ms;        /* worker time in selection steps (launch to results on the host)          */
+    double busy_steps_ms;  /* device time of the selection steps (HIP events)                         */
+} im_server_counters;
+
+/* A request server over resident graphs (Algorithm 1 per request, full-label
+ * sketches), with continuous batching: a worker thread admits requests as query
+ * slots and HBM free up (sketch sets cached per graph, model and R, least
+ * recently used unreferenced sets evicted under hbm_budget), builds missing
+ * sketch sets on its own stream, and advances every admitted request by
+ * rounds_per_step rounds per step in one batched launch (requests join and leave
+ * between steps).  Each request's seeds and gains equal
+ * im_select_seeds(graph, prob, R, k, sample_seed) alone.  The graphs must stay
+ * alive until im_server_destroy.  While a server exists its worker thread issues
+ * work on the context's device; other calls may use the same context. */
+im_status im_server_create(im_ctx *ctx, const im_graph *const *graphs, uint32_t ngraphs,
+                           const im_server_config *cfg, im_server **out);
+/* Queues a request on graphs[graph]; *ticket identifies it.  EINVAL: bad
+ * arguments (R > max_R, k > max_k or > n, bad prob); EBUSY: its sketch set can
+ * never fit hbm_budget. */
+im_status im_server_submit(im_server *srv, uint32_t graph, im_prob prob, uint32_t R, uint32_t k,
+                           uint64_t *ticket);
+/* *done = 1 once the request finished (EINVAL for an unknown ticket). */
+im_status im_server_poll(im_server *srv, uint64_t ticket, int *done);
+/* Blocks until the request finishes, writes its k seeds and gains (caller-owned
+ * host arrays) and the time from submit to completion, and retires the ticket.
+ * Returns the request's own status. */
+im_status im_server_wait(im_server *srv, uint64_t ticket, uint32_t *seeds, uint64_t *gains, double *latency_ms);
+im_status im_server_stats(im_server *srv, im_server_counters *out);
+/* Finishes every queued request, then frees the server. */
+im_status im_server_destroy(im_server *srv);
+
 /* ---- device ceilings (roofline) -------------------------------------------- */
 
 /* Measures, on the context's device, (a) the rate of live-edge hash tests the

@@ -8,11 +8,13 @@
 //   k_bat_select    one workgroup per query (work-stealing counter): winning tree
 //                   built from the initial gains, then k rounds of Algorithm 5
 //                   with the frontier levels separated by workgroup barriers
-//   k_bat_bulk_eval every vertex of the queries whose next round is predicted to
-//                   re-evaluate nearly all of them (the previous seed covered a
-//                   large share of every sketch), one wave per vertex over the
-//                   whole GPU; the next k_bat_select launch rebuilds those trees
-//                   from the fresh keys and finishes the round
+//   k_bat_plan / k_bat_prepare / k_bat_tree_level
+//                   whole-GPU work a selection workgroup would do slowly alone:
+//                   initial keys and trees of new queries, and, for a query
+//                   whose next round is predicted to re-evaluate nearly every
+//                   vertex (the previous seed covered a large share of every
+//                   sketch), the marginal of every vertex and a rebuilt tree;
+//                   the next k_bat_select launch then finishes that round
 //
 // Work items of the flattened kernels are located by a binary search over the
 // per-query prefix sums.  E is never modified during selection: the CCs already
@@ -46,7 +48,9 @@ struct BatchQuery {
     uint32_t *evals;                 // [k]
     TreeDesc td;
     uint32_t rounds_done;
-    uint32_t bulk_pending;           // next round evaluates every vertex (k_bat_bulk_eval)
+    uint32_t tree_ready;             // keys, covered set and tree initialised
+    uint32_t bulk_pending;           // 1: the next round evaluates every vertex
+    uint32_t prep;                   // this phase: 1 initialise, 2 bulk evaluation, 0 none
     uint32_t err;
 };
 
@@ -271,12 +275,12 @@ __global__ void __launch_bounds__(256) k_bat_emit(const BatchQuery *__restrict__
 // a later launch continues where this one stopped.
 // order: the queries in the order workgroups take them (largest first).
 // stop_on_heavy: leave a query (bulk_pending = 1) before a round that follows a
-// seed of gain >= R*n/64, for k_bat_bulk_eval to evaluate all its vertices.
+// seed of gain >= R*n/64, for the next preparation to evaluate all its vertices.
 __global__ void __launch_bounds__(1024) k_bat_select(BatchQuery *__restrict__ qs, uint32_t nq,
                                                      const uint32_t *__restrict__ order,
                                                      uint32_t *__restrict__ next_q, uint32_t round_budget,
                                                      uint32_t stop_on_heavy) {
-    __shared__ uint32_t sh_q;
+    __shared__ uint32_t sh_q, sh_prep;
     __shared__ unsigned long long sh_delta;
     __shared__ uint32_t sh_fr[kMaxLevels + 1], sh_ev[kMaxLevels + 1];
     const uint32_t lane = lane_id(), wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
@@ -296,38 +300,21 @@ __global__ void __launch_bounds__(1024) k_bat_select(BatchQuery *__restrict__ qs
         uint64_t *key = Q.key;
         uint32_t *ids = Q.ids, *fr = Q.fr, *evl = Q.evl;
         uint32_t rd = Q.rounds_done;
-        if (rd == 0) {
-            for (uint32_t v = threadIdx.x; v < n; v += blockDim.x) {
-                key[v] = pack_key(Q.gain0[v], v, kb);
-                Q.in_s[v] = 0;
-            }
-            for (uint32_t c = threadIdx.x; c <= cmask; c += blockDim.x) Q.cov[c] = kCovEmpty;
-            __syncthreads();
-            for (int l = (int)td.D - 1; l >= 0; --l) {
-                for (uint32_t t = wave; t < td.lvl_n[l]; t += nwaves) {
-                    const uint32_t w = relink_node(td, ids, key, (uint32_t)l, t, 0, 0, 0, false);
-                    if (lane == 0) ids[td.lvl_off[l] + t] = w;
-                }
-                __syncthreads();
-            }
-        }
-        const bool bulk = Q.bulk_pending != 0;
-        if (bulk) {
-            // every key is fresh: rebuild the tree; its root is this round's seed
-            for (int l = (int)td.D - 1; l >= 0; --l) {
-                for (uint32_t t = wave; t < td.lvl_n[l]; t += nwaves) {
-                    const uint32_t w = relink_node(td, ids, key, (uint32_t)l, t, 0, 0, 0, false);
-                    if (lane == 0) ids[td.lvl_off[l] + t] = w;
-                }
-                __syncthreads();
-            }
-            if (threadIdx.x == 0) {
+        // this phase's preparation, read once by thread 0 and shared: every wave must
+        // take the same path through the barrier-separated steps below
+        if (threadIdx.x == 0) {
+            const uint32_t prep = Q.prep;
+            sh_prep = prep;
+            if (prep == 1) Q.tree_ready = 1;
+            if (prep == 2) {
                 for (int l = 0; l <= kMaxLevels; ++l) sh_ev[l] = 0;
                 sh_ev[0] = n - rd;
                 Q.bulk_pending = 0;
             }
-            __syncthreads();
+            Q.prep = 0;
         }
+        __syncthreads();
+        const bool bulk = sh_prep == 2;  // keys fresh, tree rebuilt: this round's seed is the root
         for (uint32_t budget = 0; rd < k && budget < round_budget; ++budget, ++rd) {
             if (!(bulk && budget == 0) && stop_on_heavy && rd > 0 &&
                 Q.gains[rd - 1] * 64ull >= (unsigned long long)R * n) {
@@ -436,21 +423,69 @@ __global__ void __launch_bounds__(1024) k_bat_select(BatchQuery *__restrict__ qs
     }
 }
 
-// Fresh keys for every vertex of the queries with bulk_pending (one wave per
-// vertex, items wave-uniform per query); also rearms the selection counter.
-__global__ void __launch_bounds__(256) k_bat_bulk_eval(BatchQuery *__restrict__ qs, uint32_t nq,
-                                                       const uint64_t *__restrict__ pre_n,
-                                                       uint32_t *__restrict__ next_q) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *next_q = 0;
-    const uint64_t total = pre_n[nq];
+// Decides each query's work for this phase and rearms the selection counter.
+__global__ void k_bat_plan(BatchQuery *__restrict__ qs, uint32_t nq, uint32_t *__restrict__ next_q) {
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q == 0) *next_q = 0;
+    if (q < nq) qs[q].prep = !qs[q].tree_ready ? 1u : (qs[q].bulk_pending == 1 ? 2u : 0u);
+}
+
+// Items of 64 vertices (or 64 covered-set slots); pre counts max(ceil(n/64),
+// ceil(slots/64)) per query (wave-uniform).  prep 1: initial keys, no seeds, empty
+// covered set; prep 2: every vertex's marginal.
+__global__ void __launch_bounds__(256) k_bat_prepare(BatchQuery *__restrict__ qs, uint32_t nq,
+                                                     const uint64_t *__restrict__ pre) {
+    const uint64_t total = pre[nq];
     const uint32_t lane = lane_id();
     for (uint64_t i = wave_index(); i < total; i += wave_count()) {
-        const uint32_t q = (uint32_t)__builtin_amdgcn_readfirstlane((int)find_query(pre_n, nq, i));
+        const uint32_t q = (uint32_t)__builtin_amdgcn_readfirstlane((int)find_query(pre, nq, i));
         BatchQuery &Q = qs[q];
-        if (Q.bulk_pending != 1) continue;
-        const uint32_t v = (uint32_t)(i - pre_n[q]);
-        const uint64_t g = marginal_cov(Q.E, Q.R, v, Q.cov, Q.cov_mask);
-        if (lane == 0) Q.key[v] = Q.in_s[v] ? 0ull : pack_key(g, v, Q.kb);
+        const uint32_t prep = Q.prep;
+        if (prep == 0) continue;
+        const uint32_t v0 = (uint32_t)(i - pre[q]) * kWave;
+        if (prep == 1) {
+            const uint32_t v = v0 + lane;
+            if (v < Q.n) {
+                Q.key[v] = pack_key(Q.gain0[v], v, Q.kb);
+                Q.in_s[v] = 0;
+            }
+            if (v <= Q.cov_mask) Q.cov[v] = kCovEmpty;
+        } else {
+            for (uint32_t j = 0; j < kWave && v0 + j < Q.n; j += kEvalUnroll) {
+                uint32_t vs[kEvalUnroll];
+                uint64_t g[kEvalUnroll];
+#pragma unroll
+                for (int u = 0; u < kEvalUnroll; ++u) {
+                    const uint32_t v = v0 + j + u;
+                    vs[u] = (j + u < kWave && v < Q.n) ? v : kNone;
+                }
+                marginal_cov_multi(Q.E, Q.R, vs, Q.cov, Q.cov_mask, g);
+                if (lane < kEvalUnroll && vs[lane] != kNone) {
+                    uint64_t gl = g[0];
+#pragma unroll
+                    for (int u = 1; u < kEvalUnroll; ++u) gl = lane == (uint32_t)u ? g[u] : gl;
+                    Q.key[vs[lane]] = Q.in_s[vs[lane]] ? 0ull : pack_key(gl, vs[lane], Q.kb);
+                }
+            }
+        }
+    }
+}
+
+// One level of the winning trees of the queries with prep != 0, j levels above
+// the deepest internal level (pre: per-query node counts of that level; one wave
+// per node).  Launched for j = 0, 1, ... so each level sees its children final.
+__global__ void __launch_bounds__(256) k_bat_tree_level(BatchQuery *__restrict__ qs, uint32_t nq,
+                                                        const uint64_t *__restrict__ pre, uint32_t j) {
+    const uint64_t total = pre[nq];
+    for (uint64_t i = wave_index(); i < total; i += wave_count()) {
+        const uint32_t q = (uint32_t)__builtin_amdgcn_readfirstlane((int)find_query(pre, nq, i));
+        BatchQuery &Q = qs[q];
+        if (Q.prep == 0 || j >= Q.td.D) continue;
+        const uint32_t l = Q.td.D - 1 - j;
+        const uint32_t t = (uint32_t)(i - pre[q]);
+        if (t >= Q.td.lvl_n[l]) continue;
+        const uint32_t w = relink_node(Q.td, Q.ids, Q.key, l, t, 0, 0, 0, false);
+        if (lane_id() == 0) Q.ids[Q.td.lvl_off[l] + t] = w;
     }
 }
 

@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -54,6 +55,7 @@ struct im_ctx {
     bool profiling = false;
     std::map<std::string, KTimer> timers;
     std::vector<hipEvent_t> spare_events;
+    std::mutex alloc_mu;  // device memory accounting (a server's thread allocates too)
 };
 
 struct im_graph {
@@ -122,6 +124,7 @@ im_status fail(im_ctx *ctx, im_status s, const std::string &msg) {
 im_status dev_alloc(im_ctx *ctx, size_t bytes, void **p) {
     *p = nullptr;
     if (bytes == 0) bytes = 8;
+    std::lock_guard<std::mutex> lk(ctx->alloc_mu);
     if (ctx->cap && ctx->used + bytes > ctx->cap)
         return fail(ctx, IM_ENOMEM, "allocation of " + std::to_string(bytes) + " bytes exceeds the context HBM cap");
     hipError_t e = hipMalloc(p, bytes);
@@ -137,6 +140,7 @@ im_status dev_alloc(im_ctx *ctx, size_t bytes, void **p) {
 void dev_free(im_ctx *ctx, void *p, size_t bytes) {
     if (!p) return;
     if (bytes == 0) bytes = 8;
+    std::lock_guard<std::mutex> lk(ctx->alloc_mu);
     (void)hipFree(p);
     ctx->used -= std::min(ctx->used, bytes);
 }
@@ -181,8 +185,8 @@ struct Prof {
     im_ctx *ctx;
     const char *name;
     hipEvent_t a = nullptr;
-    Prof(im_ctx *c, const char *nm) : ctx(c), name(nm) {
-        if (ctx->profiling) {
+    Prof(im_ctx *c, const char *nm, hipStream_t on = nullptr) : ctx(c), name(nm) {
+        if (ctx->profiling && (!on || on == ctx->stream)) {
             a = take_event(ctx);
             if (a) (void)hipEventRecord(a, ctx->stream);
         }
@@ -463,23 +467,38 @@ void cc_scratch_free(im_ctx *ctx, CCScratch *cs) {
 // labels in parent[b][n] (root = smallest id of the CC), member counts at the
 // roots in cnt, and (if center_rank) the smallest center rank of each CC in minc.
 void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const uint64_t *K, uint32_t b,
-                     const CCScratch &cs, uint32_t *minc, uint32_t minc_init, const uint32_t *center_rank) {
-    hipStream_t st = ctx->stream;
+                     const CCScratch &cs, uint32_t *minc, uint32_t minc_init, const uint32_t *center_rank,
+                     hipStream_t st = nullptr) {
+    if (!st) st = ctx->stream;
     const uint32_t n = g->n;
     const unsigned hook_grid = grid_for(g->m_und, 256, 256 * 16);
     dim3 gi((n + 255) / 256, b);
     k_batch_init<<<gi, 256, 0, st>>>(cs.parent, cs.cnt, minc, n, minc_init);
     {
-        Prof p(ctx, "sample_hook");
+        Prof p(ctx, "sample_hook", st);
         if (pm.kind == 0)
             k_sample_hook<0><<<hook_grid, 256, 0, st>>>(g->edges, g->m_und, K, b, pm, cs.parent, n);
         else
             k_sample_hook<1><<<hook_grid, 256, 0, st>>>(g->edges, g->m_und, K, b, pm, cs.parent, n);
     }
     {
-        Prof p(ctx, "compress");
+        Prof p(ctx, "compress", st);
         dim3 gc(std::min<unsigned>((n + 255) / 256, 64u), b);
         k_compress<<<gc, 256, 0, st>>>(cs.parent, cs.cnt, n, center_rank, minc);
+    }
+}
+
+// Full-label sketches of R sketches with keys K (key_slots(R) entries already on
+// the device): E[n][R] and the initial gains, B sketches per pass.
+void enqueue_full_build(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const uint64_t *K, uint32_t R,
+                        const CCScratch &cs, uint2 *E, uint64_t *gain0, hipStream_t st) {
+    const uint32_t n = g->n;
+    (void)hipMemsetAsync(gain0, 0, (size_t)n * 8, st);
+    for (uint32_t r0 = 0; r0 < R; r0 += cs.B) {
+        const uint32_t b = std::min(cs.B, R - r0);
+        enqueue_cc_pass(ctx, g, pm, K + r0, b, cs, nullptr, kNone, nullptr, st);
+        Prof p(ctx, "emit", st);
+        k_emit_full<<<(n + kEmitTile - 1) / kEmitTile, 256, 0, st>>>(cs.parent, cs.cnt, n, b, R, r0, E, gain0);
     }
 }
 
@@ -1037,6 +1056,25 @@ uint32_t cov_slots(uint32_t R, uint32_t k) {
     return c;
 }
 
+uint64_t prep_items(const BatchQuery &B) {
+    return std::max<uint64_t>((B.n + kWave - 1) / kWave, ((uint64_t)B.cov_mask + 1 + kWave - 1) / kWave);
+}
+
+// Whole-GPU preparation before a selection launch: plan (prep per query, counter
+// rearmed), initial keys / every marginal, then the trees level by level.
+// pre_levels[j * stride + q] are the device prefix sums of tree level j (host copy
+// in host_levels, used for the launch sizes).
+void enqueue_prepare(BatchQuery *dq, uint32_t nq, const uint64_t *pre_prep, uint64_t tot_prep,
+                     const uint64_t *pre_levels, const uint64_t *host_levels, uint32_t Dmax, uint32_t stride,
+                     uint32_t *next_q, hipStream_t st) {
+    k_bat_plan<<<(nq + 255) / 256, 256, 0, st>>>(dq, nq, next_q);
+    if (tot_prep) k_bat_prepare<<<wave_grid(tot_prep, 16384), 256, 0, st>>>(dq, nq, pre_prep);
+    for (uint32_t j = 0; j < Dmax; ++j) {
+        const uint64_t tot = host_levels[(size_t)j * stride + nq];
+        if (tot) k_bat_tree_level<<<wave_grid(tot, 16384), 256, 0, st>>>(dq, nq, pre_levels + (size_t)j * stride, j);
+    }
+}
+
 // K(0, SALT_TRIV), computed on the device once per context.
 im_status trivalency_key(im_ctx *ctx, uint64_t *out) {
     uint64_t *d = nullptr;
@@ -1123,13 +1161,16 @@ extern "C" im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_
         B.td = td;
     }
     const size_t desc_at = take(sizeof(BatchQuery) * nq);
-    const size_t pre_at = take(sizeof(uint64_t) * 4 * (nq + 1));
+    uint32_t Dmax = 0;
+    for (uint32_t q = 0; q < nq; ++q) Dmax = std::max(Dmax, hq[q].td.D);
+    const uint32_t npre = 4 + Dmax;  // (sketch, vertex), hook items, tiles, prepare items, tree levels
+    const size_t pre_at = take(sizeof(uint64_t) * npre * (nq + 1));
     const size_t next_at = take(64);
     const size_t order_at = take(sizeof(uint32_t) * nq);
     char *arena = nullptr;
     rc = dev_alloc(ctx, total, (void **)&arena);
     if (rc != IM_OK) return rc;
-    std::vector<uint64_t> pre(4 * (nq + 1), 0);
+    std::vector<uint64_t> pre((size_t)npre * (nq + 1), 0);
     for (uint32_t q = 0; q < nq; ++q) {
         BatchQuery &B = hq[q];
         const Off &o = off[q];
@@ -1151,7 +1192,11 @@ extern "C" im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_
         const uint64_t hook = (uint64_t)((B.R + 63) / 64) * B.m;
         pre[(nq + 1) + q + 1] = pre[(nq + 1) + q] + ((hook + 63) & ~63ull);                 // (pass, edge), wave-padded
         pre[2 * (nq + 1) + q + 1] = pre[2 * (nq + 1) + q] + (B.n + kEmitTile - 1) / kEmitTile;  // 64-vertex tiles
-        pre[3 * (nq + 1) + q + 1] = pre[3 * (nq + 1) + q] + B.n;                                 // vertices
+        pre[3 * (nq + 1) + q + 1] = pre[3 * (nq + 1) + q] + prep_items(B);                       // prepare items
+        for (uint32_t j = 0; j < Dmax; ++j) {                                                        // tree level j
+            const uint64_t nodes = j < B.td.D ? B.td.lvl_n[B.td.D - 1 - j] : 0;
+            pre[(4 + j) * (nq + 1) + q + 1] = pre[(4 + j) * (nq + 1) + q] + nodes;
+        }
         k_sketch_keys<<<grid_for(key_slots(B.R), 256, 1u << 20), 256, 0, st>>>(queries[q].seed, key_slots(B.R),
                                                                               const_cast<uint64_t *>(B.K));
     }
@@ -1174,8 +1219,7 @@ extern "C" im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_
         return fail(ctx, IM_EDEVICE, "batched setup copy failed");
     }
     const uint64_t tot_vn = pre[nq], tot_hook = pre[2 * nq + 1], tot_tiles = pre[3 * nq + 2];
-    const uint64_t tot_n = pre[4 * nq + 3];
-    const unsigned g_bulk = wave_grid(tot_n, 16384);
+    const uint64_t tot_prep = pre[4 * nq + 3];
     const unsigned g_init = grid_for(tot_vn, 256, 256 * 64);
     const unsigned g_hook = c.hook_grid ? c.hook_grid : grid_for(tot_hook, c.hook_block, 256 * 64);
     const unsigned g_comp = grid_for(tot_vn, 256, 256 * 32);
@@ -1193,11 +1237,13 @@ extern "C" im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_
         k_bat_hook<<<g_hook, c.hook_block, 0, st>>>(dq, nq, dpre + (nq + 1));
         k_bat_compress<<<g_comp, 256, 0, st>>>(dq, nq, dpre);
         k_bat_emit<<<g_emit, 256, 0, st>>>(dq, nq, dpre + 2 * (nq + 1));
-        // selection; before a round predicted to re-evaluate nearly every vertex a query
-        // pauses, the whole GPU evaluates its vertices, and the next launch finishes it
+        // selection phases: the whole GPU prepares keys and trees (new queries; queries
+        // paused before a round predicted to re-evaluate nearly every vertex), then one
+        // workgroup per query runs rounds until done or until the next such round
         for (int phase = 0; phase < 3; ++phase) {
+            enqueue_prepare(dq, nq, dpre + 3 * (nq + 1), tot_prep, dpre + 4 * (nq + 1), pre.data() + 4 * (nq + 1),
+                            Dmax, nq + 1, next_q, st);
             k_bat_select<<<g_sel, c.select_block, 0, st>>>(dq, nq, dorder, next_q, 0xFFFFFFFFu, phase < 2 ? 1u : 0u);
-            if (phase < 2) k_bat_bulk_eval<<<g_bulk, 256, 0, st>>>(dq, nq, dpre + 3 * (nq + 1), next_q);
         }
         hipError_t ec = hipStreamEndCapture(st, &graph);
         if (ec != hipSuccess || !graph) rc = fail(ctx, IM_EDEVICE, std::string("capture: ") + hipGetErrorString(ec));
@@ -1255,3 +1301,6 @@ extern "C" im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_
     dev_free(ctx, arena, total);
     return rc;
 }
+
+// ---------------------------------------------------------------- serving
+#include "server.h"

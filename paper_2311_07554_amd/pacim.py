@@ -50,6 +50,19 @@ class im_query(ctypes.Structure):
                 ("seed", ctypes.c_uint64)]
 
 
+class im_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_active", ctypes.c_uint32), ("rounds_per_step", ctypes.c_uint32),
+                ("max_R", ctypes.c_uint32), ("max_k", ctypes.c_uint32), ("sample_seed", ctypes.c_uint64)]
+
+
+class im_server_counters(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("steps", ctypes.c_uint64),
+                ("builds", ctypes.c_uint64), ("cache_hits", ctypes.c_uint64), ("evictions", ctypes.c_uint64),
+                ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t), ("cached_sets", ctypes.c_uint32),
+                ("admit_ms", ctypes.c_double), ("build_wait_ms", ctypes.c_double), ("step_ms", ctypes.c_double),
+                ("busy_steps_ms", ctypes.c_double)]
+
+
 class im_batch_config(ctypes.Structure):
     _fields_ = [("hook_block", ctypes.c_uint32), ("hook_grid", ctypes.c_uint32), ("select_block", ctypes.c_uint32),
                 ("select_grid", ctypes.c_uint32)]
@@ -77,6 +90,14 @@ _SIGS = {
     "im_sketches_stats": (ctypes.c_int, [_vp, ctypes.POINTER(im_sketch_stats)]),
     "im_select_trace": (ctypes.c_int, [_vp, _vp, _u32p, ctypes.c_uint32]),
     "im_probe_device": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "im_server_create": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_uint32, ctypes.POINTER(im_server_config),
+                                        ctypes.POINTER(_vp)]),
+    "im_server_submit": (ctypes.c_int, [_vp, ctypes.c_uint32, im_prob, ctypes.c_uint32, ctypes.c_uint32,
+                                        ctypes.POINTER(ctypes.c_uint64)]),
+    "im_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]),
+    "im_server_wait": (ctypes.c_int, [_vp, ctypes.c_uint64, _u32p, _u64p, ctypes.POINTER(ctypes.c_double)]),
+    "im_server_stats": (ctypes.c_int, [_vp, ctypes.POINTER(im_server_counters)]),
+    "im_server_destroy": (ctypes.c_int, [_vp]),
     "im_select_seeds_batched": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.POINTER(im_query),
                                                ctypes.POINTER(im_batch_config), ctypes.POINTER(_u32p),
                                                ctypes.POINTER(_u64p), ctypes.POINTER(ctypes.c_double)]),
@@ -267,6 +288,50 @@ def im_select_seeds_batched(ctx, queries, cfg=None):
     return [(a[:q[4]], b[:q[4]]) for (a, b), q in zip(outs, queries)], ms.value
 
 
+def im_server_create(ctx, graph_handles, hbm_budget=0, max_active=0, rounds_per_step=0, max_R=0, max_k=0,
+                     sample_seed=1):
+    arr = (_vp * len(graph_handles))(*graph_handles)
+    cfg = im_server_config(hbm_budget, max_active, rounds_per_step, max_R, max_k, sample_seed)
+    h = _vp()
+    _check(ctx, load().im_server_create(ctx, arr, len(graph_handles), ctypes.byref(cfg), ctypes.byref(h)))
+    return h.value
+
+
+def _srv_check(rc, what):
+    if rc != IM_OK:
+        raise ImError(rc, what)
+
+
+def im_server_submit(srv, graph: int, kind: int, p: float, R: int, k: int) -> int:
+    t = ctypes.c_uint64()
+    _srv_check(load().im_server_submit(srv, graph, _prob(kind, p), R, k, ctypes.byref(t)), "im_server_submit")
+    return t.value
+
+
+def im_server_poll(srv, ticket: int) -> bool:
+    d = ctypes.c_int()
+    _srv_check(load().im_server_poll(srv, ticket, ctypes.byref(d)), "im_server_poll")
+    return bool(d.value)
+
+
+def im_server_wait(srv, ticket: int, k: int):
+    seeds = np.empty(max(k, 1), dtype=np.uint32)
+    gains = np.empty(max(k, 1), dtype=np.uint64)
+    lat = ctypes.c_double()
+    _srv_check(load().im_server_wait(srv, ticket, _u32(seeds), _u64(gains), ctypes.byref(lat)), "im_server_wait")
+    return seeds[:k], gains[:k], lat.value
+
+
+def im_server_stats(srv) -> dict:
+    c = im_server_counters()
+    _srv_check(load().im_server_stats(srv, ctypes.byref(c)), "im_server_stats")
+    return {f: getattr(c, f) for f, _ in im_server_counters._fields_}
+
+
+def im_server_destroy(srv):
+    _srv_check(load().im_server_destroy(srv), "im_server_destroy")
+
+
 def im_sketches_stats(s) -> dict:
     st = im_sketch_stats()
     rc = load().im_sketches_stats(s, ctypes.byref(st))
@@ -366,3 +431,38 @@ class Sketches:
 
     def trace(self):
         return im_select_trace(self.ctx.h, self.h, int(self.stats()["seeds_chosen"]))
+
+
+class Server:
+    """Request server over resident graphs (continuous batching in the library)."""
+
+    def __init__(self, ctx: Context, graphs, **cfg):
+        self.ctx = ctx
+        self.graphs = list(graphs)
+        self.h = im_server_create(ctx.h, [g.h for g in self.graphs], **cfg)
+        self._k = {}
+
+    def submit(self, graph: int, kind: int, p: float, R: int, k: int) -> int:
+        t = im_server_submit(self.h, graph, kind, p, R, k)
+        self._k[t] = k
+        return t
+
+    def poll(self, ticket: int) -> bool:
+        return im_server_poll(self.h, ticket)
+
+    def wait(self, ticket: int):
+        return im_server_wait(self.h, ticket, self._k.pop(ticket))
+
+    def stats(self):
+        return im_server_stats(self.h)
+
+    def close(self):
+        if self.h:
+            im_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
