@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--load", type=float, default=1.0,
                     help="serving: offered load as a multiple of the plain path's measured capacity")
     ap.add_argument("--baseline-sample", type=int, default=100, help="serving: requests timed on the plain path")
+    ap.add_argument("--budget-gib", type=float, default=160.0,
+                    help="serving: HBM budget of the server (query slots, build scratch, cached sketch sets)")
     ap.add_argument("--no-autotune", action="store_true")
     return ap.parse_args()
 
@@ -178,7 +180,8 @@ def run_serving(args):
           file=sys.stderr, flush=True)
     arrivals = inputs.poisson_arrivals(len(reqs), qps, seed=5)
     tickets = [None] * len(reqs)
-    srv = pacim.Server(ctx, grs, hbm_budget=64 << 30, max_active=32, rounds_per_step=16, sample_seed=sample_seed)
+    srv = pacim.Server(ctx, grs, hbm_budget=int(args.budget_gib * (1 << 30)), max_active=32, rounds_per_step=16,
+                       sample_seed=sample_seed)
 
     def submitter():
         t_start = time.perf_counter()
@@ -226,7 +229,8 @@ def run_serving(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": f"serving_rmat16-22_x16_{len(reqs)}req", "graphs": [g.n for g in graphs],
                    "p": [0.01, 0.02, 0.05], "R": [64, 256], "k": [10, 50, 100], "parallelism": "single GPU"},
-        "serving": {"offered_qps": qps, "throughput_qps": len(reqs) / t_all,
+        "serving": {"offered_qps": qps, "offered_load": args.load, "hbm_budget_gib": args.budget_gib,
+                    "throughput_qps": len(reqs) / t_all,
                     "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                     "mean_ms": float(lat.mean()), "max_ms": float(lat.max()), "stats": st},
         "plain_one_request_at_a_time": {"sample": ns, "mean_ms": float(np.mean(base)),
