@@ -24,12 +24,44 @@ sys.path.insert(0, ROOT)
 
 METRIC = "sampled edges/s for Sketch; seeds/s for k-seed select; HBM GB/s vs peak"
 HBM_PEAK_GBS = 8000.0
-# Integer VALU ceiling of the live-edge hash: 256 CUs x 64 lanes x 2.4 GHz full-rate
-# 32-bit lane-ops, and one hash costs 20 full-rate + 6 quarter-rate VALU
-# instructions (44 issue slots) in the sampling loop.
-VALU_LANE_OPS = 256 * 64 * 2.4e9
-SLOTS_PER_HASH = 44.0
-HASH_PEAK_G = VALU_LANE_OPS / SLOTS_PER_HASH / 1e9
+# Integer VALU ceiling of the live-edge test: 256 CUs x 4 SIMDs x 16 lanes at
+# 2.4 GHz issue 39.3e12 lane-instructions/s, and the compiled test loop of the
+# sampling kernel spends 175 VALU instructions per 8 tests (64 v_xor_b32,
+# 32 v_mul_lo_u32, 24 v_lshrrev_b64, 16 v_mad_u64_u32, 16 v_add3_u32, 8 v_cmp_lt_u64
+# and 15 to build the mask), each taken as one issue; the device probe's hash
+# loop, the same instructions with no memory traffic, reaches about 90% of this.
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+VALU_PER_HASH = 175.0 / 8.0
+HASH_PEAK_G = VALU_LANE_OPS / VALU_PER_HASH / 1e9
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_sample_hook_rmat20_traffic.txt")
+
+
+def sampling_kernel_traffic():
+    """HBM bytes per launch of the sampling kernel from its committed counter
+    profile (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for
+    a copy kernel of known size), or None when the profile is missing or the
+    kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        fields = {}
+        with open(TRAFFIC_PROFILE) as f:
+            for line in f:
+                if ":" in line and not line.startswith(" "):
+                    k, v = line.split(":", 1)
+                    fields[k.strip()] = v.strip()
+        h = hashlib.sha256()
+        for rel in fields["kernel_sources"].split():
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != fields["kernel_sources_sha256"]:
+            return None
+        return {"bytes": float(fields["traffic_bytes"]), "fetch_bytes": float(fields["traffic_fetch_bytes"]),
+                "write_bytes": float(fields["traffic_write_bytes"]),
+                "profile": os.path.relpath(TRAFFIC_PROFILE, ROOT)}
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -334,11 +366,17 @@ def main():
     roofline = None
     if hk["avg_ms"]:
         achieved = hashes_per_launch / (hk["avg_ms"] / 1e3) / 1e9
+        tr = sampling_kernel_traffic() if (args.scale == 20 and B == 64 and q.R == 256) else None
         roofline = {"bound": "alu", "kernel": hk_name, "achieved": achieved, "peak": HASH_PEAK_G,
-                    "unit": "Ghash/s", "frac": achieved / HASH_PEAK_G, "traffic": None,
+                    "unit": "Ghash/s", "frac": achieved / HASH_PEAK_G,
+                    "traffic": tr["bytes"] if tr else None,
                     "per_launch_hashes": hashes_per_launch, "avg_launch_ms": hk["avg_ms"],
                     "measured_ceiling": probe_hash / 1e9,
                     "frac_of_measured_ceiling": achieved / (probe_hash / 1e9)}
+        if tr:
+            # the union-find's random parent accesses, not the hashes, move these bytes
+            roofline["traffic_detail"] = dict(tr, achieved_GB_s=tr["bytes"] / (hk["avg_ms"] / 1e3) / 1e9,
+                                              algorithmic_bytes=8.0 * m_und)
 
     out = {
         "metric": METRIC,

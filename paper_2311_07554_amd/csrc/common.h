@@ -69,6 +69,17 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
     return x;
 }
 
+// Inclusive prefix sum over the lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= (uint32_t)off) x += y;
+    }
+    return x;
+}
+
 // Wave-aggregated append: lanes with pred reserve consecutive slots of a
 // global counter with one atomic per wave.  Returns the slot (valid if pred)
 // and writes the wave's total to *total.

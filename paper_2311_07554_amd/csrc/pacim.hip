@@ -471,15 +471,15 @@ void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const ui
                      hipStream_t st = nullptr) {
     if (!st) st = ctx->stream;
     const uint32_t n = g->n;
-    const unsigned hook_grid = grid_for(g->m_und, 256, 256 * 16);
+    const unsigned hook_grid = grid_for(g->m_und, kHookBlock, 256 * 16);
     dim3 gi((n + 255) / 256, b);
     k_batch_init<<<gi, 256, 0, st>>>(cs.parent, cs.cnt, minc, n, minc_init);
     {
         Prof p(ctx, "sample_hook", st);
         if (pm.kind == 0)
-            k_sample_hook<0><<<hook_grid, 256, 0, st>>>(g->edges, g->m_und, K, b, pm, cs.parent, n);
+            k_sample_hook<0><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->m_und, K, b, pm, cs.parent, n);
         else
-            k_sample_hook<1><<<hook_grid, 256, 0, st>>>(g->edges, g->m_und, K, b, pm, cs.parent, n);
+            k_sample_hook<1><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->m_und, K, b, pm, cs.parent, n);
     }
     {
         Prof p(ctx, "compress", st);

@@ -76,34 +76,42 @@ __device__ __forceinline__ void uf_unite(uint32_t *P, uint32_t a, uint32_t b) {
     }
 }
 
-// K must hold round_up(B, 8) keys.
+// Live mask of one edge word x over sketches [0, B): bit b set iff the edge is
+// live in sketch b.  K must hold round_up(B, 8) keys.
 template <int KIND>
-__global__ void __launch_bounds__(256) k_sample_hook(const uint2 *__restrict__ edges, uint64_t m,
-                                                     const uint64_t *__restrict__ K, uint32_t B, ProbDev pm,
-                                                     uint32_t *__restrict__ parent, uint32_t n) {
+__device__ __forceinline__ uint64_t live_mask(uint64_t x, const uint64_t *__restrict__ K, uint32_t B,
+                                              const ProbDev &pm) {
+    uint64_t T;
+    if (KIND == 0) {
+        T = pm.t0;
+    } else {
+        const uint64_t c = mix64(x ^ pm.ktriv) % 3u;
+        T = c == 0 ? pm.t0 : (c == 1 ? pm.t1 : pm.t2);
+    }
+    const uint64_t all = B >= 64 ? ~0ull : ((1ull << B) - 1ull);
+    if (T == kAllLive) return all;
+    uint64_t live = 0;
+    for (uint32_t b0 = 0; b0 < B; b0 += 8) {
+        uint32_t chunk = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) chunk |= (mix64(x ^ K[b0 + j]) < T) ? (1u << j) : 0u;
+        live |= (uint64_t)chunk << b0;
+    }
+    return live & all;
+}
+
+constexpr uint32_t kHookBlock = 256;
+
+// One thread per undirected edge: its live mask over the pass's sketches, then
+// one union per live sketch.
+template <int KIND>
+__global__ void __launch_bounds__(kHookBlock) k_sample_hook(const uint2 *__restrict__ edges, uint64_t m,
+                                                            const uint64_t *__restrict__ K, uint32_t B, ProbDev pm,
+                                                            uint32_t *__restrict__ parent, uint32_t n) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
         const uint2 uv = edges[e];
-        const uint64_t x = ((uint64_t)uv.x << 32) | uv.y;
-        uint64_t T;
-        if (KIND == 0) {
-            T = pm.t0;
-        } else {
-            const uint64_t c = mix64(x ^ pm.ktriv) % 3u;
-            T = c == 0 ? pm.t0 : (c == 1 ? pm.t1 : pm.t2);
-        }
-        uint64_t live = 0;
-        if (T == kAllLive) {
-            live = B >= 64 ? ~0ull : ((1ull << B) - 1ull);
-        } else {
-            for (uint32_t b0 = 0; b0 < B; b0 += 8) {
-                uint32_t chunk = 0;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) chunk |= (mix64(x ^ K[b0 + j]) < T) ? (1u << j) : 0u;
-                live |= (uint64_t)chunk << b0;
-            }
-            live &= B >= 64 ? ~0ull : ((1ull << B) - 1ull);
-        }
+        uint64_t live = live_mask<KIND>(((uint64_t)uv.x << 32) | uv.y, K, B, pm);
         while (live) {
             const uint32_t b = (uint32_t)__builtin_ctzll(live);
             live &= live - 1ull;
