@@ -18,6 +18,16 @@ constexpr int kFan = 64;        // winning-tree fan-out: one wave lane per child
 constexpr int kFanLog = 6;
 constexpr int kMaxLevels = 8;   // internal tree levels; 64^6 > 2^32 vertices
 
+// Distance in elements between two sketches' arrays in the labelling scratch
+// (parent, member counts, smallest center ranks; [B][stride]).  n is rounded up
+// to 256 bytes and, from 2^16 vertices on, padded by 65 x 256 bytes: with a
+// power-of-two stride the same vertex of the B sketches falls on one memory
+// channel, and the hooking pass, which touches a vertex in several sketches at
+// once, ran 25% slower on 2^20 vertices.  Small arrays stay in cache anyway.
+__host__ __device__ constexpr size_t sketch_stride(uint32_t n) {
+    return (((size_t)n + 63) & ~(size_t)63) + (n >= (1u << 16) ? 4160 : 0);
+}
+
 // SplitMix64 output function (Steele, Lea, Flood 2014).  Two 64-bit multiplies.
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     z ^= z >> 30;

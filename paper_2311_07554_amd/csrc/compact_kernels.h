@@ -282,7 +282,7 @@ __global__ void __launch_bounds__(256) k_bulk_seed_roots(const SelState *__restr
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t b = (uint32_t)(i / ns), j = (uint32_t)(i % ns);
-        const size_t base = (size_t)b * n;
+        const size_t base = (size_t)b * sketch_stride(n);
         flag[base + parent[base + seeds[j]]] = 1u;
     }
 }
@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(256) k_bulk_accum(const uint32_t *__restrict__
     if (v >= n) return;
     uint64_t s = 0;
     for (uint32_t b = 0; b < B; ++b) {
-        const size_t base = (size_t)b * n;
+        const size_t base = (size_t)b * sketch_stride(n);
         const uint32_t root = parent[base + v];
         s += flag[base + root] ? 0u : 1u + cnt[base + root];
     }

@@ -397,10 +397,14 @@ extern "C" im_status im_graph_free(im_graph *g) {
 // ---------------------------------------------------------------- sketches
 namespace {
 
+// Labelling scratch of one build: PACIM_SCRATCH_MB, else a quarter of the free
+// device memory up to 16 GiB (64 sketches of a 2^24-vertex graph take 12.9 GB).
 size_t g_scratch_budget() {
     const char *e = getenv("PACIM_SCRATCH_MB");
-    size_t mb = e ? (size_t)strtoull(e, nullptr, 10) : 768;
-    return std::max<size_t>(mb, 1) << 20;
+    if (e) return std::max<size_t>((size_t)strtoull(e, nullptr, 10), 1) << 20;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)4 << 30;
+    return std::max<size_t>(std::min<size_t>((size_t)16 << 30, free_b / 4), (size_t)256 << 20);
 }
 
 uint32_t g_batch_override() {
@@ -445,7 +449,7 @@ struct CCScratch {
 
 im_status cc_scratch_alloc(im_ctx *ctx, const im_graph *g, uint32_t R, bool with_minc, CCScratch *cs) {
     const uint32_t n = g->n;
-    const size_t per_sketch = (size_t)n * 4 * (with_minc ? 3 : 2);
+    const size_t per_sketch = sketch_stride(n) * 4 * (with_minc ? 3 : 2);
     uint32_t B = (uint32_t)std::min<size_t>({(size_t)R, (size_t)64, std::max<size_t>(1, g_scratch_budget() / per_sketch)});
     if (uint32_t ov = g_batch_override()) B = std::min<uint32_t>({ov, R, 64u});
     cs->B = B;
@@ -453,8 +457,8 @@ im_status cc_scratch_alloc(im_ctx *ctx, const im_graph *g, uint32_t R, bool with
     im_status st = dev_alloc(ctx, cs->bytes, &cs->block);
     if (st != IM_OK) return st;
     cs->parent = static_cast<uint32_t *>(cs->block);
-    cs->cnt = cs->parent + (size_t)B * n;
-    cs->minc = with_minc ? cs->cnt + (size_t)B * n : nullptr;
+    cs->cnt = cs->parent + (size_t)B * sketch_stride(n);
+    cs->minc = with_minc ? cs->cnt + (size_t)B * sketch_stride(n) : nullptr;
     return IM_OK;
 }
 

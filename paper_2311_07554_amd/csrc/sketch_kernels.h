@@ -31,7 +31,7 @@ __global__ void k_salt_key(uint64_t seed, uint64_t salt, uint64_t *__restrict__ 
 __global__ void k_batch_init(uint32_t *__restrict__ parent, uint32_t *__restrict__ cnt, uint32_t *__restrict__ minc,
                              uint32_t n, uint32_t minc_init) {
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t at = (size_t)blockIdx.y * n + v;
+    const size_t at = (size_t)blockIdx.y * sketch_stride(n) + v;
     if (v < n) {
         parent[at] = v;
         cnt[at] = 0;
@@ -108,6 +108,7 @@ template <int KIND>
 __global__ void __launch_bounds__(kHookBlock) k_sample_hook(const uint2 *__restrict__ edges, uint64_t m,
                                                             const uint64_t *__restrict__ K, uint32_t B, ProbDev pm,
                                                             uint32_t *__restrict__ parent, uint32_t n) {
+    const size_t ns = sketch_stride(n);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
         const uint2 uv = edges[e];
@@ -115,7 +116,7 @@ __global__ void __launch_bounds__(kHookBlock) k_sample_hook(const uint2 *__restr
         while (live) {
             const uint32_t b = (uint32_t)__builtin_ctzll(live);
             live &= live - 1ull;
-            uf_unite(parent + (size_t)b * n, uv.x, uv.y);
+            uf_unite(parent + (size_t)b * ns, uv.x, uv.y);
         }
     }
 }
@@ -131,7 +132,7 @@ __global__ void __launch_bounds__(256) k_compress(uint32_t *__restrict__ parent,
                                                   uint32_t n, const uint32_t *__restrict__ center_rank,
                                                   uint32_t *__restrict__ minc) {
     const uint32_t lane = lane_id();
-    const size_t base = (size_t)blockIdx.y * n;
+    const size_t base = (size_t)blockIdx.y * sketch_stride(n);
     uint32_t *P = parent + base;
     uint32_t hot = kNone, hot_cnt = 0, hot_min = kNone;  // wave-uniform
     const uint32_t stride = gridDim.x * blockDim.x;
@@ -198,7 +199,7 @@ __global__ void __launch_bounds__(256) k_emit_full(const uint32_t *__restrict__ 
     for (uint32_t idx = threadIdx.x; idx < kEmitTile * B; idx += blockDim.x) {
         const uint32_t b = idx / kEmitTile, vi = idx % kEmitTile, v = v0 + vi;
         if (v < n) {
-            const size_t base = (size_t)b * n;
+            const size_t base = (size_t)b * sketch_stride(n);
             const uint32_t root = parent[base + v];
             const uint32_t s = 1u + cnt[base + root];
             tile[vi][b] = make_uint2(root, root == v ? s : 0u);
@@ -230,7 +231,7 @@ __global__ void __launch_bounds__(256) k_emit_compact(const uint32_t *__restrict
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= rho) return;
     const uint32_t b = blockIdx.y;
-    const size_t base = (size_t)b * n;
+    const size_t base = (size_t)b * sketch_stride(n);
     const uint32_t v = centers[i];
     const uint32_t root = parent[base + v];
     const uint32_t l = minc[base + root];
@@ -245,7 +246,7 @@ __global__ void __launch_bounds__(256) k_gain0(const uint32_t *__restrict__ pare
     if (v >= n) return;
     uint64_t s = 0;
     for (uint32_t b = 0; b < B; ++b) {
-        const size_t base = (size_t)b * n;
+        const size_t base = (size_t)b * sketch_stride(n);
         s += 1u + cnt[base + parent[base + v]];
     }
     gain0[v] += s;
