@@ -192,21 +192,16 @@ __device__ __forceinline__ void add_delta(SelState *st, unsigned long long *part
 }
 
 // eval(l) on CompactSketch: one wave per (listed vertex, sketch), sketch-major;
-// searches that outgrow the LDS queue are listed for k_overflow_bfs.
-__global__ void __launch_bounds__(kBfsBlock) k_eval_compact_bfs(uint32_t l, SelState *__restrict__ st,
-                                                                const uint32_t *__restrict__ evl,
-                                                                unsigned long long *__restrict__ partial,
-                                                                GraphDev g, ProbDev pm, const uint64_t *__restrict__ K,
-                                                                uint32_t R, CompactDev cd, uint32_t kb,
-                                                                const uint8_t *__restrict__ in_s,
-                                                                uint64_t *__restrict__ key,
-                                                                uint2 *__restrict__ ov, uint32_t ov_cap) {
-    __shared__ uint32_t lds[kBfsWaves][kQCap + kHCap];
-    uint32_t *q = lds[threadIdx.x / kWave];
-    uint32_t *hs = q + kQCap;
+// searches that outgrow the LDS queue are listed for the global-memory step.
+// q / hs: this wave's LDS queue (kQCap) and hash set (kHCap).
+__device__ __forceinline__ void eval_compact_level(uint32_t l, SelState *st, const uint32_t *evl,
+                                                   unsigned long long *partial, const GraphDev &g, const ProbDev &pm,
+                                                   const uint64_t *K, uint32_t R, const CompactDev &cd, uint32_t kb,
+                                                   const uint8_t *in_s, uint64_t *key, uint2 *ov, uint32_t ov_cap,
+                                                   uint32_t *q, uint32_t *hs, uint32_t wi, uint32_t wc) {
     const uint32_t ne = st->ev_cnt[l];
     const uint64_t total = (uint64_t)ne * R;
-    for (uint64_t task = wave_index(); task < total; task += wave_count()) {
+    for (uint64_t task = wi; task < total; task += wc) {
         const uint32_t r = (uint32_t)(task / ne), e = (uint32_t)(task % ne);
         const uint32_t v = evl[e];
         const BfsOut o = getcenter_lds(g, pm, K[r], cd, r, in_s, v, q, hs);
@@ -218,20 +213,19 @@ __global__ void __launch_bounds__(kBfsBlock) k_eval_compact_bfs(uint32_t l, SelS
 }
 
 // Global-memory searches for the tasks of one step that overflowed (count in
-// st->ov_cnt[slot]).  mode 0: evaluation of level `slot` (add the delta);
-// mode 1: MarkSeed of st->last_seed (zero size_c[r][label]).
-__global__ void __launch_bounds__(64) k_overflow_bfs(int mode, uint32_t slot, SelState *__restrict__ st,
-                                                     const uint32_t *__restrict__ evl,
-                                                     unsigned long long *__restrict__ partial, GraphDev g,
-                                                     ProbDev pm, const uint64_t *__restrict__ K, CompactDev cd,
-                                                     uint32_t kb, const uint8_t *__restrict__ in_s,
-                                                     uint64_t *__restrict__ key, const uint2 *__restrict__ ov,
-                                                     uint32_t ov_cap, uint32_t *__restrict__ slot_q,
-                                                     uint32_t *__restrict__ slot_vis, uint32_t n) {
+// st->ov_cnt[slot]); searcher `who` of `nwho` uses queue/bitmap slot `who`.
+// mode 0: evaluation of level `slot` (add the delta); mode 1: MarkSeed of
+// st->last_seed (zero size_c[r][label]).
+__device__ __forceinline__ void overflow_level(int mode, uint32_t slot, SelState *st, const uint32_t *evl,
+                                               unsigned long long *partial, const GraphDev &g, const ProbDev &pm,
+                                               const uint64_t *K, const CompactDev &cd, uint32_t kb,
+                                               const uint8_t *in_s, uint64_t *key, const uint2 *ov, uint32_t ov_cap,
+                                               uint32_t *slot_q, uint32_t *slot_vis, uint32_t n, uint32_t who,
+                                               uint32_t nwho) {
     const uint32_t cnt = min(st->ov_cnt[slot], ov_cap);
-    uint32_t *gq = slot_q + (size_t)blockIdx.x * n;
-    uint32_t *gvis = slot_vis + (size_t)blockIdx.x * ((n + 31) / 32);
-    for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+    uint32_t *gq = slot_q + (size_t)who * n;
+    uint32_t *gvis = slot_vis + (size_t)who * ((n + 31) / 32);
+    for (uint32_t i = who; i < cnt; i += nwho) {
         const uint2 t = ov[i];
         const uint32_t r = t.y;
         const uint32_t v = (mode == 0) ? evl[t.x] : st->last_seed;
@@ -244,21 +238,54 @@ __global__ void __launch_bounds__(64) k_overflow_bfs(int mode, uint32_t slot, Se
 }
 
 // MarkSeed on CompactSketch: one wave per sketch, GetCenter from the new seed.
-__global__ void __launch_bounds__(kBfsBlock) k_markseed_compact(SelState *__restrict__ st, GraphDev g, ProbDev pm,
-                                                                const uint64_t *__restrict__ K, uint32_t R,
-                                                                CompactDev cd, const uint8_t *__restrict__ in_s,
-                                                                uint2 *__restrict__ ov, uint32_t ov_cap) {
-    __shared__ uint32_t lds[kBfsWaves][kQCap + kHCap];
-    uint32_t *q = lds[threadIdx.x / kWave];
-    uint32_t *hs = q + kQCap;
+__device__ __forceinline__ void markseed_compact_level(SelState *st, const GraphDev &g, const ProbDev &pm,
+                                                       const uint64_t *K, uint32_t R, const CompactDev &cd,
+                                                       const uint8_t *in_s, uint2 *ov, uint32_t ov_cap, uint32_t *q,
+                                                       uint32_t *hs, uint32_t wi, uint32_t wc) {
     const uint32_t s = st->last_seed;
-    for (uint32_t r = wave_index(); r < R; r += wave_count()) {
+    for (uint32_t r = wi; r < R; r += wc) {
         const BfsOut o = getcenter_lds(g, pm, K[r], cd, r, in_s, s, q, hs);
         if (lane_id() == 0) {
             if (o.overflow) push_overflow(st, &st->ov_cnt[kMaxLevels + 1], ov, ov_cap, s, r);
             else if (o.label != kNone) cd.size_c[(size_t)r * cd.rho + o.label] = 0;
         }
     }
+}
+
+__global__ void __launch_bounds__(kBfsBlock) k_eval_compact_bfs(uint32_t l, SelState *__restrict__ st,
+                                                                const uint32_t *__restrict__ evl,
+                                                                unsigned long long *__restrict__ partial,
+                                                                GraphDev g, ProbDev pm, const uint64_t *__restrict__ K,
+                                                                uint32_t R, CompactDev cd, uint32_t kb,
+                                                                const uint8_t *__restrict__ in_s,
+                                                                uint64_t *__restrict__ key,
+                                                                uint2 *__restrict__ ov, uint32_t ov_cap) {
+    __shared__ uint32_t lds[kBfsWaves][kQCap + kHCap];
+    uint32_t *q = lds[threadIdx.x / kWave];
+    eval_compact_level(l, st, evl, partial, g, pm, K, R, cd, kb, in_s, key, ov, ov_cap, q, q + kQCap, wave_index(),
+                       wave_count());
+}
+
+// grid: one 64-thread block per queue/bitmap slot.
+__global__ void __launch_bounds__(64) k_overflow_bfs(int mode, uint32_t slot, SelState *__restrict__ st,
+                                                     const uint32_t *__restrict__ evl,
+                                                     unsigned long long *__restrict__ partial, GraphDev g,
+                                                     ProbDev pm, const uint64_t *__restrict__ K, CompactDev cd,
+                                                     uint32_t kb, const uint8_t *__restrict__ in_s,
+                                                     uint64_t *__restrict__ key, const uint2 *__restrict__ ov,
+                                                     uint32_t ov_cap, uint32_t *__restrict__ slot_q,
+                                                     uint32_t *__restrict__ slot_vis, uint32_t n) {
+    overflow_level(mode, slot, st, evl, partial, g, pm, K, cd, kb, in_s, key, ov, ov_cap, slot_q, slot_vis, n,
+                   blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBfsBlock) k_markseed_compact(SelState *__restrict__ st, GraphDev g, ProbDev pm,
+                                                                const uint64_t *__restrict__ K, uint32_t R,
+                                                                CompactDev cd, const uint8_t *__restrict__ in_s,
+                                                                uint2 *__restrict__ ov, uint32_t ov_cap) {
+    __shared__ uint32_t lds[kBfsWaves][kQCap + kHCap];
+    uint32_t *q = lds[threadIdx.x / kWave];
+    markseed_compact_level(st, g, pm, K, R, cd, in_s, ov, ov_cap, q, q + kQCap, wave_index(), wave_count());
 }
 
 // ---- bulk round -------------------------------------------------------------

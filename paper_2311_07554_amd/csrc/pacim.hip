@@ -29,6 +29,7 @@
 #include "common.h"
 #include "batch_kernels.h"
 #include "compact_kernels.h"
+#include "persist_kernels.h"
 #include "probe_kernels.h"
 #include "select_kernels.h"
 #include "sketch_kernels.h"
@@ -56,6 +57,8 @@ struct im_ctx {
     std::map<std::string, KTimer> timers;
     std::vector<hipEvent_t> spare_events;
     std::mutex alloc_mu;  // device memory accounting (a server's thread allocates too)
+    unsigned persist_grid = 0;  // workgroups of the persistent selection kernel (all resident)
+    uint64_t clock_hz = 0;      // wall_clock64() rate
 };
 
 struct im_graph {
@@ -99,6 +102,7 @@ struct im_sketches {
     void *bulk_cs = nullptr;           // CCScratch of bulk rounds, allocated at the first one
     uint64_t last_gain = 0;            // gain of the latest seed (decides bulk rounds)
     uint32_t bulk_rounds = 0;
+    PersistCtl *ctl = nullptr;         // step hand-off of the persistent selection kernel
     // bookkeeping
     std::vector<std::pair<void *, size_t>> allocs;
     uint32_t chosen = 0;
@@ -656,6 +660,7 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
     SK_TRY(sk_alloc(s, tn, &s->fr));
     SK_TRY(sk_alloc(s, n, &s->evl));
     SK_TRY(sk_alloc(s, 1, &s->st));
+    SK_TRY(sk_alloc(s, 1, &s->ctl));
     SK_TRY(sk_alloc(s, n, &s->seeds_d));
     SK_TRY(sk_alloc(s, n, &s->gains_d));
     SK_TRY(sk_alloc(s, n, &s->evals_d));
@@ -703,7 +708,10 @@ void enqueue_markseed_compact(im_sketches *s) {
                                             s->in_s, s->key, s->ov, s->ov_cap, s->slot_q, s->slot_vis, s->n);
 }
 
-im_status enqueue_lazy_round(im_sketches *s) {
+// The per-level kernels of one round, from the evaluation of level l0 on
+// (begin: start a new round first).  The persistent kernel hands rounds over
+// at such a level.
+im_status enqueue_round_part(im_sketches *s, bool begin, uint32_t l0) {
     im_ctx *ctx = s->ctx;
     hipStream_t st = ctx->stream;
     const TreeDesc &td = s->td;
@@ -721,9 +729,9 @@ im_status enqueue_lazy_round(im_sketches *s) {
                                                     s->in_s, s->key, s->ov, s->ov_cap, s->slot_q, s->slot_vis, s->n);
         }
     };
-    k_round_begin<<<1, 64, 0, st>>>(td, s->st, s->ids, s->fr, s->evl, s->partial, pinit);
-    eval(0);
-    for (uint32_t l = 0; l < td.D; ++l) {
+    if (begin) k_round_begin<<<1, 64, 0, st>>>(td, s->st, s->ids, s->fr, s->evl, s->partial, pinit);
+    eval(l0);
+    for (uint32_t l = l0; l < td.D; ++l) {
         k_check<<<wave_grid(td.lvl_n[l], 8192), 256, 0, st>>>(td, l, s->st, s->ids, s->key, s->fr, s->evl, s->partial,
                                                                 pinit);
         eval(l + 1);
@@ -735,6 +743,83 @@ im_status enqueue_lazy_round(im_sketches *s) {
     if (s->compact) enqueue_markseed_compact(s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(ctx, IM_EDEVICE, std::string("select launch: ") + hipGetErrorString(e));
+    return IM_OK;
+}
+
+im_status enqueue_lazy_round(im_sketches *s) { return enqueue_round_part(s, true, 0); }
+
+// Up to max_rounds lazy rounds in one persistent launch (stops early after a
+// round whose gain reaches bulk_min, if nonzero, or mid-round at a large
+// evaluation step).  Waits for it; *done = rounds completed, *stop_level = the
+// level whose evaluation is pending (kNone if stopped at a round boundary),
+// *last_gain = gain of the last completed round.
+im_status run_persistent_rounds(im_sketches *s, uint32_t max_rounds, unsigned long long bulk_min, uint32_t *done,
+                                uint32_t *stop_level, uint64_t *last_gain) {
+    im_ctx *ctx = s->ctx;
+    hipStream_t st = ctx->stream;
+    if (!ctx->persist_grid) {
+        int per_cu = 0, cus = 0, khz = 0;
+        HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_select_persist, kPersistBlock, 0));
+        HIP_TRY(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        HIP_TRY(ctx, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device));
+        if (per_cu < 1 || cus < 1 || khz < 1) return fail(ctx, IM_EDEVICE, "persistent selection: no resident workgroup");
+        ctx->persist_grid = (unsigned)cus;  // one workgroup per CU
+        ctx->clock_hz = (uint64_t)khz * 1000ull;
+    }
+    SelState h0{};
+    HIP_TRY(ctx, hipMemcpyAsync(&h0, s->st, sizeof(SelState), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemsetAsync(s->ctl, 0, sizeof(PersistCtl), st));
+    PersistArgs a{};
+    a.td = s->td;
+    a.st = s->st;
+    a.ids = s->ids;
+    a.key = s->key;
+    a.fr = s->fr;
+    a.evl = s->evl;
+    a.partial = s->partial;
+    a.pinit = (unsigned long long)s->R << kPartialShift;
+    a.in_s = s->in_s;
+    a.kb = s->kb;
+    a.R = s->R;
+    a.n = s->n;
+    a.seeds_out = s->seeds_d;
+    a.gains_out = s->gains_d;
+    a.evals_out = s->evals_d;
+    a.E = s->compact ? nullptr : s->E;
+    a.g = GraphDev{s->g->off, s->g->cols};
+    a.pm = s->pm;
+    a.K = s->K;
+    a.cd = CompactDev{s->center_rank, s->label_c, s->size_c, s->rho};
+    a.ov = s->ov;
+    a.ov_cap = s->ov_cap;
+    a.slot_q = s->slot_q;
+    a.slot_vis = s->slot_vis;
+    a.slots = s->slots;
+    a.max_rounds = max_rounds;
+    a.max_step_tasks = s->compact ? (1ull << 20) : 2048ull;
+    a.bulk_gain_min = bulk_min;
+    a.ctl = s->ctl;
+    a.spin_ticks = 120ull * ctx->clock_hz;  // two minutes
+    void *args[] = {&a};
+    const unsigned grid = s->compact ? ctx->persist_grid : 1u;
+    HIP_TRY(ctx, hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_select_persist), dim3(grid),
+                                            dim3(kPersistBlock), args, 0, st));
+    SelState h1{};
+    PersistCtl c{};
+    HIP_TRY(ctx, hipMemcpyAsync(&h1, s->st, sizeof(SelState), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(&c, s->ctl, sizeof(PersistCtl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    if (c.err) return fail(ctx, IM_EINTERNAL, "persistent selection: a step exceeded its time limit");
+    if (h1.round < h0.round || h1.round - h0.round > max_rounds)
+        return fail(ctx, IM_EINTERNAL, "persistent selection: round counter mismatch");
+    *done = h1.round - h0.round;
+    *stop_level = h1.stop_level;
+    *last_gain = 0;
+    if (*done) {
+        unsigned long long g = 0;
+        HIP_TRY(ctx, hipMemcpy(&g, s->gains_d + h1.round - 1, 8, hipMemcpyDeviceToHost));
+        *last_gain = g;
+    }
     return IM_OK;
 }
 
@@ -786,15 +871,6 @@ int bulk_policy() {
     return 0;
 }
 
-bool bulk_gain(const im_sketches *s, uint64_t gain) { return gain * 64 >= (uint64_t)s->R * s->n; }
-
-bool want_bulk(const im_sketches *s) {
-    if (!s->compact || s->chosen == 0) return false;
-    const int pol = bulk_policy();
-    if (pol != 0) return pol > 0;
-    return bulk_gain(s, s->last_gain);
-}
-
 }  // namespace
 
 extern "C" im_status im_select_seeds_from(im_ctx *ctx, im_sketches *s, uint32_t k, uint32_t *seeds_out,
@@ -812,33 +888,57 @@ extern "C" im_status im_select_seeds_from(im_ctx *ctx, im_sketches *s, uint32_t 
     im_status rc = IM_OK;
     {
         Prof p(ctx, "select");
-        if (!s->compact) {
-            for (uint32_t i = 0; i < k && rc == IM_OK; ++i) rc = enqueue_lazy_round(s);
-        } else {
-            // compact: while a bulk round is still possible, each seed's gain is read back to
-            // choose the next round's kind.  Gains never increase, so once one falls below
-            // the bulk threshold no later round can be bulk and the read-backs stop.
-            const uint32_t base = s->chosen;
-            bool watch = bulk_policy() == 0 && (s->chosen == 0 || bulk_gain(s, s->last_gain));
-            for (uint32_t i = 0; i < k && rc == IM_OK; ++i) {
-                rc = want_bulk(s) ? enqueue_bulk_round(s) : enqueue_lazy_round(s);
+        // Lazy rounds run in persistent launches.  CompactSketch: a round follows as a
+        // bulk round when the previous seed's gain reaches the bulk threshold (the
+        // persistent kernel stops after such a round); gains never increase, so
+        // once one is below it every later round is lazy.
+        const int pol = s->compact ? bulk_policy() : -1;
+        const unsigned long long bmin =
+            pol == 0 ? (unsigned long long)(((uint64_t)s->R * s->n + 63) / 64) : 0ull;
+        uint32_t cur = s->chosen;
+        uint64_t last = s->last_gain;
+        for (uint32_t i = 0; i < k && rc == IM_OK;) {
+            const bool bulk = cur > 0 && (pol > 0 || (pol == 0 && last >= bmin));
+            if (bulk) {
+                rc = enqueue_bulk_round(s);
                 if (rc != IM_OK) break;
-                ++s->chosen;  // provisional, restored below
-                if (!watch) {
-                    s->last_gain = 0;
-                    continue;
-                }
                 unsigned long long g = 0;
-                hipError_t e1 = hipMemcpyAsync(&g, s->gains_d + base + i, 8, hipMemcpyDeviceToHost, st);
+                hipError_t e1 = hipMemcpyAsync(&g, s->gains_d + cur, 8, hipMemcpyDeviceToHost, st);
                 hipError_t e2 = hipStreamSynchronize(st);
                 if (e1 != hipSuccess || e2 != hipSuccess) {
                     rc = fail(ctx, IM_EDEVICE, "select: gain read-back failed");
                     break;
                 }
-                s->last_gain = g;
-                watch = bulk_gain(s, g);
+                last = g;
+                ++cur;
+                ++i;
+                continue;
             }
-            s->chosen = base;
+            const uint32_t want = pol > 0 ? 1u : k - i;
+            uint32_t done = 0, stop_level = kNone;
+            uint64_t g = 0;
+            rc = run_persistent_rounds(s, want, bmin, &done, &stop_level, &g);
+            if (rc != IM_OK) break;
+            cur += done;
+            i += done;
+            if (done) last = g;
+            if (stop_level != kNone) {
+                // the persistent kernel left a large evaluation step to the per-level kernels
+                rc = enqueue_round_part(s, false, stop_level);
+                if (rc != IM_OK) break;
+                unsigned long long g2 = 0;
+                hipError_t e1 = hipMemcpyAsync(&g2, s->gains_d + cur, 8, hipMemcpyDeviceToHost, st);
+                hipError_t e2 = hipStreamSynchronize(st);
+                if (e1 != hipSuccess || e2 != hipSuccess) {
+                    rc = fail(ctx, IM_EDEVICE, "select: gain read-back failed");
+                    break;
+                }
+                last = g2;
+                ++cur;
+                ++i;
+            } else if (done == 0) {
+                rc = fail(ctx, IM_EINTERNAL, "persistent selection made no progress");
+            }
         }
     }
     (void)hipEventRecord(t1, st);

@@ -43,6 +43,8 @@ struct SelState {
     uint32_t round;                  // seeds chosen so far
     uint32_t last_seed;
     uint32_t err;
+    uint32_t stop_level;             // persistent rounds: level whose evaluation was left to the
+                                     // per-level kernels (kNone: stopped at a round boundary)
 };
 
 // ---- Marginal on full labels ------------------------------------------------
@@ -97,34 +99,35 @@ __global__ void __launch_bounds__(256) k_tree_build_level(TreeDesc td, uint32_t 
 }
 
 // ---- one round ---------------------------------------------------------------
-// round_begin: the root is always stale; it is the one level-0 evaluation.
-// partial (CompactSketch only): per listed vertex, (tasks left << 40) + summed
-// deltas, started at partial_init = R << 40.
-__global__ void k_round_begin(TreeDesc td, SelState *__restrict__ st, const uint32_t *__restrict__ ids,
-                              uint32_t *__restrict__ fr, uint32_t *__restrict__ evl,
-                              unsigned long long *__restrict__ partial, unsigned long long partial_init) {
-    if (threadIdx.x == 0) {
-        st->delta = 0;
-        for (int l = 0; l <= kMaxLevels; ++l) { st->fr_cnt[l] = 0; st->ev_cnt[l] = 0; }
-        for (int l = 0; l < kMaxLevels + 2; ++l) st->ov_cnt[l] = 0;
-        st->fr_cnt[0] = 1;
-        fr[td.lvl_off[0]] = 0;
-        st->ev_cnt[0] = 1;
-        evl[0] = ids[td.lvl_off[0]];
-        if (partial) partial[0] = partial_init;
-    }
+// The steps of a round are written as device functions over a range of waves
+// (wave wi of wc) so that the per-level kernels below and the persistent
+// selection kernel run the same code.
+
+// round_begin (one thread): the root is always stale; it is the one level-0
+// evaluation.  partial (CompactSketch only): per listed vertex, (tasks left << 40)
+// + summed deltas, started at partial_init = R << 40.
+__device__ __forceinline__ void round_begin_one(const TreeDesc &td, SelState *st, const uint32_t *ids,
+                                                uint32_t *fr, uint32_t *evl, unsigned long long *partial,
+                                                unsigned long long partial_init) {
+    st->delta = 0;
+    for (int l = 0; l <= kMaxLevels; ++l) { st->fr_cnt[l] = 0; st->ev_cnt[l] = 0; }
+    for (int l = 0; l < kMaxLevels + 2; ++l) st->ov_cnt[l] = 0;
+    st->fr_cnt[0] = 1;
+    fr[td.lvl_off[0]] = 0;
+    st->ev_cnt[0] = 1;
+    evl[0] = ids[td.lvl_off[0]];
+    if (partial) partial[0] = partial_init;
 }
 
 // check(l): one wave per frontier node t of level l, one lane per child.
-__global__ void __launch_bounds__(256) k_check(TreeDesc td, uint32_t l, SelState *__restrict__ st,
-                                               const uint32_t *__restrict__ ids, const uint64_t *__restrict__ key,
-                                               uint32_t *__restrict__ fr, uint32_t *__restrict__ evl,
-                                               unsigned long long *__restrict__ partial,
-                                               unsigned long long partial_init) {
+__device__ __forceinline__ void check_level(const TreeDesc &td, uint32_t l, SelState *st, const uint32_t *ids,
+                                            const uint64_t *key, uint32_t *fr, uint32_t *evl,
+                                            unsigned long long *partial, unsigned long long partial_init,
+                                            uint32_t wi, uint32_t wc) {
     const uint32_t nf = st->fr_cnt[l];
     const uint64_t delta = __hip_atomic_load(&st->delta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const bool leaf_children = (l + 1 == td.D);
-    for (uint32_t i = wave_index(); i < nf; i += wave_count()) {
+    for (uint32_t i = wi; i < nf; i += wc) {
         const uint32_t t = fr[td.lvl_off[l] + i];
         const uint32_t pid = ids[td.lvl_off[l] + t];
         const uint32_t c = t * kFan + lane_id();
@@ -149,13 +152,12 @@ __global__ void __launch_bounds__(256) k_check(TreeDesc td, uint32_t l, SelState
 }
 
 // eval(l) on full labels: one wave per listed vertex.
-__global__ void __launch_bounds__(256) k_eval_full(uint32_t l, SelState *__restrict__ st,
-                                                   const uint32_t *__restrict__ evl, const uint2 *__restrict__ E,
-                                                   uint32_t R, uint32_t kb, const uint8_t *__restrict__ in_s,
-                                                   uint64_t *__restrict__ key) {
+__device__ __forceinline__ void eval_full_level(uint32_t l, SelState *st, const uint32_t *evl, const uint2 *E,
+                                                uint32_t R, uint32_t kb, const uint8_t *in_s, uint64_t *key,
+                                                uint32_t wi, uint32_t wc) {
     const uint32_t ne = st->ev_cnt[l];
     uint64_t best = 0;
-    for (uint32_t i = wave_index(); i < ne; i += wave_count()) {
+    for (uint32_t i = wi; i < ne; i += wc) {
         const uint32_t v = evl[i];
         const uint64_t g = marginal_full(E, R, v);
         const uint64_t nk = in_s[v] ? 0ull : pack_key(g, v, kb);
@@ -166,11 +168,10 @@ __global__ void __launch_bounds__(256) k_eval_full(uint32_t l, SelState *__restr
 }
 
 // relink(l): one wave per frontier node of level l (children already final).
-__global__ void __launch_bounds__(256) k_relink(TreeDesc td, uint32_t l, const SelState *__restrict__ st,
-                                                uint32_t *__restrict__ ids, const uint64_t *__restrict__ key,
-                                                const uint32_t *__restrict__ fr) {
+__device__ __forceinline__ void relink_level(const TreeDesc &td, uint32_t l, const SelState *st, uint32_t *ids,
+                                             const uint64_t *key, const uint32_t *fr, uint32_t wi, uint32_t wc) {
     const uint32_t nf = st->fr_cnt[l];
-    for (uint32_t i = wave_index(); i < nf; i += wave_count()) {
+    for (uint32_t i = wi; i < nf; i += wc) {
         const uint32_t t = fr[td.lvl_off[l] + i];
         const uint32_t w = relink_node(td, ids, key, l, t, 0, 0, 0, false);
         if (lane_id() == 0) ids[td.lvl_off[l] + t] = w;
@@ -181,26 +182,17 @@ __global__ void __launch_bounds__(256) k_relink(TreeDesc td, uint32_t l, const S
 // relink its leaf-to-root path so the next round starts from the best stale
 // key; with full labels also MarkSeed: zero the size at the seed's label in
 // every sketch.
-__global__ void __launch_bounds__(64) k_round_end(TreeDesc td, SelState *__restrict__ st, uint32_t *__restrict__ ids,
-                                                  uint64_t *__restrict__ key, uint8_t *__restrict__ in_s,
-                                                  uint32_t kb, uint32_t *__restrict__ seeds_out,
-                                                  unsigned long long *__restrict__ gains_out,
-                                                  uint32_t *__restrict__ evals_out, uint2 *__restrict__ E,
-                                                  uint32_t R) {
+__device__ __forceinline__ void round_end_wave(const TreeDesc &td, SelState *st, uint32_t *ids, uint64_t *key,
+                                               uint8_t *in_s, uint32_t kb, uint32_t *seeds_out,
+                                               unsigned long long *gains_out, uint32_t *evals_out, uint2 *E,
+                                               uint32_t R) {
     const uint32_t lane = lane_id();
     const uint32_t s = ids[td.lvl_off[0]];
     const uint64_t ks = key[s];
     const uint32_t round = st->round;
-    const uint32_t evs = [&] {
-        uint32_t t = 0;
-        for (int l = 0; l <= kMaxLevels; ++l) t += st->ev_cnt[l];
-        return t;
-    }();
-    const uint32_t ovs = [&] {
-        uint32_t t = 0;
-        for (int l = 0; l < kMaxLevels + 2; ++l) t += st->ov_cnt[l];
-        return t;
-    }();
+    uint32_t evs = 0, ovs = 0;
+    for (int l = 0; l <= kMaxLevels; ++l) evs += st->ev_cnt[l];
+    for (int l = 0; l < kMaxLevels + 2; ++l) ovs += st->ov_cnt[l];
     if (lane == 0) {
         if (ks == 0 || in_s[s]) st->err = 1;
         seeds_out[round] = s;
@@ -232,6 +224,42 @@ __global__ void __launch_bounds__(64) k_round_end(TreeDesc td, SelState *__restr
         }
     }
     if (lane == 0) st->round = round + 1;
+}
+
+__global__ void k_round_begin(TreeDesc td, SelState *__restrict__ st, const uint32_t *__restrict__ ids,
+                              uint32_t *__restrict__ fr, uint32_t *__restrict__ evl,
+                              unsigned long long *__restrict__ partial, unsigned long long partial_init) {
+    if (threadIdx.x == 0) round_begin_one(td, st, ids, fr, evl, partial, partial_init);
+}
+
+__global__ void __launch_bounds__(256) k_check(TreeDesc td, uint32_t l, SelState *__restrict__ st,
+                                               const uint32_t *__restrict__ ids, const uint64_t *__restrict__ key,
+                                               uint32_t *__restrict__ fr, uint32_t *__restrict__ evl,
+                                               unsigned long long *__restrict__ partial,
+                                               unsigned long long partial_init) {
+    check_level(td, l, st, ids, key, fr, evl, partial, partial_init, wave_index(), wave_count());
+}
+
+__global__ void __launch_bounds__(256) k_eval_full(uint32_t l, SelState *__restrict__ st,
+                                                   const uint32_t *__restrict__ evl, const uint2 *__restrict__ E,
+                                                   uint32_t R, uint32_t kb, const uint8_t *__restrict__ in_s,
+                                                   uint64_t *__restrict__ key) {
+    eval_full_level(l, st, evl, E, R, kb, in_s, key, wave_index(), wave_count());
+}
+
+__global__ void __launch_bounds__(256) k_relink(TreeDesc td, uint32_t l, const SelState *__restrict__ st,
+                                                uint32_t *__restrict__ ids, const uint64_t *__restrict__ key,
+                                                const uint32_t *__restrict__ fr) {
+    relink_level(td, l, st, ids, key, fr, wave_index(), wave_count());
+}
+
+__global__ void __launch_bounds__(64) k_round_end(TreeDesc td, SelState *__restrict__ st, uint32_t *__restrict__ ids,
+                                                  uint64_t *__restrict__ key, uint8_t *__restrict__ in_s,
+                                                  uint32_t kb, uint32_t *__restrict__ seeds_out,
+                                                  unsigned long long *__restrict__ gains_out,
+                                                  uint32_t *__restrict__ evals_out, uint2 *__restrict__ E,
+                                                  uint32_t R) {
+    round_end_wave(td, st, ids, key, in_s, kb, seeds_out, gains_out, evals_out, E, R);
 }
 
 }  // namespace pacim
