@@ -796,7 +796,9 @@ im_status run_persistent_rounds(im_sketches *s, uint32_t max_rounds, unsigned lo
     a.slot_vis = s->slot_vis;
     a.slots = s->slots;
     a.max_rounds = max_rounds;
-    a.max_step_tasks = s->compact ? (1ull << 20) : 2048ull;
+    // PACIM_PERSIST_STEP (tests) lowers the limit so that rounds are handed over
+    const char *ov = getenv("PACIM_PERSIST_STEP");
+    a.max_step_tasks = ov ? std::max<uint64_t>(strtoull(ov, nullptr, 10), 1) : (s->compact ? (1ull << 20) : 2048ull);
     a.bulk_gain_min = bulk_min;
     a.ctl = s->ctl;
     a.spin_ticks = 120ull * ctx->clock_hz;  // two minutes

@@ -1,0 +1,110 @@
+"""GPU parity at the full size of the R-MAT scale-20 workload.
+
+2^20 vertices, 2^24 undirected pairs, trivalency probabilities, R = 256,
+k = 100; full labels and CompactSketch (alpha = 0.1), in the configuration the
+benchmark times.  The oracle labels all 256 sketches (threaded BFS).  Running
+its plain greedy whole at this size takes too long, so the seed sequence is
+checked output by output:
+
+* sampled sketches' labels and sizes, and every vertex's initial gain;
+* every seed's gain against the coverage function: gain_i = f(S_i) - f(S_{i-1});
+* at sampled rounds, the seed against the argmax (smallest id on ties) of the
+  marginals of all n vertices given the earlier seeds;
+* CompactSketch: sampled sketches' triples, and seeds and gains equal to the
+  full-label ones (alpha-equivalence).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2311_07554_amd import inputs, pacim
+from tests.gpu_util import upload
+
+pytestmark = pytest.mark.gpu
+
+SAMPLED_SKETCHES = (0, 77, 131, 255)
+SAMPLED_ROUNDS = (0, 1, 2, 7, 31, 64, 99)
+workload_results = {}  # full-label seeds and gains, for the CompactSketch check
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = pacim.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def workload():
+    q = inputs.rmat20().queries[0]
+    threads = max(1, min(16, os.cpu_count() or 1))
+    _say(f"case rmat20 full size: oracle labels of {q.R} sketches on {threads} threads")
+    lab, siz = oracle.sketches(q.graph, q.prob_kind, q.p, q.seed, q.R, threads=threads)
+    return q, lab, siz, threads
+
+
+def test_rmat20_full_labels_sampled_parity(ctx, workload):
+    q, lab, siz, threads = workload
+    g = q.graph
+    gr = upload(ctx, g)
+    sk = gr.sketches(q.prob_kind, q.p, q.R, q.seed, 1.0)
+    for r in SAMPLED_SKETCHES:
+        gl, gs = sk.dump(r)
+        assert np.array_equal(gl, lab[r]), r
+        assert np.array_equal(gs, siz[r]), r
+    assert np.array_equal(sk.initial_gains(), siz.astype(np.uint64).sum(axis=0))
+    seeds, gains = sk.select(q.k)
+    sk.close()
+    gr.close()
+    _say("  seeds", seeds[:8], "gains", gains[:8])
+
+    cov = oracle.Coverage(lab, siz)
+    assert len(set(seeds.tolist())) == q.k
+    for i, s in enumerate(seeds):
+        s = int(s)
+        if i in SAMPLED_ROUNDS:
+            m = cov.all_marginals(threads)
+            best = int(m.max())
+            assert int(gains[i]) == best, i
+            assert s == int(np.flatnonzero(m == best)[0]), i
+        else:
+            assert int(cov.marginals(s, s + 1)[0]) == int(gains[i]), i
+        cov.cover(s)
+    assert np.all(np.diff(gains.astype(np.int64)) <= 0)
+    workload_results[q.graph.name] = (seeds, gains)
+
+
+def test_rmat20_compact_sampled_parity(ctx, workload):
+    q, lab, siz, _ = workload
+    g = q.graph
+    alpha = 0.1
+    cents = oracle.centers(g.n, q.seed, alpha)
+    gr = upload(ctx, g)
+    sk = gr.sketches(q.prob_kind, q.p, q.R, q.seed, alpha)
+    assert np.array_equal(sk.centers(), cents)
+    for r in SAMPLED_SKETCHES:
+        lc, sc = oracle.compact(lab[r], siz[r], cents)
+        gl, gs = sk.dump(r)
+        assert np.array_equal(gl, lc) and np.array_equal(gs, sc), r
+    assert np.array_equal(sk.initial_gains(), siz.astype(np.uint64).sum(axis=0))
+    seeds, gains = sk.select(q.k)
+    st = sk.stats()
+    sk.close()
+    gr.close()
+    _say("  compact: bulk rounds", st["bulk_rounds"], "evaluations", st["evaluations"])
+    if q.graph.name in workload_results:
+        fs, fg = workload_results[q.graph.name]
+        assert np.array_equal(seeds, fs) and np.array_equal(gains, fg)
+    else:
+        cov = oracle.Coverage(lab, siz)
+        for i, s in enumerate(seeds):
+            assert int(cov.marginals(int(s), int(s) + 1)[0]) == int(gains[i]), i
+            cov.cover(int(s))

@@ -160,6 +160,22 @@ def test_resume_equals_one_shot(ctx):
     assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
 
 
+@pytest.mark.parametrize("step", ["1", "3", "200"])
+def test_persistent_handoff_matches_oracle(ctx, step, monkeypatch):
+    # The persistent selection kernel hands a round to the per-level kernels when an
+    # evaluation step exceeds its limit; lowering the limit forces hand-overs at
+    # every level (step 1), at some levels (3), or only for CompactSketch (200).
+    monkeypatch.setenv("PACIM_PERSIST_STEP", step)
+    g = inputs.rmat_graph(12, 16 << 12, seed=17)
+    R, k, seed = 24, 30, 6
+    _say(f"case persistent hand-off step={step}")
+    lab, siz = oracle.sketches(g, TRI, 0.0, seed, R)
+    ws, wg = oracle.greedy(lab, siz, k)
+    for alpha in (1.0, 0.2):
+        s, gn, _ = run_select(ctx, g, TRI, 0.0, R, k, seed, alpha=alpha, chunks=[5, 25])
+        assert np.array_equal(s, ws) and np.array_equal(gn, wg), alpha
+
+
 def test_deterministic_repeats(ctx):
     g = inputs.rmat_graph(13, 16 << 13, seed=8)
     ref = run_select(ctx, g, TRI, 0.0, 48, 20, 2)
