@@ -11,7 +11,17 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
-    config.addinivalue_line("markers", "slow: long CPU-side oracle work (full-size configurations)")
+    config.addinivalue_line("markers", "slow: minutes of host-side work (the 2^24-vertex configuration); "
+                                       "runs only with PACIM_SLOW=1")
+
+
+def pytest_collection_modifyitems(config, items):
+    if os.environ.get("PACIM_SLOW") == "1":
+        return
+    skip = pytest.mark.skip(reason="slow full-size configuration: set PACIM_SLOW=1 to run it")
+    for it in items:
+        if "slow" in it.keywords:
+            it.add_marker(skip)
 
 
 def _ensure_host_libs():

@@ -1,4 +1,4 @@
-"""GPU parity at the full size of the R-MAT scale-20 workload.
+"""GPU parity at full size: the R-MAT scale-20 workload and the scale-24 one.
 
 2^20 vertices, 2^24 undirected pairs, trivalency probabilities, R = 256,
 k = 100; full labels and CompactSketch (alpha = 0.1), in the configuration the
@@ -108,3 +108,47 @@ def test_rmat20_compact_sampled_parity(ctx, workload):
         for i, s in enumerate(seeds):
             assert int(cov.marginals(int(s), int(s) + 1)[0]) == int(gains[i]), i
             cov.cover(int(s))
+
+
+def test_rmat24_compact_full_size(ctx):
+    """R-MAT scale 24 (2^24 vertices, 2^28 pairs), uniform p = 0.02, R = 256,
+    k = 200, CompactSketch alpha = 0.1.  The oracle labels sampled sketches (one
+    BFS each); the seed sequence is checked by properties that hold at any size
+    and against the full-label path on the GPU (alpha-equivalence: two different
+    Marginal computations, 34 GB of labels on one side)."""
+    q = inputs.rmat24().queries[0]
+    g = q.graph
+    _say(f"case rmat24 full size: n={g.n} m={g.m_und}")
+    cents = oracle.centers(g.n, q.seed, q.alpha)
+    gr = upload(ctx, g)
+    sk = gr.sketches(q.prob_kind, q.p, q.R, q.seed, q.alpha)
+    assert np.array_equal(sk.centers(), cents)
+    sampled = {}
+    for r in (0, 255):
+        lab_r, siz_r = oracle.sketch(g, q.prob_kind, q.p, q.seed, r)
+        sampled[r] = (lab_r, siz_r)
+        lc, sc = oracle.compact(lab_r, siz_r, cents)
+        gl, gs = sk.dump(r)
+        assert np.array_equal(gl, lc) and np.array_equal(gs, sc), r
+        roots = lab_r == np.arange(g.n, dtype=np.uint32)
+        assert int(siz_r[roots].astype(np.uint64).sum()) == g.n  # the components partition the vertices
+    g0 = sk.initial_gains()
+    seeds, gains = sk.select(q.k)
+    st = sk.stats()
+    sk.close()
+    _say("  compact: seeds", seeds[:6], "gains", gains[:6], "bulk rounds", st["bulk_rounds"])
+    assert len(set(seeds.tolist())) == q.k
+    assert np.all(np.diff(gains.astype(np.int64)) <= 0)      # submodular coverage
+    assert int(gains.sum()) <= q.R * g.n                      # coverage of R sketches
+    top = int(g0.max())
+    assert int(gains[0]) == top and int(seeds[0]) == int(np.flatnonzero(g0 == top)[0])
+
+    fk = gr.sketches(q.prob_kind, q.p, q.R, q.seed, 1.0)
+    for r, (lab_r, siz_r) in sampled.items():
+        gl, gs = fk.dump(r)
+        assert np.array_equal(gl, lab_r) and np.array_equal(gs, siz_r), r
+    assert np.array_equal(fk.initial_gains(), g0)
+    s2, g2 = fk.select(q.k)
+    fk.close()
+    gr.close()
+    assert np.array_equal(s2, seeds) and np.array_equal(g2, gains)
