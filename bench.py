@@ -279,7 +279,7 @@ def run_serving(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for {args.gpus}).",
+        print(f"bench.py measures one GPU only: the library has no multi-GPU path (asked for {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched":
