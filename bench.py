@@ -320,7 +320,7 @@ def main():
             sk.close()
             if record is not None:
                 record.setdefault(m, []).append((st["build_ms"], st["select_ms"], st["evaluations"],
-                                                 st["sketches_per_pass"]))
+                                                 st["sketches_per_pass"], st["bulk_rounds"], st["bulk_resampled"]))
             per[m] = (s, gn)
         return per
 
@@ -357,6 +357,8 @@ def main():
             "seeds_per_s_select": q.k / (s.mean() / 1e3),
             "evaluations": int(rows[-1][2]),
             "sketches_per_pass": int(rows[-1][3]),
+            "bulk_rounds": int(rows[-1][4]),
+            "bulk_rounds_resampled": int(rows[-1][5]),
         }
     # dominant kernel: the sampling + hooking pass over the edge list
     hk = kern["sample_hook"]

@@ -163,6 +163,9 @@ typedef struct {
     uint32_t bulk_rounds;        /* CompactSketch rounds that evaluated every
                                     vertex at once (after a seed that covered a
                                     large share of every sketch)                   */
+    uint32_t bulk_resampled;     /* of those, rounds that re-derived the sampled
+                                    graphs' components (the others used the
+                                    largest-component bitmaps kept by the build)   */
 } im_sketch_stats;
 im_status im_sketches_stats(const im_sketches *s, im_sketch_stats *out);
 

@@ -18,6 +18,7 @@
 
 #include "common.h"
 #include "select_kernels.h"
+#include "sketch_kernels.h"
 
 namespace pacim {
 
@@ -337,6 +338,128 @@ __global__ void __launch_bounds__(256) k_bulk_keys(SelState *__restrict__ st,
                                                    uint64_t *__restrict__ key) {
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v < n) key[v] = in_s[v] ? 0ull : pack_key(partial[v], v, kb);
+    if (v == 0) {
+        for (int l = 0; l <= kMaxLevels; ++l) { st->fr_cnt[l] = 0; st->ev_cnt[l] = 0; }
+        for (int l = 0; l < kMaxLevels + 2; ++l) st->ov_cnt[l] = 0;
+        st->ev_cnt[0] = n - st->round;
+    }
+}
+
+// ---- bulk round from the largest components' bitmaps ------------------------
+// The build keeps, per sketch, the largest component's size and membership
+// bitmap (n bits).  Marginal(S, v) = gain0[v] - sum over sketches r whose
+// component of v holds a seed of |CC_r(v)|.  A seed inside the largest
+// component of r covers it (one flag per sketch, then one bitmap test per
+// vertex); a seed outside it covers a smaller component, enumerated by a
+// search from the seed, whose size is subtracted at each of its vertices.
+// Searches are capped per sketch; past the cap the round falls back to
+// re-deriving the components.
+
+// The whole component of v in sketch kr, appended to gq from position tail
+// (visited bits in gvis); returns the new tail.  Stops once tail exceeds cap
+// (every vertex it marked is still queued, so the caller can clear the bits).
+__device__ uint32_t component_global(const GraphDev &g, const ProbDev &pm, uint64_t kr, uint32_t v, uint32_t *gq,
+                                     uint32_t *gvis, uint32_t tail, uint32_t cap) {
+    const uint32_t lane = lane_id();
+    if (lane == 0) {
+        gq[tail] = v;
+        atomicOr(&gvis[v >> 5], 1u << (v & 31));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    uint32_t head = tail;
+    ++tail;
+    while (head < tail && tail <= cap) {
+        const uint32_t u = __hip_atomic_load(&gq[head], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        ++head;
+        const uint64_t o1 = g.off[u + 1];
+        for (uint64_t base = g.off[u]; base < o1; base += kWave) {
+            const uint64_t j = base + lane;
+            bool ins = false;
+            uint32_t w = 0;
+            if (j < o1) {
+                w = g.cols[j];
+                const uint64_t x = edge_word(u, w);
+                if (is_live(x, kr, edge_threshold(pm, x))) {
+                    const uint32_t bit = 1u << (w & 31);
+                    ins = (atomicOr(&gvis[w >> 5], bit) & bit) == 0;
+                }
+            }
+            const uint64_t im = __ballot(ins);
+            if (ins) gq[tail + (uint32_t)__popcll(im & ((1ull << lane) - 1ull))] = w;
+            tail += (uint32_t)__popcll(im);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    return tail;
+}
+
+// One 64-thread block per queue/bitmap slot, sketches r = slot, slot + grid, ...:
+// covered[r] = [some seed lies in r's largest component]; sub[w] += |C| for every
+// vertex w of every other covered component C.  *abort = 1 if a sketch's
+// searches passed cap vertices.
+__global__ void __launch_bounds__(64) k_bulk_bits_search(const SelState *__restrict__ st,
+                                                         const uint32_t *__restrict__ seeds, GraphDev g, ProbDev pm,
+                                                         const uint64_t *__restrict__ K, uint32_t R, uint32_t n,
+                                                         const uint64_t *__restrict__ gbits, uint32_t nw,
+                                                         uint8_t *__restrict__ covered,
+                                                         unsigned long long *__restrict__ sub,
+                                                         uint32_t *__restrict__ slot_q, uint32_t *__restrict__ slot_vis,
+                                                         uint32_t cap, uint32_t *__restrict__ abort_flag) {
+    const uint32_t lane = lane_id();
+    const uint32_t ns = st->round;
+    uint32_t *gq = slot_q + (size_t)blockIdx.x * n;
+    uint32_t *gvis = slot_vis + (size_t)blockIdx.x * ((n + 31) / 32);
+    for (uint32_t r = blockIdx.x; r < R; r += gridDim.x) {
+        const uint64_t *bits = gbits + (size_t)r * nw;
+        bool giant = false;
+        uint32_t tail = 0;
+        for (uint32_t j = 0; j < ns && tail <= cap; ++j) {
+            const uint32_t s = seeds[j];
+            if ((bits[s >> 6] >> (s & 63)) & 1ull) {
+                giant = true;
+                continue;
+            }
+            const uint32_t seen = __hip_atomic_load(&gvis[s >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if ((seen >> (s & 31)) & 1u) continue;  // its component is already counted
+            const uint32_t start = tail;
+            tail = component_global(g, pm, K[r], s, gq, gvis, tail, cap);
+            if (tail > cap) break;
+            const uint32_t size = tail - start;
+            for (uint32_t i = start + lane; i < tail; i += kWave) {
+                const uint32_t w = __hip_atomic_load(&gq[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                atomicAdd(&sub[w], (unsigned long long)size);
+            }
+        }
+        if (tail > cap && lane == 0) atomicOr(abort_flag, 1u);
+        for (uint32_t i = lane; i < tail; i += kWave) {
+            const uint32_t w = __hip_atomic_load(&gq[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            atomicAnd(&gvis[w >> 5], ~(1u << (w & 31)));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        if (lane == 0) covered[r] = giant ? 1 : 0;
+    }
+}
+
+// Fresh keys of every vertex from the bitmaps (nothing if *abort_flag); the
+// round's evaluation count is every unselected vertex.
+__global__ void __launch_bounds__(256) k_bulk_bits_keys(SelState *__restrict__ st, const uint64_t *__restrict__ gain0,
+                                                        const unsigned long long *__restrict__ sub,
+                                                        const uint64_t *__restrict__ gbits, uint32_t nw,
+                                                        const uint8_t *__restrict__ covered,
+                                                        const unsigned long long *__restrict__ gbest, uint32_t R,
+                                                        uint32_t n,
+                                                        uint32_t kb, const uint8_t *__restrict__ in_s,
+                                                        uint64_t *__restrict__ key,
+                                                        const uint32_t *__restrict__ abort_flag) {
+    if (*abort_flag) return;
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    uint64_t c = 0;
+    for (uint32_t r = 0; r < R; ++r)
+        if (covered[r] && ((gbits[(size_t)r * nw + (v >> 6)] >> (v & 63)) & 1ull)) c += giant_size_of(gbest[r]);
+    key[v] = in_s[v] ? 0ull : pack_key(gain0[v] - sub[v] - c, v, kb);
     if (v == 0) {
         for (int l = 0; l <= kMaxLevels; ++l) { st->fr_cnt[l] = 0; st->ev_cnt[l] = 0; }
         for (int l = 0; l < kMaxLevels + 2; ++l) st->ov_cnt[l] = 0;

@@ -103,6 +103,13 @@ struct im_sketches {
     uint64_t last_gain = 0;            // gain of the latest seed (decides bulk rounds)
     uint32_t bulk_rounds = 0;
     PersistCtl *ctl = nullptr;         // step hand-off of the persistent selection kernel
+    // CompactSketch: each sketch's largest component (bulk rounds without re-sampling)
+    uint64_t *gbits = nullptr;         // [R][nw] membership bitmaps
+    uint32_t nw = 0;                   // 64-bit words per bitmap
+    unsigned long long *gbest = nullptr;  // [R] (size << 32) | (2^32 - 1 - root) of the largest
+    uint8_t *gcov = nullptr;           // [R] largest component covered by a seed
+    uint32_t *bulk_abort = nullptr;
+    uint32_t bulk_resampled = 0;
     // bookkeeping
     std::vector<std::pair<void *, size_t>> allocs;
     uint32_t chosen = 0;
@@ -624,6 +631,12 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
         k_center_write<<<nch, 256, 0, st>>>(n, seed, Ta, chunk, s->center_rank, s->centers);
         SK_TRY(sk_alloc(s, (size_t)R * std::max<uint32_t>(rho, 1), &s->label_c));
         SK_TRY(sk_alloc(s, (size_t)R * std::max<uint32_t>(rho, 1), &s->size_c));
+        s->nw = (n + 63) / 64;
+        SK_TRY(sk_alloc(s, (size_t)R * s->nw, &s->gbits));
+        SK_TRY(sk_alloc(s, R, &s->gbest));
+        SK_HIP(hipMemsetAsync(s->gbest, 0, (size_t)R * 8, st));
+        SK_TRY(sk_alloc(s, R, &s->gcov));
+        SK_TRY(sk_alloc(s, 1, &s->bulk_abort));
     } else {
         s->rho = n;
         SK_TRY(sk_alloc(s, (size_t)n * R, &s->E));
@@ -643,7 +656,10 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
             Prof p(ctx, "emit");
             dim3 ge((std::max<uint32_t>(s->rho, 1) + 255) / 256, b);
             if (s->rho) k_emit_compact<<<ge, 256, 0, st>>>(parent, cnt, minc, s->centers, s->rho, n, r0, s->label_c, s->size_c);
-            k_gain0<<<(n + 255) / 256, 256, 0, st>>>(parent, cnt, n, b, s->gain0);
+            k_giant_root<<<dim3(std::min<uint32_t>((n + 255) / 256, 64u), b), 256, 0, st>>>(parent, cnt, n,
+                                                                                        s->gbest + r0);
+            k_gain0<<<(n + 255) / 256, 256, 0, st>>>(parent, cnt, n, b, s->gain0, s->gbest + r0,
+                                                     s->gbits + (size_t)r0 * s->nw, s->nw);
         } else {
             Prof p(ctx, "emit");
             k_emit_full<<<(n + kEmitTile - 1) / kEmitTile, 256, 0, st>>>(parent, cnt, n, b, R, r0, s->E, s->gain0);
@@ -825,12 +841,52 @@ im_status run_persistent_rounds(im_sketches *s, uint32_t max_rounds, unsigned lo
     return IM_OK;
 }
 
-// A round that evaluates every unselected vertex (compact sketches): re-derive the
-// R sampled graphs' components, sum the uncovered CC sizes, rebuild the tree.
+// A round that evaluates every unselected vertex (compact sketches), then
+// rebuilds the tree.  First from the build's largest-component bitmaps (a search
+// per seed outside its sketch's largest component, capped); past the cap, by
+// re-deriving the R sampled graphs' components: sum the uncovered CC sizes.
+uint32_t bulk_search_cap(const im_sketches *s) {
+    const char *e = getenv("PACIM_BULK_SEARCH_CAP");  // tests: force the re-deriving path
+    if (e) return (uint32_t)strtoul(e, nullptr, 10);
+    return std::max<uint32_t>(1024u, std::min<uint32_t>(65536u, s->n / 16));
+}
+
+im_status finish_bulk_round(im_sketches *s) {
+    hipStream_t st = s->ctx->stream;
+    const TreeDesc &td = s->td;
+    for (int l = (int)td.D - 1; l >= 0; --l)
+        k_tree_build_level<<<wave_grid(td.lvl_n[l], 8192), 256, 0, st>>>(td, (uint32_t)l, s->ids, s->key);
+    k_round_end<<<1, 64, 0, st>>>(td, s->st, s->ids, s->key, s->in_s, s->kb, s->seeds_d, s->gains_d, s->evals_d,
+                                  nullptr, s->R);
+    enqueue_markseed_compact(s);
+    ++s->bulk_rounds;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(s->ctx, IM_EDEVICE, std::string("bulk round launch: ") + hipGetErrorString(e));
+    return IM_OK;
+}
+
 im_status enqueue_bulk_round(im_sketches *s) {
     im_ctx *ctx = s->ctx;
     hipStream_t st = ctx->stream;
     const uint32_t n = s->n;
+    const uint32_t cap = bulk_search_cap(s);
+    if (s->gbits && cap > 0) {
+        GraphDev gd{s->g->off, s->g->cols};
+        uint32_t aborted = 1;
+        HIP_TRY(ctx, hipMemsetAsync(s->partial, 0, (size_t)n * 8, st));
+        HIP_TRY(ctx, hipMemsetAsync(s->bulk_abort, 0, 4, st));
+        k_bulk_bits_search<<<std::min(s->slots, s->R), 64, 0, st>>>(s->st, s->seeds_d, gd, s->pm, s->K, s->R, n, s->gbits,
+                                                                 s->nw, s->gcov, s->partial, s->slot_q, s->slot_vis,
+                                                                 cap, s->bulk_abort);
+        HIP_TRY(ctx, hipMemcpyAsync(&aborted, s->bulk_abort, 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(ctx, hipStreamSynchronize(st));
+        if (!aborted) {
+            k_bulk_bits_keys<<<(n + 255) / 256, 256, 0, st>>>(s->st, s->gain0, s->partial, s->gbits, s->nw, s->gcov,
+                                                              s->gbest, s->R, n, s->kb, s->in_s, s->key, s->bulk_abort);
+            return finish_bulk_round(s);
+        }
+    }
+    ++s->bulk_resampled;
     if (!s->bulk_cs) {
         CCScratch *c = new (std::nothrow) CCScratch();
         if (!c) return fail(ctx, IM_ENOMEM, "host allocation");
@@ -841,7 +897,6 @@ im_status enqueue_bulk_round(im_sketches *s) {
     const CCScratch &cs = *static_cast<CCScratch *>(s->bulk_cs);
     const uint32_t B = cs.B;
     uint32_t *parent = cs.parent, *cnt = cs.cnt, *flag = cs.minc;
-    const TreeDesc &td = s->td;
     hipError_t e0 = hipMemsetAsync(s->partial, 0, (size_t)n * 8, st);
     if (e0 != hipSuccess) return fail(ctx, IM_EDEVICE, std::string("bulk round: ") + hipGetErrorString(e0));
     for (uint32_t r0 = 0; r0 < s->R; r0 += B) {
@@ -851,15 +906,7 @@ im_status enqueue_bulk_round(im_sketches *s) {
         k_bulk_accum<<<(n + 255) / 256, 256, 0, st>>>(parent, cnt, flag, n, b, s->partial);
     }
     k_bulk_keys<<<(n + 255) / 256, 256, 0, st>>>(s->st, s->partial, n, s->kb, s->in_s, s->key);
-    for (int l = (int)td.D - 1; l >= 0; --l)
-        k_tree_build_level<<<wave_grid(td.lvl_n[l], 8192), 256, 0, st>>>(td, (uint32_t)l, s->ids, s->key);
-    k_round_end<<<1, 64, 0, st>>>(td, s->st, s->ids, s->key, s->in_s, s->kb, s->seeds_d, s->gains_d, s->evals_d,
-                                  nullptr, s->R);
-    enqueue_markseed_compact(s);
-    ++s->bulk_rounds;
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(ctx, IM_EDEVICE, std::string("bulk round launch: ") + hipGetErrorString(e));
-    return IM_OK;
+    return finish_bulk_round(s);
 }
 
 // Policy for compact sketches: a round is run in bulk when the previous seed's
@@ -1071,6 +1118,7 @@ extern "C" im_status im_sketches_stats(const im_sketches *s, im_sketch_stats *ou
     out->sketches_per_pass = s->B;
     out->sketch_bytes = s->bytes;
     out->bulk_rounds = s->bulk_rounds;
+    out->bulk_resampled = s->bulk_resampled;
     return IM_OK;
 }
 

@@ -11,7 +11,9 @@
 //                     rank recorded at the root (CompactSketch)
 //   k_emit_full       (label, size) per (v, r) into E[n][R] and the initial gains
 //   k_emit_compact    CompactSketch triple label_c / size_c [R][rho]
-//   k_gain0           initial gains when only the compact triple is kept
+//   k_giant_root      the largest component of each sketch (CompactSketch)
+//   k_gain0           initial gains when only the compact triple is kept, and
+//                     the largest components' membership bitmaps
 //   k_center_*        hashed Bernoulli(alpha) centers, ranked by id
 #pragma once
 
@@ -240,16 +242,52 @@ __global__ void __launch_bounds__(256) k_emit_compact(const uint32_t *__restrict
     size_c[at] = (l == i) ? 1u + cnt[base + root] : 0u;
 }
 
+// Largest component of each sketch of the pass, smallest root on equal sizes:
+// gbest[b] = max over roots of (size << 32) | (2^32 - 1 - root), zeroed by the
+// caller.  grid (G, B): the blocks of sketch blockIdx.y stride over its vertices.
+__device__ __forceinline__ uint32_t giant_root_of(uint64_t gbest) { return 0xFFFFFFFFu - (uint32_t)gbest; }
+__device__ __forceinline__ uint32_t giant_size_of(uint64_t gbest) { return (uint32_t)(gbest >> 32); }
+
+__global__ void __launch_bounds__(256) k_giant_root(const uint32_t *__restrict__ parent,
+                                                    const uint32_t *__restrict__ cnt, uint32_t n,
+                                                    unsigned long long *__restrict__ gbest) {
+    __shared__ uint64_t best_w[256 / kWave];
+    const size_t base = (size_t)blockIdx.y * sketch_stride(n);
+    uint64_t best = 0;
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        if (parent[base + v] == v) {
+            const uint64_t k = ((uint64_t)(cnt[base + v] + 1u) << 32) | (uint64_t)(0xFFFFFFFFu - v);
+            best = k > best ? k : best;
+        }
+    best = wave_max_u64(best);
+    if (lane_id() == 0) best_w[threadIdx.x / kWave] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (uint32_t w = 1; w < blockDim.x / kWave; ++w) best = best_w[w] > best ? best_w[w] : best;
+        if (best) atomicMax(&gbest[blockIdx.y], (unsigned long long)best);
+    }
+}
+
+// Initial gains when only the compact triple is kept, and (gbits non-null) the
+// membership bitmap of each sketch's largest component: bit v of
+// gbits[b][v / 64] = [v lies in the component rooted at giant_root_of(gbest[b])].
 __global__ void __launch_bounds__(256) k_gain0(const uint32_t *__restrict__ parent, const uint32_t *__restrict__ cnt,
-                                               uint32_t n, uint32_t B, uint64_t *__restrict__ gain0) {
+                                               uint32_t n, uint32_t B, uint64_t *__restrict__ gain0,
+                                               const unsigned long long *__restrict__ gbest,
+                                               uint64_t *__restrict__ gbits, uint32_t nw) {
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
+    const bool valid = v < n;
     uint64_t s = 0;
     for (uint32_t b = 0; b < B; ++b) {
         const size_t base = (size_t)b * sketch_stride(n);
-        s += 1u + cnt[base + parent[base + v]];
+        const uint32_t root = valid ? parent[base + v] : kNone;
+        if (valid) s += 1u + cnt[base + root];
+        if (gbits) {
+            const uint64_t m = __ballot(valid && root == giant_root_of(gbest[b]));
+            if (lane_id() == 0 && (v >> 6) < nw) gbits[(size_t)b * nw + (v >> 6)] = m;
+        }
     }
-    gain0[v] += s;
+    if (valid) gain0[v] += s;
 }
 
 // ---- centers: flag, per-chunk counts, scan, ranks --------------------------

@@ -99,7 +99,8 @@ def test_rmat20_compact_sampled_parity(ctx, workload):
     st = sk.stats()
     sk.close()
     gr.close()
-    _say("  compact: bulk rounds", st["bulk_rounds"], "evaluations", st["evaluations"])
+    _say("  compact: bulk rounds", st["bulk_rounds"], "re-derived", st["bulk_resampled"], "evaluations",
+         st["evaluations"])
     if q.graph.name in workload_results:
         fs, fg = workload_results[q.graph.name]
         assert np.array_equal(seeds, fs) and np.array_equal(gains, fg)
@@ -136,7 +137,8 @@ def test_rmat24_compact_full_size(ctx):
     seeds, gains = sk.select(q.k)
     st = sk.stats()
     sk.close()
-    _say("  compact: seeds", seeds[:6], "gains", gains[:6], "bulk rounds", st["bulk_rounds"])
+    _say("  compact: seeds", seeds[:6], "gains", gains[:6], "bulk rounds", st["bulk_rounds"], "re-derived",
+         st["bulk_resampled"])
     assert len(set(seeds.tolist())) == q.k
     assert np.all(np.diff(gains.astype(np.int64)) <= 0)      # submodular coverage
     assert int(gains.sum()) <= q.R * g.n                      # coverage of R sketches

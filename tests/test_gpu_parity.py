@@ -92,18 +92,26 @@ def test_rmat_compact_matches_oracle(ctx, alpha):
     gr.close()
 
 
-@pytest.mark.parametrize("policy", ["always", "never", "auto"])
-def test_compact_bulk_rounds_match_oracle(ctx, policy, monkeypatch):
+@pytest.mark.parametrize("policy,cap", [("always", None), ("never", None), ("auto", None), ("always", "1"),
+                                        ("auto", "1")])
+def test_compact_bulk_rounds_match_oracle(ctx, policy, cap, monkeypatch):
     # uniform p = 0.1 on R-MAT gives a giant component, so the first seed covers a
     # large share of every sketch and "auto" switches the next round to bulk.
+    # cap "1": a seed's component outside its sketch's largest one makes the bulk
+    # round re-derive the sketches instead of using the build's bitmaps.
     monkeypatch.setenv("PACIM_BULK", policy)
+    if cap is not None:
+        monkeypatch.setenv("PACIM_BULK_SEARCH_CAP", cap)
     g = inputs.rmat_graph(12, 16 << 12, seed=31)
     R, k, seed, alpha = 32, 25, 5, 0.1
-    _say(f"case compact bulk={policy}")
+    _say(f"case compact bulk={policy} cap={cap}")
     lab, siz = oracle.sketches(g, U, 0.1, seed, R, threads=8)
     ws, wg = oracle.greedy(lab, siz, k)
     s, gn, st = run_select(ctx, g, U, 0.1, R, k, seed, alpha=alpha)
     assert np.array_equal(s, ws) and np.array_equal(gn, wg)
+    _say("  bulk rounds", st["bulk_rounds"], "re-derived", st["bulk_resampled"])
+    if policy == "always" and cap == "1":
+        assert st["bulk_resampled"] >= 1
     if policy == "always":
         assert st["bulk_rounds"] == k - 1
     elif policy == "never":
