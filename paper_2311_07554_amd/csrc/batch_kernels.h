@@ -180,11 +180,7 @@ __global__ void __launch_bounds__(1024) k_bat_hook(const BatchQuery *__restrict_
             }
             live &= nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
         }
-        while (live) {
-            const uint32_t b = (uint32_t)__builtin_ctzll(live);
-            live &= live - 1ull;
-            uf_unite(Q.parent + (size_t)(b0 + b) * Q.n, uv.x, uv.y);
-        }
+        unite_live(Q.parent + (size_t)b0 * Q.n, Q.n, live, uv.x, uv.y);
     }
 }
 

@@ -486,7 +486,7 @@ void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const ui
                      hipStream_t st = nullptr) {
     if (!st) st = ctx->stream;
     const uint32_t n = g->n;
-    const unsigned hook_grid = grid_for(g->m_und, kHookBlock, 256 * 16);
+    const unsigned hook_grid = grid_for(g->m_und, kHookBlock, 256 * 32);
     dim3 gi((n + 255) / 256, b);
     k_batch_init<<<gi, 256, 0, st>>>(cs.parent, cs.cnt, minc, n, minc_init);
     {

@@ -60,21 +60,35 @@ __device__ __forceinline__ uint32_t uf_find(uint32_t *P, uint32_t x) {
     }
 }
 
+// uf_find continuing from x whose parent p the caller already loaded.
+__device__ __forceinline__ uint32_t uf_find_from(uint32_t *P, uint32_t x, uint32_t p) {
+    for (;;) {
+        if (p == x) return x;
+        const uint32_t gp = uf_load(P + p);
+        if (gp == p) return p;
+        __hip_atomic_store(P + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x = gp;
+        p = uf_load(P + x);
+    }
+}
+
 // Union by hooking the larger root under the smaller, so the last root of every
 // component is its smallest vertex id whatever the schedule.  A failed CAS
 // returns the root's fresh parent, strictly smaller, so a+b strictly decreases
-// on every retry: the loop ends even when uf_find read old values.
-__device__ __forceinline__ void uf_unite(uint32_t *P, uint32_t a, uint32_t b) {
+// on every retry: the loop ends even when uf_find read old values.  pa / pb:
+// the parents of a and b, already loaded.
+__device__ __forceinline__ void uf_unite_from(uint32_t *P, uint32_t a, uint32_t pa, uint32_t b, uint32_t pb) {
+    a = uf_find_from(P, a, pa);
+    b = uf_find_from(P, b, pb);
     for (;;) {
-        a = uf_find(P, a);
-        b = uf_find(P, b);
         if (a == b) return;
         if (a < b) { uint32_t t = a; a = b; b = t; }
         uint32_t expected = a;
         if (__hip_atomic_compare_exchange_strong(P + a, &expected, b, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT))
             return;
-        a = expected;
+        a = uf_find(P, expected);
+        b = uf_find(P, b);
     }
 }
 
@@ -103,6 +117,37 @@ __device__ __forceinline__ uint64_t live_mask(uint64_t x, const uint64_t *__rest
 }
 
 constexpr uint32_t kHookBlock = 256;
+constexpr int kHookIlp = 4;  // live sketches of an edge whose first parent loads are issued together
+
+// Unions of edge (u, v) in every sketch whose bit is set in live (sketch b's
+// forest at parent + b * stride).  The parents of both endpoints in up to
+// kHookIlp sketches are loaded before any of those unions walks on, so a thread
+// keeps several independent memory accesses in flight instead of one chain.
+__device__ __forceinline__ void unite_live(uint32_t *parent, size_t stride, uint64_t live, uint32_t u, uint32_t v) {
+    while (live) {
+        uint32_t bs[kHookIlp], pu[kHookIlp], pv[kHookIlp];
+        int c = 0;
+#pragma unroll
+        for (int i = 0; i < kHookIlp; ++i) {
+            bs[i] = 0;
+            if (live) {
+                bs[i] = (uint32_t)__builtin_ctzll(live);
+                live &= live - 1ull;
+                ++c;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kHookIlp; ++i)
+            if (i < c) {
+                const uint32_t *P = parent + (size_t)bs[i] * stride;
+                pu[i] = uf_load(P + u);
+                pv[i] = uf_load(P + v);
+            }
+#pragma unroll
+        for (int i = 0; i < kHookIlp; ++i)
+            if (i < c) uf_unite_from(parent + (size_t)bs[i] * stride, u, pu[i], v, pv[i]);
+    }
+}
 
 // One thread per undirected edge: its live mask over the pass's sketches, then
 // one union per live sketch.
@@ -114,12 +159,7 @@ __global__ void __launch_bounds__(kHookBlock) k_sample_hook(const uint2 *__restr
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
         const uint2 uv = edges[e];
-        uint64_t live = live_mask<KIND>(((uint64_t)uv.x << 32) | uv.y, K, B, pm);
-        while (live) {
-            const uint32_t b = (uint32_t)__builtin_ctzll(live);
-            live &= live - 1ull;
-            uf_unite(parent + (size_t)b * ns, uv.x, uv.y);
-        }
+        unite_live(parent, ns, live_mask<KIND>(((uint64_t)uv.x << 32) | uv.y, K, B, pm), uv.x, uv.y);
     }
 }
 
