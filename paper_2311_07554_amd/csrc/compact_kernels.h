@@ -443,23 +443,42 @@ __global__ void __launch_bounds__(64) k_bulk_bits_search(const SelState *__restr
 }
 
 // Fresh keys of every vertex from the bitmaps (nothing if *abort_flag); the
-// round's evaluation count is every unselected vertex.
+// round's evaluation count is every unselected vertex.  One wave per 64-vertex
+// bitmap word: lane l loads the word and covered size of sketches r0 + l, and
+// every lane then walks them with lane reads (no memory latency per sketch).
 __global__ void __launch_bounds__(256) k_bulk_bits_keys(SelState *__restrict__ st, const uint64_t *__restrict__ gain0,
                                                         const unsigned long long *__restrict__ sub,
                                                         const uint64_t *__restrict__ gbits, uint32_t nw,
                                                         const uint8_t *__restrict__ covered,
                                                         const unsigned long long *__restrict__ gbest, uint32_t R,
-                                                        uint32_t n,
-                                                        uint32_t kb, const uint8_t *__restrict__ in_s,
+                                                        uint32_t n, uint32_t kb, const uint8_t *__restrict__ in_s,
                                                         uint64_t *__restrict__ key,
                                                         const uint32_t *__restrict__ abort_flag) {
     if (*abort_flag) return;
-    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
+    const uint32_t lane = lane_id();
+    const uint32_t w = wave_index();
+    if (w >= nw) return;
     uint64_t c = 0;
-    for (uint32_t r = 0; r < R; ++r)
-        if (covered[r] && ((gbits[(size_t)r * nw + (v >> 6)] >> (v & 63)) & 1ull)) c += giant_size_of(gbest[r]);
-    key[v] = in_s[v] ? 0ull : pack_key(gain0[v] - sub[v] - c, v, kb);
+    for (uint32_t r0 = 0; r0 < R; r0 += kWave) {
+        const uint32_t r = r0 + lane;
+        uint32_t lo = 0, hi = 0, mult = 0;
+        if (r < R && covered[r]) {
+            const uint64_t word = gbits[(size_t)r * nw + w];
+            lo = (uint32_t)word;
+            hi = (uint32_t)(word >> 32);
+            mult = giant_size_of(gbest[r]);
+        }
+        const uint32_t cntr = min((uint32_t)kWave, R - r0);
+        for (uint32_t i = 0; i < cntr; ++i) {
+            const uint32_t m = (uint32_t)__builtin_amdgcn_readlane((int)mult, (int)i);
+            if (m == 0) continue;
+            const uint32_t wlo = (uint32_t)__builtin_amdgcn_readlane((int)lo, (int)i);
+            const uint32_t whi = (uint32_t)__builtin_amdgcn_readlane((int)hi, (int)i);
+            if ((((lane < 32) ? wlo : whi) >> (lane & 31)) & 1u) c += m;
+        }
+    }
+    const uint32_t v = w * kWave + lane;
+    if (v < n) key[v] = in_s[v] ? 0ull : pack_key(gain0[v] - sub[v] - c, v, kb);
     if (v == 0) {
         for (int l = 0; l <= kMaxLevels; ++l) { st->fr_cnt[l] = 0; st->ev_cnt[l] = 0; }
         for (int l = 0; l < kMaxLevels + 2; ++l) st->ov_cnt[l] = 0;

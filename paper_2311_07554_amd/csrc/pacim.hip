@@ -58,6 +58,11 @@ struct im_ctx {
     std::vector<hipEvent_t> spare_events;
     std::mutex alloc_mu;  // device memory accounting (a server's thread allocates too)
     unsigned persist_grid = 0;  // workgroups of the persistent selection kernel (all resident)
+    // Freed device blocks kept for reuse, by exact (rounded) size: hipMalloc / hipFree
+    // of the build's arrays cost milliseconds per build, and hipFree synchronises the
+    // device.  Callers free a block only once the work that used it has completed.
+    std::multimap<size_t, void *> cache;
+    size_t cached = 0;
     uint64_t clock_hz = 0;      // wall_clock64() rate
 };
 
@@ -132,13 +137,36 @@ im_status fail(im_ctx *ctx, im_status s, const std::string &msg) {
             return fail((ctx), IM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+constexpr size_t kCacheLimit = (size_t)48 << 30;  // device bytes the reuse cache may hold
+
+size_t alloc_size(size_t bytes) { return ((bytes ? bytes : 8) + 4095) & ~(size_t)4095; }
+
+void release_cache_locked(im_ctx *ctx) {
+    for (auto &kv : ctx->cache) (void)hipFree(kv.second);
+    ctx->cache.clear();
+    ctx->cached = 0;
+}
+
 im_status dev_alloc(im_ctx *ctx, size_t bytes, void **p) {
     *p = nullptr;
-    if (bytes == 0) bytes = 8;
+    bytes = alloc_size(bytes);
     std::lock_guard<std::mutex> lk(ctx->alloc_mu);
     if (ctx->cap && ctx->used + bytes > ctx->cap)
         return fail(ctx, IM_ENOMEM, "allocation of " + std::to_string(bytes) + " bytes exceeds the context HBM cap");
+    auto it = ctx->cache.find(bytes);
+    if (it != ctx->cache.end()) {
+        *p = it->second;
+        ctx->cache.erase(it);
+        ctx->cached -= bytes;
+        ctx->used += bytes;
+        return IM_OK;
+    }
     hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess && !ctx->cache.empty()) {
+        (void)hipGetLastError();
+        release_cache_locked(ctx);
+        e = hipMalloc(p, bytes);
+    }
     if (e != hipSuccess) {
         *p = nullptr;
         (void)hipGetLastError();
@@ -150,10 +178,15 @@ im_status dev_alloc(im_ctx *ctx, size_t bytes, void **p) {
 
 void dev_free(im_ctx *ctx, void *p, size_t bytes) {
     if (!p) return;
-    if (bytes == 0) bytes = 8;
+    bytes = alloc_size(bytes);
     std::lock_guard<std::mutex> lk(ctx->alloc_mu);
-    (void)hipFree(p);
     ctx->used -= std::min(ctx->used, bytes);
+    if (ctx->cached + bytes <= kCacheLimit) {
+        ctx->cache.emplace(bytes, p);
+        ctx->cached += bytes;
+    } else {
+        (void)hipFree(p);
+    }
 }
 
 template <typename T>
@@ -287,6 +320,10 @@ extern "C" im_status im_ctx_destroy(im_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     drain_timers(ctx);
+    {
+        std::lock_guard<std::mutex> lk(ctx->alloc_mu);
+        release_cache_locked(ctx);
+    }
     for (hipEvent_t e : ctx->spare_events) (void)hipEventDestroy(e);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -488,7 +525,7 @@ void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const ui
     const uint32_t n = g->n;
     const unsigned hook_grid = grid_for(g->m_und, kHookBlock, 256 * 32);
     dim3 gi((n + 255) / 256, b);
-    k_batch_init<<<gi, 256, 0, st>>>(cs.parent, cs.cnt, minc, n, minc_init);
+    k_batch_init<<<gi, 256, 0, st>>>(cs.parent, cs.cnt, minc, n, minc_init, center_rank);
     {
         Prof p(ctx, "sample_hook", st);
         if (pm.kind == 0)
@@ -881,7 +918,7 @@ im_status enqueue_bulk_round(im_sketches *s) {
         HIP_TRY(ctx, hipMemcpyAsync(&aborted, s->bulk_abort, 4, hipMemcpyDeviceToHost, st));
         HIP_TRY(ctx, hipStreamSynchronize(st));
         if (!aborted) {
-            k_bulk_bits_keys<<<(n + 255) / 256, 256, 0, st>>>(s->st, s->gain0, s->partial, s->gbits, s->nw, s->gcov,
+            k_bulk_bits_keys<<<(s->nw + 3) / 4, 256, 0, st>>>(s->st, s->gain0, s->partial, s->gbits, s->nw, s->gcov,
                                                               s->gbest, s->R, n, s->kb, s->in_s, s->key, s->bulk_abort);
             return finish_bulk_round(s);
         }

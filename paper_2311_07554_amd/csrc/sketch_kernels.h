@@ -2,7 +2,7 @@
 // B sketches per pass over the edge list.
 //
 //   k_sketch_keys     K(seed, r) for every sketch
-//   k_batch_init      parent[b][v] = v, cnt = 0, minc = none
+//   k_batch_init      parent[b][v] = v, cnt = 0, minc = v's center rank (or a given value)
 //   k_sample_hook     one thread per undirected edge: B live tests (Sample(e, r),
 //                     fused: sampled graphs are never stored), then union by
 //                     hooking the larger root under the smaller one
@@ -30,14 +30,16 @@ __global__ void k_salt_key(uint64_t seed, uint64_t salt, uint64_t *__restrict__ 
     if (threadIdx.x == 0 && blockIdx.x == 0) *out = sketch_key(seed, salt);
 }
 
+// minc starts at each vertex's own center rank when center_rank is given (so a
+// root's own rank needs no atomic), else at minc_init.
 __global__ void k_batch_init(uint32_t *__restrict__ parent, uint32_t *__restrict__ cnt, uint32_t *__restrict__ minc,
-                             uint32_t n, uint32_t minc_init) {
+                             uint32_t n, uint32_t minc_init, const uint32_t *__restrict__ center_rank) {
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     const size_t at = (size_t)blockIdx.y * sketch_stride(n) + v;
     if (v < n) {
         parent[at] = v;
         cnt[at] = 0;
-        if (minc) minc[at] = minc_init;
+        if (minc) minc[at] = center_rank ? center_rank[v] : minc_init;
     }
 }
 
@@ -204,7 +206,7 @@ __global__ void __launch_bounds__(256) k_compress(uint32_t *__restrict__ parent,
         }
         if (center_rank) {
             const uint32_t cr = valid ? center_rank[v] : kNone;
-            bool cneed = cr != kNone;
+            bool cneed = cr != kNone && r != v;  // a root's own rank is already in minc
             uint32_t hm = (cneed && r == hot) ? cr : kNone;
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) hm = min(hm, (uint32_t)__shfl_xor(hm, off));
