@@ -169,6 +169,11 @@ __device__ BfsOut getcenter_global(const GraphDev &g, const ProbDev &pm, uint64_
     return BfsOut{met ? 0ull : (uint64_t)tail, kNone, false};
 }
 
+// The overflow list holds ov_cap tasks: evaluation searches in its first half,
+// MarkSeed searches in its second, so that one step may produce both.
+__device__ __forceinline__ uint2 *mark_list(uint2 *ov, uint32_t ov_cap) { return ov + ov_cap / 2; }
+__device__ __forceinline__ const uint2 *mark_list(const uint2 *ov, uint32_t ov_cap) { return ov + ov_cap / 2; }
+
 // Overflow tasks of one step go to list ovl (capacity ov_cap), counted in *ocnt.
 __device__ __forceinline__ void push_overflow(SelState *st, uint32_t *ocnt, uint2 *ov, uint32_t ov_cap, uint32_t a,
                                               uint32_t r) {
@@ -207,7 +212,7 @@ __device__ __forceinline__ void eval_compact_level(uint32_t l, SelState *st, con
         const uint32_t v = evl[e];
         const BfsOut o = getcenter_lds(g, pm, K[r], cd, r, in_s, v, q, hs);
         if (lane_id() == 0) {
-            if (o.overflow) push_overflow(st, &st->ov_cnt[l], ov, ov_cap, e, r);
+            if (o.overflow) push_overflow(st, &st->ov_cnt[l], ov, ov_cap / 2, e, r);
             else add_delta(st, partial, e, o.delta, evl, kb, in_s, key);
         }
     }
@@ -223,11 +228,12 @@ __device__ __forceinline__ void overflow_level(int mode, uint32_t slot, SelState
                                                const uint8_t *in_s, uint64_t *key, const uint2 *ov, uint32_t ov_cap,
                                                uint32_t *slot_q, uint32_t *slot_vis, uint32_t n, uint32_t who,
                                                uint32_t nwho) {
-    const uint32_t cnt = min(st->ov_cnt[slot], ov_cap);
+    const uint32_t cnt = min(st->ov_cnt[slot], ov_cap / 2);
+    const uint2 *list = (mode == 0) ? ov : mark_list(ov, ov_cap);
     uint32_t *gq = slot_q + (size_t)who * n;
     uint32_t *gvis = slot_vis + (size_t)who * ((n + 31) / 32);
     for (uint32_t i = who; i < cnt; i += nwho) {
-        const uint2 t = ov[i];
+        const uint2 t = list[i];
         const uint32_t r = t.y;
         const uint32_t v = (mode == 0) ? evl[t.x] : st->last_seed;
         const BfsOut o = getcenter_global(g, pm, K[r], cd, r, in_s, v, gq, gvis);
@@ -247,8 +253,41 @@ __device__ __forceinline__ void markseed_compact_level(SelState *st, const Graph
     for (uint32_t r = wi; r < R; r += wc) {
         const BfsOut o = getcenter_lds(g, pm, K[r], cd, r, in_s, s, q, hs);
         if (lane_id() == 0) {
-            if (o.overflow) push_overflow(st, &st->ov_cnt[kMaxLevels + 1], ov, ov_cap, s, r);
+            if (o.overflow) push_overflow(st, &st->ov_cnt[kMaxLevels + 1], mark_list(ov, ov_cap), ov_cap / 2, s, r);
             else if (o.label != kNone) cd.size_c[(size_t)r * cd.rho + o.label] = 0;
+        }
+    }
+}
+
+// MarkSeed of the previous round's seed and the evaluation of this round's root
+// (evl[0], the level-0 list) in one step: per sketch, the same wave first zeroes
+// the seed's CC (so the root's search sees it covered) and then searches from the
+// root.  If the MarkSeed search overflows, the root's search in that sketch is
+// deferred to the evaluation overflow list, which runs after the MarkSeed one.
+__device__ __forceinline__ void markseed_eval_root_level(SelState *st, const uint32_t *evl,
+                                                         unsigned long long *partial, const GraphDev &g,
+                                                         const ProbDev &pm, const uint64_t *K, uint32_t R,
+                                                         const CompactDev &cd, uint32_t kb, const uint8_t *in_s,
+                                                         uint64_t *key, uint2 *ov, uint32_t ov_cap, uint32_t *q,
+                                                         uint32_t *hs, uint32_t wi, uint32_t wc) {
+    const uint32_t s = st->last_seed;
+    const uint32_t v = evl[0];
+    for (uint32_t r = wi; r < R; r += wc) {
+        const BfsOut m = getcenter_lds(g, pm, K[r], cd, r, in_s, s, q, hs);
+        if (m.overflow) {
+            if (lane_id() == 0) {
+                push_overflow(st, &st->ov_cnt[kMaxLevels + 1], mark_list(ov, ov_cap), ov_cap / 2, s, r);
+                push_overflow(st, &st->ov_cnt[0], ov, ov_cap / 2, 0, r);
+            }
+            continue;
+        }
+        if (lane_id() == 0 && m.label != kNone) cd.size_c[(size_t)r * cd.rho + m.label] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        const BfsOut o = getcenter_lds(g, pm, K[r], cd, r, in_s, v, q, hs);
+        if (lane_id() == 0) {
+            if (o.overflow) push_overflow(st, &st->ov_cnt[0], ov, ov_cap / 2, 0, r);
+            else add_delta(st, partial, 0, o.delta, evl, kb, in_s, key);
         }
     }
 }

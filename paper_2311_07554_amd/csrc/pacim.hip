@@ -776,7 +776,7 @@ im_status enqueue_round_part(im_sketches *s, bool begin, uint32_t l0) {
         if (!s->compact) {
             k_eval_full<<<wave_grid(cap, 8192), 256, 0, st>>>(l, s->st, s->evl, s->E, s->R, s->kb, s->in_s, s->key);
         } else {
-            k_eval_compact_bfs<<<wave_grid(cap * s->R, 16384), kBfsBlock, 0, st>>>(
+            k_eval_compact_bfs<<<wave_grid(cap * s->R, 65536), kBfsBlock, 0, st>>>(
                 l, s->st, s->evl, s->partial, gd, s->pm, s->K, s->R, cd, s->kb, s->in_s, s->key, s->ov, s->ov_cap);
             k_overflow_bfs<<<s->slots, 64, 0, st>>>(0, l, s->st, s->evl, s->partial, gd, s->pm, s->K, cd, s->kb,
                                                     s->in_s, s->key, s->ov, s->ov_cap, s->slot_q, s->slot_vis, s->n);
@@ -785,12 +785,12 @@ im_status enqueue_round_part(im_sketches *s, bool begin, uint32_t l0) {
     if (begin) k_round_begin<<<1, 64, 0, st>>>(td, s->st, s->ids, s->fr, s->evl, s->partial, pinit);
     eval(l0);
     for (uint32_t l = l0; l < td.D; ++l) {
-        k_check<<<wave_grid(td.lvl_n[l], 8192), 256, 0, st>>>(td, l, s->st, s->ids, s->key, s->fr, s->evl, s->partial,
+        k_check<<<wave_grid(td.lvl_n[l], 65536), 256, 0, st>>>(td, l, s->st, s->ids, s->key, s->fr, s->evl, s->partial,
                                                                 pinit);
         eval(l + 1);
     }
     for (int l = (int)td.D - 1; l >= 0; --l)
-        k_relink<<<wave_grid(td.lvl_n[l], 8192), 256, 0, st>>>(td, (uint32_t)l, s->st, s->ids, s->key, s->fr);
+        k_relink<<<wave_grid(td.lvl_n[l], 65536), 256, 0, st>>>(td, (uint32_t)l, s->st, s->ids, s->key, s->fr);
     k_round_end<<<1, 64, 0, st>>>(td, s->st, s->ids, s->key, s->in_s, s->kb, s->seeds_d, s->gains_d,
                                   s->evals_d, s->compact ? nullptr : s->E, s->R);
     if (s->compact) enqueue_markseed_compact(s);

@@ -31,7 +31,9 @@ constexpr uint32_t kPersistBlock = 256;
 constexpr uint32_t kPersistWaves = kPersistBlock / kWave;
 constexpr uint32_t kLeaderItems = 8 * kPersistWaves;  // larger steps go to the whole grid
 
-enum : uint32_t { kPhExit = 0, kPhCheck, kPhRelink, kPhEvalFull, kPhEvalCompact, kPhOverflow, kPhMarkseed };
+enum : uint32_t {
+    kPhExit = 0, kPhCheck, kPhRelink, kPhEvalFull, kPhEvalCompact, kPhOverflow, kPhMarkseed, kPhMarkEvalRoot
+};
 
 struct PersistCtl {
     uint32_t gen;   // generation of the published step
@@ -114,6 +116,10 @@ __device__ __forceinline__ void persist_step(const PersistArgs &a, uint32_t kind
         break;
     case kPhMarkseed:
         markseed_compact_level(a.st, a.g, a.pm, a.K, a.R, a.cd, a.in_s, a.ov, a.ov_cap, q, hs, wi, wc);
+        break;
+    case kPhMarkEvalRoot:
+        markseed_eval_root_level(a.st, a.evl, a.partial, a.g, a.pm, a.K, a.R, a.cd, a.kb, a.in_s, a.key, a.ov,
+                                 a.ov_cap, q, hs, wi, wc);
         break;
     default:
         break;
@@ -200,13 +206,29 @@ __global__ void __launch_bounds__(kPersistBlock) k_select_persist(PersistArgs a)
         return true;
     };
 
+    // CompactSketch: a round's MarkSeed is deferred into the next round's first
+    // step (the root's evaluation) when that round runs in this launch.
+    auto markseed_step = [&]() {
+        grid_step(kPhMarkseed, 0, 0);
+        if (ok && uniform_read(&a.st->ov_cnt[kMaxLevels + 1])) grid_step(kPhOverflow, kMaxLevels + 1, 1);
+    };
+    const bool fuse = !a.E && (uint64_t)a.R <= a.max_step_tasks;
+    bool mark_pending = false;
+
     if (tid == 0) a.st->stop_level = kNone;
     __syncthreads();
     for (uint32_t r = 0; r < a.max_rounds && ok; ++r) {
         if (tid == 0) round_begin_one(a.td, a.st, a.ids, a.fr, a.evl, a.E ? nullptr : a.partial, a.pinit);
         __syncthreads();
         uint32_t pending = kNone;
-        if (!eval_step(0)) pending = 0;
+        if (mark_pending) {
+            mark_pending = false;
+            grid_step(kPhMarkEvalRoot, 0, 0);
+            if (ok && uniform_read(&a.st->ov_cnt[kMaxLevels + 1])) grid_step(kPhOverflow, kMaxLevels + 1, 1);
+            if (ok && uniform_read(&a.st->ov_cnt[0])) grid_step(kPhOverflow, 0, 0);
+        } else if (!eval_step(0)) {
+            pending = 0;
+        }
         for (uint32_t l = 0; l < a.td.D && pending == kNone && ok; ++l) {
             tree_step(kPhCheck, l);
             if (!eval_step(l + 1)) pending = l + 1;
@@ -220,10 +242,7 @@ __global__ void __launch_bounds__(kPersistBlock) k_select_persist(PersistArgs a)
         if (w == 0) round_end_wave(a.td, a.st, a.ids, a.key, a.in_s, a.kb, a.seeds_out, a.gains_out, a.evals_out, a.E,
                                    a.R);
         __syncthreads();
-        if (!a.E) {
-            grid_step(kPhMarkseed, 0, 0);
-            if (ok && uniform_read(&a.st->ov_cnt[kMaxLevels + 1])) grid_step(kPhOverflow, kMaxLevels + 1, 1);
-        }
+        bool stop = r + 1 >= a.max_rounds;
         if (a.bulk_gain_min) {
             __syncthreads();  // every wave has read sh_val's previous value
             if (tid == 0) {
@@ -231,8 +250,13 @@ __global__ void __launch_bounds__(kPersistBlock) k_select_persist(PersistArgs a)
                 sh_val = a.gains_out[rd - 1] >= a.bulk_gain_min ? 1u : 0u;
             }
             __syncthreads();
-            if (sh_val) break;
+            stop = stop || sh_val != 0;
         }
+        if (!a.E) {
+            if (fuse && !stop) mark_pending = true;
+            else markseed_step();
+        }
+        if (stop) break;
     }
     grid_step(kPhExit, 0, 0);
 }

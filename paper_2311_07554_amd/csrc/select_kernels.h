@@ -50,12 +50,24 @@ struct SelState {
 // ---- Marginal on full labels ------------------------------------------------
 // E[v][r] = (label, size-at-label).  Uncovered size of v in sketch r is the
 // size field of the label's own entry, zeroed by MarkSeed.
+// Four row entries per lane are loaded before their label gathers, so a wave has
+// all of them in flight at once.
 __device__ __forceinline__ uint64_t marginal_full(const uint2 *__restrict__ E, uint32_t R, uint32_t v) {
+    constexpr int U = 4;
     const uint2 *row = E + (size_t)v * R;
     uint64_t s = 0;
-    for (uint32_t r = lane_id(); r < R; r += kWave) {
-        const uint2 e = row[r];
-        s += (e.x == v) ? e.y : E[(size_t)e.x * R + r].y;
+    for (uint32_t r0 = lane_id(); r0 < R; r0 += U * kWave) {
+        uint2 e[U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            const uint32_t r = r0 + i * kWave;
+            e[i] = r < R ? row[r] : make_uint2(v, 0u);
+        }
+        uint32_t y[U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) y[i] = (e[i].x == v) ? e[i].y : E[(size_t)e[i].x * R + r0 + i * kWave].y;
+#pragma unroll
+        for (int i = 0; i < U; ++i) s += y[i];
     }
     return wave_sum_u64(s);
 }
