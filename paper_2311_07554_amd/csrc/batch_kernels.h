@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(256) k_bat_compress(const BatchQuery *__restri
     if (lane == 0 && hot && hot_cnt) atomicAdd(reinterpret_cast<uint32_t *>(hot), hot_cnt);
 }
 
-// One block of 256 threads per (query, 64-vertex tile); the R sketches are
+// One block of 256 threads per (query, kEmitTile-vertex tile); the R sketches are
 // staged 64 at a time in LDS so E row segments are written by consecutive lanes.
 __global__ void __launch_bounds__(256) k_bat_emit(const BatchQuery *__restrict__ qs, uint32_t nq,
                                                   const uint64_t *__restrict__ pre_tiles) {

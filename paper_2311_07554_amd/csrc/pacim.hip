@@ -1382,7 +1382,7 @@ extern "C" im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_
         pre[q + 1] = pre[q] + (uint64_t)B.R * B.n;                                          // (sketch, vertex)
         const uint64_t hook = (uint64_t)((B.R + 63) / 64) * B.m;
         pre[(nq + 1) + q + 1] = pre[(nq + 1) + q] + ((hook + 63) & ~63ull);                 // (pass, edge), wave-padded
-        pre[2 * (nq + 1) + q + 1] = pre[2 * (nq + 1) + q] + (B.n + kEmitTile - 1) / kEmitTile;  // 64-vertex tiles
+        pre[2 * (nq + 1) + q + 1] = pre[2 * (nq + 1) + q] + (B.n + kEmitTile - 1) / kEmitTile;  // vertex tiles
         pre[3 * (nq + 1) + q + 1] = pre[3 * (nq + 1) + q] + prep_items(B);                       // prepare items
         for (uint32_t j = 0; j < Dmax; ++j) {                                                        // tree level j
             const uint64_t nodes = j < B.td.D ? B.td.lvl_n[B.td.D - 1 - j] : 0;

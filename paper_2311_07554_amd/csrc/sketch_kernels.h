@@ -229,39 +229,44 @@ __global__ void __launch_bounds__(256) k_compress(uint32_t *__restrict__ parent,
     }
 }
 
-// One block of 256 threads per tile of 64 vertices; B <= 64.  The (label, size)
-// entries of the tile are staged in LDS so that each E row segment
-// E[v][r0 .. r0+B) is written by consecutive lanes.
-constexpr int kEmitTile = 64;
+// One block of 256 threads per tile of 32 vertices; B <= 64.  The (label, size)
+// entries of the tile are staged in LDS (17 KB, so that many blocks share a CU)
+// and each E row segment E[v][r0 .. r0+B) is written by consecutive lanes.
+// Thread t reads the entries of vertex t % 32 in sketches t / 32, t / 32 + 8, ...
+// and keeps their sizes' sum for the initial gains.
+constexpr int kEmitTile = 32;
+constexpr int kEmitGroups = 256 / kEmitTile;
 __global__ void __launch_bounds__(256) k_emit_full(const uint32_t *__restrict__ parent,
                                                    const uint32_t *__restrict__ cnt, uint32_t n, uint32_t B,
                                                    uint32_t R, uint32_t r0, uint2 *__restrict__ E,
                                                    uint64_t *__restrict__ gain0) {
     __shared__ uint2 tile[kEmitTile][65];
-    __shared__ uint32_t gsz[kEmitTile][65];
+    __shared__ uint64_t part[kEmitGroups][kEmitTile];
     const uint32_t v0 = blockIdx.x * kEmitTile;
-    for (uint32_t idx = threadIdx.x; idx < kEmitTile * B; idx += blockDim.x) {
-        const uint32_t b = idx / kEmitTile, vi = idx % kEmitTile, v = v0 + vi;
-        if (v < n) {
-            const size_t base = (size_t)b * sketch_stride(n);
+    const uint32_t vi = threadIdx.x % kEmitTile, grp = threadIdx.x / kEmitTile, v = v0 + vi;
+    const size_t ns = sketch_stride(n);
+    uint64_t acc = 0;
+    if (v < n) {
+#pragma unroll 4
+        for (uint32_t b = grp; b < B; b += kEmitGroups) {
+            const size_t base = (size_t)b * ns;
             const uint32_t root = parent[base + v];
-            const uint32_t s = 1u + cnt[base + root];
-            tile[vi][b] = make_uint2(root, root == v ? s : 0u);
-            gsz[vi][b] = s;
+            const uint32_t sz = 1u + cnt[base + root];
+            tile[vi][b] = make_uint2(root, root == v ? sz : 0u);
+            acc += sz;
         }
     }
+    part[grp][vi] = acc;
     __syncthreads();
     for (uint32_t idx = threadIdx.x; idx < kEmitTile * B; idx += blockDim.x) {
-        const uint32_t vi = idx / B, b = idx % B, v = v0 + vi;
-        if (v < n) E[(size_t)v * R + r0 + b] = tile[vi][b];
+        const uint32_t ti = idx / B, b = idx % B, tv = v0 + ti;
+        if (tv < n) E[(size_t)tv * R + r0 + b] = tile[ti][b];
     }
-    if (threadIdx.x < kEmitTile) {
-        const uint32_t v = v0 + threadIdx.x;
-        if (v < n) {
-            uint64_t s = 0;
-            for (uint32_t b = 0; b < B; ++b) s += gsz[threadIdx.x][b];
-            gain0[v] += s;
-        }
+    if (threadIdx.x < kEmitTile && v0 + threadIdx.x < n) {
+        uint64_t s = 0;
+#pragma unroll
+        for (int g = 0; g < kEmitGroups; ++g) s += part[g][threadIdx.x];
+        gain0[v0 + threadIdx.x] += s;
     }
 }
 
