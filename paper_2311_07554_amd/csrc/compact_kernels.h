@@ -37,6 +37,7 @@ struct CompactDev {
     const uint32_t *label_c;       // [R][rho]
     uint32_t *size_c;              // [R][rho]
     uint32_t rho;
+    uint64_t kc, Ta;               // center test: mix64(v ^ kc) < Ta (a hash, no memory access)
 };
 
 struct BfsOut {
@@ -59,8 +60,7 @@ __device__ BfsOut getcenter_lds(const GraphDev &g, const ProbDev &pm, uint64_t k
                                 uint32_t r, const uint8_t *__restrict__ in_s, uint32_t v, uint32_t *q,
                                 uint32_t *hs) {
     const uint32_t lane = lane_id();
-    const uint32_t cr0 = cd.center_rank[v];
-    if (cr0 != kNone) return center_hit(cd, r, cr0);
+    if (center_flag(v, cd.kc, cd.Ta)) return center_hit(cd, r, cd.center_rank[v]);
     for (uint32_t i = lane; i < kHCap; i += kWave) hs[i] = kNone;
     __builtin_amdgcn_wave_barrier();
     if (lane == 0) {
@@ -83,10 +83,9 @@ __device__ BfsOut getcenter_lds(const GraphDev &g, const ProbDev &pm, uint64_t k
                 const uint64_t x = edge_word(u, w);
                 live = is_live(x, kr, edge_threshold(pm, x));
             }
-            const uint32_t wr = live ? cd.center_rank[w] : kNone;
-            const uint64_t cm = __ballot(wr != kNone);
+            const uint64_t cm = __ballot(live && center_flag(w, cd.kc, cd.Ta));
             if (cm) {
-                found = __shfl(wr, (int)__builtin_ctzll(cm));
+                found = cd.center_rank[__shfl(w, (int)__builtin_ctzll(cm))];
                 break;
             }
             bool ins = false;
@@ -118,8 +117,7 @@ __device__ BfsOut getcenter_global(const GraphDev &g, const ProbDev &pm, uint64_
                                    uint32_t r, const uint8_t *__restrict__ in_s, uint32_t v, uint32_t *gq,
                                    uint32_t *gvis) {
     const uint32_t lane = lane_id();
-    const uint32_t cr0 = cd.center_rank[v];
-    if (cr0 != kNone) return center_hit(cd, r, cr0);
+    if (center_flag(v, cd.kc, cd.Ta)) return center_hit(cd, r, cd.center_rank[v]);
     if (lane == 0) {
         gq[0] = v;
         atomicOr(&gvis[v >> 5], 1u << (v & 31));
@@ -141,10 +139,9 @@ __device__ BfsOut getcenter_global(const GraphDev &g, const ProbDev &pm, uint64_
                 const uint64_t x = edge_word(u, w);
                 live = is_live(x, kr, edge_threshold(pm, x));
             }
-            const uint32_t wr = live ? cd.center_rank[w] : kNone;
-            const uint64_t cm = __ballot(wr != kNone);
+            const uint64_t cm = __ballot(live && center_flag(w, cd.kc, cd.Ta));
             if (cm) {
-                found = __shfl(wr, (int)__builtin_ctzll(cm));
+                found = cd.center_rank[__shfl(w, (int)__builtin_ctzll(cm))];
                 break;
             }
             bool ins = false;

@@ -85,6 +85,7 @@ struct im_sketches {
     ProbDev pm{};
     uint32_t kb = 1;
     uint32_t rho = 0;
+    uint64_t kc = 0, Ta = 0;  // center test of CompactSketch: mix64(v ^ kc) < Ta
     uint32_t B = 1;
     // arrays
     uint64_t *K = nullptr;
@@ -640,15 +641,20 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
     } while (0)
 
     SK_HIP(hipEventRecord(t0, st));
-    // keys of sketches 0 .. Rpad-1 (the sampling kernel reads them 8 at a time), then K(0, SALT_TRIV)
+    // keys of sketches 0 .. Rpad-1 (the sampling kernel reads them 8 at a time), then
+    // K(0, SALT_TRIV) and K(seed, SALT_CENTER)
     const uint32_t Rpad = key_slots(R);
-    SK_TRY(sk_alloc(s, (size_t)Rpad + 1, &s->K));
+    SK_TRY(sk_alloc(s, (size_t)Rpad + 2, &s->K));
     k_sketch_keys<<<grid_for(Rpad, 256, 1u << 20), 256, 0, st>>>(seed, Rpad, s->K);
     k_salt_key<<<1, 64, 0, st>>>(0, kSaltTriv, s->K + Rpad);
+    k_salt_key<<<1, 64, 0, st>>>(seed, kSaltCenter, s->K + Rpad + 1);
     SK_HIP(hipGetLastError());
-    // the trivalency key is read back once (8 bytes) so it can travel by value
-    SK_HIP(hipMemcpyAsync(&s->pm.ktriv, s->K + Rpad, 8, hipMemcpyDeviceToHost, st));
+    // the two salt keys are read back once so they can travel by value
+    uint64_t salts[2] = {0, 0};
+    SK_HIP(hipMemcpyAsync(salts, s->K + Rpad, 16, hipMemcpyDeviceToHost, st));
     SK_HIP(hipStreamSynchronize(st));
+    s->pm.ktriv = salts[0];
+    s->kc = salts[1];
 
     // centers (CompactSketch)
     if (s->compact) {
@@ -658,6 +664,7 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
         SK_TRY(sk_alloc(s, 1, &rho_d));
         SK_TRY(sk_alloc(s, n, &s->center_rank));
         const uint64_t Ta = threshold_of(alpha);
+        s->Ta = Ta;
         k_center_count<<<nch, 256, 0, st>>>(n, seed, Ta, chunk);
         k_center_scan<<<1, 1024, 0, st>>>(nch, chunk, rho_d);
         uint32_t rho = 0;
@@ -754,7 +761,7 @@ namespace {
 void enqueue_markseed_compact(im_sketches *s) {
     hipStream_t st = s->ctx->stream;
     GraphDev gd{s->g->off, s->g->cols};
-    CompactDev cd{s->center_rank, s->label_c, s->size_c, s->rho};
+    CompactDev cd{s->center_rank, s->label_c, s->size_c, s->rho, s->kc, s->Ta};
     k_markseed_compact<<<wave_grid(s->R, 4096), kBfsBlock, 0, st>>>(s->st, gd, s->pm, s->K, s->R, cd, s->in_s, s->ov,
                                                                      s->ov_cap);
     k_overflow_bfs<<<s->slots, 64, 0, st>>>(1, kMaxLevels + 1, s->st, s->evl, s->partial, gd, s->pm, s->K, cd, s->kb,
@@ -769,7 +776,7 @@ im_status enqueue_round_part(im_sketches *s, bool begin, uint32_t l0) {
     hipStream_t st = ctx->stream;
     const TreeDesc &td = s->td;
     GraphDev gd{s->g->off, s->g->cols};
-    CompactDev cd{s->center_rank, s->label_c, s->size_c, s->rho};
+    CompactDev cd{s->center_rank, s->label_c, s->size_c, s->rho, s->kc, s->Ta};
     const unsigned long long pinit = (unsigned long long)s->R << kPartialShift;
     auto eval = [&](uint32_t l) {
         uint64_t cap = (l == 0) ? 1 : std::min<uint64_t>((uint64_t)s->n, (uint64_t)td.lvl_n[l - 1] * kFan);
@@ -842,7 +849,7 @@ im_status run_persistent_rounds(im_sketches *s, uint32_t max_rounds, unsigned lo
     a.g = GraphDev{s->g->off, s->g->cols};
     a.pm = s->pm;
     a.K = s->K;
-    a.cd = CompactDev{s->center_rank, s->label_c, s->size_c, s->rho};
+    a.cd = CompactDev{s->center_rank, s->label_c, s->size_c, s->rho, s->kc, s->Ta};
     a.ov = s->ov;
     a.ov_cap = s->ov_cap;
     a.slot_q = s->slot_q;
