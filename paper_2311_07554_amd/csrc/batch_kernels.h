@@ -136,16 +136,28 @@ __device__ __forceinline__ uint64_t marginal_cov(const uint2 *__restrict__ E, ui
     return wave_sum_u64(s);
 }
 
+// (sketch, vertex) items: each query's R rows of n vertices are padded to whole
+// waves (npad = n rounded up to 64), so a wave never straddles two rows and finds
+// its query and sketch once.
+__device__ __forceinline__ uint32_t row_pad(uint32_t n) { return (n + 63u) & ~63u; }
+
 __global__ void __launch_bounds__(256) k_bat_init(const BatchQuery *__restrict__ qs, uint32_t nq,
                                                   const uint64_t *__restrict__ pre_vn,
                                                   uint32_t *__restrict__ next_q) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *next_q = 0;
     const uint64_t total = pre_vn[nq], stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-        const uint32_t q = find_query(pre_vn, nq, i);
-        const uint64_t local = i - pre_vn[q];
-        qs[q].parent[local] = (uint32_t)(local % qs[q].n);
-        qs[q].cnt[local] = 0;
+        const uint64_t i0 = i & ~63ull;
+        const uint32_t q = (uint32_t)__builtin_amdgcn_readfirstlane((int)find_query(pre_vn, nq, i0));
+        const BatchQuery &Q = qs[q];
+        const uint32_t npad = row_pad(Q.n);
+        const uint64_t wl = i0 - pre_vn[q];
+        const uint32_t b = (uint32_t)(wl / npad);
+        const uint32_t v = (uint32_t)(wl - (uint64_t)b * npad) + lane_id();
+        if (v < Q.n) {
+            Q.parent[(size_t)b * Q.n + v] = v;
+            Q.cnt[(size_t)b * Q.n + v] = 0;
+        }
     }
 }
 
@@ -184,9 +196,10 @@ __global__ void __launch_bounds__(1024) k_bat_hook(const BatchQuery *__restrict_
     }
 }
 
-// Roots and member counts.  A wave may straddle two (query, sketch) segments, so
-// lanes are grouped by the address of their root's counter; each wave keeps one
-// hot counter (in practice a giant component's root) in a register.
+// Roots and member counts, one wave per 64 vertices of one (query, sketch) row.
+// Each wave keeps one hot counter (in practice a giant component's root) in a
+// register, across rows (it is an address); members of other roots are
+// combined per distinct root in the wave and added with one atomic per root.
 __global__ void __launch_bounds__(256) k_bat_compress(const BatchQuery *__restrict__ qs, uint32_t nq,
                                                       const uint64_t *__restrict__ pre_vn) {
     const uint32_t lane = lane_id();
@@ -194,19 +207,20 @@ __global__ void __launch_bounds__(256) k_bat_compress(const BatchQuery *__restri
     unsigned long long hot = 0;
     uint32_t hot_cnt = 0;
     for (uint64_t wb = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~63ull; wb < total; wb += stride) {
-        const uint64_t i = wb + lane;
+        const uint32_t q = (uint32_t)__builtin_amdgcn_readfirstlane((int)find_query(pre_vn, nq, wb));
+        const BatchQuery &Q = qs[q];
+        const uint32_t n = Q.n, npad = row_pad(n);
+        const uint64_t wl = wb - pre_vn[q];
+        const uint32_t b = (uint32_t)(wl / npad);
+        const uint32_t v = (uint32_t)(wl - (uint64_t)b * npad) + lane;
+        uint32_t *P = Q.parent + (size_t)b * n;
         unsigned long long target = 0;
-        if (i < total) {
-            const uint32_t q = find_query(pre_vn, nq, i);
-            const BatchQuery &Q = qs[q];
-            const uint64_t local = i - pre_vn[q];
-            const uint32_t b = (uint32_t)(local / Q.n), v = (uint32_t)(local - (uint64_t)b * Q.n);
-            uint32_t *P = Q.parent + (size_t)b * Q.n;
+        if (v < n) {
             uint32_t r = v, p = P[v];
             while (p != r) { r = p; p = P[r]; }
             if (r != v) {
                 P[v] = r;
-                target = (unsigned long long)(Q.cnt + (size_t)b * Q.n + r);
+                target = (unsigned long long)(Q.cnt + (size_t)b * n + r);
             }
         }
         bool need = target != 0;

@@ -1386,7 +1386,7 @@ extern "C" im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_
         B.seeds = reinterpret_cast<uint32_t *>(arena + o.seeds);
         B.gains = reinterpret_cast<unsigned long long *>(arena + o.gains);
         B.evals = reinterpret_cast<uint32_t *>(arena + o.evals);
-        pre[q + 1] = pre[q] + (uint64_t)B.R * B.n;                                          // (sketch, vertex)
+        pre[q + 1] = pre[q] + (uint64_t)B.R * ((B.n + 63) & ~63u);                          // (sketch, vertex), rows wave-padded
         const uint64_t hook = (uint64_t)((B.R + 63) / 64) * B.m;
         pre[(nq + 1) + q + 1] = pre[(nq + 1) + q] + ((hook + 63) & ~63ull);                 // (pass, edge), wave-padded
         pre[2 * (nq + 1) + q + 1] = pre[2 * (nq + 1) + q] + (B.n + kEmitTile - 1) / kEmitTile;  // vertex tiles
