@@ -699,9 +699,9 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
         if (s->compact) {
             Prof p(ctx, "emit");
             dim3 ge((std::max<uint32_t>(s->rho, 1) + 255) / 256, b);
-            if (s->rho) k_emit_compact<<<ge, 256, 0, st>>>(parent, cnt, minc, s->centers, s->rho, n, r0, s->label_c, s->size_c);
-            k_giant_root<<<dim3(std::min<uint32_t>((n + 255) / 256, 64u), b), 256, 0, st>>>(parent, cnt, n,
-                                                                                        s->gbest + r0);
+            if (s->rho)
+                k_emit_compact<<<ge, 256, 0, st>>>(parent, cnt, minc, s->centers, s->rho, n, r0, s->label_c, s->size_c,
+                                                   s->gbest + r0);
             k_gain0<<<(n + 255) / 256, 256, 0, st>>>(parent, cnt, n, b, s->gain0, s->gbest + r0,
                                                      s->gbits + (size_t)r0 * s->nw, s->nw);
         } else {

@@ -10,8 +10,8 @@
 //                     non-root members counted at the root; centers' smallest
 //                     rank recorded at the root (CompactSketch)
 //   k_emit_full       (label, size) per (v, r) into E[n][R] and the initial gains
-//   k_emit_compact    CompactSketch triple label_c / size_c [R][rho]
-//   k_giant_root      the largest component of each sketch (CompactSketch)
+//   k_emit_compact    CompactSketch triple label_c / size_c [R][rho], and the
+//                     largest component holding a center per sketch
 //   k_gain0           initial gains when only the compact triple is kept, and
 //                     the largest components' membership bitmaps
 //   k_center_*        hashed Bernoulli(alpha) centers, ranked by id
@@ -270,53 +270,48 @@ __global__ void __launch_bounds__(256) k_emit_full(const uint32_t *__restrict__ 
     }
 }
 
-// grid: (ceil(rho/256), B)
+// grid: (ceil(rho/256), B).  Also the sketch's largest component among those
+// holding a center (smallest root on equal sizes): gbest[b] = max of
+// (size << 32) | (2^32 - 1 - root), zeroed by the caller.  The largest component
+// of a sketch holds a center unless it is smaller than about 1/alpha; the
+// bitmap bulk rounds need some large component, not necessarily the largest.
 __global__ void __launch_bounds__(256) k_emit_compact(const uint32_t *__restrict__ parent,
                                                       const uint32_t *__restrict__ cnt,
                                                       const uint32_t *__restrict__ minc,
                                                       const uint32_t *__restrict__ centers, uint32_t rho,
                                                       uint32_t n, uint32_t r0, uint32_t *__restrict__ label_c,
-                                                      uint32_t *__restrict__ size_c) {
+                                                      uint32_t *__restrict__ size_c,
+                                                      unsigned long long *__restrict__ gbest) {
+    __shared__ unsigned long long best_w[256 / kWave];
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= rho) return;
     const uint32_t b = blockIdx.y;
-    const size_t base = (size_t)b * sketch_stride(n);
-    const uint32_t v = centers[i];
-    const uint32_t root = parent[base + v];
-    const uint32_t l = minc[base + root];
-    const size_t at = (size_t)(r0 + b) * rho + i;
-    label_c[at] = l;
-    size_c[at] = (l == i) ? 1u + cnt[base + root] : 0u;
-}
-
-// Largest component of each sketch of the pass, smallest root on equal sizes:
-// gbest[b] = max over roots of (size << 32) | (2^32 - 1 - root), zeroed by the
-// caller.  grid (G, B): the blocks of sketch blockIdx.y stride over its vertices.
-__device__ __forceinline__ uint32_t giant_root_of(uint64_t gbest) { return 0xFFFFFFFFu - (uint32_t)gbest; }
-__device__ __forceinline__ uint32_t giant_size_of(uint64_t gbest) { return (uint32_t)(gbest >> 32); }
-
-__global__ void __launch_bounds__(256) k_giant_root(const uint32_t *__restrict__ parent,
-                                                    const uint32_t *__restrict__ cnt, uint32_t n,
-                                                    unsigned long long *__restrict__ gbest) {
-    __shared__ uint64_t best_w[256 / kWave];
-    const size_t base = (size_t)blockIdx.y * sketch_stride(n);
-    uint64_t best = 0;
-    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-        if (parent[base + v] == v) {
-            const uint64_t k = ((uint64_t)(cnt[base + v] + 1u) << 32) | (uint64_t)(0xFFFFFFFFu - v);
-            best = k > best ? k : best;
-        }
+    unsigned long long best = 0;
+    if (i < rho) {
+        const size_t base = (size_t)b * sketch_stride(n);
+        const uint32_t v = centers[i];
+        const uint32_t root = parent[base + v];
+        const uint32_t l = minc[base + root];
+        const uint32_t sz = 1u + cnt[base + root];
+        const size_t at = (size_t)(r0 + b) * rho + i;
+        label_c[at] = l;
+        size_c[at] = (l == i) ? sz : 0u;
+        best = ((unsigned long long)sz << 32) | (0xFFFFFFFFull - root);
+    }
     best = wave_max_u64(best);
     if (lane_id() == 0) best_w[threadIdx.x / kWave] = best;
     __syncthreads();
     if (threadIdx.x == 0) {
         for (uint32_t w = 1; w < blockDim.x / kWave; ++w) best = best_w[w] > best ? best_w[w] : best;
-        if (best) atomicMax(&gbest[blockIdx.y], (unsigned long long)best);
+        if (best) atomicMax(&gbest[b], best);
     }
 }
 
+// The largest component recorded for a sketch, as packed by k_emit_compact.
+__device__ __forceinline__ uint32_t giant_root_of(uint64_t gbest) { return 0xFFFFFFFFu - (uint32_t)gbest; }
+__device__ __forceinline__ uint32_t giant_size_of(uint64_t gbest) { return (uint32_t)(gbest >> 32); }
+
 // Initial gains when only the compact triple is kept, and (gbits non-null) the
-// membership bitmap of each sketch's largest component: bit v of
+// membership bitmap of each sketch's recorded largest component: bit v of
 // gbits[b][v / 64] = [v lies in the component rooted at giant_root_of(gbest[b])].
 __global__ void __launch_bounds__(256) k_gain0(const uint32_t *__restrict__ parent, const uint32_t *__restrict__ cnt,
                                                uint32_t n, uint32_t B, uint64_t *__restrict__ gain0,
