@@ -77,13 +77,18 @@ im_status im_ctx_create(int device, void *hip_stream, size_t hbm_cap, im_ctx **o
 im_status im_ctx_destroy(im_ctx *ctx);
 /* Text of the last error on ctx ("" if none).  Valid until the next call on ctx. */
 const char *im_last_error(const im_ctx *ctx);
-/* Bytes of device memory the context currently holds. */
+/* Bytes of device memory the context's live objects hold (used) and its cap.
+ * Blocks freed by the library are kept for reuse by later requests of the same
+ * size (up to 48 GB, and within the cap together with used); they are released
+ * when an allocation fails, when the cap needs them, and by im_ctx_destroy. */
 im_status im_ctx_memory(const im_ctx *ctx, size_t *used, size_t *cap);
 /* Turns per-kernel HIP-event timing on (1) or off (0); see im_kernel_time. */
 im_status im_ctx_set_profiling(im_ctx *ctx, int on);
 /* Accumulated launches and milliseconds of one kernel family since profiling was
- * turned on: "sample_hook", "compress", "emit", "marginal", "select_round", ...
- * Unknown names give count 0. */
+ * turned on: "sample_hook" (sampling and hooking pass), "compress" (pointer
+ * jumping and counting), "emit" (full labels, or the compact triple and initial
+ * gains), "select" (a whole im_select_seeds_from call).  Unknown names give
+ * count 0. */
 im_status im_kernel_time(im_ctx *ctx, const char *name, uint64_t *launches, double *ms);
 
 /* ---- graph ---------------------------------------------------------------- */

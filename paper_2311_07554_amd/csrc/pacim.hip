@@ -155,6 +155,8 @@ im_status dev_alloc(im_ctx *ctx, size_t bytes, void **p) {
     if (ctx->cap && ctx->used + bytes > ctx->cap)
         return fail(ctx, IM_ENOMEM, "allocation of " + std::to_string(bytes) + " bytes exceeds the context HBM cap");
     auto it = ctx->cache.find(bytes);
+    // cached blocks count against the cap too: past it, they are given back first
+    if (ctx->cap && it == ctx->cache.end() && ctx->used + ctx->cached + bytes > ctx->cap) release_cache_locked(ctx);
     if (it != ctx->cache.end()) {
         *p = it->second;
         ctx->cache.erase(it);
@@ -182,7 +184,7 @@ void dev_free(im_ctx *ctx, void *p, size_t bytes) {
     bytes = alloc_size(bytes);
     std::lock_guard<std::mutex> lk(ctx->alloc_mu);
     ctx->used -= std::min(ctx->used, bytes);
-    if (ctx->cached + bytes <= kCacheLimit) {
+    if (ctx->cached + bytes <= kCacheLimit && (!ctx->cap || ctx->used + ctx->cached + bytes <= ctx->cap)) {
         ctx->cache.emplace(bytes, p);
         ctx->cached += bytes;
     } else {
