@@ -38,7 +38,22 @@ struct CompactDev {
     uint32_t *size_c;              // [R][rho]
     uint32_t rho;
     uint64_t kc, Ta;               // center test: mix64(v ^ kc) < Ta (a hash, no memory access)
+    unsigned long long *memo;      // [slots][R] GetCenter labels: (v << 32) | label, ~0 if empty
+    uint32_t memo_mask;            // slots - 1 (slots a power of two)
+    uint32_t R;
 };
+
+// GetCenter's label for (v, r) never changes (a sketch's components are fixed;
+// only their compact sizes are zeroed), so the labels a search found are kept,
+// direct-mapped by vertex, and a later search from the same vertex in the same
+// sketch (a re-evaluation, or MarkSeed from the vertex just chosen) reads the
+// size at the kept label instead.  An entry holds its vertex id, so a slot taken
+// over by another vertex is simply a miss.  Components without a center are not
+// kept (their result depends on the seeds met).
+__device__ __forceinline__ unsigned long long *memo_entry(const CompactDev &cd, uint32_t v, uint32_t r) {
+    const uint32_t slot = (v * 0x9E3779B1u ^ (v >> 16)) & cd.memo_mask;
+    return cd.memo + (size_t)slot * cd.R + r;
+}
 
 struct BfsOut {
     uint64_t delta;
@@ -166,6 +181,37 @@ __device__ BfsOut getcenter_global(const GraphDev &g, const ProbDev &pm, uint64_
     return BfsOut{met ? 0ull : (uint64_t)tail, kNone, false};
 }
 
+// GetCenter through the kept labels (all lanes take part; lane 0 writes).
+__device__ __forceinline__ BfsOut getcenter_memo_lds(const GraphDev &g, const ProbDev &pm, uint64_t kr,
+                                                     const CompactDev &cd, uint32_t r, const uint8_t *in_s, uint32_t v,
+                                                     uint32_t *q, uint32_t *hs) {
+    unsigned long long *e = memo_entry(cd, v, r);
+    const unsigned long long x = __hip_atomic_load(e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint32_t)(x >> 32) == v) {
+        const uint32_t l = (uint32_t)x;
+        return BfsOut{cd.size_c[(size_t)r * cd.rho + l], l, false};
+    }
+    const BfsOut o = getcenter_lds(g, pm, kr, cd, r, in_s, v, q, hs);
+    if (!o.overflow && o.label != kNone && lane_id() == 0)
+        __hip_atomic_store(e, ((unsigned long long)v << 32) | o.label, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return o;
+}
+
+__device__ __forceinline__ BfsOut getcenter_memo_global(const GraphDev &g, const ProbDev &pm, uint64_t kr,
+                                                        const CompactDev &cd, uint32_t r, const uint8_t *in_s,
+                                                        uint32_t v, uint32_t *gq, uint32_t *gvis) {
+    unsigned long long *e = memo_entry(cd, v, r);
+    const unsigned long long x = __hip_atomic_load(e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint32_t)(x >> 32) == v) {
+        const uint32_t l = (uint32_t)x;
+        return BfsOut{cd.size_c[(size_t)r * cd.rho + l], l, false};
+    }
+    const BfsOut o = getcenter_global(g, pm, kr, cd, r, in_s, v, gq, gvis);
+    if (o.label != kNone && lane_id() == 0)
+        __hip_atomic_store(e, ((unsigned long long)v << 32) | o.label, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return o;
+}
+
 // The overflow list holds ov_cap tasks: evaluation searches in its first half,
 // MarkSeed searches in its second, so that one step may produce both.
 __device__ __forceinline__ uint2 *mark_list(uint2 *ov, uint32_t ov_cap) { return ov + ov_cap / 2; }
@@ -207,7 +253,7 @@ __device__ __forceinline__ void eval_compact_level(uint32_t l, SelState *st, con
     for (uint64_t task = wi; task < total; task += wc) {
         const uint32_t r = (uint32_t)(task / ne), e = (uint32_t)(task % ne);
         const uint32_t v = evl[e];
-        const BfsOut o = getcenter_lds(g, pm, K[r], cd, r, in_s, v, q, hs);
+        const BfsOut o = getcenter_memo_lds(g, pm, K[r], cd, r, in_s, v, q, hs);
         if (lane_id() == 0) {
             if (o.overflow) push_overflow(st, &st->ov_cnt[l], ov, ov_cap / 2, e, r);
             else add_delta(st, partial, e, o.delta, evl, kb, in_s, key);
@@ -233,7 +279,7 @@ __device__ __forceinline__ void overflow_level(int mode, uint32_t slot, SelState
         const uint2 t = list[i];
         const uint32_t r = t.y;
         const uint32_t v = (mode == 0) ? evl[t.x] : st->last_seed;
-        const BfsOut o = getcenter_global(g, pm, K[r], cd, r, in_s, v, gq, gvis);
+        const BfsOut o = getcenter_memo_global(g, pm, K[r], cd, r, in_s, v, gq, gvis);
         if (lane_id() == 0) {
             if (mode == 0) add_delta(st, partial, t.x, o.delta, evl, kb, in_s, key);
             else if (o.label != kNone) cd.size_c[(size_t)r * cd.rho + o.label] = 0;
@@ -248,7 +294,7 @@ __device__ __forceinline__ void markseed_compact_level(SelState *st, const Graph
                                                        uint32_t *hs, uint32_t wi, uint32_t wc) {
     const uint32_t s = st->last_seed;
     for (uint32_t r = wi; r < R; r += wc) {
-        const BfsOut o = getcenter_lds(g, pm, K[r], cd, r, in_s, s, q, hs);
+        const BfsOut o = getcenter_memo_lds(g, pm, K[r], cd, r, in_s, s, q, hs);
         if (lane_id() == 0) {
             if (o.overflow) push_overflow(st, &st->ov_cnt[kMaxLevels + 1], mark_list(ov, ov_cap), ov_cap / 2, s, r);
             else if (o.label != kNone) cd.size_c[(size_t)r * cd.rho + o.label] = 0;
@@ -270,7 +316,7 @@ __device__ __forceinline__ void markseed_eval_root_level(SelState *st, const uin
     const uint32_t s = st->last_seed;
     const uint32_t v = evl[0];
     for (uint32_t r = wi; r < R; r += wc) {
-        const BfsOut m = getcenter_lds(g, pm, K[r], cd, r, in_s, s, q, hs);
+        const BfsOut m = getcenter_memo_lds(g, pm, K[r], cd, r, in_s, s, q, hs);
         if (m.overflow) {
             if (lane_id() == 0) {
                 push_overflow(st, &st->ov_cnt[kMaxLevels + 1], mark_list(ov, ov_cap), ov_cap / 2, s, r);
@@ -281,7 +327,7 @@ __device__ __forceinline__ void markseed_eval_root_level(SelState *st, const uin
         if (lane_id() == 0 && m.label != kNone) cd.size_c[(size_t)r * cd.rho + m.label] = 0;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();
-        const BfsOut o = getcenter_lds(g, pm, K[r], cd, r, in_s, v, q, hs);
+        const BfsOut o = getcenter_memo_lds(g, pm, K[r], cd, r, in_s, v, q, hs);
         if (lane_id() == 0) {
             if (o.overflow) push_overflow(st, &st->ov_cnt[0], ov, ov_cap / 2, 0, r);
             else add_delta(st, partial, 0, o.delta, evl, kb, in_s, key);

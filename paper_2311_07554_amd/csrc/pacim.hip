@@ -86,6 +86,8 @@ struct im_sketches {
     uint32_t kb = 1;
     uint32_t rho = 0;
     uint64_t kc = 0, Ta = 0;  // center test of CompactSketch: mix64(v ^ kc) < Ta
+    unsigned long long *memo = nullptr;  // kept GetCenter labels, [memo_mask + 1][R]
+    uint32_t memo_mask = 0;
     uint32_t B = 1;
     // arrays
     uint64_t *K = nullptr;
@@ -683,6 +685,11 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
         SK_HIP(hipMemsetAsync(s->gbest, 0, (size_t)R * 8, st));
         SK_TRY(sk_alloc(s, R, &s->gcov));
         SK_TRY(sk_alloc(s, 1, &s->bulk_abort));
+        uint32_t slots = 64;
+        while (slots < n && slots < 4096) slots <<= 1;
+        s->memo_mask = slots - 1;
+        SK_TRY(sk_alloc(s, (size_t)slots * R, &s->memo));
+        SK_HIP(hipMemsetAsync(s->memo, 0xFF, (size_t)slots * R * 8, st));
     } else {
         s->rho = n;
         SK_TRY(sk_alloc(s, (size_t)n * R, &s->E));
@@ -763,7 +770,7 @@ namespace {
 void enqueue_markseed_compact(im_sketches *s) {
     hipStream_t st = s->ctx->stream;
     GraphDev gd{s->g->off, s->g->cols};
-    CompactDev cd{s->center_rank, s->label_c, s->size_c, s->rho, s->kc, s->Ta};
+    CompactDev cd{s->center_rank, s->label_c, s->size_c, s->rho, s->kc, s->Ta, s->memo, s->memo_mask, s->R};
     k_markseed_compact<<<wave_grid(s->R, 4096), kBfsBlock, 0, st>>>(s->st, gd, s->pm, s->K, s->R, cd, s->in_s, s->ov,
                                                                      s->ov_cap);
     k_overflow_bfs<<<s->slots, 64, 0, st>>>(1, kMaxLevels + 1, s->st, s->evl, s->partial, gd, s->pm, s->K, cd, s->kb,
@@ -778,7 +785,7 @@ im_status enqueue_round_part(im_sketches *s, bool begin, uint32_t l0) {
     hipStream_t st = ctx->stream;
     const TreeDesc &td = s->td;
     GraphDev gd{s->g->off, s->g->cols};
-    CompactDev cd{s->center_rank, s->label_c, s->size_c, s->rho, s->kc, s->Ta};
+    CompactDev cd{s->center_rank, s->label_c, s->size_c, s->rho, s->kc, s->Ta, s->memo, s->memo_mask, s->R};
     const unsigned long long pinit = (unsigned long long)s->R << kPartialShift;
     auto eval = [&](uint32_t l) {
         uint64_t cap = (l == 0) ? 1 : std::min<uint64_t>((uint64_t)s->n, (uint64_t)td.lvl_n[l - 1] * kFan);
@@ -851,7 +858,7 @@ im_status run_persistent_rounds(im_sketches *s, uint32_t max_rounds, unsigned lo
     a.g = GraphDev{s->g->off, s->g->cols};
     a.pm = s->pm;
     a.K = s->K;
-    a.cd = CompactDev{s->center_rank, s->label_c, s->size_c, s->rho, s->kc, s->Ta};
+    a.cd = CompactDev{s->center_rank, s->label_c, s->size_c, s->rho, s->kc, s->Ta, s->memo, s->memo_mask, s->R};
     a.ov = s->ov;
     a.ov_cap = s->ov_cap;
     a.slot_q = s->slot_q;
@@ -865,7 +872,9 @@ im_status run_persistent_rounds(im_sketches *s, uint32_t max_rounds, unsigned lo
     a.ctl = s->ctl;
     a.spin_ticks = 120ull * ctx->clock_hz;  // two minutes
     void *args[] = {&a};
-    const unsigned grid = s->compact ? ctx->persist_grid : 1u;
+    // CompactSketch: about one wave per sketch (the GetCenter steps have R searches
+    // per listed vertex); every extra workgroup costs each step a completion.
+    const unsigned grid = s->compact ? std::min<unsigned>(ctx->persist_grid, std::max<unsigned>(8u, (s->R + kPersistWaves - 1) / kPersistWaves)) : 1u;
     HIP_TRY(ctx, hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_select_persist), dim3(grid),
                                             dim3(kPersistBlock), args, 0, st));
     SelState h1{};
