@@ -165,12 +165,14 @@ typedef struct {
     double select_ms;            /* device time of all im_select_seeds_from calls  */
     uint32_t sketches_per_pass;  /* sketches sampled per pass over the edge list  */
     uint64_t sketch_bytes;       /* device bytes held by the sketch arrays         */
-    uint32_t bulk_rounds;        /* CompactSketch rounds that evaluated every
-                                    vertex at once (after a seed that covered a
-                                    large share of every sketch)                   */
-    uint32_t bulk_resampled;     /* of those, rounds that re-derived the sampled
-                                    graphs' components (the others used the
-                                    largest-component bitmaps kept by the build)   */
+    uint32_t bulk_rounds;        /* rounds that evaluated every vertex at once
+                                    (after a seed that covered a large share of
+                                    every sketch): from E with full labels; from
+                                    the kept bitmaps, or by re-deriving the
+                                    sketches, with CompactSketch                   */
+    uint32_t bulk_resampled;     /* of those, CompactSketch rounds that re-derived
+                                    the sampled graphs' components (the others
+                                    used the largest-component bitmaps)            */
 } im_sketch_stats;
 im_status im_sketches_stats(const im_sketches *s, im_sketch_stats *out);
 

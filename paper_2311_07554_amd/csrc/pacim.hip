@@ -964,9 +964,25 @@ im_status enqueue_bulk_round(im_sketches *s) {
     return finish_bulk_round(s);
 }
 
-// Policy for compact sketches: a round is run in bulk when the previous seed's
-// gain shows it covered at least 1/64 of the vertices per sketch on average
-// (PACIM_BULK=always|never overrides, for tests).
+// Full labels: a round that evaluates every unselected vertex from E in vertex
+// order, then rebuilds the tree and ends the round.
+im_status enqueue_full_bulk_round(im_sketches *s) {
+    hipStream_t st = s->ctx->stream;
+    const TreeDesc &td = s->td;
+    k_bulk_full_keys<<<wave_grid(s->n, 65536), 256, 0, st>>>(s->st, s->E, s->R, s->n, s->kb, s->in_s, s->key);
+    for (int l = (int)td.D - 1; l >= 0; --l)
+        k_tree_build_level<<<wave_grid(td.lvl_n[l], 8192), 256, 0, st>>>(td, (uint32_t)l, s->ids, s->key);
+    k_round_end<<<1, 64, 0, st>>>(td, s->st, s->ids, s->key, s->in_s, s->kb, s->seeds_d, s->gains_d, s->evals_d,
+                                  s->E, s->R);
+    ++s->bulk_rounds;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(s->ctx, IM_EDEVICE, std::string("bulk round launch: ") + hipGetErrorString(e));
+    return IM_OK;
+}
+
+// Policy of bulk rounds (both label kinds): a round is run in bulk when the
+// previous seed's gain shows it covered at least 1/64 of the vertices per sketch
+// on average (PACIM_BULK=always|never overrides, for tests).
 int bulk_policy() {
     const char *e = getenv("PACIM_BULK");
     if (!e) return 0;
@@ -996,7 +1012,8 @@ extern "C" im_status im_select_seeds_from(im_ctx *ctx, im_sketches *s, uint32_t 
         // bulk round when the previous seed's gain reaches the bulk threshold (the
         // persistent kernel stops after such a round); gains never increase, so
         // once one is below it every later round is lazy.
-        const int pol = s->compact ? bulk_policy() : -1;
+        // Full labels: the same rule, the bulk round evaluating every vertex from E.
+        const int pol = bulk_policy();
         const unsigned long long bmin =
             pol == 0 ? (unsigned long long)(((uint64_t)s->R * s->n + 63) / 64) : 0ull;
         uint32_t cur = s->chosen;
@@ -1004,7 +1021,7 @@ extern "C" im_status im_select_seeds_from(im_ctx *ctx, im_sketches *s, uint32_t 
         for (uint32_t i = 0; i < k && rc == IM_OK;) {
             const bool bulk = cur > 0 && (pol > 0 || (pol == 0 && last >= bmin));
             if (bulk) {
-                rc = enqueue_bulk_round(s);
+                rc = s->compact ? enqueue_bulk_round(s) : enqueue_full_bulk_round(s);
                 if (rc != IM_OK) break;
                 unsigned long long g = 0;
                 hipError_t e1 = hipMemcpyAsync(&g, s->gains_d + cur, 8, hipMemcpyDeviceToHost, st);

@@ -259,6 +259,25 @@ __global__ void __launch_bounds__(256) k_eval_full(uint32_t l, SelState *__restr
     eval_full_level(l, st, evl, E, R, kb, in_s, key, wave_index(), wave_count());
 }
 
+// Every unselected vertex evaluated on full labels, in vertex order (one wave per
+// vertex): the round after a seed that covered a large share of every sketch,
+// where the lazy search would re-evaluate nearly every vertex anyway.  The tree
+// is rebuilt from the keys afterwards; the round's evaluation count is every
+// unselected vertex.
+__global__ void __launch_bounds__(256) k_bulk_full_keys(SelState *__restrict__ st, const uint2 *__restrict__ E,
+                                                        uint32_t R, uint32_t n, uint32_t kb,
+                                                        const uint8_t *__restrict__ in_s, uint64_t *__restrict__ key) {
+    for (uint32_t v = wave_index(); v < n; v += wave_count()) {
+        const uint64_t g = marginal_full(E, R, v);
+        if (lane_id() == 0) key[v] = in_s[v] ? 0ull : pack_key(g, v, kb);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int l = 0; l <= kMaxLevels; ++l) { st->fr_cnt[l] = 0; st->ev_cnt[l] = 0; }
+        for (int l = 0; l < kMaxLevels + 2; ++l) st->ov_cnt[l] = 0;
+        st->ev_cnt[0] = n - st->round;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_relink(TreeDesc td, uint32_t l, const SelState *__restrict__ st,
                                                 uint32_t *__restrict__ ids, const uint64_t *__restrict__ key,
                                                 const uint32_t *__restrict__ fr) {
