@@ -129,6 +129,7 @@ __device__ __forceinline__ void persist_step(const PersistArgs &a, uint32_t kind
 __global__ void __launch_bounds__(kPersistBlock) k_select_persist(PersistArgs a) {
     __shared__ uint32_t lds[kPersistWaves][kQCap + kHCap];
     __shared__ uint32_t sh_kind, sh_arg, sh_mode, sh_ok, sh_val;
+    __shared__ uint32_t sh_nf[kMaxLevels + 1];  // the round's frontier sizes, level by level
     const uint32_t tid = threadIdx.x, w = tid / kWave;
     uint32_t *q = lds[w], *hs = q + kQCap;
     PersistCtl *ctl = a.ctl;
@@ -185,14 +186,25 @@ __global__ void __launch_bounds__(kPersistBlock) k_select_persist(PersistArgs a)
         persist_step(a, kind, arg, 0, w, kPersistWaves, q, hs);
         __syncthreads();
     };
-    // items of a check/relink step: the level's frontier
+    // items of a check/relink step: the level's frontier (sh_nf, final once the
+    // level above was checked)
     auto tree_step = [&](uint32_t kind, uint32_t l) {
-        if (uniform_read(&a.st->fr_cnt[l]) > kLeaderItems) grid_step(kind, l, 0);
+        if (sh_nf[l] > kLeaderItems) grid_step(kind, l, 0);
         else local_step(kind, l);
     };
-    // evaluation of level l; false if it is left to the host
-    auto eval_step = [&](uint32_t l) -> bool {
-        const uint32_t ne = uniform_read(&a.st->ev_cnt[l]);
+    // after check(l): the frontier size of level l + 1 into sh_nf and its number of
+    // evaluations returned, both read by one thread between one pair of barriers
+    auto read_level = [&](uint32_t l1) -> uint32_t {
+        __syncthreads();
+        if (tid == 0) {
+            sh_nf[l1] = __hip_atomic_load(&a.st->fr_cnt[l1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            sh_val = __hip_atomic_load(&a.st->ev_cnt[l1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        __syncthreads();
+        return sh_val;
+    };
+    // evaluation of ne listed vertices of level l; false if it is left to the host
+    auto eval_step = [&](uint32_t l, uint32_t ne) -> bool {
         if (ne == 0) return true;
         if (a.E) {
             if (ne > a.max_step_tasks) return false;
@@ -218,7 +230,10 @@ __global__ void __launch_bounds__(kPersistBlock) k_select_persist(PersistArgs a)
     if (tid == 0) a.st->stop_level = kNone;
     __syncthreads();
     for (uint32_t r = 0; r < a.max_rounds && ok; ++r) {
-        if (tid == 0) round_begin_one(a.td, a.st, a.ids, a.fr, a.evl, a.E ? nullptr : a.partial, a.pinit);
+        if (tid == 0) {
+            round_begin_one(a.td, a.st, a.ids, a.fr, a.evl, a.E ? nullptr : a.partial, a.pinit);
+            sh_nf[0] = 1;  // the root, also the one level-0 evaluation
+        }
         __syncthreads();
         uint32_t pending = kNone;
         if (mark_pending) {
@@ -226,12 +241,12 @@ __global__ void __launch_bounds__(kPersistBlock) k_select_persist(PersistArgs a)
             grid_step(kPhMarkEvalRoot, 0, 0);
             if (ok && uniform_read(&a.st->ov_cnt[kMaxLevels + 1])) grid_step(kPhOverflow, kMaxLevels + 1, 1);
             if (ok && uniform_read(&a.st->ov_cnt[0])) grid_step(kPhOverflow, 0, 0);
-        } else if (!eval_step(0)) {
+        } else if (!eval_step(0, 1)) {
             pending = 0;
         }
         for (uint32_t l = 0; l < a.td.D && pending == kNone && ok; ++l) {
             tree_step(kPhCheck, l);
-            if (!eval_step(l + 1)) pending = l + 1;
+            if (!eval_step(l + 1, read_level(l + 1))) pending = l + 1;
         }
         if (pending != kNone) {
             if (tid == 0) a.st->stop_level = pending;
