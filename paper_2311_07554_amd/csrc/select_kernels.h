@@ -264,12 +264,45 @@ __global__ void __launch_bounds__(256) k_eval_full(uint32_t l, SelState *__restr
 // where the lazy search would re-evaluate nearly every vertex anyway.  The tree
 // is rebuilt from the keys afterwards; the round's evaluation count is every
 // unselected vertex.
+// A lane keeps the last label it gathered for each of its sketches (E is not
+// written during the round): most vertices of a sketch share one giant
+// component, and re-reading that label's entry from every wave would make one
+// row of E the target of most gathers.
 __global__ void __launch_bounds__(256) k_bulk_full_keys(SelState *__restrict__ st, const uint2 *__restrict__ E,
                                                         uint32_t R, uint32_t n, uint32_t kb,
                                                         const uint8_t *__restrict__ in_s, uint64_t *__restrict__ key) {
+    constexpr int U = 4;  // sketches per lane kept (R <= 256); larger R loops without the cache
+    uint32_t last_l[U], last_y[U];
+#pragma unroll
+    for (int i = 0; i < U; ++i) last_l[i] = kNone, last_y[i] = 0;
+    const uint32_t lane = lane_id();
     for (uint32_t v = wave_index(); v < n; v += wave_count()) {
-        const uint64_t g = marginal_full(E, R, v);
-        if (lane_id() == 0) key[v] = in_s[v] ? 0ull : pack_key(g, v, kb);
+        const uint2 *row = E + (size_t)v * R;
+        uint64_t g = 0;
+        if (R <= (uint32_t)(U * kWave)) {
+            uint2 e[U];
+#pragma unroll
+            for (int i = 0; i < U; ++i) {
+                const uint32_t r = lane + i * kWave;
+                e[i] = r < R ? row[r] : make_uint2(v, 0u);
+            }
+#pragma unroll
+            for (int i = 0; i < U; ++i) {
+                uint32_t y = e[i].y;
+                if (e[i].x != v) {
+                    if (e[i].x != last_l[i]) {
+                        last_l[i] = e[i].x;
+                        last_y[i] = E[(size_t)e[i].x * R + lane + i * kWave].y;
+                    }
+                    y = last_y[i];
+                }
+                g += y;
+            }
+            g = wave_sum_u64(g);
+        } else {
+            g = marginal_full(E, R, v);
+        }
+        if (lane == 0) key[v] = in_s[v] ? 0ull : pack_key(g, v, kb);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         for (int l = 0; l <= kMaxLevels; ++l) { st->fr_cnt[l] = 0; st->ev_cnt[l] = 0; }
