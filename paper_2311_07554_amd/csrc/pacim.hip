@@ -875,8 +875,22 @@ im_status run_persistent_rounds(im_sketches *s, uint32_t max_rounds, unsigned lo
     // CompactSketch: about one wave per sketch (the GetCenter steps have R searches
     // per listed vertex); every extra workgroup costs each step a completion.
     const unsigned grid = s->compact ? std::min<unsigned>(ctx->persist_grid, std::max<unsigned>(8u, (s->R + kPersistWaves - 1) / kPersistWaves)) : 1u;
-    HIP_TRY(ctx, hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_select_persist), dim3(grid),
-                                            dim3(kPersistBlock), args, 0, st));
+    const hipError_t le = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_select_persist), dim3(grid),
+                                                     dim3(kPersistBlock), args, 0, st);
+    if (le != hipSuccess) {
+        // no cooperative launch here: one round with the per-level kernels instead
+        (void)hipGetLastError();
+        HIP_TRY(ctx, hipStreamSynchronize(st));  // h0 is read below
+        im_status rc = enqueue_lazy_round(s);
+        if (rc != IM_OK) return rc;
+        unsigned long long g = 0;
+        HIP_TRY(ctx, hipMemcpyAsync(&g, s->gains_d + h0.round, 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(ctx, hipStreamSynchronize(st));
+        *done = 1;
+        *stop_level = kNone;
+        *last_gain = g;
+        return IM_OK;
+    }
     SelState h1{};
     PersistCtl c{};
     HIP_TRY(ctx, hipMemcpyAsync(&h1, s->st, sizeof(SelState), hipMemcpyDeviceToHost, st));
