@@ -875,8 +875,11 @@ im_status run_persistent_rounds(im_sketches *s, uint32_t max_rounds, unsigned lo
     // CompactSketch: about one wave per sketch (the GetCenter steps have R searches
     // per listed vertex); every extra workgroup costs each step a completion.
     const unsigned grid = s->compact ? std::min<unsigned>(ctx->persist_grid, std::max<unsigned>(8u, (s->R + kPersistWaves - 1) / kPersistWaves)) : 1u;
-    const hipError_t le = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_select_persist), dim3(grid),
-                                                     dim3(kPersistBlock), args, 0, st);
+    const char *np = getenv("PACIM_PERSIST");  // "0" (tests): take the path below as if refused
+    const hipError_t le = (np && !strcmp(np, "0"))
+                              ? hipErrorNotSupported
+                              : hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_select_persist),
+                                                           dim3(grid), dim3(kPersistBlock), args, 0, st);
     if (le != hipSuccess) {
         // no cooperative launch here: one round with the per-level kernels instead
         (void)hipGetLastError();

@@ -184,6 +184,20 @@ def test_persistent_handoff_matches_oracle(ctx, step, monkeypatch):
         assert np.array_equal(s, ws) and np.array_equal(gn, wg), alpha
 
 
+def test_per_level_rounds_match_oracle(ctx, monkeypatch):
+    # without the persistent kernel (where a cooperative launch is refused) every
+    # lazy round runs as per-level kernels
+    monkeypatch.setenv("PACIM_PERSIST", "0")
+    g = inputs.rmat_graph(12, 16 << 12, seed=19)
+    R, k, seed = 24, 20, 8
+    _say("case per-level rounds")
+    lab, siz = oracle.sketches(g, TRI, 0.0, seed, R)
+    ws, wg = oracle.greedy(lab, siz, k)
+    for alpha in (1.0, 0.2):
+        s, gn, _ = run_select(ctx, g, TRI, 0.0, R, k, seed, alpha=alpha, chunks=[3, 17])
+        assert np.array_equal(s, ws) and np.array_equal(gn, wg), alpha
+
+
 def test_deterministic_repeats(ctx):
     g = inputs.rmat_graph(13, 16 << 13, seed=8)
     ref = run_select(ctx, g, TRI, 0.0, 48, 20, 2)
