@@ -93,11 +93,25 @@ def cpu_baseline(g, kind, p, R, k, seed, nsk):
     """The oracle as it stands (single thread) on nsk of the R sketches plus the plain
     greedy over them; scaled linearly in R to the full query."""
     import oracle
-    t0 = time.perf_counter()
-    lab, siz = oracle.sketches(g, kind, p, seed, nsk, threads=1)
-    t1 = time.perf_counter()
-    oracle.greedy(lab, siz, k)
-    t2 = time.perf_counter()
+    host = {"logical_cpus": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as f:
+            host["cpu"] = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
+    # one thread, pinned to one core while it is timed
+    old_aff = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
+    if old_aff:
+        os.sched_setaffinity(0, {min(old_aff)})
+    try:
+        t0 = time.perf_counter()
+        lab, siz = oracle.sketches(g, kind, p, seed, nsk, threads=1)
+        t1 = time.perf_counter()
+        oracle.greedy(lab, siz, k)
+        t2 = time.perf_counter()
+    finally:
+        if old_aff:
+            os.sched_setaffinity(0, old_aff)
     scale = R / nsk
     t_query = (t1 - t0) * scale + (t2 - t1) * scale
     return {
@@ -109,6 +123,7 @@ def cpu_baseline(g, kind, p, R, k, seed, nsk):
                   f"{t2 - t0:.1f} s measured, times scaled x{scale:g} to R={R}",
         "sketch_edges_per_s": nsk * g.m_und / (t1 - t0),
         "greedy_s_measured": t2 - t1,
+        "host": host,
     }
 
 
@@ -320,7 +335,8 @@ def main():
             sk.close()
             if record is not None:
                 record.setdefault(m, []).append((st["build_ms"], st["select_ms"], st["evaluations"],
-                                                 st["sketches_per_pass"], st["bulk_rounds"], st["bulk_resampled"]))
+                                                 st["sketches_per_pass"], st["bulk_rounds"], st["bulk_resampled"],
+                                                 st["bfs_visits"]))
             per[m] = (s, gn)
         return per
 
@@ -360,6 +376,10 @@ def main():
             "bulk_rounds": int(rows[-1][4]),
             "bulk_rounds_resampled": int(rows[-1][5]),
         }
+        if alphas[m] < 1.0:
+            # GetCenter work of the CompactSketch selection (Marginal, compact)
+            breakdown[m]["getcenter_vertices_scanned"] = int(rows[-1][6])
+            breakdown[m]["getcenter_vertices_per_s"] = rows[-1][6] / (s.mean() / 1e3)
     # dominant kernel: the sampling + hooking pass over the edge list
     hk = kern["sample_hook"]
     hk_name = "k_sample_hook"

@@ -161,6 +161,7 @@ typedef struct {
     uint32_t rho;
     uint64_t evaluations;        /* vertex re-evaluations by NextSeed, all rounds  */
     uint64_t bfs_overflow;       /* GetCenter searches that left the on-chip queue */
+    uint64_t bfs_visits;         /* vertices whose adjacency GetCenter scanned     */
     double build_ms;             /* last im_build_sketches, device time            */
     double select_ms;            /* device time of all im_select_seeds_from calls  */
     uint32_t sketches_per_pass;  /* sketches sampled per pass over the edge list  */

@@ -59,6 +59,7 @@ struct BfsOut {
     uint64_t delta;
     uint32_t label;   // label_c of the reached center, or kNone
     bool overflow;
+    uint32_t visits;  // vertices whose adjacency the search scanned
 };
 
 __device__ __forceinline__ uint32_t hs_slot(uint32_t w) { return (w * 0x9E3779B1u) >> (32 - 10); }
@@ -67,7 +68,7 @@ static_assert(kHCap == 1024, "hs_slot assumes 2^10 slots");
 __device__ __forceinline__ BfsOut center_hit(const CompactDev &cd, uint32_t r, uint32_t rank) {
     const size_t row = (size_t)r * cd.rho;
     const uint32_t l = cd.label_c[row + rank];
-    return BfsOut{cd.size_c[row + l], l, false};
+    return BfsOut{cd.size_c[row + l], l, false, 0};
 }
 
 // GetCenter with the queue and visited set in LDS (q: kQCap, hs: kHCap words).
@@ -115,15 +116,19 @@ __device__ BfsOut getcenter_lds(const GraphDev &g, const ProbDev &pm, uint64_t k
             }
             const uint64_t im = __ballot(ins);
             const uint32_t ni = (uint32_t)__popcll(im);
-            if (tail + ni > kQCap) return BfsOut{0, kNone, true};
+            if (tail + ni > kQCap) return BfsOut{0, kNone, true, head};
             if (ins) q[tail + (uint32_t)__popcll(im & ((1ull << lane) - 1ull))] = w;
             if (__ballot(ins && in_s[w] != 0)) met = true;
             tail += ni;
             __builtin_amdgcn_wave_barrier();
         }
     }
-    if (found != kNone) return center_hit(cd, r, found);
-    return BfsOut{met ? 0ull : (uint64_t)tail, kNone, false};
+    if (found != kNone) {
+        BfsOut o = center_hit(cd, r, found);
+        o.visits = head;
+        return o;
+    }
+    return BfsOut{met ? 0ull : (uint64_t)tail, kNone, false, head};
 }
 
 // The same search with an n-entry queue and an n-bit visited bitmap in global
@@ -177,8 +182,12 @@ __device__ BfsOut getcenter_global(const GraphDev &g, const ProbDev &pm, uint64_
         atomicAnd(&gvis[w >> 5], ~(1u << (w & 31)));
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    if (found != kNone) return center_hit(cd, r, found);
-    return BfsOut{met ? 0ull : (uint64_t)tail, kNone, false};
+    if (found != kNone) {
+        BfsOut o = center_hit(cd, r, found);
+        o.visits = head;
+        return o;
+    }
+    return BfsOut{met ? 0ull : (uint64_t)tail, kNone, false, head};
 }
 
 // GetCenter through the kept labels (all lanes take part; lane 0 writes).
@@ -189,7 +198,7 @@ __device__ __forceinline__ BfsOut getcenter_memo_lds(const GraphDev &g, const Pr
     const unsigned long long x = __hip_atomic_load(e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if ((uint32_t)(x >> 32) == v) {
         const uint32_t l = (uint32_t)x;
-        return BfsOut{cd.size_c[(size_t)r * cd.rho + l], l, false};
+        return BfsOut{cd.size_c[(size_t)r * cd.rho + l], l, false, 0};
     }
     const BfsOut o = getcenter_lds(g, pm, kr, cd, r, in_s, v, q, hs);
     if (!o.overflow && o.label != kNone && lane_id() == 0)
@@ -204,7 +213,7 @@ __device__ __forceinline__ BfsOut getcenter_memo_global(const GraphDev &g, const
     const unsigned long long x = __hip_atomic_load(e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if ((uint32_t)(x >> 32) == v) {
         const uint32_t l = (uint32_t)x;
-        return BfsOut{cd.size_c[(size_t)r * cd.rho + l], l, false};
+        return BfsOut{cd.size_c[(size_t)r * cd.rho + l], l, false, 0};
     }
     const BfsOut o = getcenter_global(g, pm, kr, cd, r, in_s, v, gq, gvis);
     if (o.label != kNone && lane_id() == 0)
@@ -255,6 +264,7 @@ __device__ __forceinline__ void eval_compact_level(uint32_t l, SelState *st, con
         const uint32_t v = evl[e];
         const BfsOut o = getcenter_memo_lds(g, pm, K[r], cd, r, in_s, v, q, hs);
         if (lane_id() == 0) {
+            if (o.visits) atomicAdd(&st->visits, (unsigned long long)o.visits);
             if (o.overflow) push_overflow(st, &st->ov_cnt[l], ov, ov_cap / 2, e, r);
             else add_delta(st, partial, e, o.delta, evl, kb, in_s, key);
         }
@@ -281,6 +291,7 @@ __device__ __forceinline__ void overflow_level(int mode, uint32_t slot, SelState
         const uint32_t v = (mode == 0) ? evl[t.x] : st->last_seed;
         const BfsOut o = getcenter_memo_global(g, pm, K[r], cd, r, in_s, v, gq, gvis);
         if (lane_id() == 0) {
+            if (o.visits) atomicAdd(&st->visits, (unsigned long long)o.visits);
             if (mode == 0) add_delta(st, partial, t.x, o.delta, evl, kb, in_s, key);
             else if (o.label != kNone) cd.size_c[(size_t)r * cd.rho + o.label] = 0;
         }
@@ -296,6 +307,7 @@ __device__ __forceinline__ void markseed_compact_level(SelState *st, const Graph
     for (uint32_t r = wi; r < R; r += wc) {
         const BfsOut o = getcenter_memo_lds(g, pm, K[r], cd, r, in_s, s, q, hs);
         if (lane_id() == 0) {
+            if (o.visits) atomicAdd(&st->visits, (unsigned long long)o.visits);
             if (o.overflow) push_overflow(st, &st->ov_cnt[kMaxLevels + 1], mark_list(ov, ov_cap), ov_cap / 2, s, r);
             else if (o.label != kNone) cd.size_c[(size_t)r * cd.rho + o.label] = 0;
         }
@@ -317,6 +329,7 @@ __device__ __forceinline__ void markseed_eval_root_level(SelState *st, const uin
     const uint32_t v = evl[0];
     for (uint32_t r = wi; r < R; r += wc) {
         const BfsOut m = getcenter_memo_lds(g, pm, K[r], cd, r, in_s, s, q, hs);
+        if (lane_id() == 0 && m.visits) atomicAdd(&st->visits, (unsigned long long)m.visits);
         if (m.overflow) {
             if (lane_id() == 0) {
                 push_overflow(st, &st->ov_cnt[kMaxLevels + 1], mark_list(ov, ov_cap), ov_cap / 2, s, r);
@@ -329,6 +342,7 @@ __device__ __forceinline__ void markseed_eval_root_level(SelState *st, const uin
         __builtin_amdgcn_wave_barrier();
         const BfsOut o = getcenter_memo_lds(g, pm, K[r], cd, r, in_s, v, q, hs);
         if (lane_id() == 0) {
+            if (o.visits) atomicAdd(&st->visits, (unsigned long long)o.visits);
             if (o.overflow) push_overflow(st, &st->ov_cnt[0], ov, ov_cap / 2, 0, r);
             else add_delta(st, partial, 0, o.delta, evl, kb, in_s, key);
         }

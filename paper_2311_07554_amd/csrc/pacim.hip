@@ -1202,6 +1202,7 @@ extern "C" im_status im_sketches_stats(const im_sketches *s, im_sketch_stats *ou
     out->rho = s->rho;
     out->evaluations = hst.evals;
     out->bfs_overflow = hst.overflow;
+    out->bfs_visits = hst.visits;
     out->build_ms = s->build_ms;
     out->select_ms = s->select_ms;
     out->sketches_per_pass = s->B;

@@ -36,6 +36,7 @@ struct SelState {
     unsigned long long delta;        // Delta*: best fresh key this round
     unsigned long long evals;        // re-evaluations over all rounds
     unsigned long long overflow;     // GetCenter searches sent to the global-memory path
+    unsigned long long visits;       // vertices scanned by GetCenter searches
     uint32_t fr_cnt[kMaxLevels + 1];
     uint32_t ev_cnt[kMaxLevels + 1];
     uint32_t ov_cnt[kMaxLevels + 2]; // GetCenter searches left for the global-memory path:

@@ -35,7 +35,8 @@ class im_prob(ctypes.Structure):
 
 class im_sketch_stats(ctypes.Structure):
     _fields_ = [("seeds_chosen", ctypes.c_uint32), ("rho", ctypes.c_uint32), ("evaluations", ctypes.c_uint64),
-                ("bfs_overflow", ctypes.c_uint64), ("build_ms", ctypes.c_double), ("select_ms", ctypes.c_double),
+                ("bfs_overflow", ctypes.c_uint64), ("bfs_visits", ctypes.c_uint64), ("build_ms", ctypes.c_double),
+                ("select_ms", ctypes.c_double),
                 ("sketches_per_pass", ctypes.c_uint32), ("sketch_bytes", ctypes.c_uint64),
                 ("bulk_rounds", ctypes.c_uint32), ("bulk_resampled", ctypes.c_uint32)]
 
