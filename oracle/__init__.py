@@ -70,6 +70,8 @@ def _load():
                                            u32, _u32p, _u64p, _u64p]
         lib.orc_celf_evaluations.restype = i32
         lib.orc_celf_evaluations.argtypes = [u32, u32, _u32p, _u32p, u32, _u32p, _u64p, _u64p]
+        lib.orc_ptree.restype = i32
+        lib.orc_ptree.argtypes = [u32, u32, _u32p, _u32p, u32, _u32p, _u64p, _u64p]
         _lib = lib
     return _lib
 
@@ -249,6 +251,22 @@ def celf(label: np.ndarray, size: np.ndarray, k: int):
     ev = np.empty(max(k, 1), dtype=np.uint64)
     rc = _load().orc_celf_evaluations(n, R, _p(label, _u32p), _p(size, _u32p), k, _p(seeds, _u32p),
                                       _p(gains, _u64p), _p(ev, _u64p))
+    if rc != 0:
+        raise ValueError("bad k")
+    return seeds[:k], gains[:k], ev[:k]
+
+
+def ptree(label: np.ndarray, size: np.ndarray, k: int):
+    """NextSeed by prefix doubling over a totally ordered queue (Algorithm 4, Sec. 4):
+    (seeds, gains, evaluations per round)."""
+    R, n = label.shape
+    label = np.ascontiguousarray(label, dtype=np.uint32)
+    size = np.ascontiguousarray(size, dtype=np.uint32)
+    seeds = np.empty(max(k, 1), dtype=np.uint32)
+    gains = np.empty(max(k, 1), dtype=np.uint64)
+    ev = np.empty(max(k, 1), dtype=np.uint64)
+    rc = _load().orc_ptree(n, R, _p(label, _u32p), _p(size, _u32p), k, _p(seeds, _u32p), _p(gains, _u64p),
+                           _p(ev, _u64p))
     if rc != 0:
         raise ValueError("bad k")
     return seeds[:k], gains[:k], ev[:k]

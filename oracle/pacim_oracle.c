@@ -35,6 +35,10 @@
  * components, brute-force reachability and exact IC spread on tiny graphs,
  * closed forms).  orc_celf_evaluations is a measurement aid whose count is not
  * unique (it depends on the queue's tie handling): parity unpinned.
+ * orc_ptree's per-round evaluation counts are unique (the queue's order is total)
+ * and pinned by hand-worked rounds of Algorithm 4, by Theorem 4.1 (the plain
+ * greedy's seeds, also under many ties) and by Theorem 4.2 (at most twice CELF's
+ * evaluations).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -342,5 +346,86 @@ int orc_celf_evaluations(uint32_t n, uint32_t R, const uint32_t *label, const ui
         if (evals_per_round) evals_per_round[i] = ev;
     }
     free(covered); free(key); free(h);
+    return 0;
+}
+
+/* NextSeed by prefix doubling over a parallel BST (Sec. 4, Algorithm 4 and its
+ * P-tree priority queue), over full labels, single-threaded.
+ *
+ * T holds every unselected vertex keyed by its stale score; it is a plain array
+ * kept in T's total order (larger score first, smaller id first on equal
+ * scores, the greedy's tie rule), read from index `head` on:
+ *   SplitAndRemove(m)  = the m entries at head..head+m-1, head advanced;
+ *   Max()              = the entry at head (none once T is empty);
+ *   BatchInsert(B)     = B sorted into the same order, then merged with the
+ *                        entries left in T into a fresh array.
+ * Each round takes batches B_0, B_1, ... of 1, 2, 4, ... entries (fewer if T
+ * runs out), evaluates every vertex of a batch, keeps s*, the best (score, id)
+ * evaluated in the round, and stops once s* ranks above Max() or T is empty.
+ * s* is the seed; every other evaluated vertex goes back into T with its new
+ * score.  Initial scores are Marginal(empty, v), exact for round 0.
+ * seeds/gains are the picks; evals_per_round[i] = |B_0| + |B_1| + ...  */
+typedef struct { uint64_t score; uint32_t id; } orc_pt_entry;
+
+static int orc_pt_before(const orc_pt_entry *a, const orc_pt_entry *b) {
+    if (a->score != b->score) return a->score > b->score;
+    return a->id < b->id;
+}
+static int orc_pt_cmp(const void *pa, const void *pb) {
+    const orc_pt_entry *a = (const orc_pt_entry *)pa, *b = (const orc_pt_entry *)pb;
+    if (orc_pt_before(a, b)) return -1;
+    if (orc_pt_before(b, a)) return 1;
+    return 0;
+}
+
+int orc_ptree(uint32_t n, uint32_t R, const uint32_t *label, const uint32_t *size, uint32_t k,
+              uint32_t *seeds, uint64_t *gains, uint64_t *evals_per_round) {
+    if (k > n || n == 0) return -1;
+    uint8_t *covered = (uint8_t *)calloc((size_t)R * n + 1, 1);
+    orc_pt_entry *T = (orc_pt_entry *)malloc((size_t)n * sizeof(orc_pt_entry));
+    orc_pt_entry *fresh = (orc_pt_entry *)malloc((size_t)n * sizeof(orc_pt_entry));
+    orc_pt_entry *next = (orc_pt_entry *)malloc((size_t)n * sizeof(orc_pt_entry));
+    uint64_t *g0 = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    orc_marginals(n, R, label, size, covered, 0, n, g0);
+    for (uint32_t v = 0; v < n; ++v) { T[v].score = g0[v]; T[v].id = v; }
+    qsort(T, n, sizeof(orc_pt_entry), orc_pt_cmp);
+    uint32_t head = 0, len = n;
+    for (uint32_t i = 0; i < k; ++i) {
+        /* the repeat-until loop of NextSeed */
+        uint32_t nfresh = 0;
+        orc_pt_entry best = {0, ORC_NONE};
+        for (uint64_t batch = 1;; batch *= 2) {
+            uint32_t m = (uint32_t)(batch < (uint64_t)(len - head) ? batch : (uint64_t)(len - head));
+            for (uint32_t t = 0; t < m; ++t) {          /* B_j = SplitAndRemove(2^j) */
+                uint32_t v = T[head + t].id;
+                uint64_t g;
+                orc_marginals(n, R, label, size, covered, v, v + 1, &g);   /* Marginal(S, v) */
+                fresh[nfresh].score = g;
+                fresh[nfresh].id = v;
+                if (best.id == ORC_NONE || orc_pt_before(&fresh[nfresh], &best)) best = fresh[nfresh];
+                ++nfresh;
+            }
+            head += m;
+            if (head == len || orc_pt_before(&best, &T[head])) break;   /* s* beats Max() */
+        }
+        seeds[i] = best.id;
+        gains[i] = best.score;
+        if (evals_per_round) evals_per_round[i] = nfresh;
+        orc_cover(n, R, label, covered, best.id);                        /* MarkSeed(s*) */
+        /* BatchInsert(B_0 u B_1 u ... minus s*) */
+        uint32_t nb = 0;
+        for (uint32_t t = 0; t < nfresh; ++t)
+            if (fresh[t].id != best.id) fresh[nb++] = fresh[t];
+        qsort(fresh, nb, sizeof(orc_pt_entry), orc_pt_cmp);
+        uint32_t a = head, b = 0, o = 0;
+        while (a < len || b < nb) {
+            if (b == nb || (a < len && orc_pt_before(&T[a], &fresh[b]))) next[o++] = T[a++];
+            else next[o++] = fresh[b++];
+        }
+        orc_pt_entry *sw = T; T = next; next = sw;
+        head = 0;
+        len = o;
+    }
+    free(covered); free(T); free(fresh); free(next); free(g0);
     return 0;
 }

@@ -6,6 +6,7 @@ brute-force reachability / enumeration on tiny graphs, the exact IC cascade
 spread, or a closed form.  A plausible slip in the oracle (a dropped term, a
 flipped comparison, a wrong index or tie rule) fails at least one of them.
 """
+import json
 import math
 import os
 from fractions import Fraction
@@ -360,3 +361,71 @@ def test_generators_are_deterministic_and_simple():
     assert 0 < c.size <= 30000
     e = inputs.er_keys(1000, 5000, 1)
     assert e.size == 5000
+
+
+# ---------------------------------------------------------------- NextSeed by prefix doubling (Algorithm 4)
+
+def _ptree_cases():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "ptree_worked_examples.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _ptree_cases(), ids=lambda c: c["name"])
+def test_ptree_worked_examples(case):
+    lab = np.array([case["labels"]], dtype=np.uint32)
+    siz = np.array([case["sizes"]], dtype=np.uint32)
+    s, g, ev = oracle.ptree(lab, siz, case["k"])
+    assert list(s) == case["seeds"] and list(g) == case["gains"] and list(ev) == case["evals"]
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5, 6])
+def test_ptree_selects_the_greedy_seeds_within_twice_celf(seed):
+    # Theorem 4.1: the seed of every round is the plain greedy's (largest marginal
+    # gain, smallest id on ties); Theorem 4.2: at most twice CELF's evaluations.
+    g = inputs.rmat_graph(11, 16 << 11, seed=seed)
+    lab, siz = oracle.sketches(g, 1, 0.0, seed, 16)
+    k = 40
+    s1, g1 = oracle.greedy(lab, siz, k)
+    s2, g2, ev = oracle.ptree(lab, siz, k)
+    _, _, ev_celf = oracle.celf(lab, siz, k)
+    assert np.array_equal(s1, s2) and np.array_equal(g1, g2)
+    assert int(ev.sum()) <= 2 * int(ev_celf.sum())
+    assert ev[0] == 1 and ev_celf[0] == 1
+
+
+def test_ptree_round_sizes_are_whole_doubling_prefixes():
+    # a round takes whole batches 1, 2, 4, ..., so it evaluates 2^(j+1) - 1 vertices,
+    # unless the queue ran out: then exactly every unselected vertex
+    g = inputs.rmat_graph(10, 8 << 10, seed=9)
+    lab, siz = oracle.sketches(g, 1, 0.0, 9, 8)
+    n = g.n
+    k = n
+    s, gn, ev = oracle.ptree(lab, siz, k)
+    s1, g1 = oracle.greedy(lab, siz, k)
+    assert np.array_equal(s, s1) and np.array_equal(gn, g1)
+    assert sorted(s.tolist()) == list(range(n))
+    for i, e in enumerate(ev.tolist()):
+        left = n - i
+        assert e == left or (e & (e + 1)) == 0, (i, e, left)
+        assert 1 <= e <= left
+
+
+def test_ptree_ties_everywhere():
+    # no live edge: every vertex scores R in every round, so each round evaluates only
+    # the first entry of the queue and the seeds come out in id order
+    g = inputs.rmat_graph(9, 4 << 9, seed=2)
+    lab, siz = oracle.sketches(g, 0, 0.0, 1, 4)
+    s, gn, ev = oracle.ptree(lab, siz, 20)
+    assert list(s) == list(range(20)) and set(gn.tolist()) == {4} and set(ev.tolist()) == {1}
+
+
+def test_ptree_matches_greedy_with_many_ties():
+    # small R on small graphs: equal scores at the top of the queue are common, so a
+    # wrong tie rule in s* or in the stop test shows up as a different seed order
+    for seed in range(1, 13):
+        g = inputs.rmat_graph(7, 3 << 7, seed=seed)
+        for R in (1, 2, 3):
+            lab, siz = oracle.sketches(g, 0, 0.3, seed, R)
+            s, gn, _ = oracle.ptree(lab, siz, g.n)
+            s1, g1 = oracle.greedy(lab, siz, g.n)
+            assert np.array_equal(s, s1) and np.array_equal(gn, g1), (seed, R)
