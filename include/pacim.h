@@ -132,6 +132,22 @@ im_status im_sketches_free(im_sketches *s);
 im_status im_select_seeds_from(im_ctx *ctx, im_sketches *s, uint32_t k, uint32_t *seeds_out,
                                uint64_t *gains_out);
 
+/* Selects the next k seeds like im_select_seeds_from, with NextSeed by prefix
+ * doubling (Sec. 4, Algorithm 4) instead of the winning tree: the unselected
+ * vertices are kept in decreasing order of stale key (larger gain, then smaller
+ * id) -- the P-tree's order, held as sorted runs -- and each round takes batches
+ * of 1, 2, 4, ... vertices from the front, re-evaluates each batch in parallel,
+ * and stops once the best re-evaluated vertex ranks above the first vertex left;
+ * the others go back with their new keys.  Seeds and gains equal the winning
+ * tree's (Theorem 4.1); the per-round evaluation counts (im_select_trace) are
+ * unique and at most twice CELF's in total (Theorem 4.2).  Both selections may
+ * be mixed on one handle (each rebuilds its structure from the current keys).
+ * Device memory: five arrays of n 64-bit keys, allocated at the first call and
+ * held by the handle.  The host waits for each batch.  Errors as
+ * im_select_seeds_from, plus ENOMEM. */
+im_status im_select_seeds_ptree(im_ctx *ctx, im_sketches *s, uint32_t k, uint32_t *seeds_out,
+                                uint64_t *gains_out);
+
 /* One shot with full labels: build R sketches, select k seeds, free.
  * Same errors as im_build_sketches and im_select_seeds_from. */
 im_status im_select_seeds(im_ctx *ctx, const im_graph *g, im_prob prob, uint32_t R, uint32_t k,

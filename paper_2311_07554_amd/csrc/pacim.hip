@@ -31,6 +31,7 @@
 #include "compact_kernels.h"
 #include "persist_kernels.h"
 #include "probe_kernels.h"
+#include "ptree_kernels.h"
 #include "select_kernels.h"
 #include "sketch_kernels.h"
 
@@ -118,6 +119,16 @@ struct im_sketches {
     uint8_t *gcov = nullptr;           // [R] largest component covered by a seed
     uint32_t *bulk_abort = nullptr;
     uint32_t bulk_resampled = 0;
+    bool tree_valid = true;            // the winning tree's internal nodes agree with key[]
+    // NextSeed by prefix doubling (Algorithm 4): the queue's sorted runs X and Y
+    // live in two of five n-key buffers (the other three are sort and merge space);
+    // unread parts X[hx, nx), Y[hy, ny).
+    uint64_t *pt_buf[5] = {};
+    int pt_x = 0, pt_y = 1;
+    uint32_t pt_hx = 0, pt_nx = 0, pt_hy = 0, pt_ny = 0;
+    bool pt_valid = false;             // the runs hold the current key of every unselected vertex
+    PtState *pt_state = nullptr;       // device
+    PtState *pt_host = nullptr;        // pinned host copy read after each batch
     // bookkeeping
     std::vector<std::pair<void *, size_t>> allocs;
     uint32_t chosen = 0;
@@ -560,6 +571,10 @@ void enqueue_full_build(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const
 }
 
 void free_sketches(im_sketches *s) {
+    if (s->pt_host) {
+        (void)hipHostFree(s->pt_host);
+        s->pt_host = nullptr;
+    }
     if (s->bulk_cs) {
         cc_scratch_free(s->ctx, static_cast<CCScratch *>(s->bulk_cs));
         delete static_cast<CCScratch *>(s->bulk_cs);
@@ -1025,6 +1040,13 @@ extern "C" im_status im_select_seeds_from(im_ctx *ctx, im_sketches *s, uint32_t 
     im_status rc = IM_OK;
     {
         Prof p(ctx, "select");
+        if (!s->tree_valid) {  // rounds by prefix doubling moved keys: rebuild the tree from them
+            for (int l = (int)s->td.D - 1; l >= 0; --l)
+                k_tree_build_level<<<wave_grid(s->td.lvl_n[l], 8192), 256, 0, st>>>(s->td, (uint32_t)l, s->ids,
+                                                                                  s->key);
+            s->tree_valid = true;
+        }
+        s->pt_valid = false;
         // Lazy rounds run in persistent launches.  CompactSketch: a round follows as a
         // bulk round when the previous seed's gain reaches the bulk threshold (the
         // persistent kernel stops after such a round); gains never increase, so
@@ -1096,6 +1118,198 @@ extern "C" im_status im_select_seeds_from(im_ctx *ctx, im_sketches *s, uint32_t 
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     if (rc != IM_OK) return rc;
+    if (hst.err) return fail(ctx, IM_EINTERNAL, "selection consistency check failed (code " + std::to_string(hst.err) + ")");
+    if (hst.round != s->chosen + k) return fail(ctx, IM_EINTERNAL, "round counter mismatch");
+    for (uint32_t i = 0; i < k; ++i) {
+        seeds_out[i] = seeds[i];
+        gains_out[i] = gains[i];
+    }
+    s->chosen += k;
+    s->last_gain = gains[k - 1];
+    return IM_OK;
+}
+
+// ---------------------------------------------------------------- NextSeed by prefix doubling
+namespace {
+
+unsigned span_grid(uint64_t items) {
+    const uint64_t threads = (items + kPtSpan - 1) / kPtSpan;
+    return (unsigned)std::max<uint64_t>(1, (threads + kPtBlock - 1) / kPtBlock);
+}
+
+// Sorts in[0, len) into decreasing order; a and b (n keys each, distinct from in)
+// hold the passes.  Returns the one holding the result.
+uint64_t *pt_sort(hipStream_t st, const uint64_t *in, uint32_t len, uint64_t *a, uint64_t *b) {
+    if (len == 0) return a;
+    k_pt_sort_tiles<<<(len + kPtTile - 1) / kPtTile, kPtBlock, 0, st>>>(in, len, a);
+    uint64_t *src = a, *dst = b;
+    for (uint64_t L = kPtTile; L < len; L *= 2) {
+        k_pt_merge_pass<<<span_grid(len), kPtBlock, 0, st>>>(src, len, (uint32_t)L, dst);
+        std::swap(src, dst);
+    }
+    return src;
+}
+
+// The three buffers holding neither X nor Y.
+void pt_spare(const im_sketches *s, int f[3]) {
+    int c = 0;
+    for (int i = 0; i < 5; ++i)
+        if (i != s->pt_x && i != s->pt_y) f[c++] = i;
+}
+
+int pt_index(const im_sketches *s, const uint64_t *p) {
+    for (int i = 0; i < 5; ++i)
+        if (s->pt_buf[i] == p) return i;
+    return -1;
+}
+
+// Builds the queue from key[] (0 for seeds, which sort last): X = the n - chosen
+// unselected vertices in decreasing key order, Y empty.
+im_status pt_build(im_sketches *s) {
+    im_ctx *ctx = s->ctx;
+    hipStream_t st = ctx->stream;
+    if (!s->pt_buf[0]) {
+        for (int i = 0; i < 5; ++i) {
+            im_status a = sk_alloc(s, s->n, &s->pt_buf[i]);
+            if (a != IM_OK) return a;
+        }
+        im_status a = sk_alloc(s, 1, &s->pt_state);
+        if (a != IM_OK) return a;
+        HIP_TRY(ctx, hipHostMalloc((void **)&s->pt_host, sizeof(PtState), hipHostMallocDefault));
+    }
+    s->pt_x = 0;
+    s->pt_y = 1;
+    int f[3];
+    pt_spare(s, f);
+    const uint64_t *sorted = pt_sort(st, s->key, s->n, s->pt_buf[f[0]], s->pt_buf[f[1]]);
+    s->pt_x = pt_index(s, sorted);
+    s->pt_y = (s->pt_x == f[0]) ? f[2] : f[0];
+    s->pt_hx = 0;
+    s->pt_nx = s->n - s->chosen;
+    s->pt_hy = s->pt_ny = 0;
+    s->pt_valid = true;
+    HIP_TRY(ctx, hipGetLastError());
+    return IM_OK;
+}
+
+// One round of Algorithm 4: batches of 1, 2, 4, ... vertices taken from the
+// queue and evaluated until the best evaluated key ranks above the queue's Max();
+// that vertex is the seed (MarkSeed follows); the others are put back with their
+// new keys.  The host reads the stop flag after each batch.
+im_status pt_round(im_sketches *s) {
+    im_ctx *ctx = s->ctx;
+    hipStream_t st = ctx->stream;
+    GraphDev gd{s->g->off, s->g->cols};
+    CompactDev cd{s->center_rank, s->label_c, s->size_c, s->rho, s->kc, s->Ta, s->memo, s->memo_mask, s->R};
+    const unsigned long long pinit = (unsigned long long)s->R << kPartialShift;
+    k_pt_round_begin<<<1, 64, 0, st>>>(s->st);
+    uint32_t off = 0;
+    for (uint64_t batch = 1;; batch *= 2) {
+        const uint32_t nxl = s->pt_nx - s->pt_hx, nyl = s->pt_ny - s->pt_hy;
+        const uint32_t m = (uint32_t)std::min<uint64_t>(batch, (uint64_t)nxl + nyl);
+        if (m == 0) return fail(ctx, IM_EINTERNAL, "prefix-doubling round ran out of vertices");
+        const uint64_t *X = s->pt_buf[s->pt_x] + s->pt_hx, *Y = s->pt_buf[s->pt_y] + s->pt_hy;
+        uint32_t *evl = s->evl + off;
+        unsigned long long *part = s->compact ? s->partial + off : nullptr;
+        k_pt_extract<<<span_grid(m), kPtBlock, 0, st>>>(X, nxl, Y, nyl, m, s->kb, evl, part, pinit, s->pt_state,
+                                                         s->st);
+        if (!s->compact) {
+            k_eval_full<<<wave_grid(m, 8192), 256, 0, st>>>(0, s->st, evl, s->E, s->R, s->kb, s->in_s, s->key);
+        } else {
+            k_eval_compact_bfs<<<wave_grid((uint64_t)m * s->R, 65536), kBfsBlock, 0, st>>>(
+                0, s->st, evl, part, gd, s->pm, s->K, s->R, cd, s->kb, s->in_s, s->key, s->ov, s->ov_cap);
+            k_overflow_bfs<<<s->slots, 64, 0, st>>>(0, 0, s->st, evl, part, gd, s->pm, s->K, cd, s->kb, s->in_s,
+                                                    s->key, s->ov, s->ov_cap, s->slot_q, s->slot_vis, s->n);
+        }
+        k_pt_check<<<1, 64, 0, st>>>(X, nxl, Y, nyl, m, s->pt_state, s->st);
+        HIP_TRY(ctx, hipGetLastError());
+        HIP_TRY(ctx, hipMemcpyAsync(s->pt_host, s->pt_state, sizeof(PtState), hipMemcpyDeviceToHost, st));
+        HIP_TRY(ctx, hipStreamSynchronize(st));
+        const uint32_t take = s->pt_host->take;
+        if (take > nxl || m - take > nyl) return fail(ctx, IM_EINTERNAL, "prefix-doubling split out of range");
+        s->pt_hx += take;
+        s->pt_hy += m - take;
+        off += m;
+        if (s->pt_host->stop) break;
+    }
+    const uint32_t tot = off;
+    k_pt_round_end<<<1, 64, 0, st>>>(s->st, s->key, s->in_s, s->n, s->kb, tot, s->seeds_d, s->gains_d, s->evals_d,
+                                     s->compact ? nullptr : s->E, s->R);
+    if (s->compact) enqueue_markseed_compact(s);
+    // BatchInsert of the round's other evaluated vertices (s*'s key is now 0 and
+    // sorts last), merged with Y's unread part
+    if (tot > 1) {
+        int f[3];
+        pt_spare(s, f);
+        k_pt_gather<<<(tot + 255) / 256, 256, 0, st>>>(s->evl, tot, s->key, s->pt_buf[f[0]]);
+        const uint64_t *sorted = pt_sort(st, s->pt_buf[f[0]], tot, s->pt_buf[f[1]], s->pt_buf[f[0]]);
+        const int si = pt_index(s, sorted);
+        const int out = (si == f[0]) ? f[1] : f[0];
+        const uint32_t nyl = s->pt_ny - s->pt_hy;
+        k_pt_merge2<<<span_grid((uint64_t)tot - 1 + nyl), kPtBlock, 0, st>>>(
+            sorted, tot - 1, s->pt_buf[s->pt_y] + s->pt_hy, nyl, s->pt_buf[out]);
+        s->pt_y = out;
+        s->pt_hy = 0;
+        s->pt_ny = tot - 1 + nyl;
+    }
+    // Y is merged into X once it outgrows X's unread part, so that re-inserting
+    // stays proportional to what was re-inserted since
+    const uint32_t nxl = s->pt_nx - s->pt_hx, nyl = s->pt_ny - s->pt_hy;
+    if (nyl > nxl) {
+        int f[3];
+        pt_spare(s, f);
+        k_pt_merge2<<<span_grid((uint64_t)nxl + nyl), kPtBlock, 0, st>>>(
+            s->pt_buf[s->pt_x] + s->pt_hx, nxl, s->pt_buf[s->pt_y] + s->pt_hy, nyl, s->pt_buf[f[0]]);
+        s->pt_x = f[0];
+        s->pt_hx = 0;
+        s->pt_nx = nxl + nyl;
+        s->pt_hy = s->pt_ny = 0;
+    }
+    HIP_TRY(ctx, hipGetLastError());
+    return IM_OK;
+}
+
+}  // namespace
+
+extern "C" im_status im_select_seeds_ptree(im_ctx *ctx, im_sketches *s, uint32_t k, uint32_t *seeds_out,
+                                           uint64_t *gains_out) {
+    if (!ctx || !s || s->ctx != ctx) return IM_EINVAL;
+    if (k && (!seeds_out || !gains_out)) return fail(ctx, IM_EINVAL, "null output array");
+    if ((uint64_t)k + s->chosen > s->n) return fail(ctx, IM_EINVAL, "k exceeds the number of unselected vertices");
+    if (k == 0) return IM_OK;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    hipEvent_t t0, t1;
+    HIP_TRY(ctx, hipEventCreate(&t0));
+    HIP_TRY(ctx, hipEventCreate(&t1));
+    (void)hipEventRecord(t0, st);
+    im_status rc = IM_OK;
+    {
+        Prof p(ctx, "select_ptree");
+        if (!s->pt_valid) rc = pt_build(s);
+        s->tree_valid = false;
+        for (uint32_t i = 0; i < k && rc == IM_OK; ++i) rc = pt_round(s);
+    }
+    (void)hipEventRecord(t1, st);
+    std::vector<uint32_t> seeds(k);
+    std::vector<unsigned long long> gains(k);
+    SelState hst{};
+    if (rc == IM_OK) {
+        hipError_t e1 = hipMemcpyAsync(seeds.data(), s->seeds_d + s->chosen, (size_t)k * 4, hipMemcpyDeviceToHost, st);
+        hipError_t e2 = hipMemcpyAsync(gains.data(), s->gains_d + s->chosen, (size_t)k * 8, hipMemcpyDeviceToHost, st);
+        hipError_t e3 = hipMemcpyAsync(&hst, s->st, sizeof(SelState), hipMemcpyDeviceToHost, st);
+        hipError_t e4 = hipStreamSynchronize(st);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess)
+            rc = fail(ctx, IM_EDEVICE, std::string("select: ") + hipGetErrorString(e4 != hipSuccess ? e4 : e1));
+    }
+    float ms = 0.f;
+    if (rc == IM_OK && hipEventElapsedTime(&ms, t0, t1) == hipSuccess) s->select_ms += ms;
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (rc != IM_OK) {
+        s->pt_valid = false;
+        return rc;
+    }
     if (hst.err) return fail(ctx, IM_EINTERNAL, "selection consistency check failed (code " + std::to_string(hst.err) + ")");
     if (hst.round != s->chosen + k) return fail(ctx, IM_EINTERNAL, "round counter mismatch");
     for (uint32_t i = 0; i < k; ++i) {

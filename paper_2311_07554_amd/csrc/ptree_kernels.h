@@ -1,0 +1,210 @@
+// NextSeed by prefix doubling (Sec. 4, Algorithm 4) over a totally ordered
+// queue of stale keys: the paper's P-tree priority queue in a GPU form.
+//
+// Keys are the winning tree's packed keys (larger gain first, smaller id on equal
+// gains, all distinct), so "the top m entries" is one well-defined set.  The
+// queue is two runs sorted in decreasing key order:
+//   X  every unselected vertex, sorted once on the device when the queue is
+//      built, then read from a moving head;
+//   Y  the vertices re-inserted since (BatchInsert), merged into X whenever it
+//      outgrows X's unread part.
+// SplitAndRemove(m) takes the first m keys of merge(X, Y): a merge-path co-rank
+// splits m between the two heads and each thread copies a span of the merged
+// order out as vertex ids.  Max() is the larger of the two heads.  BatchInsert
+// sorts the round's re-evaluated keys (bitonic tiles of 4096 keys in LDS, then
+// merge passes) and merges them with Y.
+//
+// The paper's P-tree is a balanced BST with polylogarithmic-span batch
+// operations; the sorted runs give the same extraction order with sequential,
+// coalescing memory traffic instead of pointer chasing.
+#pragma once
+
+#include "common.h"
+#include "select_kernels.h"
+
+namespace pacim {
+
+constexpr uint32_t kPtTile = 4096;  // keys sorted per workgroup in LDS (32 KB)
+constexpr uint32_t kPtBlock = 256;
+constexpr uint32_t kPtSpan = 8;     // merged outputs per thread
+
+struct PtState {
+    uint32_t take;  // entries the last SplitAndRemove took from X (the rest came from Y)
+    uint32_t stop;  // the round's best evaluated key ranks above Max() of what is left
+};
+
+// Number of entries of a among the first d of merge(a, b); a and b are in
+// decreasing order and share no key.  Requires d <= na + nb.
+__device__ __forceinline__ uint32_t pt_corank(const uint64_t *a, uint32_t na, const uint64_t *b, uint32_t nb,
+                                              uint32_t d) {
+    uint32_t lo = d > nb ? d - nb : 0u, hi = d < na ? d : na;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] > b[d - 1 - mid]) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Entries [d0, d0 + cnt) of merge(a, b), handed to put(position, key) in order.
+// Requires d0 + cnt <= na + nb.
+template <class Put>
+__device__ __forceinline__ void pt_merge_span(const uint64_t *a, uint32_t na, const uint64_t *b, uint32_t nb,
+                                              uint32_t d0, uint32_t cnt, Put put) {
+    uint32_t i = pt_corank(a, na, b, nb, d0), j = d0 - i;
+    for (uint32_t t = 0; t < cnt; ++t) {
+        const bool from_a = j >= nb || (i < na && a[i] > b[j]);
+        const uint64_t kk = from_a ? a[i] : b[j];
+        if (from_a) ++i;
+        else ++j;
+        put(d0 + t, kk);
+    }
+}
+
+__device__ __forceinline__ uint64_t pt_thread_span() {
+    return ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kPtSpan;
+}
+
+// Sorts each tile of kPtTile keys of in[0, len) into decreasing order (bitonic
+// network in LDS; the tail tile is padded with 0, which sorts last and is not
+// written back).
+__global__ void __launch_bounds__(kPtBlock) k_pt_sort_tiles(const uint64_t *__restrict__ in, uint32_t len,
+                                                            uint64_t *__restrict__ out) {
+    __shared__ uint64_t t[kPtTile];
+    const uint32_t base = blockIdx.x * kPtTile;
+    const uint32_t cnt = min(kPtTile, len - base);
+    for (uint32_t i = threadIdx.x; i < kPtTile; i += kPtBlock) t[i] = i < cnt ? in[base + i] : 0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= kPtTile; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t p = threadIdx.x; p < kPtTile / 2; p += kPtBlock) {
+                const uint32_t i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
+                const uint64_t x = t[i], y = t[i + j];
+                const bool dec = (i & k) == 0;
+                if (dec ? x < y : x > y) {
+                    t[i] = y;
+                    t[i + j] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < cnt; i += kPtBlock) out[base + i] = t[i];
+}
+
+// One merge-sort pass: sorted runs of L keys (L a multiple of 2 * kPtSpan) merged
+// pairwise, in[0, len) -> out[0, len).
+__global__ void __launch_bounds__(kPtBlock) k_pt_merge_pass(const uint64_t *__restrict__ in, uint32_t len,
+                                                            uint32_t L, uint64_t *__restrict__ out) {
+    const uint64_t d = pt_thread_span();
+    if (d >= len) return;
+    const uint64_t base = d / (2ull * L) * (2ull * L);
+    const uint32_t rest = (uint32_t)(len - base);
+    const uint32_t na = min(L, rest), nb = rest > L ? min(L, rest - L) : 0u;
+    uint64_t *o = out + base;
+    pt_merge_span(in + base, na, in + base + na, nb, (uint32_t)(d - base), (uint32_t)min<uint64_t>(kPtSpan, len - d),
+                  [&](uint32_t p, uint64_t kk) { o[p] = kk; });
+}
+
+// out[0, na + nb) = merge(a, b).
+__global__ void __launch_bounds__(kPtBlock) k_pt_merge2(const uint64_t *__restrict__ a, uint32_t na,
+                                                        const uint64_t *__restrict__ b, uint32_t nb,
+                                                        uint64_t *__restrict__ out) {
+    const uint64_t d = pt_thread_span();
+    const uint64_t tot = (uint64_t)na + nb;
+    if (d >= tot) return;
+    pt_merge_span(a, na, b, nb, (uint32_t)d, (uint32_t)min<uint64_t>(kPtSpan, tot - d),
+                  [&](uint32_t p, uint64_t kk) { out[p] = kk; });
+}
+
+__global__ void k_pt_round_begin(SelState *__restrict__ st) {
+    if (threadIdx.x != 0) return;
+    st->delta = 0;
+    for (int l = 0; l <= kMaxLevels; ++l) { st->fr_cnt[l] = 0; st->ev_cnt[l] = 0; }
+    for (int l = 0; l < kMaxLevels + 2; ++l) st->ov_cnt[l] = 0;
+}
+
+// SplitAndRemove(m) from the unread parts X[0, nx), Y[0, ny) (m <= nx + ny): the
+// vertex ids of the first m keys of merge(X, Y) into evl[0, m), the split into
+// ps->take, and the batch size into the level-0 slot the evaluation kernels read.
+// CompactSketch: partial[0, m) started at pinit (R searches left, sum 0).
+__global__ void __launch_bounds__(kPtBlock) k_pt_extract(const uint64_t *__restrict__ X, uint32_t nx,
+                                                         const uint64_t *__restrict__ Y, uint32_t ny, uint32_t m,
+                                                         uint32_t kb, uint32_t *__restrict__ evl,
+                                                         unsigned long long *__restrict__ partial,
+                                                         unsigned long long pinit, PtState *__restrict__ ps,
+                                                         SelState *__restrict__ st) {
+    const uint64_t d = pt_thread_span();
+    if (d == 0) {
+        ps->take = pt_corank(X, nx, Y, ny, m);
+        st->ev_cnt[0] = m;
+        st->ov_cnt[0] = 0;
+    }
+    if (d >= m) return;
+    const uint64_t mask = (1ull << kb) - 1ull;
+    pt_merge_span(X, nx, Y, ny, (uint32_t)d, (uint32_t)min<uint64_t>(kPtSpan, m - d), [&](uint32_t p, uint64_t kk) {
+        evl[p] = (uint32_t)(mask - (kk & mask));
+        if (partial) partial[p] = pinit;
+    });
+}
+
+// The repeat-until test: does the best key evaluated this round (Delta*) rank
+// above Max() of the queue left after the last SplitAndRemove?  An empty queue
+// stops the round too (Max() = 0 and every key is positive).
+__global__ void k_pt_check(const uint64_t *__restrict__ X, uint32_t nx, const uint64_t *__restrict__ Y, uint32_t ny,
+                           uint32_t m, PtState *__restrict__ ps, SelState *__restrict__ st) {
+    if (threadIdx.x != 0) return;
+    const uint32_t i = ps->take, j = m - i;
+    uint64_t top = 0;
+    if (i < nx) top = X[i];
+    if (j < ny && Y[j] > top) top = Y[j];
+    ps->stop = st->delta > top ? 1u : 0u;
+    st->overflow += st->ov_cnt[0];
+}
+
+// The round's end: s* (the vertex of Delta*) becomes the seed, with the round's
+// evaluation count; its key is cleared so that BatchInsert's gather leaves it out
+// (it sorts last).  Full labels: MarkSeed zeroes the size at s*'s label in every
+// sketch.  One wave.
+__global__ void __launch_bounds__(64) k_pt_round_end(SelState *__restrict__ st, uint64_t *__restrict__ key,
+                                                     uint8_t *__restrict__ in_s, uint32_t n, uint32_t kb, uint32_t tot,
+                                                     uint32_t *__restrict__ seeds_out,
+                                                     unsigned long long *__restrict__ gains_out,
+                                                     uint32_t *__restrict__ evals_out, uint2 *__restrict__ E,
+                                                     uint32_t R) {
+    const uint32_t lane = lane_id();
+    const uint64_t ks = st->delta;
+    const uint64_t mask = (1ull << kb) - 1ull;
+    const uint32_t s = (uint32_t)(mask - (ks & mask));
+    if (ks == 0 || s >= n || in_s[s]) {
+        if (lane == 0) st->err = 1;
+        return;
+    }
+    const uint32_t round = st->round;
+    if (lane == 0) {
+        seeds_out[round] = s;
+        gains_out[round] = key_gain(ks, kb);
+        evals_out[round] = tot;
+        in_s[s] = 1;
+        key[s] = 0;
+        st->last_seed = s;
+        st->evals += tot;
+    }
+    if (E) {
+        const uint2 *row = E + (size_t)s * R;
+        for (uint32_t r = lane; r < R; r += kWave) {
+            const uint32_t lab = row[r].x;
+            E[(size_t)lab * R + r].y = 0;
+        }
+    }
+    if (lane == 0) st->round = round + 1;
+}
+
+// BatchInsert's input: the current keys of the round's evaluated vertices.
+__global__ void __launch_bounds__(256) k_pt_gather(const uint32_t *__restrict__ evl, uint32_t cnt,
+                                                   const uint64_t *__restrict__ key, uint64_t *__restrict__ out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) out[i] = key[evl[i]];
+}
+
+}  // namespace pacim

@@ -83,6 +83,7 @@ _SIGS = {
                                          ctypes.POINTER(_vp)]),
     "im_sketches_free": (ctypes.c_int, [_vp]),
     "im_select_seeds_from": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _u32p, _u64p]),
+    "im_select_seeds_ptree": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _u32p, _u64p]),
     "im_select_seeds": (ctypes.c_int, [_vp, _vp, im_prob, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
                                        _u32p, _u64p]),
     "im_sketches_dump": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _u32p, _u32p]),
@@ -222,6 +223,13 @@ def im_select_seeds_from(ctx, s, k: int):
     seeds = np.empty(max(k, 1), dtype=np.uint32)
     gains = np.empty(max(k, 1), dtype=np.uint64)
     _check(ctx, load().im_select_seeds_from(ctx, s, k, _u32(seeds), _u64(gains)))
+    return seeds[:k], gains[:k]
+
+
+def im_select_seeds_ptree(ctx, s, k: int):
+    seeds = np.empty(max(k, 1), dtype=np.uint32)
+    gains = np.empty(max(k, 1), dtype=np.uint64)
+    _check(ctx, load().im_select_seeds_ptree(ctx, s, k, _u32(seeds), _u64(gains)))
     return seeds[:k], gains[:k]
 
 
@@ -416,6 +424,9 @@ class Sketches:
 
     def select(self, k):
         return im_select_seeds_from(self.ctx.h, self.h, k)
+
+    def select_ptree(self, k):
+        return im_select_seeds_ptree(self.ctx.h, self.h, k)
 
     def centers(self):
         return im_centers(self.ctx.h, self.h)
