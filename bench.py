@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--alpha", type=float, default=0.1, help="CompactSketch alpha of the second query")
     ap.add_argument("--modes", default="full,compact")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ptree", action="store_true",
+                    help="skip the untimed comparison with NextSeed by prefix doubling")
     ap.add_argument("--cpu-sketches", type=int, default=16)
     ap.add_argument("--workload", default="rmat20", choices=("rmat20", "batched", "serving"),
                     help="rmat20: the headline workload; batched: 64 Chung-Lu graphs in one launch; "
@@ -400,6 +402,25 @@ def main():
             roofline["traffic_detail"] = dict(tr, achieved_GB_s=tr["bytes"] / (hk["avg_ms"] / 1e3) / 1e9,
                                               algorithmic_bytes=8.0 * m_und)
 
+    # NextSeed by prefix doubling (Algorithm 4) on the same sketches, outside the
+    # timed steps: its selection time and evaluations beside the winning tree's
+    trees = {}
+    if not args.no_ptree:
+        for m in modes:
+            times, evs = [], 0
+            for _ in range(max(1, min(3, args.steps))):
+                sk = gr.sketches(q.prob_kind, q.p, q.R, q.seed, alphas[m])
+                s, gn = sk.select_ptree(q.k)
+                st = sk.stats()
+                sk.close()
+                assert np.array_equal(s, res[m][0]) and np.array_equal(gn, res[m][1]), m
+                times.append(st["select_ms"])
+                evs = int(st["evaluations"])
+            trees[m] = {"ptree_select_ms": float(np.mean(times)), "ptree_evaluations": evs,
+                        "winning_tree_select_ms": breakdown[m]["select_ms"],
+                        "winning_tree_evaluations": breakdown[m]["evaluations"]}
+        print(f"[bench] prefix-doubling selection: {trees}", file=sys.stderr, flush=True)
+
     out = {
         "metric": METRIC,
         "value": len(modes) * R * m_und / (ms_step / 1e3),
@@ -417,6 +438,7 @@ def main():
                    "n": n, "m_und": m_und, "R": R, "k": q.k, "alpha_compact": args.alpha,
                    "prob": "trivalency {0.1,0.01,0.001}", "parallelism": "single GPU"},
         "breakdown": breakdown,
+        "selection_structures": trees or None,
         "kernels": kern,
         "roofline": roofline,
         "device_probe": {"hash_loop_Ghash_s": probe_hash / 1e9, "stream_copy_GB_s": probe_copy / 1e9,

@@ -952,7 +952,10 @@ im_status finish_bulk_round(im_sketches *s) {
     return IM_OK;
 }
 
-im_status enqueue_bulk_round(im_sketches *s) {
+// Fresh keys of every unselected vertex on CompactSketch (Marginal for the seeds
+// chosen so far), from the largest-component bitmaps, else by re-deriving the
+// sampled graphs' components.  Leaves the round open.
+im_status enqueue_bulk_keys(im_sketches *s) {
     im_ctx *ctx = s->ctx;
     hipStream_t st = ctx->stream;
     const uint32_t n = s->n;
@@ -970,7 +973,8 @@ im_status enqueue_bulk_round(im_sketches *s) {
         if (!aborted) {
             k_bulk_bits_keys<<<(s->nw + 3) / 4, 256, 0, st>>>(s->st, s->gain0, s->partial, s->gbits, s->nw, s->gcov,
                                                               s->gbest, s->R, n, s->kb, s->in_s, s->key, s->bulk_abort);
-            return finish_bulk_round(s);
+            HIP_TRY(ctx, hipGetLastError());
+            return IM_OK;
         }
     }
     ++s->bulk_resampled;
@@ -993,7 +997,13 @@ im_status enqueue_bulk_round(im_sketches *s) {
         k_bulk_accum<<<(n + 255) / 256, 256, 0, st>>>(parent, cnt, flag, n, b, s->partial);
     }
     k_bulk_keys<<<(n + 255) / 256, 256, 0, st>>>(s->st, s->partial, n, s->kb, s->in_s, s->key);
-    return finish_bulk_round(s);
+    HIP_TRY(ctx, hipGetLastError());
+    return IM_OK;
+}
+
+im_status enqueue_bulk_round(im_sketches *s) {
+    im_status rc = enqueue_bulk_keys(s);
+    return rc != IM_OK ? rc : finish_bulk_round(s);
 }
 
 // Full labels: a round that evaluates every unselected vertex from E in vertex
@@ -1192,6 +1202,16 @@ im_status pt_build(im_sketches *s) {
     return IM_OK;
 }
 
+// CompactSketch: the batch size from which a prefix-doubling round evaluates
+// every vertex at once from the bitmaps (the rest of the round then reads the
+// keys), instead of R GetCenter searches per listed vertex.  PACIM_PTREE_BULK
+// overrides (0: never).
+uint32_t pt_bulk_min(const im_sketches *s) {
+    const char *e = getenv("PACIM_PTREE_BULK");
+    if (e) return (uint32_t)strtoul(e, nullptr, 10);
+    return std::max<uint32_t>(64u, s->n / 4096);
+}
+
 // One round of Algorithm 4: batches of 1, 2, 4, ... vertices taken from the
 // queue and evaluated until the best evaluated key ranks above the queue's Max();
 // that vertex is the seed (MarkSeed follows); the others are put back with their
@@ -1203,6 +1223,8 @@ im_status pt_round(im_sketches *s) {
     CompactDev cd{s->center_rank, s->label_c, s->size_c, s->rho, s->kc, s->Ta, s->memo, s->memo_mask, s->R};
     const unsigned long long pinit = (unsigned long long)s->R << kPartialShift;
     k_pt_round_begin<<<1, 64, 0, st>>>(s->st);
+    const uint32_t bulk_min = s->compact ? pt_bulk_min(s) : 0u;
+    bool all_known = false;  // key[] holds every vertex's Marginal for this round
     uint32_t off = 0;
     for (uint64_t batch = 1;; batch *= 2) {
         const uint32_t nxl = s->pt_nx - s->pt_hx, nyl = s->pt_ny - s->pt_hy;
@@ -1213,7 +1235,15 @@ im_status pt_round(im_sketches *s) {
         unsigned long long *part = s->compact ? s->partial + off : nullptr;
         k_pt_extract<<<span_grid(m), kPtBlock, 0, st>>>(X, nxl, Y, nyl, m, s->kb, evl, part, pinit, s->pt_state,
                                                          s->st);
-        if (!s->compact) {
+        if (!all_known && bulk_min && m >= bulk_min) {
+            im_status rc = enqueue_bulk_keys(s);
+            if (rc != IM_OK) return rc;
+            all_known = true;
+            ++s->bulk_rounds;
+        }
+        if (all_known) {
+            k_pt_eval_known<<<(m + 255) / 256, 256, 0, st>>>(evl, m, s->key, s->st);
+        } else if (!s->compact) {
             k_eval_full<<<wave_grid(m, 8192), 256, 0, st>>>(0, s->st, evl, s->E, s->R, s->kb, s->in_s, s->key);
         } else {
             k_eval_compact_bfs<<<wave_grid((uint64_t)m * s->R, 65536), kBfsBlock, 0, st>>>(

@@ -148,6 +148,15 @@ __global__ void __launch_bounds__(kPtBlock) k_pt_extract(const uint64_t *__restr
     });
 }
 
+// Evaluation of a batch whose keys are already fresh in key[] (the round
+// computed every vertex's Marginal at once): Delta* raised to the batch's best.
+__global__ void __launch_bounds__(256) k_pt_eval_known(const uint32_t *__restrict__ evl, uint32_t m,
+                                                       const uint64_t *__restrict__ key, SelState *__restrict__ st) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t best = wave_max_u64(i < m ? key[evl[i]] : 0ull);
+    if (lane_id() == 0 && best) atomicMax(&st->delta, (unsigned long long)best);
+}
+
 // The repeat-until test: does the best key evaluated this round (Delta*) rank
 // above Max() of the queue left after the last SplitAndRemove?  An empty queue
 // stops the round too (Max() = 0 and every key is positive).

@@ -111,3 +111,34 @@ def test_ptree_within_twice_celf(ctx):
     _, _, cev = oracle.celf(lab, siz, 50)
     _, _, ev, _ = _ptree_gpu(ctx, g, TRI, 0.0, 64, 50, 9, 1.0)
     assert int(ev.sum()) <= 2 * int(cev.sum())
+
+
+@pytest.mark.parametrize("bulk,cap", [("0", None), ("1", None), ("64", None), ("1", "1"), ("64", "1")])
+def test_ptree_compact_bulk_evaluation(ctx, bulk, cap, monkeypatch):
+    # CompactSketch rounds may evaluate a large batch from every vertex's fresh key
+    # (bitmaps, or re-derived components past the search cap): same counts as the
+    # per-vertex GetCenter evaluation.  A giant component makes round 1 take
+    # batches of thousands of vertices.
+    monkeypatch.setenv("PACIM_PTREE_BULK", bulk)
+    if cap is not None:
+        monkeypatch.setenv("PACIM_BULK_SEARCH_CAP", cap)
+    g = inputs.rmat_graph(14, 8 << 14, seed=5)
+    k = 20
+    _say(f"case ptree compact bulk={bulk} cap={cap}")
+    lab, siz = oracle.sketches(g, U, 0.3, 5, 16, threads=8)
+    ws, wg, wev = oracle.ptree(lab, siz, k)
+    s, gn, ev, st = _ptree_gpu(ctx, g, U, 0.3, 16, k, 5, 0.2)
+    assert np.array_equal(s, ws) and np.array_equal(gn, wg)
+    assert np.array_equal(ev.astype(np.uint64), wev)
+    if bulk == "0":
+        assert st["bulk_rounds"] == 0
+    elif bulk == "1":
+        assert st["bulk_rounds"] == k
+    else:
+        assert st["bulk_rounds"] >= 1
+    # rounds whose seeds all lie in the largest components need no search, so
+    # they use the bitmaps even with the cap
+    if cap is None:
+        assert st["bulk_resampled"] == 0
+    elif bulk == "1":
+        assert 1 <= st["bulk_resampled"] <= st["bulk_rounds"]
