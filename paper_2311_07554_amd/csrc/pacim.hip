@@ -1206,6 +1206,8 @@ im_status pt_build(im_sketches *s) {
 // every vertex at once from the bitmaps (the rest of the round then reads the
 // keys), instead of R GetCenter searches per listed vertex.  PACIM_PTREE_BULK
 // overrides (0: never).
+constexpr uint32_t kPtListEval = 1u << 14;  // full labels: batches from this size use the label-caching kernel
+
 uint32_t pt_bulk_min(const im_sketches *s) {
     const char *e = getenv("PACIM_PTREE_BULK");
     if (e) return (uint32_t)strtoul(e, nullptr, 10);
@@ -1243,6 +1245,9 @@ im_status pt_round(im_sketches *s) {
         }
         if (all_known) {
             k_pt_eval_known<<<(m + 255) / 256, 256, 0, st>>>(evl, m, s->key, s->st);
+        } else if (!s->compact && m >= kPtListEval && s->R <= 4u * kWave) {
+            k_pt_eval_full_list<<<wave_grid(m / 16, 65536), 256, 0, st>>>(evl, m, s->E, s->R, s->kb, s->in_s, s->key,
+                                                                          s->st);
         } else if (!s->compact) {
             k_eval_full<<<wave_grid(m, 8192), 256, 0, st>>>(0, s->st, evl, s->E, s->R, s->kb, s->in_s, s->key);
         } else {

@@ -65,25 +65,44 @@ __device__ __forceinline__ uint64_t pt_thread_span() {
     return ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kPtSpan;
 }
 
-// Sorts each tile of kPtTile keys of in[0, len) into decreasing order (bitonic
-// network in LDS; the tail tile is padded with 0, which sorts last and is not
-// written back).
+// Sorts each tile of kPtTile keys of in[0, len) into decreasing order: a bitonic
+// network in LDS over the smallest power of two holding the tile's keys (a short
+// tail tile, or a small BatchInsert, runs a short network), padded with 0, which
+// sorts last and is not written back.  A stage's compare-exchanges are disjoint,
+// so each thread loads all of its pairs before writing any.
 __global__ void __launch_bounds__(kPtBlock) k_pt_sort_tiles(const uint64_t *__restrict__ in, uint32_t len,
                                                             uint64_t *__restrict__ out) {
+    constexpr uint32_t kPer = kPtTile / 2 / kPtBlock;  // pairs per thread at full size
     __shared__ uint64_t t[kPtTile];
     const uint32_t base = blockIdx.x * kPtTile;
     const uint32_t cnt = min(kPtTile, len - base);
-    for (uint32_t i = threadIdx.x; i < kPtTile; i += kPtBlock) t[i] = i < cnt ? in[base + i] : 0ull;
+    uint32_t N = 2;
+    while (N < cnt) N <<= 1;
+    for (uint32_t i = threadIdx.x; i < N; i += kPtBlock) t[i] = i < cnt ? in[base + i] : 0ull;
     __syncthreads();
-    for (uint32_t k = 2; k <= kPtTile; k <<= 1) {
+    const uint32_t pairs = N / 2;
+    for (uint32_t k = 2; k <= N; k <<= 1) {
         for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t p = threadIdx.x; p < kPtTile / 2; p += kPtBlock) {
+            uint64_t x[kPer], y[kPer];
+#pragma unroll
+            for (uint32_t q = 0; q < kPer; ++q) {
+                const uint32_t p = threadIdx.x + q * kPtBlock;
                 const uint32_t i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
-                const uint64_t x = t[i], y = t[i + j];
-                const bool dec = (i & k) == 0;
-                if (dec ? x < y : x > y) {
-                    t[i] = y;
-                    t[i + j] = x;
+                if (p < pairs) {
+                    x[q] = t[i];
+                    y[q] = t[i + j];
+                }
+            }
+#pragma unroll
+            for (uint32_t q = 0; q < kPer; ++q) {
+                const uint32_t p = threadIdx.x + q * kPtBlock;
+                const uint32_t i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
+                if (p < pairs) {
+                    const bool dec = (i & k) == 0;
+                    if (dec ? x[q] < y[q] : x[q] > y[q]) {
+                        t[i] = y[q];
+                        t[i + j] = x[q];
+                    }
                 }
             }
             __syncthreads();
@@ -146,6 +165,51 @@ __global__ void __launch_bounds__(kPtBlock) k_pt_extract(const uint64_t *__restr
         evl[p] = (uint32_t)(mask - (kk & mask));
         if (partial) partial[p] = pinit;
     });
+}
+
+// Evaluation of a large batch on full labels: like the winning tree's bulk
+// round, a wave takes many listed vertices and each lane keeps the last label it
+// gathered per sketch (most vertices of a sketch share its giant component, whose
+// entry every wave would otherwise re-read).  Keys written and Delta* raised as
+// in the per-vertex evaluation.  R <= 4 * 64.
+__global__ void __launch_bounds__(256) k_pt_eval_full_list(const uint32_t *__restrict__ evl, uint32_t m,
+                                                           const uint2 *__restrict__ E, uint32_t R, uint32_t kb,
+                                                           const uint8_t *__restrict__ in_s,
+                                                           uint64_t *__restrict__ key, SelState *__restrict__ st) {
+    constexpr int U = 4;
+    uint32_t last_l[U], last_y[U];
+#pragma unroll
+    for (int i = 0; i < U; ++i) last_l[i] = kNone, last_y[i] = 0;
+    const uint32_t lane = lane_id();
+    uint64_t best = 0;
+    for (uint32_t e = wave_index(); e < m; e += wave_count()) {
+        const uint32_t v = evl[e];
+        const uint2 *row = E + (size_t)v * R;
+        uint2 en[U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            const uint32_t r = lane + i * kWave;
+            en[i] = r < R ? row[r] : make_uint2(v, 0u);
+        }
+        uint64_t g = 0;
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            uint32_t y = en[i].y;
+            if (en[i].x != v) {
+                if (en[i].x != last_l[i]) {
+                    last_l[i] = en[i].x;
+                    last_y[i] = E[(size_t)en[i].x * R + lane + i * kWave].y;
+                }
+                y = last_y[i];
+            }
+            g += y;
+        }
+        g = wave_sum_u64(g);
+        const uint64_t nk = in_s[v] ? 0ull : pack_key(g, v, kb);
+        if (lane == 0) key[v] = nk;
+        best = nk > best ? nk : best;
+    }
+    if (lane == 0 && best) atomicMax(&st->delta, (unsigned long long)best);
 }
 
 // Evaluation of a batch whose keys are already fresh in key[] (the round

@@ -53,6 +53,7 @@ def _ptree_gpu(ctx, g, kind, p, R, k, seed, alpha, chunks=None):
     (13, U, 0.05, 64, 30, 4),
     (14, U, 0.3, 16, 20, 5),     # a giant component: round 1 re-evaluates most of 2^14 vertices
     (9, U, 0.02, 8, 512, 6),     # k = n: the queue runs empty
+    (15, U, 0.3, 8, 10, 12),     # batches of 2^14 vertices: the label-caching evaluation
 ])
 @pytest.mark.parametrize("alpha", [1.0, 0.25])
 def test_ptree_matches_oracle(ctx, scale, kind, p, R, k, seed, alpha):
