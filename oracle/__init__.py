@@ -27,6 +27,10 @@ NONE = 0xFFFFFFFF
 ALL_LIVE = 0xFFFFFFFFFFFFFFFF
 SALT_CENTER = 0xC000000000000001
 SALT_TRIV = 0xC000000000000002
+SALT_RANGE = 0xC000000000000003
+
+# edge-probability models (kind): Consistent p, trivalency, Uniform U(lo, hi) per edge, WIC 2 / (d_u + d_v)
+CONSTANT, TRIVALENCY, RANGE, WIC = 0, 1, 2, 3
 
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -47,11 +51,11 @@ def _load():
         lib.orc_threshold.restype = u64
         lib.orc_threshold.argtypes = [dbl]
         lib.orc_edge_threshold.restype = u64
-        lib.orc_edge_threshold.argtypes = [i32, dbl, u32, u32]
+        lib.orc_edge_threshold.argtypes = [i32, dbl, dbl, u32, u32, u64, u64]
         lib.orc_live.restype = i32
         lib.orc_live.argtypes = [u32, u32, u32, u64, u64]
         lib.orc_sketch.restype = ctypes.c_int64
-        lib.orc_sketch.argtypes = [u32, _u64p, _u32p, i32, dbl, u64, u32, _u32p, _u32p]
+        lib.orc_sketch.argtypes = [u32, _u64p, _u32p, i32, dbl, dbl, u64, u32, _u32p, _u32p]
         lib.orc_marginals.restype = None
         lib.orc_marginals.argtypes = [u32, u32, _u32p, _u32p, _u8p, u32, u32, _u64p]
         lib.orc_cover.restype = None
@@ -63,10 +67,10 @@ def _load():
         lib.orc_compact.restype = None
         lib.orc_compact.argtypes = [u32, u32, _u32p, _u32p, _u32p, _u32p, _u32p]
         lib.orc_getcenter.restype = u64
-        lib.orc_getcenter.argtypes = [u32, _u64p, _u32p, i32, dbl, u64, u32, _u32p, _u32p, _u32p, _u8p,
+        lib.orc_getcenter.argtypes = [u32, _u64p, _u32p, i32, dbl, dbl, u64, u32, _u32p, _u32p, _u32p, _u8p,
                                       u32, _u32p, _u8p, _u32p, _u64p]
         lib.orc_compact_greedy.restype = i32
-        lib.orc_compact_greedy.argtypes = [u32, _u64p, _u32p, i32, dbl, u64, u32, u32, _u32p, _u32p, _u32p,
+        lib.orc_compact_greedy.argtypes = [u32, _u64p, _u32p, i32, dbl, dbl, u64, u32, u32, _u32p, _u32p, _u32p,
                                            u32, _u32p, _u64p, _u64p]
         lib.orc_celf_evaluations.restype = i32
         lib.orc_celf_evaluations.argtypes = [u32, u32, _u32p, _u32p, u32, _u32p, _u64p, _u64p]
@@ -93,8 +97,16 @@ def threshold(p: float) -> int:
     return int(_load().orc_threshold(float(p)))
 
 
-def edge_threshold(kind: int, p: float, u: int, v: int) -> int:
-    return int(_load().orc_edge_threshold(kind, float(p), u, v))
+def _pp(p):
+    """p of a model: a float, or (lo, hi) for the Uniform range model."""
+    if isinstance(p, (tuple, list)):
+        return float(p[0]), float(p[1])
+    return float(p), 0.0
+
+
+def edge_threshold(kind: int, p, u: int, v: int, du: int = 0, dv: int = 0) -> int:
+    lo, hi = _pp(p)
+    return int(_load().orc_edge_threshold(kind, lo, hi, u, v, du, dv))
 
 
 def live(u: int, v: int, r: int, seed: int, T: int) -> bool:
@@ -106,7 +118,7 @@ def sketch(g, kind: int, p: float, seed: int, r: int):
     """Sketch(r) with full labels: (label[n], size[n]) by BFS."""
     lab = np.empty(max(g.n, 1), dtype=np.uint32)
     siz = np.empty(max(g.n, 1), dtype=np.uint32)
-    _load().orc_sketch(g.n, _p(g.offsets, _u64p), _p(g.cols, _u32p), kind, float(p), seed & ALL_LIVE, r,
+    _load().orc_sketch(g.n, _p(g.offsets, _u64p), _p(g.cols, _u32p), kind, *_pp(p), seed & ALL_LIVE, r,
                        _p(lab, _u32p), _p(siz, _u32p))
     return lab[: g.n], siz[: g.n]
 
@@ -119,7 +131,7 @@ def sketches(g, kind: int, p: float, seed: int, R: int, threads: int = 1, rs=Non
     lib = _load()
 
     def one(i):
-        lib.orc_sketch(g.n, _p(g.offsets, _u64p), _p(g.cols, _u32p), kind, float(p), seed & ALL_LIVE, rs[i],
+        lib.orc_sketch(g.n, _p(g.offsets, _u64p), _p(g.cols, _u32p), kind, *_pp(p), seed & ALL_LIVE, rs[i],
                        _p(lab[i], _u32p), _p(siz[i], _u32p))
 
     if threads <= 1:
@@ -215,7 +227,7 @@ def compact_greedy(g, kind: int, p: float, seed: int, cents: np.ndarray, label_c
     seeds = np.empty(max(k, 1), dtype=np.uint32)
     gains = np.empty(max(k, 1), dtype=np.uint64)
     visits = np.zeros(1, dtype=np.uint64)
-    rc = _load().orc_compact_greedy(g.n, _p(g.offsets, _u64p), _p(g.cols, _u32p), kind, float(p),
+    rc = _load().orc_compact_greedy(g.n, _p(g.offsets, _u64p), _p(g.cols, _u32p), kind, *_pp(p),
                                     seed & ALL_LIVE, R, rho, _p(cents, _u32p), _p(lc, _u32p), _p(sc, _u32p), k,
                                     _p(seeds, _u32p), _p(gains, _u64p), _p(visits, _u64p))
     if rc != 0:
@@ -235,7 +247,7 @@ def getcenter(g, kind, p, seed, r, cents, label_c_r, size_c_r, in_s, v):
     ins = np.ascontiguousarray(in_s, dtype=np.uint8)
     lc = np.ascontiguousarray(label_c_r, dtype=np.uint32)
     sc = np.ascontiguousarray(size_c_r, dtype=np.uint32)
-    d = _load().orc_getcenter(n, _p(g.offsets, _u64p), _p(g.cols, _u32p), kind, float(p), seed & ALL_LIVE, r,
+    d = _load().orc_getcenter(n, _p(g.offsets, _u64p), _p(g.cols, _u32p), kind, *_pp(p), seed & ALL_LIVE, r,
                               _p(rank, _u32p), _p(lc, _u32p), _p(sc, _u32p), _p(ins, _u8p), v, _p(l, _u32p),
                               _p(seen, _u8p), _p(queue, _u32p), _p(vis, _u64p))
     return int(d), int(l[0]), int(vis[0])

@@ -21,6 +21,11 @@
  *   - Trivalency edge probabilities: class = mix64(key ^ K(0, SALT_TRIV)) mod 3
  *     picks p in {0.1, 0.01, 0.001}; the class is a property of the edge, the
  *     same for every sketch and every sampling seed.
+ *   - Uniform model (p_e ~ U(lo, hi) once per edge): the threshold itself is
+ *     drawn, T_e = T(lo) + floor((T(hi) - T(lo)) * h_e / 2^64) with
+ *     h_e = mix64(key ^ K(0, SALT_RANGE)); a property of the edge.
+ *   - WIC model (p_e = 2 / (d_u + d_v)): T_e = floor(2^65 / (d_u + d_v)) exactly,
+ *     degrees of the undirected graph; d_u + d_v = 2 means always live.
  *   - Ties in the greedy argmax go to the smallest vertex id (Sec. 4 only says
  *     ties are broken by vertex id).
  *   - Centers of CompactSketch: v is a center iff mix64(v ^ K(seed, SALT_CENTER))
@@ -48,6 +53,7 @@
 #define ORC_PHI 0x9E3779B97F4A7C15ULL
 #define ORC_SALT_CENTER 0xC000000000000001ULL
 #define ORC_SALT_TRIV 0xC000000000000002ULL
+#define ORC_SALT_RANGE 0xC000000000000003ULL
 #define ORC_ALL_LIVE 0xFFFFFFFFFFFFFFFFULL
 #define ORC_NONE 0xFFFFFFFFu
 
@@ -78,14 +84,37 @@ static inline uint64_t orc_edge_key(uint32_t u, uint32_t v) {
     return ((uint64_t)a << 32) | b;
 }
 
-/* Edge probability model.  kind 0: uniform p on every edge.  kind 1:
- * trivalency, p_e drawn from {0.1, 0.01, 0.001} by the edge's hash class. */
-uint64_t orc_edge_threshold(int kind, double p, uint32_t u, uint32_t v) {
+/* Edge probability models, as integer thresholds T_e (edge live iff h < T_e).
+ *   kind 0 (Consistent, Sec. 5): the same p on every edge, T = T(p).
+ *   kind 1 (trivalency): p_e drawn from {0.1, 0.01, 0.001} by the edge's hash class.
+ *   kind 2 (Uniform, appendix on edge-probability distributions): p_e drawn
+ *     uniformly from [p, p_hi) once per edge.  Reading: with h_e =
+ *     mix64(key ^ K(0, SALT_RANGE)) a uniform 64-bit value of the edge,
+ *     T_e = T(p) + floor((T(p_hi) - T(p)) * h_e / 2^64), i.e. the threshold itself
+ *     is uniform over [T(p), T(p_hi)).  Requires 0 <= p <= p_hi < 1.
+ *   kind 3 (WIC, same appendix): p_e = 2 / (d_u + d_v) with d the vertex degrees
+ *     of the undirected graph.  T_e = floor(2^65 / (d_u + d_v)), the exact floor
+ *     of p_e * 2^64; d_u + d_v = 2 (an edge whose ends have no other edge) is
+ *     p_e = 1: always live.
+ * du, dv are only read by kind 3, p_hi only by kind 2. */
+uint64_t orc_edge_threshold(int kind, double p, double p_hi, uint32_t u, uint32_t v, uint64_t du, uint64_t dv) {
     if (kind == 0) return orc_threshold(p);
-    static const double tri[3] = {0.1, 0.01, 0.001};
-    uint64_t c = orc_mix64(orc_edge_key(u, v) ^ orc_key(0, ORC_SALT_TRIV)) % 3;
-    return orc_threshold(tri[c]);
+    if (kind == 1) {
+        static const double tri[3] = {0.1, 0.01, 0.001};
+        uint64_t c = orc_mix64(orc_edge_key(u, v) ^ orc_key(0, ORC_SALT_TRIV)) % 3;
+        return orc_threshold(tri[c]);
+    }
+    if (kind == 2) {
+        uint64_t lo = orc_threshold(p), hi = orc_threshold(p_hi);
+        uint64_t h = orc_mix64(orc_edge_key(u, v) ^ orc_key(0, ORC_SALT_RANGE));
+        return lo + (uint64_t)(((unsigned __int128)(hi - lo) * h) >> 64);
+    }
+    uint64_t s = du + dv;
+    if (s <= 2) return ORC_ALL_LIVE;
+    return (uint64_t)(((unsigned __int128)1 << 65) / s);
 }
+
+static inline uint64_t orc_deg(const uint64_t *offsets, uint32_t v) { return offsets[v + 1] - offsets[v]; }
 
 /* Sample(e, r) of Sec. 3: is edge {u,v} live in sketch r? */
 int orc_live(uint32_t u, uint32_t v, uint32_t r, uint64_t seed, uint64_t T) {
@@ -98,7 +127,7 @@ int orc_live(uint32_t u, uint32_t v, uint32_t r, uint64_t seed, uint64_t T) {
  * every vertex v: label[v] = smallest vertex id in v's CC of G'_r, size[v] =
  * |CC_r(v)|.  Computed by BFS from each not yet labelled vertex in increasing
  * id order, so the BFS source is the CC minimum.  Returns the number of CCs. */
-int64_t orc_sketch(uint32_t n, const uint64_t *offsets, const uint32_t *cols, int kind, double p,
+int64_t orc_sketch(uint32_t n, const uint64_t *offsets, const uint32_t *cols, int kind, double p, double p_hi,
                    uint64_t seed, uint32_t r, uint32_t *label, uint32_t *size) {
     uint32_t *queue = (uint32_t *)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
     for (uint32_t v = 0; v < n; ++v) label[v] = ORC_NONE;
@@ -113,7 +142,7 @@ int64_t orc_sketch(uint32_t n, const uint64_t *offsets, const uint32_t *cols, in
             for (uint64_t j = offsets[u]; j < offsets[u + 1]; ++j) {
                 uint32_t w = cols[j];
                 if (label[w] != ORC_NONE) continue;
-                if (!orc_live(u, w, r, seed, orc_edge_threshold(kind, p, u, w))) continue;
+                if (!orc_live(u, w, r, seed, orc_edge_threshold(kind, p, p_hi, u, w, orc_deg(offsets, u), orc_deg(offsets, w)))) continue;
                 label[w] = s;
                 queue[tail++] = w;
             }
@@ -212,7 +241,7 @@ void orc_compact(uint32_t n, uint32_t rho, const uint32_t *centers, const uint32
  * zeroed scratch array returned zeroed; queue holds n entries.  *visits gets
  * the number of vertices taken from the queue (the cost in Theorem 3.1). */
 uint64_t orc_getcenter(uint32_t n, const uint64_t *offsets, const uint32_t *cols, int kind, double p,
-                       uint64_t seed, uint32_t r, const uint32_t *center_rank, const uint32_t *label_c,
+                       double p_hi, uint64_t seed, uint32_t r, const uint32_t *center_rank, const uint32_t *label_c,
                        const uint32_t *size_c, const uint8_t *in_s, uint32_t v, uint32_t *l_out,
                        uint8_t *seen, uint32_t *queue, uint64_t *visits) {
     (void)n;
@@ -227,7 +256,7 @@ uint64_t orc_getcenter(uint32_t n, const uint64_t *offsets, const uint32_t *cols
         for (uint64_t j = offsets[u]; j < offsets[u + 1]; ++j) {
             uint32_t w = cols[j];
             if (seen[w]) continue;
-            if (!orc_live(u, w, r, seed, orc_edge_threshold(kind, p, u, w))) continue;
+            if (!orc_live(u, w, r, seed, orc_edge_threshold(kind, p, p_hi, u, w, orc_deg(offsets, u), orc_deg(offsets, w)))) continue;
             seen[w] = 1;
             queue[tail++] = w;
         }
@@ -250,7 +279,7 @@ uint64_t orc_getcenter(uint32_t n, const uint64_t *offsets, const uint32_t *cols
  * Sec. 3 say the result equals orc_greedy's on the same sketches.
  * *visits accumulates the vertices dequeued by every GetCenter call. */
 int orc_compact_greedy(uint32_t n, const uint64_t *offsets, const uint32_t *cols, int kind, double p,
-                       uint64_t seed, uint32_t R, uint32_t rho, const uint32_t *centers,
+                       double p_hi, uint64_t seed, uint32_t R, uint32_t rho, const uint32_t *centers,
                        const uint32_t *label_c, uint32_t *size_c, uint32_t k, uint32_t *seeds,
                        uint64_t *gains, uint64_t *visits) {
     if (k > n) return -1;
@@ -268,7 +297,7 @@ int orc_compact_greedy(uint32_t n, const uint64_t *offsets, const uint32_t *cols
             uint64_t g = 0;
             for (uint32_t r = 0; r < R; ++r) {
                 uint32_t l;
-                g += orc_getcenter(n, offsets, cols, kind, p, seed, r, rank, label_c + (size_t)r * rho,
+                g += orc_getcenter(n, offsets, cols, kind, p, p_hi, seed, r, rank, label_c + (size_t)r * rho,
                                    size_c + (size_t)r * rho, in_s, v, &l, seen, queue, &vis);
             }
             if (best == ORC_NONE || g > bestg) { best = v; bestg = g; }
@@ -277,7 +306,7 @@ int orc_compact_greedy(uint32_t n, const uint64_t *offsets, const uint32_t *cols
         gains[i] = bestg;
         for (uint32_t r = 0; r < R; ++r) {          /* MarkSeed */
             uint32_t l;
-            orc_getcenter(n, offsets, cols, kind, p, seed, r, rank, label_c + (size_t)r * rho,
+            orc_getcenter(n, offsets, cols, kind, p, p_hi, seed, r, rank, label_c + (size_t)r * rho,
                           size_c + (size_t)r * rho, in_s, best, &l, seen, queue, &vis);
             if (l != ORC_NONE) size_c[(size_t)r * rho + l] = 0;
         }

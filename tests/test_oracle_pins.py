@@ -167,30 +167,97 @@ def _tiny_graphs():
     return out
 
 
+def _threshold_spelled_out(kind, p, u, w, du, dw):
+    # the models' thresholds in Python integers from the published mixer, not the oracle
+    if kind == 0:
+        return oracle.threshold(p)
+    if kind == 1:
+        cls = brute.mix64_int(((u << 32) | w) ^ brute.key_int(0, oracle.SALT_TRIV)) % 3
+        return oracle.threshold((0.1, 0.01, 0.001)[cls])
+    if kind == 2:
+        lo, hi = oracle.threshold(p[0]), oracle.threshold(p[1])
+        h = brute.mix64_int(((min(u, w) << 32) | max(u, w)) ^ brute.key_int(0, oracle.SALT_RANGE))
+        return lo + (((hi - lo) * h) >> 64)
+    s_ = du + dw
+    return M64 if s_ <= 2 else (1 << 65) // s_
+
+
 def _live_edges(g, kind, p, seed, r):
     res = []
+    deg = np.diff(g.offsets.astype(np.int64))
     for u in range(g.n):
         for j in range(int(g.offsets[u]), int(g.offsets[u + 1])):
             w = int(g.cols[j])
             if u < w:
-                # the live test spelled out from the published mixer, not the oracle
-                T = oracle.threshold(p) if kind == 0 else None
-                if kind == 1:
-                    cls = brute.mix64_int(((u << 32) | w) ^ brute.key_int(0, oracle.SALT_TRIV)) % 3
-                    T = oracle.threshold((0.1, 0.01, 0.001)[cls])
+                T = _threshold_spelled_out(kind, p, u, w, int(deg[u]), int(deg[w]))
                 if T == M64 or brute.mix64_int(((u << 32) | w) ^ brute.key_int(seed, r)) < T:
                     res.append((u, w))
     return res
 
 
 @pytest.mark.parametrize("gi", range(6))
-def test_sketch_labels_match_transitive_closure(gi):
+@pytest.mark.parametrize("kind,p", [(0, 0.45), (1, 0.0), (2, (0.2, 0.7)), (3, 0.0)])
+def test_sketch_labels_match_transitive_closure(gi, kind, p):
     g = _tiny_graphs()[gi]
     for r in range(8):
-        edges = _live_edges(g, 0, 0.45, 3, r)
+        edges = _live_edges(g, kind, p, 3, r)
         lab_b, siz_b, _ = brute.closure_labels(g.n, edges)
-        lab, siz = oracle.sketch(g, 0, 0.45, 3, r)
+        lab, siz = oracle.sketch(g, kind, p, 3, r)
         assert np.array_equal(lab, lab_b) and np.array_equal(siz, siz_b)
+
+
+def test_uniform_range_thresholds():
+    # Uniform model (appendix on edge-probability distributions): one p_e per edge,
+    # uniform over [lo, hi), the same for every sketch and sampling seed
+    rng = np.random.default_rng(8)
+    lo, hi = 0.1, 0.3
+    TL, TH = oracle.threshold(lo), oracle.threshold(hi)
+    ts = []
+    for _ in range(20000):
+        a, b = (int(x) for x in rng.integers(0, 1 << 30, 2))
+        if a == b:
+            continue
+        T = oracle.edge_threshold(oracle.RANGE, (lo, hi), a, b)
+        assert T == oracle.edge_threshold(oracle.RANGE, (lo, hi), b, a)
+        assert TL <= T < TH
+        ts.append(T)
+    N = len(ts)
+    frac = np.array([t / 2.0**64 for t in ts])
+    # mean and every tenth of the range within 5 sigma of uniform
+    assert abs(frac.mean() - (lo + hi) / 2) <= 5 * (hi - lo) / math.sqrt(12 * N)
+    counts = np.histogram(frac, bins=10, range=(lo, hi))[0]
+    assert np.all(np.abs(counts - N / 10) <= 5 * math.sqrt(N * 0.1 * 0.9))
+    # lo == hi is the Consistent model
+    for a, b in [(1, 2), (5, 900), (77, 3)]:
+        assert oracle.edge_threshold(oracle.RANGE, (0.05, 0.05), a, b) == oracle.threshold(0.05)
+
+
+def test_wic_thresholds_are_exact_floors():
+    # WIC (same appendix): p_e = 2 / (d_u + d_v); T = floor(p_e * 2^64) exactly
+    for du in range(1, 60):
+        for dv in range(1, 60):
+            s_ = du + dv
+            T = oracle.edge_threshold(oracle.WIC, 0.0, 3, 9, du, dv)
+            if s_ == 2:
+                assert T == M64
+            else:
+                assert T * s_ <= 1 << 65 < (T + 1) * s_
+    for s_ in (3, 1000, 123457, (1 << 32) + 5):
+        T = oracle.edge_threshold(oracle.WIC, 0.0, 0, 1, s_ - 1, 1)
+        assert Fraction(T, 1 << 64) <= Fraction(2, s_) < Fraction(T + 1, 1 << 64)
+
+
+def test_wic_live_fraction_on_stars():
+    # star K_{1,d}: every edge has d_u + d_v = d + 1, so it is live with p = 2/(d+1);
+    # with d = 1 (a single edge) always
+    for d in (1, 3, 9):
+        g = inputs.csr_from_pairs(d + 1, [(0, i) for i in range(1, d + 1)])
+        R = 4000
+        lab, siz = oracle.sketches(g, oracle.WIC, 0.0, 17, R)
+        live = int((lab[:, 1:] == 0).sum())  # leaf i joined the center's component
+        N = R * d
+        pe = 2 / (d + 1)
+        assert abs(live - N * pe) <= 5 * math.sqrt(N * pe * (1 - pe)) + 1e-9, d
 
 
 # ---------------------------------------------------------------- greedy
