@@ -54,17 +54,26 @@ typedef struct im_ctx im_ctx;
 typedef struct im_graph im_graph;
 typedef struct im_sketches im_sketches;
 
-/* Edge-probability models (Sec. 5 uses a constant p per graph; Appendix A varies it). */
+/* Edge-probability models (Sec. 5 uses the same p on every edge; the appendix on
+ * edge-probability distributions adds per-edge Uniform and WIC assignments).
+ * Each becomes an integer threshold T_e, and edge e is live in sketch r iff
+ * mix64(((min<<32)|max) ^ K(seed, r)) < T_e, with T(p) = floor(p * 2^64). */
 typedef enum {
-    IM_PROB_UNIFORM = 0,     /* p_e = p for every edge                                    */
-    IM_PROB_TRIVALENCY = 1   /* p_e in {0.1, 0.01, 0.001}, chosen by
+    IM_PROB_UNIFORM = 0,     /* "Consistent": p_e = p for every edge                           */
+    IM_PROB_TRIVALENCY = 1,  /* p_e in {0.1, 0.01, 0.001}, chosen by
                                 mix64(((min<<32)|max) ^ K(0, 0xC000000000000002)) mod 3;
                                 a property of the edge, independent of the sampling seed */
+    IM_PROB_RANGE = 2,       /* "Uniform": p_e uniform over [p, p_hi), drawn once per edge:
+                                T_e = T(p) + floor((T(p_hi) - T(p)) * h_e / 2^64) with
+                                h_e = mix64(((min<<32)|max) ^ K(0, 0xC000000000000003))   */
+    IM_PROB_WIC = 3          /* "WIC": p_e = 2 / (d_u + d_v), d the degrees in the graph;
+                                T_e = floor(2^65 / (d_u + d_v)), always live when d_u + d_v = 2 */
 } im_prob_kind;
 
 typedef struct {
     int32_t kind;  /* im_prob_kind */
-    double p;      /* used by IM_PROB_UNIFORM; must lie in [0, 1] */
+    double p;      /* IM_PROB_UNIFORM: p in [0, 1]; IM_PROB_RANGE: the low end, 0 <= p <= p_hi */
+    double p_hi;   /* IM_PROB_RANGE: the high end, p_hi < 1; ignored otherwise */
 } im_prob;
 
 /* ---- context ------------------------------------------------------------ */

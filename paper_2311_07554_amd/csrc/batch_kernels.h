@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(1024) k_bat_hook(const BatchQuery *__restrict_
         const uint32_t b0 = pass * 64, nb = min(64u, Q.R - b0);
         const uint2 uv = Q.edges[e];
         const uint64_t x = ((uint64_t)uv.x << 32) | uv.y;
-        const uint64_t T = edge_threshold(Q.pm, x);
+        const uint64_t T = edge_threshold(Q.pm, uv.x, uv.y, x);
         uint64_t live;
         if (T == kAllLive) {
             live = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);

@@ -11,6 +11,7 @@ namespace pacim {
 constexpr uint64_t kPhi = 0x9E3779B97F4A7C15ull;
 constexpr uint64_t kSaltCenter = 0xC000000000000001ull;
 constexpr uint64_t kSaltTriv = 0xC000000000000002ull;
+constexpr uint64_t kSaltRange = 0xC000000000000003ull;
 constexpr uint64_t kAllLive = 0xFFFFFFFFFFFFFFFFull;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kWave = 64;
@@ -29,7 +30,7 @@ __host__ __device__ constexpr size_t sketch_stride(uint32_t n) {
 }
 
 // SplitMix64 output function (Steele, Lea, Flood 2014).  Two 64-bit multiplies.
-__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     z ^= z >> 30;
     z *= 0xBF58476D1CE4E5B9ull;
     z ^= z >> 27;
@@ -38,24 +39,55 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 }
 
 // K(seed, x): per-sketch (or per-salt) key of the live-edge hash.
-__device__ __forceinline__ uint64_t sketch_key(uint64_t seed, uint64_t x) { return mix64(seed * kPhi + x); }
+__host__ __device__ __forceinline__ uint64_t sketch_key(uint64_t seed, uint64_t x) { return mix64(seed * kPhi + x); }
 
 __device__ __forceinline__ uint64_t edge_word(uint32_t u, uint32_t v) {
     return u < v ? ((uint64_t)u << 32) | v : ((uint64_t)v << 32) | u;
 }
 
-// Probability model of one edge: uniform threshold, or the trivalency class.
+// Edge-probability models (the kind values of im_prob_kind) as integer
+// thresholds: an edge is live in a sketch iff its hash is below T_e.
+enum : int { kProbConstant = 0, kProbTrivalency = 1, kProbRange = 2, kProbWic = 3 };
+
 struct ProbDev {
-    int kind;          // 0 uniform, 1 trivalency
-    uint64_t t0;       // uniform threshold, or the p = 0.1 threshold
-    uint64_t t1, t2;   // p = 0.01, 0.001 thresholds (trivalency)
-    uint64_t ktriv;    // K(0, kSaltTriv)
+    int kind;
+    uint64_t t0;             // constant: T(p); trivalency: T(0.1); range: T(lo)
+    uint64_t t1, t2;         // trivalency: T(0.01), T(0.001); range: t1 = T(hi) - T(lo)
+    uint64_t ktriv;          // trivalency: K(0, kSaltTriv); range: K(0, kSaltRange)
+    const uint64_t *off;     // WIC: the graph's CSR offsets (degrees)
 };
 
-__device__ __forceinline__ uint64_t edge_threshold(const ProbDev &pm, uint64_t x) {
-    if (pm.kind == 0) return pm.t0;
-    uint64_t c = mix64(x ^ pm.ktriv) % 3u;
-    return c == 0 ? pm.t0 : (c == 1 ? pm.t1 : pm.t2);
+// floor(2^65 / s) = floor(2 / s * 2^64), the WIC threshold of an edge whose end
+// degrees sum to s (s <= 2: p = 1, always live).  64-bit operations only:
+// 2^64 - 1 = q s + r gives 2^64 = q1 s + m1, and 2^65 = 2 q1 s + 2 m1 with
+// 2 m1 < 2 s.
+__host__ __device__ __forceinline__ uint64_t wic_threshold(uint64_t s) {
+    if (s <= 2) return kAllLive;
+    const uint64_t q = ~0ull / s, r = ~0ull - q * s;
+    const bool wrap = r + 1 == s;
+    const uint64_t q1 = q + (wrap ? 1u : 0u), m1 = wrap ? 0u : r + 1;
+    return 2 * q1 + (2 * m1 >= s ? 1u : 0u);
+}
+
+// Threshold of edge {u, v} (canonical word x) under model KIND.
+template <int KIND>
+__device__ __forceinline__ uint64_t edge_threshold_of(const ProbDev &pm, uint32_t u, uint32_t v, uint64_t x) {
+    if (KIND == kProbConstant) return pm.t0;
+    if (KIND == kProbTrivalency) {
+        const uint64_t c = mix64(x ^ pm.ktriv) % 3u;
+        return c == 0 ? pm.t0 : (c == 1 ? pm.t1 : pm.t2);
+    }
+    if (KIND == kProbRange) return pm.t0 + __umul64hi(pm.t1, mix64(x ^ pm.ktriv));
+    return wic_threshold((pm.off[u + 1] - pm.off[u]) + (pm.off[v + 1] - pm.off[v]));
+}
+
+__device__ __forceinline__ uint64_t edge_threshold(const ProbDev &pm, uint32_t u, uint32_t v, uint64_t x) {
+    switch (pm.kind) {
+    case kProbConstant: return edge_threshold_of<kProbConstant>(pm, u, v, x);
+    case kProbTrivalency: return edge_threshold_of<kProbTrivalency>(pm, u, v, x);
+    case kProbRange: return edge_threshold_of<kProbRange>(pm, u, v, x);
+    default: return edge_threshold_of<kProbWic>(pm, u, v, x);
+    }
 }
 
 __device__ __forceinline__ bool is_live(uint64_t x, uint64_t kr, uint64_t T) {

@@ -223,6 +223,48 @@ uint64_t threshold_of(double p) {
     return (uint64_t)std::ldexp(p, 64);
 }
 
+// The first problem with an edge-probability model, or null if it is valid.
+const char *prob_problem(const im_prob &prob) {
+    switch (prob.kind) {
+    case IM_PROB_UNIFORM:
+        return (prob.p >= 0.0 && prob.p <= 1.0) ? nullptr : "p must lie in [0, 1]";
+    case IM_PROB_TRIVALENCY:
+    case IM_PROB_WIC:
+        return nullptr;
+    case IM_PROB_RANGE:
+        return (prob.p >= 0.0 && prob.p <= prob.p_hi && prob.p_hi < 1.0) ? nullptr
+                                                                          : "range model needs 0 <= p <= p_hi < 1";
+    default:
+        return "unknown probability model";
+    }
+}
+
+// Device form of a (valid) model on graph offsets `off` (read by WIC only).
+ProbDev prob_dev(const im_prob &prob, const uint64_t *off) {
+    ProbDev pm{};
+    pm.kind = prob.kind;
+    switch (prob.kind) {
+    case IM_PROB_UNIFORM:
+        pm.t0 = threshold_of(prob.p);
+        break;
+    case IM_PROB_TRIVALENCY:
+        pm.t0 = threshold_of(0.1);
+        pm.t1 = threshold_of(0.01);
+        pm.t2 = threshold_of(0.001);
+        pm.ktriv = sketch_key(0, kSaltTriv);
+        break;
+    case IM_PROB_RANGE:
+        pm.t0 = threshold_of(prob.p);
+        pm.t1 = threshold_of(prob.p_hi) - pm.t0;
+        pm.ktriv = sketch_key(0, kSaltRange);
+        break;
+    default:
+        pm.off = off;
+        break;
+    }
+    return pm;
+}
+
 uint32_t bit_length(uint64_t x) {
     uint32_t b = 0;
     while (x) { ++b; x >>= 1; }
@@ -544,10 +586,21 @@ void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const ui
     k_batch_init<<<gi, 256, 0, st>>>(cs.parent, cs.cnt, minc, n, minc_init, center_rank);
     {
         Prof p(ctx, "sample_hook", st);
-        if (pm.kind == 0)
-            k_sample_hook<0><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->m_und, K, b, pm, cs.parent, n);
-        else
-            k_sample_hook<1><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->m_und, K, b, pm, cs.parent, n);
+        switch (pm.kind) {
+        case kProbConstant:
+            k_sample_hook<kProbConstant><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->m_und, K, b, pm, cs.parent, n);
+            break;
+        case kProbTrivalency:
+            k_sample_hook<kProbTrivalency><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->m_und, K, b, pm, cs.parent,
+                                                                             n);
+            break;
+        case kProbRange:
+            k_sample_hook<kProbRange><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->m_und, K, b, pm, cs.parent, n);
+            break;
+        default:
+            k_sample_hook<kProbWic><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->m_und, K, b, pm, cs.parent, n);
+            break;
+        }
     }
     {
         Prof p(ctx, "compress", st);
@@ -601,10 +654,7 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
     *out = nullptr;
     if (R == 0) return fail(ctx, IM_EINVAL, "R must be >= 1");
     if (!(alpha > 0.0) || alpha > 1.0) return fail(ctx, IM_EINVAL, "alpha must lie in (0, 1]");
-    if (prob.kind != IM_PROB_UNIFORM && prob.kind != IM_PROB_TRIVALENCY)
-        return fail(ctx, IM_EINVAL, "unknown probability model");
-    if (prob.kind == IM_PROB_UNIFORM && !(prob.p >= 0.0 && prob.p <= 1.0))
-        return fail(ctx, IM_EINVAL, "p must lie in [0, 1]");
+    if (const char *why = prob_problem(prob)) return fail(ctx, IM_EINVAL, why);
     const uint32_t n = g->n;
     const uint32_t kb = std::max<uint32_t>(1, bit_length((uint64_t)n - 1));
     if (kb + bit_length((uint64_t)R * n + 1) > 64) return fail(ctx, IM_EINVAL, "R*n too large for 64-bit keys");
@@ -622,14 +672,8 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
     s->alpha = alpha;
     s->compact = alpha < 1.0;
     s->kb = kb;
-    s->pm.kind = prob.kind;
-    if (prob.kind == IM_PROB_UNIFORM) {
-        s->pm.t0 = threshold_of(prob.p);
-    } else {
-        s->pm.t0 = threshold_of(0.1);
-        s->pm.t1 = threshold_of(0.01);
-        s->pm.t2 = threshold_of(0.001);
-    }
+    s->pm = prob_dev(prob, g->off);
+    s->kc = sketch_key(seed, kSaltCenter);
     hipStream_t st = ctx->stream;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
@@ -660,20 +704,11 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
     } while (0)
 
     SK_HIP(hipEventRecord(t0, st));
-    // keys of sketches 0 .. Rpad-1 (the sampling kernel reads them 8 at a time), then
-    // K(0, SALT_TRIV) and K(seed, SALT_CENTER)
+    // keys of sketches 0 .. Rpad-1 (the sampling kernel reads them 8 at a time)
     const uint32_t Rpad = key_slots(R);
-    SK_TRY(sk_alloc(s, (size_t)Rpad + 2, &s->K));
+    SK_TRY(sk_alloc(s, (size_t)Rpad, &s->K));
     k_sketch_keys<<<grid_for(Rpad, 256, 1u << 20), 256, 0, st>>>(seed, Rpad, s->K);
-    k_salt_key<<<1, 64, 0, st>>>(0, kSaltTriv, s->K + Rpad);
-    k_salt_key<<<1, 64, 0, st>>>(seed, kSaltCenter, s->K + Rpad + 1);
     SK_HIP(hipGetLastError());
-    // the two salt keys are read back once so they can travel by value
-    uint64_t salts[2] = {0, 0};
-    SK_HIP(hipMemcpyAsync(salts, s->K + Rpad, 16, hipMemcpyDeviceToHost, st));
-    SK_HIP(hipStreamSynchronize(st));
-    s->pm.ktriv = salts[0];
-    s->kc = salts[1];
 
     // centers (CompactSketch)
     if (s->compact) {
@@ -1520,27 +1555,6 @@ namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-im_status check_prob(im_ctx *ctx, const im_prob &prob) {
-    if (prob.kind != IM_PROB_UNIFORM && prob.kind != IM_PROB_TRIVALENCY)
-        return fail(ctx, IM_EINVAL, "unknown probability model");
-    if (prob.kind == IM_PROB_UNIFORM && !(prob.p >= 0.0 && prob.p <= 1.0))
-        return fail(ctx, IM_EINVAL, "p must lie in [0, 1]");
-    return IM_OK;
-}
-
-ProbDev prob_dev(const im_prob &prob, uint64_t ktriv) {
-    ProbDev pm{};
-    pm.kind = prob.kind;
-    if (prob.kind == IM_PROB_UNIFORM) {
-        pm.t0 = threshold_of(prob.p);
-    } else {
-        pm.t0 = threshold_of(0.1);
-        pm.t1 = threshold_of(0.01);
-        pm.t2 = threshold_of(0.001);
-    }
-    pm.ktriv = ktriv;
-    return pm;
-}
 
 uint32_t cov_slots(uint32_t R, uint32_t k) {
     uint64_t need = 2ull * R * std::max<uint32_t>(k, 1) + 64;
@@ -1569,17 +1583,6 @@ void enqueue_prepare(BatchQuery *dq, uint32_t nq, const uint64_t *pre_prep, uint
 }
 
 // K(0, SALT_TRIV), computed on the device once per context.
-im_status trivalency_key(im_ctx *ctx, uint64_t *out) {
-    uint64_t *d = nullptr;
-    im_status rc = dev_alloc(ctx, 8, (void **)&d);
-    if (rc != IM_OK) return rc;
-    k_salt_key<<<1, 64, 0, ctx->stream>>>(0, kSaltTriv, d);
-    hipError_t e1 = hipMemcpyAsync(out, d, 8, hipMemcpyDeviceToHost, ctx->stream);
-    hipError_t e2 = hipStreamSynchronize(ctx->stream);
-    dev_free(ctx, d, 8);
-    if (e1 != hipSuccess || e2 != hipSuccess) return fail(ctx, IM_EDEVICE, "trivalency key read-back failed");
-    return IM_OK;
-}
 
 }  // namespace
 
@@ -1603,16 +1606,13 @@ extern "C" im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_
         if (Q.R == 0) return fail(ctx, IM_EINVAL, "R must be >= 1");
         if (Q.k > Q.graph->n) return fail(ctx, IM_EINVAL, "k exceeds n");
         if (!seeds_out[q] || !gains_out[q]) return fail(ctx, IM_EINVAL, "null output array");
-        im_status pr = check_prob(ctx, Q.prob);
-        if (pr != IM_OK) return pr;
+        if (const char *why = prob_problem(Q.prob)) return fail(ctx, IM_EINVAL, why);
         const uint32_t kb = std::max<uint32_t>(1, bit_length((uint64_t)Q.graph->n - 1));
         if (kb + bit_length((uint64_t)Q.R * Q.graph->n + 1) > 64) return fail(ctx, IM_EINVAL, "R*n too large");
     }
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
-    uint64_t ktriv = 0;
-    im_status rc = trivalency_key(ctx, &ktriv);
-    if (rc != IM_OK) return rc;
+    im_status rc = IM_OK;
 
     // one arena for every query's arrays
     std::vector<BatchQuery> hq(nq);
@@ -1649,7 +1649,7 @@ extern "C" im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_
         B.kb = std::max<uint32_t>(1, bit_length((uint64_t)n - 1));
         B.m = Q.graph->m_und;
         B.edges = Q.graph->edges;
-        B.pm = prob_dev(Q.prob, ktriv);
+        B.pm = prob_dev(Q.prob, Q.graph->off);
         B.cov_mask = cov_slots(R, Q.k) - 1;
         B.td = td;
     }

@@ -120,7 +120,6 @@ struct im_server {
     std::vector<const im_graph *> graphs;
     im_server_config cfg{};
     uint32_t nmax = 0;
-    uint64_t ktriv = 0;
     hipStream_t sel = nullptr, bld = nullptr;
     CCScratch cs;
     void *slab = nullptr;
@@ -199,7 +198,7 @@ SrvSet *srv_acquire_set(im_server *sv, const SrvTicket *t) {
     sv->peak = std::max(sv->peak, sv->sets_bytes + sv->slab_bytes);
     // build on the build stream; selection steps wait for `ready`
     k_sketch_keys<<<grid_for(key_slots(t->R), 256, 1u << 20), 256, 0, sv->bld>>>(sv->cfg.sample_seed, key_slots(t->R), s->K);
-    enqueue_full_build(sv->ctx, g, prob_dev(t->prob, sv->ktriv), s->K, t->R, sv->cs, s->E, s->gain0, sv->bld);
+    enqueue_full_build(sv->ctx, g, prob_dev(t->prob, g->off), s->K, t->R, sv->cs, s->E, s->gain0, sv->bld);
     (void)hipEventCreateWithFlags(&s->ready, hipEventDisableTiming);
     (void)hipEventRecord(s->ready, sv->bld);
     sv->sets.push_back(s);
@@ -256,7 +255,7 @@ void srv_admit(im_server *sv) {
         B.kb = std::max<uint32_t>(1, bit_length((uint64_t)g->n - 1));
         B.m = g->m_und;
         B.edges = g->edges;
-        B.pm = prob_dev(t->prob, sv->ktriv);
+        B.pm = prob_dev(t->prob, g->off);
         B.K = set->K;
         B.E = set->E;
         B.gain0 = set->gain0;
@@ -403,7 +402,7 @@ extern "C" im_status im_server_create(im_ctx *ctx, const im_graph *const *graphs
     c.max_active = std::min<uint32_t>(c.max_active, 256);
     sv->cfg = c;
     for (auto *g : sv->graphs) sv->nmax = std::max(sv->nmax, g->n);
-    im_status rc = trivalency_key(ctx, &sv->ktriv);
+    im_status rc = IM_OK;
     auto bail = [&](im_status code) {
         if (sv->sel) (void)hipStreamDestroy(sv->sel);
         if (sv->bld) (void)hipStreamDestroy(sv->bld);
@@ -471,8 +470,7 @@ extern "C" im_status im_server_submit(im_server *sv, uint32_t graph, im_prob pro
     if (!sv || !ticket) return IM_EINVAL;
     if (graph >= sv->graphs.size() || R == 0 || R > sv->cfg.max_R || k > sv->cfg.max_k || k > sv->graphs[graph]->n)
         return IM_EINVAL;
-    if (prob.kind != IM_PROB_UNIFORM && prob.kind != IM_PROB_TRIVALENCY) return IM_EINVAL;
-    if (prob.kind == IM_PROB_UNIFORM && !(prob.p >= 0.0 && prob.p <= 1.0)) return IM_EINVAL;
+    if (prob_problem(prob)) return IM_EINVAL;
     const uint32_t n = sv->graphs[graph]->n;
     const uint32_t kb = std::max<uint32_t>(1, bit_length((uint64_t)n - 1));
     if (kb + bit_length((uint64_t)R * n + 1) > 64) return IM_EINVAL;

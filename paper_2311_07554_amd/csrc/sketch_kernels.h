@@ -26,10 +26,6 @@ __global__ void k_sketch_keys(uint64_t seed, uint32_t R, uint64_t *__restrict__ 
     if (r < R) K[r] = sketch_key(seed, r);
 }
 
-__global__ void k_salt_key(uint64_t seed, uint64_t salt, uint64_t *__restrict__ out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *out = sketch_key(seed, salt);
-}
-
 // minc starts at each vertex's own center rank when center_rank is given (so a
 // root's own rank needs no atomic), else at minc_init.
 __global__ void k_batch_init(uint32_t *__restrict__ parent, uint32_t *__restrict__ cnt, uint32_t *__restrict__ minc,
@@ -97,15 +93,9 @@ __device__ __forceinline__ void uf_unite_from(uint32_t *P, uint32_t a, uint32_t 
 // Live mask of one edge word x over sketches [0, B): bit b set iff the edge is
 // live in sketch b.  K must hold round_up(B, 8) keys.
 template <int KIND>
-__device__ __forceinline__ uint64_t live_mask(uint64_t x, const uint64_t *__restrict__ K, uint32_t B,
-                                              const ProbDev &pm) {
-    uint64_t T;
-    if (KIND == 0) {
-        T = pm.t0;
-    } else {
-        const uint64_t c = mix64(x ^ pm.ktriv) % 3u;
-        T = c == 0 ? pm.t0 : (c == 1 ? pm.t1 : pm.t2);
-    }
+__device__ __forceinline__ uint64_t live_mask(uint32_t u, uint32_t v, uint64_t x, const uint64_t *__restrict__ K,
+                                              uint32_t B, const ProbDev &pm) {
+    const uint64_t T = edge_threshold_of<KIND>(pm, u, v, x);
     const uint64_t all = B >= 64 ? ~0ull : ((1ull << B) - 1ull);
     if (T == kAllLive) return all;
     uint64_t live = 0;
@@ -161,7 +151,7 @@ __global__ void __launch_bounds__(kHookBlock) k_sample_hook(const uint2 *__restr
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
         const uint2 uv = edges[e];
-        unite_live(parent, ns, live_mask<KIND>(((uint64_t)uv.x << 32) | uv.y, K, B, pm), uv.x, uv.y);
+        unite_live(parent, ns, live_mask<KIND>(uv.x, uv.y, ((uint64_t)uv.x << 32) | uv.y, K, B, pm), uv.x, uv.y);
     }
 }
 

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpacim.so")
 
 IM_OK, IM_EINVAL, IM_ENOMEM, IM_EDEVICE, IM_EBUSY, IM_EINTERNAL = range(6)
-IM_PROB_UNIFORM, IM_PROB_TRIVALENCY = 0, 1
+IM_PROB_UNIFORM, IM_PROB_TRIVALENCY, IM_PROB_RANGE, IM_PROB_WIC = 0, 1, 2, 3
 _STATUS = {0: "IM_OK", 1: "IM_EINVAL", 2: "IM_ENOMEM", 3: "IM_EDEVICE", 4: "IM_EBUSY", 5: "IM_EINTERNAL"}
 
 
@@ -30,7 +30,7 @@ class ImError(RuntimeError):
 
 
 class im_prob(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("p", ctypes.c_double)]
+    _fields_ = [("kind", ctypes.c_int32), ("p", ctypes.c_double), ("p_hi", ctypes.c_double)]
 
 
 class im_sketch_stats(ctypes.Structure):
@@ -202,8 +202,11 @@ def im_graph_free(g):
         raise ImError(rc, "im_graph_free")
 
 
-def _prob(kind: int, p: float):
-    return im_prob(int(kind), float(p))
+def _prob(kind: int, p):
+    """p: a float, or (lo, hi) for IM_PROB_RANGE."""
+    if isinstance(p, (tuple, list)):
+        return im_prob(int(kind), float(p[0]), float(p[1]))
+    return im_prob(int(kind), float(p), 0.0)
 
 
 def im_build_sketches(ctx, g, kind: int, p: float, R: int, seed: int, alpha: float = 1.0) -> int:
