@@ -78,9 +78,10 @@ def parse():
     ap.add_argument("--no-ptree", action="store_true",
                     help="skip the untimed comparison with NextSeed by prefix doubling")
     ap.add_argument("--cpu-sketches", type=int, default=16)
-    ap.add_argument("--workload", default="rmat20", choices=("rmat20", "batched", "serving"),
+    ap.add_argument("--workload", default="rmat20", choices=("rmat20", "batched", "serving", "sweep"),
                     help="rmat20: the headline workload; batched: 64 Chung-Lu graphs in one launch; "
-                         "serving: Poisson request stream over 16 resident R-MAT graphs")
+                         "serving: Poisson request stream over 16 resident R-MAT graphs; "
+                         "sweep: alpha and edge-probability models on the rmat20 graph")
     ap.add_argument("--queries", type=int, default=2000, help="serving: number of requests")
     ap.add_argument("--load", type=float, default=1.0,
                     help="serving: offered load as a multiple of the plain path's measured capacity")
@@ -293,6 +294,70 @@ def run_serving(args):
     print(json.dumps(out), flush=True)
 
 
+# edge-probability models of the sweep: Sec. 5's trivalency-like workload and the
+# appendix's per-edge assignments (Uniform U(0, 0.1) for social graphs, WIC)
+SWEEP_MODELS = [("trivalency", 1, 0.0), ("uniform U(0,0.1)", 2, (0.0, 0.1)), ("WIC 2/(du+dv)", 3, 0.0)]
+SWEEP_ALPHAS = [1.0, 0.5, 0.2, 0.1, 0.05, 0.02, 0.01]
+
+
+def run_sweep(args):
+    """Compression sweep (time and sketch memory against alpha) under each edge-probability
+    model on the rmat20 graph, with both selection structures; one JSON line."""
+    import numpy as np
+    import torch
+
+    from paper_2311_07554_amd import inputs, pacim
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    torch.cuda.set_device(0)
+    w = inputs.rmat20(R=args.R, k=args.k, scale=args.scale)
+    q = w.queries[0]
+    g = q.graph
+    ctx = pacim.Context(0)
+    gr = ctx.graph(g.n, g.offsets, g.cols)
+    rows = []
+    t_all = time.perf_counter()
+    for name, kind, p in SWEEP_MODELS:
+        for alpha in SWEEP_ALPHAS:
+            rec = {"model": name, "alpha": alpha}
+            for struct in ("winning_tree", "ptree"):
+                best = None
+                for _ in range(max(1, args.steps)):
+                    sk = gr.sketches(kind, p, q.R, q.seed, alpha)
+                    s, gn = sk.select(q.k) if struct == "winning_tree" else sk.select_ptree(q.k)
+                    st = sk.stats()
+                    sk.close()
+                    if best is None or st["select_ms"] < best[1]:
+                        best = (st["build_ms"], st["select_ms"], st["evaluations"], st["sketch_bytes"], s, gn)
+                if struct == "winning_tree":
+                    rec.update(build_ms=best[0], select_ms=best[1], evaluations=int(best[2]),
+                               sketch_bytes=int(best[3]), spread_estimate=float(best[5].sum()) / q.R)
+                    ref = (best[4], best[5])
+                else:
+                    assert np.array_equal(best[4], ref[0]) and np.array_equal(best[5], ref[1]), (name, alpha)
+                    rec.update(ptree_select_ms=best[1], ptree_evaluations=int(best[2]))
+            rows.append(rec)
+            print(f"[sweep] {name} alpha={alpha}: build {rec['build_ms']:.2f} ms, select {rec['select_ms']:.2f} ms "
+                  f"(prefix doubling {rec['ptree_select_ms']:.2f} ms), {rec['sketch_bytes'] / 2**20:.0f} MiB",
+                  file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t_all
+    gr.close()
+    ctx.close()
+    builds = len(rows) * 2 * max(1, args.steps)
+    out = {
+        "metric": "sketch build + k-seed selection time and sketch memory against alpha (paper: compression)",
+        "value": sum(r["build_ms"] + r["select_ms"] for r in rows) / len(rows),
+        "unit": "ms per (build + select), mean over the sweep",
+        "n_gpus": 1, "steps": args.steps, "warmup": 0, "ms_per_step": wall * 1e3 / builds,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"rmat{args.scale}_alpha_sweep", "n": g.n, "m_und": g.m_und, "R": q.R, "k": q.k,
+                   "models": [m[0] for m in SWEEP_MODELS], "alphas": SWEEP_ALPHAS,
+                   "parallelism": "single GPU"},
+        "rows": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -303,6 +368,8 @@ def main():
         return run_batched(args)
     if args.workload == "serving":
         return run_serving(args)
+    if args.workload == "sweep":
+        return run_sweep(args)
     import numpy as np
     import torch
 

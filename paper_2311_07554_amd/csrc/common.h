@@ -55,6 +55,8 @@ struct ProbDev {
     uint64_t t1, t2;         // trivalency: T(0.01), T(0.001); range: t1 = T(hi) - T(lo)
     uint64_t ktriv;          // trivalency: K(0, kSaltTriv); range: K(0, kSaltRange)
     const uint64_t *off;     // WIC: the graph's CSR offsets (degrees)
+    const uint64_t *csr_thr; // WIC, CompactSketch: the threshold of every CSR entry j (or null), so
+                             // that GetCenter's scans need neither the neighbour's degree nor a division
 };
 
 // floor(2^65 / s) = floor(2 / s * 2^64), the WIC threshold of an edge whose end

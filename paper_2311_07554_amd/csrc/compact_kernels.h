@@ -97,7 +97,7 @@ __device__ BfsOut getcenter_lds(const GraphDev &g, const ProbDev &pm, uint64_t k
             if (j < o1) {
                 w = g.cols[j];
                 const uint64_t x = edge_word(u, w);
-                live = is_live(x, kr, edge_threshold(pm, u, w, x));
+                live = is_live(x, kr, pm.csr_thr ? pm.csr_thr[j] : edge_threshold(pm, u, w, x));
             }
             const uint64_t cm = __ballot(live && center_flag(w, cd.kc, cd.Ta));
             if (cm) {
@@ -157,7 +157,7 @@ __device__ BfsOut getcenter_global(const GraphDev &g, const ProbDev &pm, uint64_
             if (j < o1) {
                 w = g.cols[j];
                 const uint64_t x = edge_word(u, w);
-                live = is_live(x, kr, edge_threshold(pm, u, w, x));
+                live = is_live(x, kr, pm.csr_thr ? pm.csr_thr[j] : edge_threshold(pm, u, w, x));
             }
             const uint64_t cm = __ballot(live && center_flag(w, cd.kc, cd.Ta));
             if (cm) {
@@ -476,7 +476,7 @@ __device__ uint32_t component_global(const GraphDev &g, const ProbDev &pm, uint6
             if (j < o1) {
                 w = g.cols[j];
                 const uint64_t x = edge_word(u, w);
-                if (is_live(x, kr, edge_threshold(pm, u, w, x))) {
+                if (is_live(x, kr, pm.csr_thr ? pm.csr_thr[j] : edge_threshold(pm, u, w, x))) {
                     const uint32_t bit = 1u << (w & 31);
                     ins = (atomicOr(&gvis[w >> 5], bit) & bit) == 0;
                 }

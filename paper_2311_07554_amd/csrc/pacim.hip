@@ -74,6 +74,8 @@ struct im_graph {
     uint64_t *off = nullptr;
     uint32_t *cols = nullptr;
     uint2 *edges = nullptr;
+    uint64_t *csr_thr = nullptr;  // WIC threshold per CSR entry; made by the first CompactSketch
+                                  // build under WIC (GetCenter's scans read it with the column)
 };
 
 struct im_sketches {
@@ -496,6 +498,7 @@ extern "C" im_status im_graph_free(im_graph *g) {
     dev_free(ctx, g->off, ((size_t)g->n + 1) * 8);
     dev_free(ctx, g->cols, g->m_dir * 4);
     dev_free(ctx, g->edges, g->m_und * 8);
+    if (g->csr_thr) dev_free(ctx, g->csr_thr, g->m_dir * 8);
     delete g;
     return IM_OK;
 }
@@ -674,6 +677,20 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
     s->kb = kb;
     s->pm = prob_dev(prob, g->off);
     s->kc = sketch_key(seed, kSaltCenter);
+    if (prob.kind == IM_PROB_WIC && alpha < 1.0 && g->m_dir) {
+        if (!g->csr_thr) {
+            im_graph *gm = const_cast<im_graph *>(g);
+            uint64_t *thr = nullptr;
+            const im_status a = dev_alloc(ctx, g->m_dir * 8, (void **)&thr);
+            if (a != IM_OK) {
+                delete s;
+                return a;
+            }
+            k_csr_wic_thr<<<wave_grid(g->n, 1u << 18), 256, 0, ctx->stream>>>(g->off, g->cols, g->n, thr);
+            gm->csr_thr = thr;
+        }
+        s->pm.csr_thr = g->csr_thr;
+    }
     hipStream_t st = ctx->stream;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {

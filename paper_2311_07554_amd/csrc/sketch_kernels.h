@@ -26,6 +26,21 @@ __global__ void k_sketch_keys(uint64_t seed, uint32_t R, uint64_t *__restrict__ 
     if (r < R) K[r] = sketch_key(seed, r);
 }
 
+// thr[j] = WIC threshold of CSR entry j (row u, column cols[j]); one wave per row.
+__global__ void __launch_bounds__(256) k_csr_wic_thr(const uint64_t *__restrict__ off,
+                                                     const uint32_t *__restrict__ cols, uint32_t n,
+                                                     uint64_t *__restrict__ thr) {
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+    for (uint32_t u = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; u < n; u += waves) {
+        const uint64_t o0 = off[u], o1 = off[u + 1];
+        for (uint64_t j = o0 + lane; j < o1; j += kWave) {
+            const uint32_t w = cols[j];
+            thr[j] = wic_threshold((o1 - o0) + (off[w + 1] - off[w]));
+        }
+    }
+}
+
 // minc starts at each vertex's own center rank when center_rank is given (so a
 // root's own rank needs no atomic), else at minc_init.
 __global__ void k_batch_init(uint32_t *__restrict__ parent, uint32_t *__restrict__ cnt, uint32_t *__restrict__ minc,

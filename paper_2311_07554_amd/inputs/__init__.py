@@ -35,6 +35,8 @@ _lib = None
 
 PROB_UNIFORM = 0
 PROB_TRIVALENCY = 1
+PROB_RANGE = 2
+PROB_WIC = 3
 
 
 def _load():
