@@ -74,6 +74,8 @@ def _load():
                                            u32, _u32p, _u64p, _u64p]
         lib.orc_celf_evaluations.restype = i32
         lib.orc_celf_evaluations.argtypes = [u32, u32, _u32p, _u32p, u32, _u32p, _u64p, _u64p]
+        lib.orc_influence.restype = u64
+        lib.orc_influence.argtypes = [u32, _u64p, _u32p, i32, dbl, dbl, _u32p, u32, u64, u32, u32]
         lib.orc_ptree.restype = i32
         lib.orc_ptree.argtypes = [u32, u32, _u32p, _u32p, u32, _u32p, _u64p, _u64p]
         _lib = lib
@@ -282,6 +284,25 @@ def ptree(label: np.ndarray, size: np.ndarray, k: int):
     if rc != 0:
         raise ValueError("bad k")
     return seeds[:k], gains[:k], ev[:k]
+
+
+def influence(g, kind: int, p, seeds, sim_seed: int, w0: int, sims: int, threads: int = 1) -> int:
+    """Sum over simulations w in [w0, w0 + sims) of the vertices the IC cascade from
+    `seeds` activates in live-edge world w (worlds keyed like sketches, under
+    sim_seed).  ``threads`` only splits the world range over host threads."""
+    seeds = np.ascontiguousarray(seeds, dtype=np.uint32)
+    lib = _load()
+
+    def part(ab):
+        a, b = ab
+        return int(lib.orc_influence(g.n, _p(g.offsets, _u64p), _p(g.cols, _u32p), kind, *_pp(p),
+                                     _p(seeds, _u32p), seeds.size, sim_seed & ALL_LIVE, a, b - a))
+    if threads <= 1 or sims < 2:
+        return part((w0, w0 + sims))
+    step = (sims + threads - 1) // threads
+    parts = [(a, min(w0 + sims, a + step)) for a in range(w0, w0 + sims, step)]
+    with ThreadPoolExecutor(threads) as ex:
+        return sum(ex.map(part, parts))
 
 
 def select_seeds(g, kind: int, p: float, R: int, k: int, seed: int, threads: int = 1):

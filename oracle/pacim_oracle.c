@@ -40,6 +40,9 @@
  * components, brute-force reachability and exact IC spread on tiny graphs,
  * closed forms).  orc_celf_evaluations is a measurement aid whose count is not
  * unique (it depends on the queue's tie handling): parity unpinned.
+ * orc_influence is pinned by the seeds' reach summed over worlds spelled out from
+ * the published mixer, by the IC cascade's exact expected spread (enumerated over
+ * coin flips) within 5 standard errors, and by the p = 0 / p = 1 closed forms.
  * orc_ptree's per-round evaluation counts are unique (the queue's order is total)
  * and pinned by hand-worked rounds of Algorithm 4, by Theorem 4.1 (the plain
  * greedy's seeds, also under many ties) and by Theorem 4.2 (at most twice CELF's
@@ -457,4 +460,40 @@ int orc_ptree(uint32_t n, uint32_t R, const uint32_t *label, const uint32_t *siz
     }
     free(covered); free(T); free(fresh); free(next); free(g0);
     return 0;
+}
+
+/* Influence spread of a seed set by simulation (the quality measure of Sec. 5,
+ * "influence evaluated by simulations"): under IC on an undirected graph one
+ * cascade flips every edge's coin once, so simulation w is the live-edge world
+ * of sketch key K(sim_seed, w) and the cascade from S activates every vertex
+ * connected to a seed there.  Returns the sum over worlds w in [w0, w0 + sims) of
+ * the number of activated vertices (a multi-source BFS per world); the estimate
+ * is that sum / sims.  Duplicate seeds count once.  Model arguments as
+ * orc_sketch. */
+uint64_t orc_influence(uint32_t n, const uint64_t *offsets, const uint32_t *cols, int kind, double p, double p_hi,
+                       const uint32_t *seeds, uint32_t k, uint64_t sim_seed, uint32_t w0, uint32_t sims) {
+    uint8_t *active = (uint8_t *)calloc((size_t)n + 1, 1);
+    uint32_t *queue = (uint32_t *)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
+    uint64_t total = 0;
+    for (uint32_t w = w0; w < w0 + sims; ++w) {
+        uint32_t head = 0, tail = 0;
+        for (uint32_t i = 0; i < k; ++i)
+            if (!active[seeds[i]]) { active[seeds[i]] = 1; queue[tail++] = seeds[i]; }
+        while (head < tail) {
+            uint32_t u = queue[head++];
+            for (uint64_t j = offsets[u]; j < offsets[u + 1]; ++j) {
+                uint32_t x = cols[j];
+                if (active[x]) continue;
+                if (!orc_live(u, x, w, sim_seed,
+                              orc_edge_threshold(kind, p, p_hi, u, x, orc_deg(offsets, u), orc_deg(offsets, x))))
+                    continue;
+                active[x] = 1;
+                queue[tail++] = x;
+            }
+        }
+        total += tail;
+        for (uint32_t i = 0; i < tail; ++i) active[queue[i]] = 0;
+    }
+    free(active); free(queue);
+    return total;
 }

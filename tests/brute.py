@@ -94,8 +94,10 @@ def best_k_subset(worlds, n, k):
 
 
 def exact_ic_spread(n, edges, p, S):
-    """E|activated| of the IC cascade started from S, as an exact Fraction."""
-    p = Fraction(p)
+    """E|activated| of the IC cascade started from S, as an exact Fraction.  p: one
+    probability for every edge, or a dict {(min, max): probability}."""
+    pe = {(min(u, v), max(u, v)): Fraction(p[(min(u, v), max(u, v))] if isinstance(p, dict) else p)
+          for u, v in edges}
     adj = {v: [] for v in range(n)}
     for u, v in edges:
         adj[u].append(v)
@@ -111,12 +113,13 @@ def exact_ic_spread(n, edges, p, S):
         for mask in range(1 << m):
             prob = Fraction(1)
             new = set()
-            for i, (_, w) in enumerate(attempts):
+            for i, (f, w) in enumerate(attempts):
+                q = pe[(min(f, w), max(f, w))]
                 if mask >> i & 1:
-                    prob *= p
+                    prob *= q
                     new.add(w)
                 else:
-                    prob *= 1 - p
+                    prob *= 1 - q
             if prob == 0:
                 continue
             total += prob * (rec(active | new, frozenset(new)) if new else Fraction(len(active)))

@@ -496,3 +496,44 @@ def test_ptree_matches_greedy_with_many_ties():
             s, gn, _ = oracle.ptree(lab, siz, g.n)
             s1, g1 = oracle.greedy(lab, siz, g.n)
             assert np.array_equal(s, s1) and np.array_equal(gn, g1), (seed, R)
+
+
+# ---------------------------------------------------------------- influence by simulation
+
+@pytest.mark.parametrize("gi", range(6))
+@pytest.mark.parametrize("kind,p", [(0, 0.35), (1, 0.0), (2, (0.2, 0.7)), (3, 0.0)])
+def test_influence_equals_reach_in_each_world(gi, kind, p):
+    # simulation w is live-edge world w: the sum of the seeds' reach over the worlds,
+    # with worlds spelled out from the published mixer and reach from closures
+    g = _tiny_graphs()[gi]
+    S = [0, g.n - 1, 0]
+    sims, sseed = 40, 77
+    want = 0
+    for w in range(5, 5 + sims):
+        A = brute.closure_labels(g.n, _live_edges(g, kind, p, sseed, w))[2]
+        want += brute.spread_in_world(A, sorted(set(S)))
+    assert oracle.influence(g, kind, p, S, sseed, 5, sims) == want
+
+
+def test_influence_matches_the_cascade_in_expectation():
+    # the IC cascade's exact expected spread (its definition, enumerated over coin
+    # flips) against the simulation mean, within 5 standard errors
+    n = 6
+    edges = [(0, 1), (1, 2), (2, 0), (2, 3), (3, 4), (4, 5), (1, 5)]
+    g = inputs.csr_from_pairs(n, edges)
+    deg = np.diff(g.offsets.astype(np.int64))
+    sims = 20000
+    cases = [(0, 0.5, None), (3, 0.0, {(min(u, v), max(u, v)): Fraction(2, int(deg[u] + deg[v])) for u, v in edges})]
+    for kind, p, pe in cases:
+        for S in ([0], [3, 5]):
+            exact = brute.exact_ic_spread(n, edges, pe if pe is not None else Fraction(1, 2), S)
+            est = Fraction(oracle.influence(g, kind, p, S, 123, 0, sims), sims)
+            assert abs(float(est - exact)) <= 5 * (n / 2) / math.sqrt(sims), (kind, S, float(est), float(exact))
+
+
+def test_influence_closed_forms():
+    comps = [[0, 1, 2], [3, 4], [5]]
+    g = inputs.csr_from_pairs(6, [(a, b) for c in comps for i, a in enumerate(c) for b in c[i + 1:]])
+    assert oracle.influence(g, 0, 0.0, [1, 4, 1], 5, 0, 30) == 30 * 2      # p = 0: the distinct seeds
+    assert oracle.influence(g, 0, 1.0, [1, 4, 1], 5, 0, 30) == 30 * 5      # p = 1: their components
+    assert oracle.influence(g, 0, 1.0, [5], 5, 0, 7) == 7
