@@ -162,6 +162,21 @@ im_status im_select_seeds_ptree(im_ctx *ctx, im_sketches *s, uint32_t k, uint32_
 im_status im_select_seeds(im_ctx *ctx, const im_graph *g, im_prob prob, uint32_t R, uint32_t k,
                           uint64_t seed, uint32_t *seeds_out, uint64_t *gains_out);
 
+/* ---- quality ------------------------------------------------------------- */
+
+/* Influence spread of a seed set by simulation (the quality measure of Sec. 5).
+ * Under IC on an undirected graph a cascade flips each edge's coin once, so
+ * simulation w is the live-edge world drawn like a sketch with key K(sim_seed, w),
+ * and the cascade from the seeds activates every vertex connected to one of them.
+ * *total_out = the sum over worlds w in [w0, w0 + sims) of the number of
+ * activated vertices; the spread estimate is *total_out / sims.  seeds: host
+ * array of k vertex ids (duplicates count once).  Worlds are labelled 64 per
+ * pass with the sketch kernels; device memory for that is held only during the
+ * call.  Errors: EINVAL (seed >= n, bad model, w0 + sims > 2^32), ENOMEM,
+ * EDEVICE. */
+im_status im_influence(im_ctx *ctx, const im_graph *g, im_prob prob, const uint32_t *seeds, uint32_t k,
+                       uint64_t sim_seed, uint32_t w0, uint32_t sims, uint64_t *total_out);
+
 /* ---- inspection (tests, measurement) -------------------------------------- */
 
 /* Sketch r as it was built (MarkSeed's zeroing not applied):

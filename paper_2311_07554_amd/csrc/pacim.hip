@@ -1420,6 +1420,58 @@ extern "C" im_status im_select_seeds(im_ctx *ctx, const im_graph *g, im_prob pro
     return rc;
 }
 
+// ---------------------------------------------------------------- influence by simulation
+extern "C" im_status im_influence(im_ctx *ctx, const im_graph *g, im_prob prob, const uint32_t *seeds, uint32_t k,
+                                  uint64_t sim_seed, uint32_t w0, uint32_t sims, uint64_t *total_out) {
+    if (!ctx || !g || !total_out || (k && !seeds)) return IM_EINVAL;
+    if (g->ctx != ctx) return fail(ctx, IM_EINVAL, "graph belongs to another context");
+    if (const char *why = prob_problem(prob)) return fail(ctx, IM_EINVAL, why);
+    for (uint32_t i = 0; i < k; ++i)
+        if (seeds[i] >= g->n) return fail(ctx, IM_EINVAL, "seed vertex out of range");
+    if ((uint64_t)w0 + sims > 0xFFFFFFFFull) return fail(ctx, IM_EINVAL, "world range exceeds 2^32");
+    *total_out = 0;
+    if (k == 0 || sims == 0) return IM_OK;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const ProbDev pm = prob_dev(prob, g->off);
+    const uint32_t nk = key_slots(sims);
+    auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t small = a256((size_t)nk * 8) + a256((size_t)k * 4) + 256;
+    void *blk = nullptr;
+    im_status rc = dev_alloc(ctx, small, &blk);
+    if (rc != IM_OK) return rc;
+    uint64_t *K = static_cast<uint64_t *>(blk);
+    uint32_t *sd = reinterpret_cast<uint32_t *>(static_cast<char *>(blk) + a256((size_t)nk * 8));
+    unsigned long long *tot =
+        reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(sd) + a256((size_t)k * 4));
+    CCScratch cs;
+    rc = cc_scratch_alloc(ctx, g, sims, true, &cs);
+    if (rc != IM_OK) {
+        dev_free(ctx, blk, small);
+        return rc;
+    }
+    unsigned long long host_total = 0;
+    hipError_t e = hipMemcpyAsync(sd, seeds, (size_t)k * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(tot, 0, 8, st);
+    if (e == hipSuccess) {
+        k_world_keys<<<(nk + 255) / 256, 256, 0, st>>>(sim_seed, w0, nk, K);
+        for (uint32_t a = 0; a < sims; a += cs.B) {
+            const uint32_t b = std::min(cs.B, sims - a);
+            enqueue_cc_pass(ctx, g, pm, K + a, b, cs, cs.minc, 0u, nullptr);
+            k_influence_accum<<<dim3(grid_for(k, 256, 64), b), 256, 0, st>>>(cs.parent, cs.cnt, cs.minc, g->n, sd, k,
+                                                                            tot);
+        }
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(&host_total, tot, 8, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    cc_scratch_free(ctx, &cs);
+    dev_free(ctx, blk, small);
+    if (e != hipSuccess) return fail(ctx, IM_EDEVICE, std::string("influence: ") + hipGetErrorString(e));
+    *total_out = host_total;
+    return IM_OK;
+}
+
 // ---------------------------------------------------------------- inspection
 namespace {
 

@@ -26,6 +26,29 @@ __global__ void k_sketch_keys(uint64_t seed, uint32_t R, uint64_t *__restrict__ 
     if (r < R) K[r] = sketch_key(seed, r);
 }
 
+// K(seed, first + i) for i < count: the keys of a range of simulated worlds.
+__global__ void k_world_keys(uint64_t seed, uint32_t first, uint32_t count, uint64_t *__restrict__ K) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) K[i] = sketch_key(seed, (uint64_t)first + i);
+}
+
+// Influence by simulation: for each of the pass's B worlds (labelled, compressed),
+// the seeds' distinct components, each counted once through flag[b][root], their
+// sizes (1 + members counted at the root) summed into *total.  grid (x, B).
+__global__ void __launch_bounds__(256) k_influence_accum(const uint32_t *__restrict__ parent,
+                                                         const uint32_t *__restrict__ cnt, uint32_t *__restrict__ flag,
+                                                         uint32_t n, const uint32_t *__restrict__ seeds, uint32_t k,
+                                                         unsigned long long *__restrict__ total) {
+    const size_t base = (size_t)blockIdx.y * sketch_stride(n);
+    uint64_t sum = 0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+        const uint32_t root = parent[base + seeds[i]];
+        if (atomicExch(&flag[base + root], 1u) == 0u) sum += 1u + cnt[base + root];
+    }
+    sum = wave_sum_u64(sum);
+    if (lane_id() == 0 && sum) atomicAdd(total, (unsigned long long)sum);
+}
+
 // thr[j] = WIC threshold of CSR entry j (row u, column cols[j]); one wave per row.
 __global__ void __launch_bounds__(256) k_csr_wic_thr(const uint64_t *__restrict__ off,
                                                      const uint32_t *__restrict__ cols, uint32_t n,

@@ -84,6 +84,8 @@ _SIGS = {
     "im_sketches_free": (ctypes.c_int, [_vp]),
     "im_select_seeds_from": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _u32p, _u64p]),
     "im_select_seeds_ptree": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _u32p, _u64p]),
+    "im_influence": (ctypes.c_int, [_vp, _vp, im_prob, _u32p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
+                                    ctypes.c_uint32, _u64p]),
     "im_select_seeds": (ctypes.c_int, [_vp, _vp, im_prob, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
                                        _u32p, _u64p]),
     "im_sketches_dump": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _u32p, _u32p]),
@@ -234,6 +236,14 @@ def im_select_seeds_ptree(ctx, s, k: int):
     gains = np.empty(max(k, 1), dtype=np.uint64)
     _check(ctx, load().im_select_seeds_ptree(ctx, s, k, _u32(seeds), _u64(gains)))
     return seeds[:k], gains[:k]
+
+
+def im_influence(ctx, g, kind: int, p, seeds, sim_seed: int, w0: int, sims: int) -> int:
+    sd = np.ascontiguousarray(seeds, dtype=np.uint32)
+    tot = np.zeros(1, dtype=np.uint64)
+    _check(ctx, load().im_influence(ctx, g, _prob(kind, p), _u32(sd if sd.size else np.zeros(1, np.uint32)),
+                                    int(sd.size), sim_seed & ((1 << 64) - 1), int(w0), int(sims), _u64(tot)))
+    return int(tot[0])
 
 
 def im_select_seeds(ctx, g, kind: int, p: float, R: int, k: int, seed: int):
@@ -410,6 +420,10 @@ class Graph:
 
     def select_seeds(self, kind, p, R, k, seed):
         return im_select_seeds(self.ctx.h, self.h, kind, p, R, k, seed)
+
+    def influence(self, kind, p, seeds, sim_seed, w0=0, sims=20000):
+        """Sum over simulated worlds [w0, w0 + sims) of the seeds' activated vertices."""
+        return im_influence(self.ctx.h, self.h, kind, p, seeds, sim_seed, w0, sims)
 
 
 class Sketches:
