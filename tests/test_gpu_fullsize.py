@@ -11,7 +11,9 @@ checked output by output:
 * at sampled rounds, the seed against the argmax (smallest id on ties) of the
   marginals of all n vertices given the earlier seeds;
 * CompactSketch: sampled sketches' triples, and seeds and gains equal to the
-  full-label ones (alpha-equivalence).
+  full-label ones (alpha-equivalence);
+* NextSeed by prefix doubling: seeds, gains and per-round evaluation counts
+  against the oracle's Algorithm 4 run whole on the 256 sketches.
 """
 import os
 
@@ -109,6 +111,24 @@ def test_rmat20_compact_sampled_parity(ctx, workload):
         for i, s in enumerate(seeds):
             assert int(cov.marginals(int(s), int(s) + 1)[0]) == int(gains[i]), i
             cov.cover(int(s))
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.1])
+def test_rmat20_prefix_doubling_full_size(ctx, workload, alpha):
+    # NextSeed by prefix doubling (Algorithm 4) on the benchmark's sketches: seeds, gains
+    # and every round's evaluation count against the oracle run whole (its round 1
+    # re-evaluates all but a few of the 2^20 vertices)
+    q, lab, siz, _ = workload
+    ws, wg, wev = oracle.ptree(lab, siz, q.k)
+    gr = upload(ctx, q.graph)
+    sk = gr.sketches(q.prob_kind, q.p, q.R, q.seed, alpha)
+    s, gn = sk.select_ptree(q.k)
+    ev = sk.trace()
+    sk.close()
+    gr.close()
+    _say(f"  prefix doubling alpha={alpha}: evaluations {int(ev.sum())}, largest round {int(ev.max())}")
+    assert np.array_equal(s, ws) and np.array_equal(gn, wg)
+    assert np.array_equal(ev.astype(np.uint64), wev)
 
 
 def test_rmat24_compact_full_size(ctx):
