@@ -78,8 +78,8 @@ def parse():
     ap.add_argument("--no-ptree", action="store_true",
                     help="skip the untimed comparison with NextSeed by prefix doubling")
     ap.add_argument("--cpu-sketches", type=int, default=16)
-    ap.add_argument("--workload", default="rmat20", choices=("rmat20", "batched", "serving", "sweep", "quality"),
-                    help="rmat20: the headline workload; batched: 64 Chung-Lu graphs in one launch; "
+    ap.add_argument("--workload", default="rmat20", choices=("rmat20", "rmat24", "batched", "serving", "sweep", "quality"),
+                    help="rmat20: the headline workload; rmat24: the 2^24-vertex CompactSketch configuration; batched: 64 Chung-Lu graphs in one launch; "
                          "serving: Poisson request stream over 16 resident R-MAT graphs; "
                          "sweep: alpha and edge-probability models on the rmat20 graph; "
                          "quality: spread of the seeds against R by simulation")
@@ -443,13 +443,23 @@ def main():
     assert torch.cuda.is_available(), "no GPU visible"
     torch.cuda.set_device(0)
     t = time.perf_counter()
-    w = inputs.rmat20(R=args.R, k=args.k, scale=args.scale)
+    if args.workload == "rmat24":
+        # the 2^24-vertex configuration: uniform p = 0.02, R = 256, k = 200, CompactSketch only
+        scale = 24
+        w = inputs.rmat24()
+        modes = ["compact"]
+        args.alpha = w.queries[0].alpha
+    else:
+        scale = args.scale
+        w = inputs.rmat20(R=args.R, k=args.k, scale=args.scale)
+        modes = [m for m in args.modes.split(",") if m]
     q = w.queries[0]
     g = q.graph
     print(f"[bench] graph {g.name}: n={g.n} m_und={g.m_und} generated in {time.perf_counter() - t:.1f}s",
           file=sys.stderr, flush=True)
-    modes = [m for m in args.modes.split(",") if m]
     alphas = {"full": 1.0, "compact": args.alpha}
+    prob_name = "trivalency {0.1,0.01,0.001}" if q.prob_kind == inputs.PROB_TRIVALENCY else f"uniform p={q.p}"
+    prob_tag = "trivalency" if q.prob_kind == inputs.PROB_TRIVALENCY else f"p{q.p}"
 
     stream = torch.cuda.Stream()
     ctx = pacim.Context(0, stream)
@@ -522,7 +532,8 @@ def main():
     roofline = None
     if hk["avg_ms"]:
         achieved = hashes_per_launch / (hk["avg_ms"] / 1e3) / 1e9
-        tr = sampling_kernel_traffic() if (args.scale == 20 and B == 64 and q.R == 256) else None
+        tr = sampling_kernel_traffic() if (scale == 20 and B == 64 and q.R == 256 and
+                                           q.prob_kind == inputs.PROB_TRIVALENCY) else None
         roofline = {"bound": "alu", "kernel": hk_name, "achieved": achieved, "peak": HASH_PEAK_G,
                     "unit": "Ghash/s", "frac": achieved / HASH_PEAK_G,
                     "traffic": tr["bytes"] if tr else None,
@@ -566,9 +577,9 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": f"rmat{args.scale}_trivalency_R{R}_k{q.k}_" + "+".join(modes),
+        "config": {"workload": f"rmat{scale}_{prob_tag}_R{R}_k{q.k}_" + "+".join(modes),
                    "n": n, "m_und": m_und, "R": R, "k": q.k, "alpha_compact": args.alpha,
-                   "prob": "trivalency {0.1,0.01,0.001}", "parallelism": "single GPU"},
+                   "prob": prob_name, "parallelism": "single GPU"},
         "breakdown": breakdown,
         "selection_structures": trees or None,
         "kernels": kern,
@@ -577,7 +588,7 @@ def main():
                          "hbm_peak_GB_s": HBM_PEAK_GBS},
         "seeds_head": [int(x) for x in res[modes[0]][0][:5]],
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "rmat20":
         print("[bench] timing the oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(g, q.prob_kind, q.p, R, q.k, q.seed, args.cpu_sketches)
     gr.close()

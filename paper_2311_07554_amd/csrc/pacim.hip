@@ -774,12 +774,10 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
         enqueue_cc_pass(ctx, g, s->pm, s->K + r0, b, cs, minc, kNone, s->compact ? s->center_rank : nullptr);
         if (s->compact) {
             Prof p(ctx, "emit");
-            dim3 ge((std::max<uint32_t>(s->rho, 1) + 255) / 256, b);
-            if (s->rho)
-                k_emit_compact<<<ge, 256, 0, st>>>(parent, cnt, minc, s->centers, s->rho, n, r0, s->label_c, s->size_c,
-                                                   s->gbest + r0);
-            k_gain0<<<(n + 255) / 256, 256, 0, st>>>(parent, cnt, n, b, s->gain0, s->gbest + r0,
-                                                     s->gbits + (size_t)r0 * s->nw, s->nw);
+            k_giant_sample<<<b, 256, 0, st>>>(parent, cnt, n, s->gbest + r0);
+            k_gain0_emit<<<(n + 255) / 256, 256, 0, st>>>(parent, cnt, minc, s->center_rank, s->rho, n, b, r0,
+                                                          s->label_c, s->size_c, s->gain0, s->gbest + r0,
+                                                          s->gbits + (size_t)r0 * s->nw, s->nw);
         } else {
             Prof p(ctx, "emit");
             k_emit_full<<<(n + kEmitTile - 1) / kEmitTile, 256, 0, st>>>(parent, cnt, n, b, R, r0, s->E, s->gain0);

@@ -10,10 +10,10 @@
 //                     non-root members counted at the root; centers' smallest
 //                     rank recorded at the root (CompactSketch)
 //   k_emit_full       (label, size) per (v, r) into E[n][R] and the initial gains
-//   k_emit_compact    CompactSketch triple label_c / size_c [R][rho], and the
-//                     largest component holding a center per sketch
-//   k_gain0           initial gains when only the compact triple is kept, and
-//                     the largest components' membership bitmaps
+//   k_giant_sample    per sketch, the largest component among sampled vertices'
+//   k_gain0_emit      CompactSketch: the triple label_c / size_c [R][rho], the
+//                     initial gains and that component's membership bitmap, in
+//                     one pass over the vertices
 //   k_center_*        hashed Bernoulli(alpha) centers, ranked by id
 #pragma once
 
@@ -298,63 +298,81 @@ __global__ void __launch_bounds__(256) k_emit_full(const uint32_t *__restrict__ 
     }
 }
 
-// grid: (ceil(rho/256), B).  Also the sketch's largest component among those
-// holding a center (smallest root on equal sizes): gbest[b] = max of
-// (size << 32) | (2^32 - 1 - root), zeroed by the caller.  The largest component
-// of a sketch holds a center unless it is smaller than about 1/alpha; the
-// bitmap bulk rounds need some large component, not necessarily the largest.
-__global__ void __launch_bounds__(256) k_emit_compact(const uint32_t *__restrict__ parent,
-                                                      const uint32_t *__restrict__ cnt,
-                                                      const uint32_t *__restrict__ minc,
-                                                      const uint32_t *__restrict__ centers, uint32_t rho,
-                                                      uint32_t n, uint32_t r0, uint32_t *__restrict__ label_c,
-                                                      uint32_t *__restrict__ size_c,
+// The largest component packed as (size << 32) | (2^32 - 1 - root).
+__device__ __forceinline__ uint32_t giant_root_of(uint64_t gbest) { return 0xFFFFFFFFu - (uint32_t)gbest; }
+__device__ __forceinline__ uint32_t giant_size_of(uint64_t gbest) { return (uint32_t)(gbest >> 32); }
+
+// Per sketch (one workgroup each), the largest of the components of kGiantSamples
+// evenly spaced vertices: when a sketch has a giant component (the case the
+// bitmaps serve), one of the samples lies in it.  Any component is correct for
+// the bulk rounds that use it; a small one only makes them search more.
+constexpr uint32_t kGiantSamples = 1024;
+__global__ void __launch_bounds__(256) k_giant_sample(const uint32_t *__restrict__ parent,
+                                                      const uint32_t *__restrict__ cnt, uint32_t n,
                                                       unsigned long long *__restrict__ gbest) {
     __shared__ unsigned long long best_w[256 / kWave];
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t b = blockIdx.y;
+    const size_t base = (size_t)blockIdx.x * sketch_stride(n);
     unsigned long long best = 0;
-    if (i < rho) {
-        const size_t base = (size_t)b * sketch_stride(n);
-        const uint32_t v = centers[i];
+    for (uint32_t j = threadIdx.x; j < kGiantSamples; j += blockDim.x) {
+        const uint32_t v = (uint32_t)((uint64_t)j * n / kGiantSamples);
         const uint32_t root = parent[base + v];
-        const uint32_t l = minc[base + root];
-        const uint32_t sz = 1u + cnt[base + root];
-        const size_t at = (size_t)(r0 + b) * rho + i;
-        label_c[at] = l;
-        size_c[at] = (l == i) ? sz : 0u;
-        best = ((unsigned long long)sz << 32) | (0xFFFFFFFFull - root);
+        const unsigned long long c = ((unsigned long long)(1u + cnt[base + root]) << 32) | (0xFFFFFFFFull - root);
+        best = c > best ? c : best;
     }
     best = wave_max_u64(best);
     if (lane_id() == 0) best_w[threadIdx.x / kWave] = best;
     __syncthreads();
     if (threadIdx.x == 0) {
         for (uint32_t w = 1; w < blockDim.x / kWave; ++w) best = best_w[w] > best ? best_w[w] : best;
-        if (best) atomicMax(&gbest[b], best);
+        gbest[blockIdx.x] = best;
     }
 }
 
-// The largest component recorded for a sketch, as packed by k_emit_compact.
-__device__ __forceinline__ uint32_t giant_root_of(uint64_t gbest) { return 0xFFFFFFFFu - (uint32_t)gbest; }
-__device__ __forceinline__ uint32_t giant_size_of(uint64_t gbest) { return (uint32_t)(gbest >> 32); }
-
-// Initial gains when only the compact triple is kept, and (gbits non-null) the
-// membership bitmap of each sketch's recorded largest component: bit v of
-// gbits[b][v / 64] = [v lies in the component rooted at giant_root_of(gbest[b])].
-__global__ void __launch_bounds__(256) k_gain0(const uint32_t *__restrict__ parent, const uint32_t *__restrict__ cnt,
-                                               uint32_t n, uint32_t B, uint64_t *__restrict__ gain0,
-                                               const unsigned long long *__restrict__ gbest,
-                                               uint64_t *__restrict__ gbits, uint32_t nw) {
+// One pass over every vertex of the pass's B sketches (compressed: parent[b][v] is
+// v's root) for CompactSketch:
+//   - the initial gains, sum over sketches of |CC_b(v)|;
+//   - gbits non-null: bit v of gbits[b][v / 64] = [v lies in the component of
+//     giant_root_of(gbest[b])];
+//   - for a center v of rank cr, its triple entries label_c[r0 + b][cr] = the
+//     smallest center rank in its component (minc at the root) and size_c = the
+//     component size if that rank is cr's own, else 0.
+__global__ void __launch_bounds__(256) k_gain0_emit(const uint32_t *__restrict__ parent,
+                                                    const uint32_t *__restrict__ cnt,
+                                                    const uint32_t *__restrict__ minc,
+                                                    const uint32_t *__restrict__ center_rank, uint32_t rho,
+                                                    uint32_t n, uint32_t B, uint32_t r0,
+                                                    uint32_t *__restrict__ label_c, uint32_t *__restrict__ size_c,
+                                                    uint64_t *__restrict__ gain0,
+                                                    const unsigned long long *__restrict__ gbest,
+                                                    uint64_t *__restrict__ gbits, uint32_t nw) {
+    constexpr uint32_t U = 4;  // sketches whose root and size loads are issued together (8 was slower)
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = v < n;
+    const uint32_t cr = valid ? center_rank[v] : kNone;
+    const size_t ns = sketch_stride(n);
     uint64_t s = 0;
-    for (uint32_t b = 0; b < B; ++b) {
-        const size_t base = (size_t)b * sketch_stride(n);
-        const uint32_t root = valid ? parent[base + v] : kNone;
-        if (valid) s += 1u + cnt[base + root];
-        if (gbits) {
-            const uint64_t m = __ballot(valid && root == giant_root_of(gbest[b]));
-            if (lane_id() == 0 && (v >> 6) < nw) gbits[(size_t)b * nw + (v >> 6)] = m;
+    for (uint32_t b0 = 0; b0 < B; b0 += U) {
+        uint32_t root[U], sz[U], l[U];
+#pragma unroll
+        for (uint32_t i = 0; i < U; ++i) root[i] = (valid && b0 + i < B) ? parent[(b0 + i) * ns + v] : kNone;
+#pragma unroll
+        for (uint32_t i = 0; i < U; ++i) sz[i] = root[i] != kNone ? 1u + cnt[(b0 + i) * ns + root[i]] : 0u;
+#pragma unroll
+        for (uint32_t i = 0; i < U; ++i) l[i] = (cr != kNone && root[i] != kNone) ? minc[(b0 + i) * ns + root[i]] : kNone;
+#pragma unroll
+        for (uint32_t i = 0; i < U; ++i) {
+            const uint32_t b = b0 + i;
+            if (b >= B) break;
+            s += sz[i];
+            if (cr != kNone && root[i] != kNone) {
+                const size_t at = (size_t)(r0 + b) * rho + cr;
+                label_c[at] = l[i];
+                size_c[at] = (l[i] == cr) ? sz[i] : 0u;
+            }
+            if (gbits) {
+                const uint64_t m = __ballot(valid && root[i] == giant_root_of(gbest[b]));
+                if (lane_id() == 0 && (v >> 6) < nw) gbits[(size_t)b * nw + (v >> 6)] = m;
+            }
         }
     }
     if (valid) gain0[v] += s;
