@@ -38,21 +38,31 @@ struct CompactDev {
     uint32_t *size_c;              // [R][rho]
     uint32_t rho;
     uint64_t kc, Ta;               // center test: mix64(v ^ kc) < Ta (a hash, no memory access)
-    unsigned long long *memo;      // [slots][R] GetCenter labels: (v << 32) | label, ~0 if empty
+    unsigned long long *memo;      // [slots][R][2] kept GetCenter results (below), ~0 if empty
     uint32_t memo_mask;            // slots - 1 (slots a power of two)
     uint32_t R;
+    unsigned long long *covmin;    // [R][nw] bit m: the component without a center whose smallest
+                                   // vertex is m holds a seed (set by MarkSeed)
+    uint32_t nw;                   // 64-bit words per sketch, ceil(n / 64)
 };
 
-// GetCenter's label for (v, r) never changes (a sketch's components are fixed;
-// only their compact sizes are zeroed), so the labels a search found are kept,
-// direct-mapped by vertex, and a later search from the same vertex in the same
-// sketch (a re-evaluation, or MarkSeed from the vertex just chosen) reads the
-// size at the kept label instead.  An entry holds its vertex id, so a slot taken
-// over by another vertex is simply a miss.  Components without a center are not
-// kept (their result depends on the seeds met).
+// What GetCenter finds from (v, r) never changes (a sketch's components are
+// fixed; only their compact sizes are zeroed and seeds are added), so results are
+// kept, direct-mapped by vertex, and a later search from the same vertex in the
+// same sketch (a re-evaluation, or MarkSeed from the vertex just chosen) reads
+// them instead:
+//   word 0 = (v << 32) | label             the component holds a center: delta is
+//                                           the compact size at that label;
+//   word 0 = (v << 32) | 2^31 | size,      the component has no center: delta is
+//   word 1 = (v << 32) | smallest vertex   its size unless a seed lies in it, which
+//                                           MarkSeed records in covmin by that vertex.
+// Both words carry the vertex id, and every write for (v, r) writes the same
+// values, so a slot being taken over by another vertex reads as a miss whatever
+// the interleaving.
+constexpr uint32_t kMemoNoCenter = 0x80000000u;
 __device__ __forceinline__ unsigned long long *memo_entry(const CompactDev &cd, uint32_t v, uint32_t r) {
     const uint32_t slot = (v * 0x9E3779B1u ^ (v >> 16)) & cd.memo_mask;
-    return cd.memo + (size_t)slot * cd.R + r;
+    return cd.memo + ((size_t)slot * cd.R + r) * 2;
 }
 
 struct BfsOut {
@@ -60,7 +70,19 @@ struct BfsOut {
     uint32_t label;   // label_c of the reached center, or kNone
     bool overflow;
     uint32_t visits;  // vertices whose adjacency the search scanned
+    uint32_t ccsize;  // no center reached (and no overflow): the component's size
+    uint32_t ccmin;   //   and its smallest vertex
 };
+
+__device__ __forceinline__ bool covmin_test(const CompactDev &cd, uint32_t r, uint32_t m) {
+    return (__hip_atomic_load(&cd.covmin[(size_t)r * cd.nw + (m >> 6)], __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT) >> (m & 63)) & 1ull;
+}
+
+// MarkSeed's record for a search that ended without a center (one lane).
+__device__ __forceinline__ void covmin_mark(const CompactDev &cd, uint32_t r, uint32_t m) {
+    atomicOr(&cd.covmin[(size_t)r * cd.nw + (m >> 6)], 1ull << (m & 63));
+}
 
 __device__ __forceinline__ uint32_t hs_slot(uint32_t w) { return (w * 0x9E3779B1u) >> (32 - 10); }
 static_assert(kHCap == 1024, "hs_slot assumes 2^10 slots");
@@ -128,7 +150,11 @@ __device__ BfsOut getcenter_lds(const GraphDev &g, const ProbDev &pm, uint64_t k
         o.visits = head;
         return o;
     }
-    return BfsOut{met ? 0ull : (uint64_t)tail, kNone, false, head};
+    uint32_t mn = kNone;
+    for (uint32_t i = lane; i < tail; i += kWave) mn = min(mn, q[i]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mn = min(mn, (uint32_t)__shfl_xor(mn, off));
+    return BfsOut{met ? 0ull : (uint64_t)tail, kNone, false, head, tail, mn};
 }
 
 // The same search with an n-entry queue and an n-bit visited bitmap in global
@@ -177,9 +203,11 @@ __device__ BfsOut getcenter_global(const GraphDev &g, const ProbDev &pm, uint64_
             __builtin_amdgcn_wave_barrier();
         }
     }
+    uint32_t mn = kNone;
     for (uint32_t i = lane; i < tail; i += kWave) {
         const uint32_t w = __hip_atomic_load(&gq[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         atomicAnd(&gvis[w >> 5], ~(1u << (w & 31)));
+        mn = min(mn, w);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     if (found != kNone) {
@@ -187,37 +215,58 @@ __device__ BfsOut getcenter_global(const GraphDev &g, const ProbDev &pm, uint64_
         o.visits = head;
         return o;
     }
-    return BfsOut{met ? 0ull : (uint64_t)tail, kNone, false, head};
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mn = min(mn, (uint32_t)__shfl_xor(mn, off));
+    return BfsOut{met ? 0ull : (uint64_t)tail, kNone, false, head, tail, mn};
 }
 
-// GetCenter through the kept labels (all lanes take part; lane 0 writes).
+// A kept result for (v, r), if the slot holds one (all lanes read it).
+__device__ __forceinline__ bool memo_read(const CompactDev &cd, uint32_t v, uint32_t r, BfsOut *o) {
+    const unsigned long long *e = memo_entry(cd, v, r);
+    const unsigned long long x = __hip_atomic_load(&e[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint32_t)(x >> 32) != v) return false;
+    const uint32_t p = (uint32_t)x;
+    if (!(p & kMemoNoCenter)) {
+        *o = BfsOut{cd.size_c[(size_t)r * cd.rho + p], p, false, 0, 0, 0};
+        return true;
+    }
+    const unsigned long long y = __hip_atomic_load(&e[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint32_t)(y >> 32) != v) return false;
+    const uint32_t size = p & ~kMemoNoCenter, m = (uint32_t)y;
+    *o = BfsOut{covmin_test(cd, r, m) ? 0ull : (uint64_t)size, kNone, false, 0, size, m};
+    return true;
+}
+
+// Keeps the result of a completed search from (v, r) (lane 0).
+__device__ __forceinline__ void memo_write(const CompactDev &cd, uint32_t v, uint32_t r, const BfsOut &o) {
+    unsigned long long *e = memo_entry(cd, v, r);
+    const unsigned long long tag = (unsigned long long)v << 32;
+    if (o.label != kNone) {
+        __hip_atomic_store(&e[0], tag | o.label, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (o.ccsize < kMemoNoCenter) {
+        __hip_atomic_store(&e[1], tag | o.ccmin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&e[0], tag | kMemoNoCenter | o.ccsize, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// GetCenter through the kept results (all lanes take part; lane 0 writes).
 __device__ __forceinline__ BfsOut getcenter_memo_lds(const GraphDev &g, const ProbDev &pm, uint64_t kr,
                                                      const CompactDev &cd, uint32_t r, const uint8_t *in_s, uint32_t v,
                                                      uint32_t *q, uint32_t *hs) {
-    unsigned long long *e = memo_entry(cd, v, r);
-    const unsigned long long x = __hip_atomic_load(e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((uint32_t)(x >> 32) == v) {
-        const uint32_t l = (uint32_t)x;
-        return BfsOut{cd.size_c[(size_t)r * cd.rho + l], l, false, 0};
-    }
-    const BfsOut o = getcenter_lds(g, pm, kr, cd, r, in_s, v, q, hs);
-    if (!o.overflow && o.label != kNone && lane_id() == 0)
-        __hip_atomic_store(e, ((unsigned long long)v << 32) | o.label, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    BfsOut o;
+    if (memo_read(cd, v, r, &o)) return o;
+    o = getcenter_lds(g, pm, kr, cd, r, in_s, v, q, hs);
+    if (!o.overflow && lane_id() == 0) memo_write(cd, v, r, o);
     return o;
 }
 
 __device__ __forceinline__ BfsOut getcenter_memo_global(const GraphDev &g, const ProbDev &pm, uint64_t kr,
                                                         const CompactDev &cd, uint32_t r, const uint8_t *in_s,
                                                         uint32_t v, uint32_t *gq, uint32_t *gvis) {
-    unsigned long long *e = memo_entry(cd, v, r);
-    const unsigned long long x = __hip_atomic_load(e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((uint32_t)(x >> 32) == v) {
-        const uint32_t l = (uint32_t)x;
-        return BfsOut{cd.size_c[(size_t)r * cd.rho + l], l, false, 0};
-    }
-    const BfsOut o = getcenter_global(g, pm, kr, cd, r, in_s, v, gq, gvis);
-    if (o.label != kNone && lane_id() == 0)
-        __hip_atomic_store(e, ((unsigned long long)v << 32) | o.label, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    BfsOut o;
+    if (memo_read(cd, v, r, &o)) return o;
+    o = getcenter_global(g, pm, kr, cd, r, in_s, v, gq, gvis);
+    if (lane_id() == 0) memo_write(cd, v, r, o);
     return o;
 }
 
@@ -294,6 +343,7 @@ __device__ __forceinline__ void overflow_level(int mode, uint32_t slot, SelState
             if (o.visits) atomicAdd(&st->visits, (unsigned long long)o.visits);
             if (mode == 0) add_delta(st, partial, t.x, o.delta, evl, kb, in_s, key);
             else if (o.label != kNone) cd.size_c[(size_t)r * cd.rho + o.label] = 0;
+            else covmin_mark(cd, r, o.ccmin);
         }
     }
 }
@@ -310,6 +360,7 @@ __device__ __forceinline__ void markseed_compact_level(SelState *st, const Graph
             if (o.visits) atomicAdd(&st->visits, (unsigned long long)o.visits);
             if (o.overflow) push_overflow(st, &st->ov_cnt[kMaxLevels + 1], mark_list(ov, ov_cap), ov_cap / 2, s, r);
             else if (o.label != kNone) cd.size_c[(size_t)r * cd.rho + o.label] = 0;
+            else covmin_mark(cd, r, o.ccmin);
         }
     }
 }
@@ -337,7 +388,10 @@ __device__ __forceinline__ void markseed_eval_root_level(SelState *st, const uin
             }
             continue;
         }
-        if (lane_id() == 0 && m.label != kNone) cd.size_c[(size_t)r * cd.rho + m.label] = 0;
+        if (lane_id() == 0) {
+            if (m.label != kNone) cd.size_c[(size_t)r * cd.rho + m.label] = 0;
+            else covmin_mark(cd, r, m.ccmin);
+        }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();
         const BfsOut o = getcenter_memo_lds(g, pm, K[r], cd, r, in_s, v, q, hs);

@@ -89,7 +89,8 @@ struct im_sketches {
     uint32_t kb = 1;
     uint32_t rho = 0;
     uint64_t kc = 0, Ta = 0;  // center test of CompactSketch: mix64(v ^ kc) < Ta
-    unsigned long long *memo = nullptr;  // kept GetCenter labels, [memo_mask + 1][R]
+    unsigned long long *memo = nullptr;  // kept GetCenter results, [memo_mask + 1][R][2]
+    unsigned long long *covmin = nullptr;  // [R][nw]: centerless components holding a seed, by smallest vertex
     uint32_t memo_mask = 0;
     uint32_t B = 1;
     // arrays
@@ -755,8 +756,10 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
         uint32_t slots = 64;
         while (slots < n && slots < 4096) slots <<= 1;
         s->memo_mask = slots - 1;
-        SK_TRY(sk_alloc(s, (size_t)slots * R, &s->memo));
-        SK_HIP(hipMemsetAsync(s->memo, 0xFF, (size_t)slots * R * 8, st));
+        SK_TRY(sk_alloc(s, (size_t)slots * R * 2, &s->memo));
+        SK_HIP(hipMemsetAsync(s->memo, 0xFF, (size_t)slots * R * 16, st));
+        SK_TRY(sk_alloc(s, (size_t)R * s->nw, &s->covmin));
+        SK_HIP(hipMemsetAsync(s->covmin, 0, (size_t)R * s->nw * 8, st));
     } else {
         s->rho = n;
         SK_TRY(sk_alloc(s, (size_t)n * R, &s->E));
@@ -831,11 +834,16 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
 // ---------------------------------------------------------------- selection
 namespace {
 
+CompactDev compact_dev(const im_sketches *s) {
+    return CompactDev{s->center_rank, s->label_c, s->size_c, s->rho,  s->kc,     s->Ta,
+                      s->memo,        s->memo_mask, s->R,     s->covmin, s->nw};
+}
+
 // MarkSeed on CompactSketch for st->last_seed: one GetCenter per sketch.
 void enqueue_markseed_compact(im_sketches *s) {
     hipStream_t st = s->ctx->stream;
     GraphDev gd{s->g->off, s->g->cols};
-    CompactDev cd{s->center_rank, s->label_c, s->size_c, s->rho, s->kc, s->Ta, s->memo, s->memo_mask, s->R};
+    const CompactDev cd = compact_dev(s);
     k_markseed_compact<<<wave_grid(s->R, 4096), kBfsBlock, 0, st>>>(s->st, gd, s->pm, s->K, s->R, cd, s->in_s, s->ov,
                                                                      s->ov_cap);
     k_overflow_bfs<<<s->slots, 64, 0, st>>>(1, kMaxLevels + 1, s->st, s->evl, s->partial, gd, s->pm, s->K, cd, s->kb,
@@ -850,7 +858,7 @@ im_status enqueue_round_part(im_sketches *s, bool begin, uint32_t l0) {
     hipStream_t st = ctx->stream;
     const TreeDesc &td = s->td;
     GraphDev gd{s->g->off, s->g->cols};
-    CompactDev cd{s->center_rank, s->label_c, s->size_c, s->rho, s->kc, s->Ta, s->memo, s->memo_mask, s->R};
+    const CompactDev cd = compact_dev(s);
     const unsigned long long pinit = (unsigned long long)s->R << kPartialShift;
     auto eval = [&](uint32_t l) {
         uint64_t cap = (l == 0) ? 1 : std::min<uint64_t>((uint64_t)s->n, (uint64_t)td.lvl_n[l - 1] * kFan);
@@ -923,7 +931,7 @@ im_status run_persistent_rounds(im_sketches *s, uint32_t max_rounds, unsigned lo
     a.g = GraphDev{s->g->off, s->g->cols};
     a.pm = s->pm;
     a.K = s->K;
-    a.cd = CompactDev{s->center_rank, s->label_c, s->size_c, s->rho, s->kc, s->Ta, s->memo, s->memo_mask, s->R};
+    a.cd = compact_dev(s);
     a.ov = s->ov;
     a.ov_cap = s->ov_cap;
     a.slot_q = s->slot_q;
@@ -939,7 +947,9 @@ im_status run_persistent_rounds(im_sketches *s, uint32_t max_rounds, unsigned lo
     void *args[] = {&a};
     // CompactSketch: about one wave per sketch (the GetCenter steps have R searches
     // per listed vertex); every extra workgroup costs each step a completion.
-    const unsigned grid = s->compact ? std::min<unsigned>(ctx->persist_grid, std::max<unsigned>(8u, (s->R + kPersistWaves - 1) / kPersistWaves)) : 1u;
+    unsigned grid = s->compact ? std::min<unsigned>(ctx->persist_grid, std::max<unsigned>(8u, (s->R + kPersistWaves - 1) / kPersistWaves)) : 1u;
+    if (const char *pg = getenv("PACIM_PERSIST_GRID"))  // tuning: workgroups of CompactSketch launches
+        if (s->compact) grid = std::max<unsigned>(1u, std::min<unsigned>(ctx->persist_grid, (unsigned)strtoul(pg, nullptr, 10)));
     const char *np = getenv("PACIM_PERSIST");  // "0" (tests): take the path below as if refused
     const hipError_t le = (np && !strcmp(np, "0"))
                               ? hipErrorNotSupported
@@ -1272,7 +1282,7 @@ im_status pt_round(im_sketches *s) {
     im_ctx *ctx = s->ctx;
     hipStream_t st = ctx->stream;
     GraphDev gd{s->g->off, s->g->cols};
-    CompactDev cd{s->center_rank, s->label_c, s->size_c, s->rho, s->kc, s->Ta, s->memo, s->memo_mask, s->R};
+    const CompactDev cd = compact_dev(s);
     const unsigned long long pinit = (unsigned long long)s->R << kPartialShift;
     k_pt_round_begin<<<1, 64, 0, st>>>(s->st);
     const uint32_t bulk_min = s->compact ? pt_bulk_min(s) : 0u;
