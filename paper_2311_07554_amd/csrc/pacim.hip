@@ -947,7 +947,11 @@ im_status run_persistent_rounds(im_sketches *s, uint32_t max_rounds, unsigned lo
     void *args[] = {&a};
     // CompactSketch: about one wave per sketch (the GetCenter steps have R searches
     // per listed vertex); every extra workgroup costs each step a completion.
+    // Under WIC a vertex expects at most sum_j 2 / (d_u + d_j) <= 2 live edges, so a search
+    // from a high-degree vertex scans its whole adjacency: steps are long, and one
+    // workgroup per CU runs 4x the searches at once for a small completion cost.
     unsigned grid = s->compact ? std::min<unsigned>(ctx->persist_grid, std::max<unsigned>(8u, (s->R + kPersistWaves - 1) / kPersistWaves)) : 1u;
+    if (s->compact && s->pm.kind == kProbWic) grid = ctx->persist_grid;
     if (const char *pg = getenv("PACIM_PERSIST_GRID"))  // tuning: workgroups of CompactSketch launches
         if (s->compact) grid = std::max<unsigned>(1u, std::min<unsigned>(ctx->persist_grid, (unsigned)strtoul(pg, nullptr, 10)));
     const char *np = getenv("PACIM_PERSIST");  // "0" (tests): take the path below as if refused
