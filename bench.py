@@ -4,7 +4,10 @@
 Workload (default): R-MAT scale 20 (2^20 vertices, 2^24 undirected pairs,
 a=0.57 b=c=0.19), trivalency IC probabilities, R = 256 sketches, k = 100 seeds.
 One step = the whole path twice on the resident graph: full labels (alpha = 1)
-and CompactSketch (alpha = 0.1), each = build R sketches + select k seeds.
+and CompactSketch (alpha = 0.1), each = build R sketches + select k seeds.  The
+two queries are independent; the CompactSketch one runs on a second stream,
+built first, and its selection overlaps the full-label build (--no-overlap runs
+them one after another).
 
 Prints one JSON line.  value = sampled edges per second over the step
 (2 * R * m_und sampled edges / step time); the breakdown gives the sketch-only
@@ -17,6 +20,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -75,6 +79,8 @@ def parse():
     ap.add_argument("--alpha", type=float, default=0.1, help="CompactSketch alpha of the second query")
     ap.add_argument("--modes", default="full,compact")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run the step's two queries one after another on one stream")
     ap.add_argument("--no-ptree", action="store_true",
                     help="skip the untimed comparison with NextSeed by prefix doubling")
     ap.add_argument("--cpu-sketches", type=int, default=16)
@@ -465,29 +471,63 @@ def main():
     ctx = pacim.Context(0, stream)
     gr = ctx.graph(g.n, torch.from_numpy(g.offsets.view(np.int64)).cuda(),
                    torch.from_numpy(g.cols.view(np.int32)).cuda())
+    # The step's two queries are independent: with both modes, the CompactSketch query
+    # runs on a second context and stream, and its selection (latency-bound, one wave
+    # per sketch) overlaps the full-label query's build.
+    overlap = (not args.no_overlap) and modes == ["full", "compact"]
+    ctx2 = gr2 = None
+    if overlap:
+        ctx2 = pacim.Context(0, torch.cuda.Stream())
+        gr2 = ctx2.graph(g.n, g.offsets, g.cols)
     torch.cuda.synchronize()
     probe_hash, probe_copy = ctx.probe()
     print(f"[bench] device probe: {probe_hash / 1e9:.1f} Ghash/s (hash loop alone), "
           f"{probe_copy / 1e9:.0f} GB/s (stream copy)", file=sys.stderr, flush=True)
 
-    def one_step(record):
+    def one_query(graph, m, record, per, built=None, wait=None):
+        if wait is not None:
+            wait.wait()
+        sk = graph.sketches(q.prob_kind, q.p, q.R, q.seed, alphas[m])
+        if built is not None:
+            built.set()
+        s, gn = sk.select(q.k)
+        st = sk.stats()
+        sk.close()
+        if record is not None:
+            record.setdefault(m, []).append((st["build_ms"], st["select_ms"], st["evaluations"],
+                                             st["sketches_per_pass"], st["bulk_rounds"], st["bulk_resampled"],
+                                             st["bfs_visits"]))
+        per[m] = (s, gn)
+
+    def one_step(record, sequential=False):
         per = {}
-        for m in modes:
-            sk = gr.sketches(q.prob_kind, q.p, q.R, q.seed, alphas[m])
-            s, gn = sk.select(q.k)
-            st = sk.stats()
-            sk.close()
-            if record is not None:
-                record.setdefault(m, []).append((st["build_ms"], st["select_ms"], st["evaluations"],
-                                                 st["sketches_per_pass"], st["bulk_rounds"], st["bulk_resampled"],
-                                                 st["bfs_visits"]))
-            per[m] = (s, gn)
+        if not overlap or sequential:
+            for m in modes:
+                one_query(gr, m, record, per)
+            return per
+        # CompactSketch build, then its selection while the full-label query builds
+        built = threading.Event()
+        tc = threading.Thread(target=one_query, args=(gr2, "compact", record, per, built, None))
+        tf = threading.Thread(target=one_query, args=(gr, "full", record, per, None, built))
+        tc.start()
+        tf.start()
+        tc.join()
+        tf.join()
+        if len(per) != 2:
+            raise RuntimeError("a query of the step failed")
         return per
 
     for i in range(args.warmup):
         one_step(None)
         print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    isolated = {}
+    if overlap:  # per-query times without the overlap, outside the timed steps
+        iso = {}
+        one_step(iso, sequential=True)
+        isolated = {m: {"sketch_ms": v[0][0], "select_ms": v[0][1]} for m, v in iso.items()}
     ctx.profiling(True)
+    if ctx2 is not None:
+        ctx2.profiling(True)
     rec = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -501,8 +541,15 @@ def main():
     kern = {}
     for name in ("sample_hook", "compress", "emit", "select"):
         n_l, ms = ctx.kernel_time(name)
+        if ctx2 is not None:
+            n2, ms2 = ctx2.kernel_time(name)
+            n_l, ms = n_l + n2, ms + ms2
         kern[name] = {"launches": n_l, "avg_ms": (ms / n_l) if n_l else None, "total_ms": ms}
     ctx.profiling(False)
+    if ctx2 is not None:
+        ctx2.profiling(False)
+        gr2.close()
+        ctx2.close()
 
     R, m_und, n = q.R, g.m_und, g.n
     breakdown = {}
@@ -560,7 +607,8 @@ def main():
                 times.append(st["select_ms"])
                 evs = int(st["evaluations"])
             trees[m] = {"ptree_select_ms": float(np.mean(times)), "ptree_evaluations": evs,
-                        "winning_tree_select_ms": breakdown[m]["select_ms"],
+                        "winning_tree_select_ms": (isolated[m]["select_ms"] if isolated
+                                                   else breakdown[m]["select_ms"]),
                         "winning_tree_evaluations": breakdown[m]["evaluations"]}
         print(f"[bench] prefix-doubling selection: {trees}", file=sys.stderr, flush=True)
 
@@ -581,6 +629,9 @@ def main():
                    "n": n, "m_und": m_und, "R": R, "k": q.k, "alpha_compact": args.alpha,
                    "prob": prob_name, "parallelism": "single GPU"},
         "breakdown": breakdown,
+        "step_schedule": ("CompactSketch query on a second stream; its selection overlaps the full-label build"
+                          if overlap else "queries one after another"),
+        "breakdown_isolated": isolated or None,
         "selection_structures": trees or None,
         "kernels": kern,
         "roofline": roofline,
