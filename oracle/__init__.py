@@ -29,12 +29,14 @@ SALT_CENTER = 0xC000000000000001
 SALT_TRIV = 0xC000000000000002
 SALT_RANGE = 0xC000000000000003
 
-# edge-probability models (kind): Consistent p, trivalency, Uniform U(lo, hi) per edge, WIC 2 / (d_u + d_v)
-CONSTANT, TRIVALENCY, RANGE, WIC = 0, 1, 2, 3
+# edge-probability models (kind): Consistent p, trivalency, Uniform U(lo, hi) per edge, WIC 2 / (d_u + d_v),
+# per-edge p given for every CSR entry
+CONSTANT, TRIVALENCY, RANGE, WIC, PER_EDGE = 0, 1, 2, 3, 4
 
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _u32p = ctypes.POINTER(ctypes.c_uint32)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
+_dblp = ctypes.POINTER(ctypes.c_double)
 
 
 def _load():
@@ -55,7 +57,7 @@ def _load():
         lib.orc_live.restype = i32
         lib.orc_live.argtypes = [u32, u32, u32, u64, u64]
         lib.orc_sketch.restype = ctypes.c_int64
-        lib.orc_sketch.argtypes = [u32, _u64p, _u32p, i32, dbl, dbl, u64, u32, _u32p, _u32p]
+        lib.orc_sketch.argtypes = [u32, _u64p, _u32p, i32, dbl, dbl, _dblp, u64, u32, _u32p, _u32p]
         lib.orc_marginals.restype = None
         lib.orc_marginals.argtypes = [u32, u32, _u32p, _u32p, _u8p, u32, u32, _u64p]
         lib.orc_cover.restype = None
@@ -67,15 +69,15 @@ def _load():
         lib.orc_compact.restype = None
         lib.orc_compact.argtypes = [u32, u32, _u32p, _u32p, _u32p, _u32p, _u32p]
         lib.orc_getcenter.restype = u64
-        lib.orc_getcenter.argtypes = [u32, _u64p, _u32p, i32, dbl, dbl, u64, u32, _u32p, _u32p, _u32p, _u8p,
+        lib.orc_getcenter.argtypes = [u32, _u64p, _u32p, i32, dbl, dbl, _dblp, u64, u32, _u32p, _u32p, _u32p, _u8p,
                                       u32, _u32p, _u8p, _u32p, _u64p]
         lib.orc_compact_greedy.restype = i32
-        lib.orc_compact_greedy.argtypes = [u32, _u64p, _u32p, i32, dbl, dbl, u64, u32, u32, _u32p, _u32p, _u32p,
+        lib.orc_compact_greedy.argtypes = [u32, _u64p, _u32p, i32, dbl, dbl, _dblp, u64, u32, u32, _u32p, _u32p, _u32p,
                                            u32, _u32p, _u64p, _u64p]
         lib.orc_celf_evaluations.restype = i32
         lib.orc_celf_evaluations.argtypes = [u32, u32, _u32p, _u32p, u32, _u32p, _u64p, _u64p]
         lib.orc_influence.restype = u64
-        lib.orc_influence.argtypes = [u32, _u64p, _u32p, i32, dbl, dbl, _u32p, u32, u64, u32, u32]
+        lib.orc_influence.argtypes = [u32, _u64p, _u32p, i32, dbl, dbl, _dblp, _u32p, u32, u64, u32, u32]
         lib.orc_ptree.restype = i32
         lib.orc_ptree.argtypes = [u32, u32, _u32p, _u32p, u32, _u32p, _u64p, _u64p]
         _lib = lib
@@ -100,14 +102,19 @@ def threshold(p: float) -> int:
 
 
 def _pp(p):
-    """p of a model: a float, or (lo, hi) for the Uniform range model."""
+    """p of a model as (p, p_hi, p_edge): a float; (lo, hi) for the Uniform range model;
+    or an array with one probability per CSR entry for the per-edge model (the
+    array must outlive the call)."""
+    if isinstance(p, np.ndarray):
+        assert p.dtype == np.float64 and p.flags.c_contiguous
+        return 0.0, 0.0, _p(p, _dblp)
     if isinstance(p, (tuple, list)):
-        return float(p[0]), float(p[1])
-    return float(p), 0.0
+        return float(p[0]), float(p[1]), None
+    return float(p), 0.0, None
 
 
 def edge_threshold(kind: int, p, u: int, v: int, du: int = 0, dv: int = 0) -> int:
-    lo, hi = _pp(p)
+    lo, hi, _ = _pp(p)
     return int(_load().orc_edge_threshold(kind, lo, hi, u, v, du, dv))
 
 

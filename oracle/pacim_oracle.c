@@ -26,6 +26,8 @@
  *     h_e = mix64(key ^ K(0, SALT_RANGE)); a property of the edge.
  *   - WIC model (p_e = 2 / (d_u + d_v)): T_e = floor(2^65 / (d_u + d_v)) exactly,
  *     degrees of the undirected graph; d_u + d_v = 2 means always live.
+ *   - Per-edge model: the caller's p_e for every CSR entry (equal on both
+ *     directions of an edge), T_e = T(p_e).
  *   - Ties in the greedy argmax go to the smallest vertex id (Sec. 4 only says
  *     ties are broken by vertex id).
  *   - Centers of CompactSketch: v is a center iff mix64(v ^ K(seed, SALT_CENTER))
@@ -119,6 +121,16 @@ uint64_t orc_edge_threshold(int kind, double p, double p_hi, uint32_t u, uint32_
 
 static inline uint64_t orc_deg(const uint64_t *offsets, uint32_t v) { return offsets[v + 1] - offsets[v]; }
 
+/* kind 4 (per-edge probabilities given by the caller, the general p_e of Sec. 2's
+ * IC definition): p_edge[j] for CSR entry j, the same value on both directions
+ * of an edge; T_e = T(p_e).  Threshold of CSR entry j (row u, column w) under
+ * any model. */
+static inline uint64_t orc_entry_threshold(int kind, double p, double p_hi, const double *p_edge,
+                                           const uint64_t *offsets, uint32_t u, uint64_t j, uint32_t w) {
+    if (kind == 4) return orc_threshold(p_edge[j]);
+    return orc_edge_threshold(kind, p, p_hi, u, w, orc_deg(offsets, u), orc_deg(offsets, w));
+}
+
 /* Sample(e, r) of Sec. 3: is edge {u,v} live in sketch r? */
 int orc_live(uint32_t u, uint32_t v, uint32_t r, uint64_t seed, uint64_t T) {
     if (T == ORC_ALL_LIVE) return 1;
@@ -131,7 +143,7 @@ int orc_live(uint32_t u, uint32_t v, uint32_t r, uint64_t seed, uint64_t T) {
  * |CC_r(v)|.  Computed by BFS from each not yet labelled vertex in increasing
  * id order, so the BFS source is the CC minimum.  Returns the number of CCs. */
 int64_t orc_sketch(uint32_t n, const uint64_t *offsets, const uint32_t *cols, int kind, double p, double p_hi,
-                   uint64_t seed, uint32_t r, uint32_t *label, uint32_t *size) {
+                   const double *p_edge, uint64_t seed, uint32_t r, uint32_t *label, uint32_t *size) {
     uint32_t *queue = (uint32_t *)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
     for (uint32_t v = 0; v < n; ++v) label[v] = ORC_NONE;
     int64_t ncc = 0;
@@ -145,7 +157,7 @@ int64_t orc_sketch(uint32_t n, const uint64_t *offsets, const uint32_t *cols, in
             for (uint64_t j = offsets[u]; j < offsets[u + 1]; ++j) {
                 uint32_t w = cols[j];
                 if (label[w] != ORC_NONE) continue;
-                if (!orc_live(u, w, r, seed, orc_edge_threshold(kind, p, p_hi, u, w, orc_deg(offsets, u), orc_deg(offsets, w)))) continue;
+                if (!orc_live(u, w, r, seed, orc_entry_threshold(kind, p, p_hi, p_edge, offsets, u, j, w))) continue;
                 label[w] = s;
                 queue[tail++] = w;
             }
@@ -244,7 +256,7 @@ void orc_compact(uint32_t n, uint32_t rho, const uint32_t *centers, const uint32
  * zeroed scratch array returned zeroed; queue holds n entries.  *visits gets
  * the number of vertices taken from the queue (the cost in Theorem 3.1). */
 uint64_t orc_getcenter(uint32_t n, const uint64_t *offsets, const uint32_t *cols, int kind, double p,
-                       double p_hi, uint64_t seed, uint32_t r, const uint32_t *center_rank, const uint32_t *label_c,
+                       double p_hi, const double *p_edge, uint64_t seed, uint32_t r, const uint32_t *center_rank, const uint32_t *label_c,
                        const uint32_t *size_c, const uint8_t *in_s, uint32_t v, uint32_t *l_out,
                        uint8_t *seen, uint32_t *queue, uint64_t *visits) {
     (void)n;
@@ -259,7 +271,7 @@ uint64_t orc_getcenter(uint32_t n, const uint64_t *offsets, const uint32_t *cols
         for (uint64_t j = offsets[u]; j < offsets[u + 1]; ++j) {
             uint32_t w = cols[j];
             if (seen[w]) continue;
-            if (!orc_live(u, w, r, seed, orc_edge_threshold(kind, p, p_hi, u, w, orc_deg(offsets, u), orc_deg(offsets, w)))) continue;
+            if (!orc_live(u, w, r, seed, orc_entry_threshold(kind, p, p_hi, p_edge, offsets, u, j, w))) continue;
             seen[w] = 1;
             queue[tail++] = w;
         }
@@ -282,7 +294,7 @@ uint64_t orc_getcenter(uint32_t n, const uint64_t *offsets, const uint32_t *cols
  * Sec. 3 say the result equals orc_greedy's on the same sketches.
  * *visits accumulates the vertices dequeued by every GetCenter call. */
 int orc_compact_greedy(uint32_t n, const uint64_t *offsets, const uint32_t *cols, int kind, double p,
-                       double p_hi, uint64_t seed, uint32_t R, uint32_t rho, const uint32_t *centers,
+                       double p_hi, const double *p_edge, uint64_t seed, uint32_t R, uint32_t rho, const uint32_t *centers,
                        const uint32_t *label_c, uint32_t *size_c, uint32_t k, uint32_t *seeds,
                        uint64_t *gains, uint64_t *visits) {
     if (k > n) return -1;
@@ -300,7 +312,7 @@ int orc_compact_greedy(uint32_t n, const uint64_t *offsets, const uint32_t *cols
             uint64_t g = 0;
             for (uint32_t r = 0; r < R; ++r) {
                 uint32_t l;
-                g += orc_getcenter(n, offsets, cols, kind, p, p_hi, seed, r, rank, label_c + (size_t)r * rho,
+                g += orc_getcenter(n, offsets, cols, kind, p, p_hi, p_edge, seed, r, rank, label_c + (size_t)r * rho,
                                    size_c + (size_t)r * rho, in_s, v, &l, seen, queue, &vis);
             }
             if (best == ORC_NONE || g > bestg) { best = v; bestg = g; }
@@ -309,7 +321,7 @@ int orc_compact_greedy(uint32_t n, const uint64_t *offsets, const uint32_t *cols
         gains[i] = bestg;
         for (uint32_t r = 0; r < R; ++r) {          /* MarkSeed */
             uint32_t l;
-            orc_getcenter(n, offsets, cols, kind, p, p_hi, seed, r, rank, label_c + (size_t)r * rho,
+            orc_getcenter(n, offsets, cols, kind, p, p_hi, p_edge, seed, r, rank, label_c + (size_t)r * rho,
                           size_c + (size_t)r * rho, in_s, best, &l, seen, queue, &vis);
             if (l != ORC_NONE) size_c[(size_t)r * rho + l] = 0;
         }
@@ -471,7 +483,7 @@ int orc_ptree(uint32_t n, uint32_t R, const uint32_t *label, const uint32_t *siz
  * is that sum / sims.  Duplicate seeds count once.  Model arguments as
  * orc_sketch. */
 uint64_t orc_influence(uint32_t n, const uint64_t *offsets, const uint32_t *cols, int kind, double p, double p_hi,
-                       const uint32_t *seeds, uint32_t k, uint64_t sim_seed, uint32_t w0, uint32_t sims) {
+                       const double *p_edge, const uint32_t *seeds, uint32_t k, uint64_t sim_seed, uint32_t w0, uint32_t sims) {
     uint8_t *active = (uint8_t *)calloc((size_t)n + 1, 1);
     uint32_t *queue = (uint32_t *)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
     uint64_t total = 0;
@@ -484,8 +496,7 @@ uint64_t orc_influence(uint32_t n, const uint64_t *offsets, const uint32_t *cols
             for (uint64_t j = offsets[u]; j < offsets[u + 1]; ++j) {
                 uint32_t x = cols[j];
                 if (active[x]) continue;
-                if (!orc_live(u, x, w, sim_seed,
-                              orc_edge_threshold(kind, p, p_hi, u, x, orc_deg(offsets, u), orc_deg(offsets, x))))
+                if (!orc_live(u, x, w, sim_seed, orc_entry_threshold(kind, p, p_hi, p_edge, offsets, u, j, x)))
                     continue;
                 active[x] = 1;
                 queue[tail++] = x;

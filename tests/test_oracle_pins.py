@@ -182,6 +182,14 @@ def _threshold_spelled_out(kind, p, u, w, du, dw):
     return M64 if s_ <= 2 else (1 << 65) // s_
 
 
+def per_edge_p(g, salt=0):
+    """A symmetric probability per CSR entry, from the pair (min, max)."""
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.offsets.astype(np.int64)))
+    cols = g.cols.astype(np.int64)
+    a, b = np.minimum(rows, cols), np.maximum(rows, cols)
+    return np.ascontiguousarray(((a * 7919 + b * 104729 + salt * 31) % 1000) / 1000.0, dtype=np.float64)
+
+
 def _live_edges(g, kind, p, seed, r):
     res = []
     deg = np.diff(g.offsets.astype(np.int64))
@@ -189,16 +197,21 @@ def _live_edges(g, kind, p, seed, r):
         for j in range(int(g.offsets[u]), int(g.offsets[u + 1])):
             w = int(g.cols[j])
             if u < w:
-                T = _threshold_spelled_out(kind, p, u, w, int(deg[u]), int(deg[w]))
+                if kind == 4:
+                    T = oracle.threshold(float(p[j]))
+                else:
+                    T = _threshold_spelled_out(kind, p, u, w, int(deg[u]), int(deg[w]))
                 if T == M64 or brute.mix64_int(((u << 32) | w) ^ brute.key_int(seed, r)) < T:
                     res.append((u, w))
     return res
 
 
 @pytest.mark.parametrize("gi", range(6))
-@pytest.mark.parametrize("kind,p", [(0, 0.45), (1, 0.0), (2, (0.2, 0.7)), (3, 0.0)])
+@pytest.mark.parametrize("kind,p", [(0, 0.45), (1, 0.0), (2, (0.2, 0.7)), (3, 0.0), (4, None)])
 def test_sketch_labels_match_transitive_closure(gi, kind, p):
     g = _tiny_graphs()[gi]
+    if kind == 4:
+        p = per_edge_p(g, gi)
     for r in range(8):
         edges = _live_edges(g, kind, p, 3, r)
         lab_b, siz_b, _ = brute.closure_labels(g.n, edges)
@@ -501,11 +514,13 @@ def test_ptree_matches_greedy_with_many_ties():
 # ---------------------------------------------------------------- influence by simulation
 
 @pytest.mark.parametrize("gi", range(6))
-@pytest.mark.parametrize("kind,p", [(0, 0.35), (1, 0.0), (2, (0.2, 0.7)), (3, 0.0)])
+@pytest.mark.parametrize("kind,p", [(0, 0.35), (1, 0.0), (2, (0.2, 0.7)), (3, 0.0), (4, None)])
 def test_influence_equals_reach_in_each_world(gi, kind, p):
     # simulation w is live-edge world w: the sum of the seeds' reach over the worlds,
     # with worlds spelled out from the published mixer and reach from closures
     g = _tiny_graphs()[gi]
+    if kind == 4:
+        p = per_edge_p(g, gi)
     S = [0, g.n - 1, 0]
     sims, sseed = 40, 77
     want = 0
@@ -537,3 +552,25 @@ def test_influence_closed_forms():
     assert oracle.influence(g, 0, 0.0, [1, 4, 1], 5, 0, 30) == 30 * 2      # p = 0: the distinct seeds
     assert oracle.influence(g, 0, 1.0, [1, 4, 1], 5, 0, 30) == 30 * 5      # p = 1: their components
     assert oracle.influence(g, 0, 1.0, [5], 5, 0, 7) == 7
+
+
+def test_per_edge_model_reduces_to_constant_and_matches_cascade():
+    # the same p on every entry is the Consistent model, sketch for sketch
+    g = inputs.rmat_graph(9, 4 << 9, seed=12)
+    const = np.full(g.cols.size, 0.13)
+    la, sa = oracle.sketches(g, oracle.PER_EDGE, const, 5, 6)
+    lb, sb = oracle.sketches(g, oracle.CONSTANT, 0.13, 5, 6)
+    assert np.array_equal(la, lb) and np.array_equal(sa, sb)
+    # per-edge probabilities against the cascade's exact expected spread
+    n = 6
+    edges = [(0, 1), (1, 2), (2, 0), (2, 3), (3, 4), (4, 5), (1, 5)]
+    t = inputs.csr_from_pairs(n, edges)
+    pe = per_edge_p(t, 3)
+    rows = np.repeat(np.arange(n), np.diff(t.offsets.astype(np.int64)))
+    exact_p = {(min(int(u), int(w)), max(int(u), int(w))): Fraction(float(x))
+               for u, w, x in zip(rows, t.cols, pe)}
+    sims = 20000
+    for S in ([0], [2, 4]):
+        exact = brute.exact_ic_spread(n, edges, exact_p, S)
+        est = oracle.influence(t, oracle.PER_EDGE, pe, S, 321, 0, sims) / sims
+        assert abs(est - float(exact)) <= 5 * (n / 2) / math.sqrt(sims), (S, est, float(exact))
