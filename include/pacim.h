@@ -66,14 +66,19 @@ typedef enum {
     IM_PROB_RANGE = 2,       /* "Uniform": p_e uniform over [p, p_hi), drawn once per edge:
                                 T_e = T(p) + floor((T(p_hi) - T(p)) * h_e / 2^64) with
                                 h_e = mix64(((min<<32)|max) ^ K(0, 0xC000000000000003))   */
-    IM_PROB_WIC = 3          /* "WIC": p_e = 2 / (d_u + d_v), d the degrees in the graph;
+    IM_PROB_WIC = 3,         /* "WIC": p_e = 2 / (d_u + d_v), d the degrees in the graph;
                                 T_e = floor(2^65 / (d_u + d_v)), always live when d_u + d_v = 2 */
+    IM_PROB_PER_EDGE = 4     /* p_e given by the caller for every CSR entry (p_edge), T_e = T(p_e);
+                                im_build_sketches, im_select_seeds and im_influence only */
 } im_prob_kind;
 
 typedef struct {
-    int32_t kind;  /* im_prob_kind */
-    double p;      /* IM_PROB_UNIFORM: p in [0, 1]; IM_PROB_RANGE: the low end, 0 <= p <= p_hi */
-    double p_hi;   /* IM_PROB_RANGE: the high end, p_hi < 1; ignored otherwise */
+    int32_t kind;          /* im_prob_kind */
+    double p;              /* IM_PROB_UNIFORM: p in [0, 1]; IM_PROB_RANGE: the low end, 0 <= p <= p_hi */
+    double p_hi;           /* IM_PROB_RANGE: the high end, p_hi < 1; ignored otherwise */
+    const double *p_edge;  /* IM_PROB_PER_EDGE: host array of m_dir probabilities in [0, 1], entry j
+                              for the graph's CSR entry j as uploaded; both directions of an edge must
+                              carry the same value (else EINVAL).  Read during the call only. */
 } im_prob;
 
 /* ---- context ------------------------------------------------------------ */

@@ -47,7 +47,7 @@ __device__ __forceinline__ uint64_t edge_word(uint32_t u, uint32_t v) {
 
 // Edge-probability models (the kind values of im_prob_kind) as integer
 // thresholds: an edge is live in a sketch iff its hash is below T_e.
-enum : int { kProbConstant = 0, kProbTrivalency = 1, kProbRange = 2, kProbWic = 3 };
+enum : int { kProbConstant = 0, kProbTrivalency = 1, kProbRange = 2, kProbWic = 3, kProbPerEdge = 4 };
 
 struct ProbDev {
     int kind;
@@ -55,8 +55,10 @@ struct ProbDev {
     uint64_t t1, t2;         // trivalency: T(0.01), T(0.001); range: t1 = T(hi) - T(lo)
     uint64_t ktriv;          // trivalency: K(0, kSaltTriv); range: K(0, kSaltRange)
     const uint64_t *off;     // WIC: the graph's CSR offsets (degrees)
-    const uint64_t *csr_thr; // WIC, CompactSketch: the threshold of every CSR entry j (or null), so
-                             // that GetCenter's scans need neither the neighbour's degree nor a division
+    const uint64_t *csr_thr; // the threshold of every CSR entry j (or null): WIC with CompactSketch, so
+                             // that GetCenter's scans need neither the neighbour's degree nor a division,
+                             // and the per-edge model
+    const uint64_t *edge_thr;  // per-edge model: the threshold of every undirected edge, edge-list order
 };
 
 // floor(2^65 / s) = floor(2 / s * 2^64), the WIC threshold of an edge whose end
@@ -71,9 +73,12 @@ __host__ __device__ __forceinline__ uint64_t wic_threshold(uint64_t s) {
     return 2 * q1 + (2 * m1 >= s ? 1u : 0u);
 }
 
-// Threshold of edge {u, v} (canonical word x) under model KIND.
+// Threshold of edge {u, v} (canonical word x, index e in the edge list, used by the
+// per-edge model only) under model KIND.
 template <int KIND>
-__device__ __forceinline__ uint64_t edge_threshold_of(const ProbDev &pm, uint32_t u, uint32_t v, uint64_t x) {
+__device__ __forceinline__ uint64_t edge_threshold_of(const ProbDev &pm, uint32_t u, uint32_t v, uint64_t x,
+                                                      uint64_t e = 0) {
+    if (KIND == kProbPerEdge) return pm.edge_thr[e];
     if (KIND == kProbConstant) return pm.t0;
     if (KIND == kProbTrivalency) {
         const uint64_t c = mix64(x ^ pm.ktriv) % 3u;
@@ -83,12 +88,15 @@ __device__ __forceinline__ uint64_t edge_threshold_of(const ProbDev &pm, uint32_
     return wic_threshold((pm.off[u + 1] - pm.off[u]) + (pm.off[v + 1] - pm.off[v]));
 }
 
+// Threshold of edge {u, v} where only its end points are known (not the per-edge
+// model, whose searches read csr_thr and whose edge passes know the index).
 __device__ __forceinline__ uint64_t edge_threshold(const ProbDev &pm, uint32_t u, uint32_t v, uint64_t x) {
     switch (pm.kind) {
     case kProbConstant: return edge_threshold_of<kProbConstant>(pm, u, v, x);
     case kProbTrivalency: return edge_threshold_of<kProbTrivalency>(pm, u, v, x);
     case kProbRange: return edge_threshold_of<kProbRange>(pm, u, v, x);
-    default: return edge_threshold_of<kProbWic>(pm, u, v, x);
+    case kProbWic: return edge_threshold_of<kProbWic>(pm, u, v, x);
+    default: return 0;
     }
 }
 

@@ -237,12 +237,15 @@ const char *prob_problem(const im_prob &prob) {
     case IM_PROB_RANGE:
         return (prob.p >= 0.0 && prob.p <= prob.p_hi && prob.p_hi < 1.0) ? nullptr
                                                                           : "range model needs 0 <= p <= p_hi < 1";
+    case IM_PROB_PER_EDGE:
+        return prob.p_edge ? nullptr : "per-edge model needs p_edge";
     default:
         return "unknown probability model";
     }
 }
 
-// Device form of a (valid) model on graph offsets `off` (read by WIC only).
+// Device form of a (valid) model on graph offsets `off` (read by WIC only).  The
+// per-edge model's threshold arrays are set by the caller.
 ProbDev prob_dev(const im_prob &prob, const uint64_t *off) {
     ProbDev pm{};
     pm.kind = prob.kind;
@@ -261,8 +264,10 @@ ProbDev prob_dev(const im_prob &prob, const uint64_t *off) {
         pm.t1 = threshold_of(prob.p_hi) - pm.t0;
         pm.ktriv = sketch_key(0, kSaltRange);
         break;
-    default:
+    case IM_PROB_WIC:
         pm.off = off;
+        break;
+    default:
         break;
     }
     return pm;
@@ -577,6 +582,57 @@ void cc_scratch_free(im_ctx *ctx, CCScratch *cs) {
     *cs = CCScratch();
 }
 
+// Thresholds of the per-edge model: csr[j] = T(p_edge[j]) for every CSR entry,
+// edge[e] for the undirected edges in edge-list order (ascending (u, v), u < v).
+// Rejects probabilities outside [0, 1] and edges whose two entries differ.
+im_status per_edge_thresholds(im_ctx *ctx, const im_graph *g, const double *p_edge, std::vector<uint64_t> &csr,
+                              std::vector<uint64_t> &edge) {
+    const uint32_t n = g->n;
+    const uint64_t md = g->m_dir;
+    std::vector<uint64_t> off((size_t)n + 1);
+    std::vector<uint32_t> col(md);
+    HIP_TRY(ctx, hipMemcpy(off.data(), g->off, off.size() * 8, hipMemcpyDeviceToHost));
+    if (md) HIP_TRY(ctx, hipMemcpy(col.data(), g->cols, md * 4, hipMemcpyDeviceToHost));
+    csr.resize(md);
+    for (uint64_t j = 0; j < md; ++j) {
+        const double p = p_edge[j];
+        if (!(p >= 0.0 && p <= 1.0)) return fail(ctx, IM_EINVAL, "per-edge probability outside [0, 1]");
+        csr[j] = threshold_of(p);
+    }
+    // each row's entries in increasing column order (positions within the row)
+    std::vector<uint32_t> ord(md);
+    for (uint32_t u = 0; u < n; ++u) {
+        const uint64_t o0 = off[u], d = off[u + 1] - off[u];
+        for (uint64_t k = 0; k < d; ++k) ord[o0 + k] = (uint32_t)k;
+        std::sort(ord.begin() + (ptrdiff_t)o0, ord.begin() + (ptrdiff_t)(o0 + d),
+                  [&](uint32_t a, uint32_t b) { return col[o0 + a] < col[o0 + b]; });
+    }
+    edge.resize(g->m_und);
+    uint64_t e = 0;
+    for (uint32_t u = 0; u < n; ++u) {
+        for (uint64_t k = off[u]; k < off[u + 1]; ++k) {
+            const uint64_t j = off[u] + ord[k];
+            const uint32_t w = col[j];
+            if (w > u) {
+                if (e >= edge.size()) return fail(ctx, IM_EINTERNAL, "edge count mismatch");
+                edge[e++] = csr[j];
+                continue;
+            }
+            // the entry (w, u) of the same edge, by binary search in row w
+            uint64_t lo = off[w], hi = off[w + 1];
+            while (lo < hi) {
+                const uint64_t mid = (lo + hi) / 2;
+                if (col[off[w] + ord[mid]] < u) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo == off[w + 1] || col[off[w] + ord[lo]] != u || csr[off[w] + ord[lo]] != csr[j])
+                return fail(ctx, IM_EINVAL, "per-edge probabilities differ between the two directions of an edge");
+        }
+    }
+    if (e != g->m_und) return fail(ctx, IM_EINTERNAL, "edge count mismatch");
+    return IM_OK;
+}
+
 // One pass over the edge list for b <= cs.B sketches (keys K[0..b)): union-find
 // labels in parent[b][n] (root = smallest id of the CC), member counts at the
 // roots in cnt, and (if center_rank) the smallest center rank of each CC in minc.
@@ -601,8 +657,12 @@ void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const ui
         case kProbRange:
             k_sample_hook<kProbRange><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->m_und, K, b, pm, cs.parent, n);
             break;
-        default:
+        case kProbWic:
             k_sample_hook<kProbWic><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->m_und, K, b, pm, cs.parent, n);
+            break;
+        default:
+            k_sample_hook<kProbPerEdge><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->m_und, K, b, pm, cs.parent,
+                                                                          n);
             break;
         }
     }
@@ -727,6 +787,18 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
     SK_TRY(sk_alloc(s, (size_t)Rpad, &s->K));
     k_sketch_keys<<<grid_for(Rpad, 256, 1u << 20), 256, 0, st>>>(seed, Rpad, s->K);
     SK_HIP(hipGetLastError());
+    if (prob.kind == IM_PROB_PER_EDGE) {
+        // thresholds by edge (the sampling pass) and by CSR entry (GetCenter), held with the sketches
+        std::vector<uint64_t> tc, te;
+        SK_TRY(per_edge_thresholds(ctx, g, prob.p_edge, tc, te));
+        uint64_t *dc = nullptr, *de = nullptr;
+        SK_TRY(sk_alloc(s, std::max<size_t>(tc.size(), 1), &dc));
+        SK_TRY(sk_alloc(s, std::max<size_t>(te.size(), 1), &de));
+        if (!tc.empty()) SK_HIP(hipMemcpy(dc, tc.data(), tc.size() * 8, hipMemcpyHostToDevice));
+        if (!te.empty()) SK_HIP(hipMemcpy(de, te.data(), te.size() * 8, hipMemcpyHostToDevice));
+        s->pm.csr_thr = dc;
+        s->pm.edge_thr = de;
+    }
 
     // centers (CompactSketch)
     if (s->compact) {
@@ -1445,7 +1517,26 @@ extern "C" im_status im_influence(im_ctx *ctx, const im_graph *g, im_prob prob, 
     if (k == 0 || sims == 0) return IM_OK;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
-    const ProbDev pm = prob_dev(prob, g->off);
+    ProbDev pm = prob_dev(prob, g->off);
+    uint64_t *pe_dev = nullptr;  // per-edge model: thresholds by edge, for the call
+    if (prob.kind == IM_PROB_PER_EDGE && g->m_und) {
+        std::vector<uint64_t> tc, te;
+        im_status r0 = per_edge_thresholds(ctx, g, prob.p_edge, tc, te);
+        if (r0 != IM_OK) return r0;
+        r0 = dev_alloc(ctx, te.size() * 8, (void **)&pe_dev);
+        if (r0 != IM_OK) return r0;
+        if (hipMemcpy(pe_dev, te.data(), te.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+            dev_free(ctx, pe_dev, te.size() * 8);
+            return fail(ctx, IM_EDEVICE, "influence: threshold upload failed");
+        }
+        pm.edge_thr = pe_dev;
+    }
+    struct PeFree {  // the per-edge thresholds go with the call
+        im_ctx *c;
+        uint64_t *p;
+        size_t bytes;
+        ~PeFree() { if (p) dev_free(c, p, bytes); }
+    } pe_free{ctx, pe_dev, (size_t)g->m_und * 8};
     const uint32_t nk = key_slots(sims);
     auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t small = a256((size_t)nk * 8) + a256((size_t)k * 4) + 256;
@@ -1688,6 +1779,8 @@ extern "C" im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_
         if (Q.k > Q.graph->n) return fail(ctx, IM_EINVAL, "k exceeds n");
         if (!seeds_out[q] || !gains_out[q]) return fail(ctx, IM_EINVAL, "null output array");
         if (const char *why = prob_problem(Q.prob)) return fail(ctx, IM_EINVAL, why);
+        if (Q.prob.kind == IM_PROB_PER_EDGE)
+            return fail(ctx, IM_EINVAL, "per-edge probabilities are not supported in batched queries");
         const uint32_t kb = std::max<uint32_t>(1, bit_length((uint64_t)Q.graph->n - 1));
         if (kb + bit_length((uint64_t)Q.R * Q.graph->n + 1) > 64) return fail(ctx, IM_EINVAL, "R*n too large");
     }

@@ -470,7 +470,7 @@ extern "C" im_status im_server_submit(im_server *sv, uint32_t graph, im_prob pro
     if (!sv || !ticket) return IM_EINVAL;
     if (graph >= sv->graphs.size() || R == 0 || R > sv->cfg.max_R || k > sv->cfg.max_k || k > sv->graphs[graph]->n)
         return IM_EINVAL;
-    if (prob_problem(prob)) return IM_EINVAL;
+    if (prob_problem(prob) || prob.kind == IM_PROB_PER_EDGE) return IM_EINVAL;
     const uint32_t n = sv->graphs[graph]->n;
     const uint32_t kb = std::max<uint32_t>(1, bit_length((uint64_t)n - 1));
     if (kb + bit_length((uint64_t)R * n + 1) > 64) return IM_EINVAL;

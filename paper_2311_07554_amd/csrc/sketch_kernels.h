@@ -131,9 +131,9 @@ __device__ __forceinline__ void uf_unite_from(uint32_t *P, uint32_t a, uint32_t 
 // Live mask of one edge word x over sketches [0, B): bit b set iff the edge is
 // live in sketch b.  K must hold round_up(B, 8) keys.
 template <int KIND>
-__device__ __forceinline__ uint64_t live_mask(uint32_t u, uint32_t v, uint64_t x, const uint64_t *__restrict__ K,
-                                              uint32_t B, const ProbDev &pm) {
-    const uint64_t T = edge_threshold_of<KIND>(pm, u, v, x);
+__device__ __forceinline__ uint64_t live_mask(uint32_t u, uint32_t v, uint64_t x, uint64_t e,
+                                              const uint64_t *__restrict__ K, uint32_t B, const ProbDev &pm) {
+    const uint64_t T = edge_threshold_of<KIND>(pm, u, v, x, e);
     const uint64_t all = B >= 64 ? ~0ull : ((1ull << B) - 1ull);
     if (T == kAllLive) return all;
     uint64_t live = 0;
@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(kHookBlock) k_sample_hook(const uint2 *__restr
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
         const uint2 uv = edges[e];
-        unite_live(parent, ns, live_mask<KIND>(uv.x, uv.y, ((uint64_t)uv.x << 32) | uv.y, K, B, pm), uv.x, uv.y);
+        unite_live(parent, ns, live_mask<KIND>(uv.x, uv.y, ((uint64_t)uv.x << 32) | uv.y, e, K, B, pm), uv.x, uv.y);
     }
 }
 

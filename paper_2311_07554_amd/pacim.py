@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpacim.so")
 
 IM_OK, IM_EINVAL, IM_ENOMEM, IM_EDEVICE, IM_EBUSY, IM_EINTERNAL = range(6)
-IM_PROB_UNIFORM, IM_PROB_TRIVALENCY, IM_PROB_RANGE, IM_PROB_WIC = 0, 1, 2, 3
+IM_PROB_UNIFORM, IM_PROB_TRIVALENCY, IM_PROB_RANGE, IM_PROB_WIC, IM_PROB_PER_EDGE = 0, 1, 2, 3, 4
 _STATUS = {0: "IM_OK", 1: "IM_EINVAL", 2: "IM_ENOMEM", 3: "IM_EDEVICE", 4: "IM_EBUSY", 5: "IM_EINTERNAL"}
 
 
@@ -30,7 +30,8 @@ class ImError(RuntimeError):
 
 
 class im_prob(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("p", ctypes.c_double), ("p_hi", ctypes.c_double)]
+    _fields_ = [("kind", ctypes.c_int32), ("p", ctypes.c_double), ("p_hi", ctypes.c_double),
+                ("p_edge", ctypes.c_void_p)]
 
 
 class im_sketch_stats(ctypes.Structure):
@@ -205,10 +206,15 @@ def im_graph_free(g):
 
 
 def _prob(kind: int, p):
-    """p: a float, or (lo, hi) for IM_PROB_RANGE."""
+    """p: a float; (lo, hi) for IM_PROB_RANGE; a float64 array with one probability per
+    CSR entry for IM_PROB_PER_EDGE (the caller keeps it alive for the call)."""
+    if isinstance(p, np.ndarray):
+        if p.dtype != np.float64 or not p.flags.c_contiguous:
+            raise ValueError("per-edge probabilities must be a contiguous float64 array")
+        return im_prob(int(kind), 0.0, 0.0, p.ctypes.data)
     if isinstance(p, (tuple, list)):
-        return im_prob(int(kind), float(p[0]), float(p[1]))
-    return im_prob(int(kind), float(p), 0.0)
+        return im_prob(int(kind), float(p[0]), float(p[1]), None)
+    return im_prob(int(kind), float(p), 0.0, None)
 
 
 def im_build_sketches(ctx, g, kind: int, p: float, R: int, seed: int, alpha: float = 1.0) -> int:

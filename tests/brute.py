@@ -129,3 +129,11 @@ def exact_ic_spread(n, edges, p, S):
     if not S:
         return Fraction(0)
     return rec(S, S)
+
+
+def per_edge_p(g, salt=0):
+    """A symmetric probability per CSR entry of graph g, from the pair (min, max)."""
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.offsets.astype(np.int64)))
+    cols = g.cols.astype(np.int64)
+    a, b = np.minimum(rows, cols), np.maximum(rows, cols)
+    return np.ascontiguousarray(((a * 7919 + b * 104729 + salt * 31) % 1000) / 1000.0, dtype=np.float64)

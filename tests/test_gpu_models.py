@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 from paper_2311_07554_amd import inputs, pacim
+from tests import brute
 from tests.gpu_util import run_select, upload
 
 pytestmark = pytest.mark.gpu
@@ -111,6 +112,64 @@ def test_model_arguments(ctx):
     sk.close()
     sk = gr.sketches(pacim.IM_PROB_UNIFORM, 0.2, 4, 1)
     s2, g2 = sk.select(10)
+    sk.close()
+    gr.close()
+    assert np.array_equal(s1, s2) and np.array_equal(g1, g2)
+
+
+PER_EDGE = pacim.IM_PROB_PER_EDGE
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.2])
+def test_per_edge_model_matches_oracle(ctx, alpha):
+    # the caller's probability for every CSR entry (symmetric), converted once to thresholds
+    scale, R, k, seed = 12, 36, 20, 6
+    g = inputs.rmat_graph(scale, 16 << scale, seed=43)
+    pe = brute.per_edge_p(g, 5) * 0.2  # p_e in [0, 0.2)
+    _say(f"case per-edge alpha={alpha}")
+    lab, siz = oracle.sketches(g, oracle.PER_EDGE, pe, seed, R, threads=8)
+    gr = upload(ctx, g)
+    sk = gr.sketches(PER_EDGE, pe, R, seed, alpha)
+    if alpha == 1.0:
+        for r in range(0, R, 5):
+            gl, gs = sk.dump(r)
+            assert np.array_equal(gl, lab[r]) and np.array_equal(gs, siz[r]), r
+    else:
+        cents = oracle.centers(g.n, seed, alpha)
+        lc, sc = oracle.compact_all(lab, siz, cents)
+        for r in range(0, R, 5):
+            gl, gs = sk.dump(r)
+            assert np.array_equal(gl, lc[r]) and np.array_equal(gs, sc[r]), r
+    assert np.array_equal(sk.initial_gains(), siz.astype(np.uint64).sum(axis=0))
+    s, gn = sk.select(k)
+    sk.close()
+    ws, wg = oracle.greedy(lab, siz, k)
+    assert np.array_equal(s, ws) and np.array_equal(gn, wg)
+    got = gr.influence(PER_EDGE, pe, s, 11, 100, 70)
+    gr.close()
+    assert got == oracle.influence(g, oracle.PER_EDGE, pe, s, 11, 100, 70, threads=8)
+
+
+def test_per_edge_model_arguments(ctx):
+    g = inputs.er_graph(60, 150, seed=3)
+    gr = upload(ctx, g)
+    pe = brute.per_edge_p(g, 1)
+    bad = pe.copy()
+    bad[0] = 1.5
+    asym = pe.copy()
+    asym[0] = (asym[0] + 0.5) % 1.0   # one direction of an edge only
+    for p in (bad, asym):
+        with pytest.raises(pacim.ImError) as e:
+            gr.sketches(PER_EDGE, p, 4, 1)
+        assert e.value.status == pacim.IM_EINVAL
+    with pytest.raises(pacim.ImError) as e:
+        ctx.select_batched([(gr, PER_EDGE, pe, 4, 3, 1)], None)
+    assert e.value.status == pacim.IM_EINVAL
+    sk = gr.sketches(PER_EDGE, np.full(g.cols.size, 0.3), 8, 2)   # constant: the Consistent model
+    s1, g1 = sk.select(6)
+    sk.close()
+    sk = gr.sketches(pacim.IM_PROB_UNIFORM, 0.3, 8, 2)
+    s2, g2 = sk.select(6)
     sk.close()
     gr.close()
     assert np.array_equal(s1, s2) and np.array_equal(g1, g2)

@@ -182,14 +182,6 @@ def _threshold_spelled_out(kind, p, u, w, du, dw):
     return M64 if s_ <= 2 else (1 << 65) // s_
 
 
-def per_edge_p(g, salt=0):
-    """A symmetric probability per CSR entry, from the pair (min, max)."""
-    rows = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.offsets.astype(np.int64)))
-    cols = g.cols.astype(np.int64)
-    a, b = np.minimum(rows, cols), np.maximum(rows, cols)
-    return np.ascontiguousarray(((a * 7919 + b * 104729 + salt * 31) % 1000) / 1000.0, dtype=np.float64)
-
-
 def _live_edges(g, kind, p, seed, r):
     res = []
     deg = np.diff(g.offsets.astype(np.int64))
@@ -211,7 +203,7 @@ def _live_edges(g, kind, p, seed, r):
 def test_sketch_labels_match_transitive_closure(gi, kind, p):
     g = _tiny_graphs()[gi]
     if kind == 4:
-        p = per_edge_p(g, gi)
+        p = brute.per_edge_p(g, gi)
     for r in range(8):
         edges = _live_edges(g, kind, p, 3, r)
         lab_b, siz_b, _ = brute.closure_labels(g.n, edges)
@@ -520,7 +512,7 @@ def test_influence_equals_reach_in_each_world(gi, kind, p):
     # with worlds spelled out from the published mixer and reach from closures
     g = _tiny_graphs()[gi]
     if kind == 4:
-        p = per_edge_p(g, gi)
+        p = brute.per_edge_p(g, gi)
     S = [0, g.n - 1, 0]
     sims, sseed = 40, 77
     want = 0
@@ -565,7 +557,7 @@ def test_per_edge_model_reduces_to_constant_and_matches_cascade():
     n = 6
     edges = [(0, 1), (1, 2), (2, 0), (2, 3), (3, 4), (4, 5), (1, 5)]
     t = inputs.csr_from_pairs(n, edges)
-    pe = per_edge_p(t, 3)
+    pe = brute.per_edge_p(t, 3)
     rows = np.repeat(np.arange(n), np.diff(t.offsets.astype(np.int64)))
     exact_p = {(min(int(u), int(w)), max(int(u), int(w))): Fraction(float(x))
                for u, w, x in zip(rows, t.cols, pe)}
