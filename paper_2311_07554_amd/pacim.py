@@ -501,3 +501,26 @@ class Server:
 
     def __exit__(self, *a):
         self.close()
+
+
+def select_seeds(offsets, cols, kind: int, p, R: int, k: int, seed: int, alpha: float = 1.0, stream=None):
+    """One query on the current torch device: upload the CSR (torch tensors -- int64
+    offsets, int32 cols, on the device or the host -- or numpy arrays), build R sketches
+    (full labels for alpha = 1, CompactSketch below), select k seeds, free everything.
+    Work is issued on `stream` (default: torch's current stream); torch only supplies
+    the memory and the stream.  Returns (seeds uint32[k], gains uint64[k])."""
+    import torch
+    dev = torch.cuda.current_device()
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    n = int(offsets.numel() if hasattr(offsets, "numel") else len(offsets)) - 1
+    with Context(dev, stream) as ctx:
+        g = ctx.graph(n, offsets, cols)
+        try:
+            sk = g.sketches(kind, p, R, seed, alpha)
+            try:
+                return sk.select(k)
+            finally:
+                sk.close()
+        finally:
+            g.close()

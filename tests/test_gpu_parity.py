@@ -237,3 +237,16 @@ def test_invalid_arguments(ctx):
     sk.close()
     gr.close()
     assert lib.im_ctx_memory(ctx.h)[0] == 0
+
+
+def test_module_level_select_from_torch_tensors():
+    # CSR handed over as device tensors on torch's current stream; full labels and CompactSketch
+    import torch
+    g = inputs.rmat_graph(11, 16 << 11, seed=44)
+    off = torch.from_numpy(g.offsets.view(np.int64)).cuda()
+    cols = torch.from_numpy(g.cols.view(np.int32)).cuda()
+    lab, siz = oracle.sketches(g, TRI, 0.0, 3, 24, threads=8)
+    ws, wg = oracle.greedy(lab, siz, 12)
+    for alpha in (1.0, 0.25):
+        s, gn = pacim.select_seeds(off, cols, TRI, 0.0, 24, 12, 3, alpha=alpha)
+        assert np.array_equal(s, ws) and np.array_equal(gn, wg), alpha
