@@ -132,6 +132,8 @@ struct im_sketches {
     bool pt_valid = false;             // the runs hold the current key of every unselected vertex
     PtState *pt_state = nullptr;       // device
     PtState *pt_host = nullptr;        // pinned host copy read after each batch
+    PtDev *pt_dev = nullptr;           // device rounds (full labels): runs and stop state, device
+    PtDev *pt_dev_host = nullptr;      // its pinned host copy
     // bookkeeping
     std::vector<std::pair<void *, size_t>> allocs;
     uint32_t chosen = 0;
@@ -691,6 +693,10 @@ void free_sketches(im_sketches *s) {
     if (s->pt_host) {
         (void)hipHostFree(s->pt_host);
         s->pt_host = nullptr;
+    }
+    if (s->pt_dev_host) {
+        (void)hipHostFree(s->pt_dev_host);
+        s->pt_dev_host = nullptr;
     }
     if (s->bulk_cs) {
         cc_scratch_free(s->ctx, static_cast<CCScratch *>(s->bulk_cs));
@@ -1321,7 +1327,10 @@ im_status pt_build(im_sketches *s) {
         }
         im_status a = sk_alloc(s, 1, &s->pt_state);
         if (a != IM_OK) return a;
+        a = sk_alloc(s, 1, &s->pt_dev);
+        if (a != IM_OK) return a;
         HIP_TRY(ctx, hipHostMalloc((void **)&s->pt_host, sizeof(PtState), hipHostMallocDefault));
+        HIP_TRY(ctx, hipHostMalloc((void **)&s->pt_dev_host, sizeof(PtDev), hipHostMallocDefault));
     }
     s->pt_x = 0;
     s->pt_y = 1;
@@ -1354,17 +1363,18 @@ uint32_t pt_bulk_min(const im_sketches *s) {
 // queue and evaluated until the best evaluated key ranks above the queue's Max();
 // that vertex is the seed (MarkSeed follows); the others are put back with their
 // new keys.  The host reads the stop flag after each batch.
-im_status pt_round(im_sketches *s) {
+// Batches of one round from `off` vertices evaluated and batch size `batch` on,
+// until the best evaluated key ranks above the queue's Max(); *tot = the round's
+// evaluation count.  The host reads the stop flag after each batch.
+im_status pt_batches(im_sketches *s, uint32_t off, uint64_t batch, uint32_t *tot) {
     im_ctx *ctx = s->ctx;
     hipStream_t st = ctx->stream;
     GraphDev gd{s->g->off, s->g->cols};
     const CompactDev cd = compact_dev(s);
     const unsigned long long pinit = (unsigned long long)s->R << kPartialShift;
-    k_pt_round_begin<<<1, 64, 0, st>>>(s->st);
     const uint32_t bulk_min = s->compact ? pt_bulk_min(s) : 0u;
     bool all_known = false;  // key[] holds every vertex's Marginal for this round
-    uint32_t off = 0;
-    for (uint64_t batch = 1;; batch *= 2) {
+    for (;; batch *= 2) {
         const uint32_t nxl = s->pt_nx - s->pt_hx, nyl = s->pt_ny - s->pt_hy;
         const uint32_t m = (uint32_t)std::min<uint64_t>(batch, (uint64_t)nxl + nyl);
         if (m == 0) return fail(ctx, IM_EINTERNAL, "prefix-doubling round ran out of vertices");
@@ -1403,12 +1413,22 @@ im_status pt_round(im_sketches *s) {
         off += m;
         if (s->pt_host->stop) break;
     }
-    const uint32_t tot = off;
+    *tot = off;
+    return IM_OK;
+}
+
+// The round's end (seed, MarkSeed) for a round of tot evaluations.
+void pt_end(im_sketches *s, uint32_t tot) {
+    hipStream_t st = s->ctx->stream;
     k_pt_round_end<<<1, 64, 0, st>>>(s->st, s->key, s->in_s, s->n, s->kb, tot, s->seeds_d, s->gains_d, s->evals_d,
                                      s->compact ? nullptr : s->E, s->R);
     if (s->compact) enqueue_markseed_compact(s);
-    // BatchInsert of the round's other evaluated vertices (s*'s key is now 0 and
-    // sorts last), merged with Y's unread part
+}
+
+// BatchInsert of the round's other evaluated vertices (s*'s key is now 0 and
+// sorts last), merged with Y's unread part.
+im_status pt_insert(im_sketches *s, uint32_t tot) {
+    hipStream_t st = s->ctx->stream;
     if (tot > 1) {
         int f[3];
         pt_spare(s, f);
@@ -1423,8 +1443,14 @@ im_status pt_round(im_sketches *s) {
         s->pt_hy = 0;
         s->pt_ny = tot - 1 + nyl;
     }
-    // Y is merged into X once it outgrows X's unread part, so that re-inserting
-    // stays proportional to what was re-inserted since
+    HIP_TRY(s->ctx, hipGetLastError());
+    return IM_OK;
+}
+
+// Y is merged into X once it outgrows X's unread part, so that re-inserting stays
+// proportional to what was re-inserted since.
+im_status pt_fold(im_sketches *s) {
+    hipStream_t st = s->ctx->stream;
     const uint32_t nxl = s->pt_nx - s->pt_hx, nyl = s->pt_ny - s->pt_hy;
     if (nyl > nxl) {
         int f[3];
@@ -1436,8 +1462,79 @@ im_status pt_round(im_sketches *s) {
         s->pt_nx = nxl + nyl;
         s->pt_hy = s->pt_ny = 0;
     }
-    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(s->ctx, hipGetLastError());
     return IM_OK;
+}
+
+// One round of Algorithm 4 with the host driving each batch.
+im_status pt_round(im_sketches *s) {
+    k_pt_round_begin<<<1, 64, 0, s->ctx->stream>>>(s->st);
+    uint32_t tot = 0;
+    im_status rc = pt_batches(s, 0, 1, &tot);
+    if (rc != IM_OK) return rc;
+    pt_end(s, tot);
+    rc = pt_insert(s, tot);
+    return rc != IM_OK ? rc : pt_fold(s);
+}
+
+// Up to max_rounds rounds on the device (full labels), finishing on the host the
+// round or step it stopped at.  *done = rounds completed.
+im_status pt_device_rounds(im_sketches *s, uint32_t max_rounds, uint32_t *done) {
+    im_ctx *ctx = s->ctx;
+    hipStream_t st = ctx->stream;
+    PtDev &h = *s->pt_dev_host;
+    for (int i = 0; i < 5; ++i) h.buf[i] = s->pt_buf[i];
+    h.x = s->pt_x;
+    h.y = s->pt_y;
+    h.hx = s->pt_hx;
+    h.nx = s->pt_nx;
+    h.hy = s->pt_hy;
+    h.ny = s->pt_ny;
+    HIP_TRY(ctx, hipMemcpyAsync(s->pt_dev, &h, sizeof(PtDev), hipMemcpyHostToDevice, st));
+    k_pt_rounds<<<1, kPtRoundBlock, 0, st>>>(s->pt_dev, max_rounds, s->st, s->key, s->in_s, s->n, s->kb, s->seeds_d,
+                                             s->gains_d, s->evals_d, s->E, s->R, s->evl);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipMemcpyAsync(&h, s->pt_dev, sizeof(PtDev), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    s->pt_x = h.x;
+    s->pt_y = h.y;
+    s->pt_hx = h.hx;
+    s->pt_nx = h.nx;
+    s->pt_hy = h.hy;
+    s->pt_ny = h.ny;
+    uint32_t rounds = h.rounds;
+    im_status rc = IM_OK;
+    switch (h.stop) {
+    case kPtStopDone:
+        break;
+    case kPtStopMidRound: {
+        uint32_t tot = 0;
+        rc = pt_batches(s, h.off, h.batch, &tot);
+        if (rc != IM_OK) break;
+        pt_end(s, tot);
+        rc = pt_insert(s, tot);
+        if (rc == IM_OK) rc = pt_fold(s);
+        ++rounds;
+        break;
+    }
+    case kPtStopInsert:
+        rc = pt_insert(s, h.off);
+        if (rc == IM_OK) rc = pt_fold(s);
+        break;
+    case kPtStopFold:
+        rc = pt_fold(s);
+        break;
+    default:
+        rc = fail(ctx, IM_EINTERNAL, "device prefix-doubling rounds: bad stop state");
+    }
+    if (rc == IM_OK && rounds == 0) rc = fail(ctx, IM_EINTERNAL, "device prefix-doubling rounds made no progress");
+    *done = rounds;
+    return rc;
+}
+
+bool pt_device_enabled() {
+    const char *e = getenv("PACIM_PTREE_DEVICE");  // "0" (tests): every batch from the host
+    return !(e && !strcmp(e, "0"));
 }
 
 }  // namespace
@@ -1459,7 +1556,16 @@ extern "C" im_status im_select_seeds_ptree(im_ctx *ctx, im_sketches *s, uint32_t
         Prof p(ctx, "select_ptree");
         if (!s->pt_valid) rc = pt_build(s);
         s->tree_valid = false;
-        for (uint32_t i = 0; i < k && rc == IM_OK; ++i) rc = pt_round(s);
+        for (uint32_t i = 0; i < k && rc == IM_OK;) {
+            if (!s->compact && pt_device_enabled()) {
+                uint32_t done = 0;
+                rc = pt_device_rounds(s, k - i, &done);
+                i += done;
+            } else {
+                rc = pt_round(s);
+                ++i;
+            }
+        }
     }
     (void)hipEventRecord(t1, st);
     std::vector<uint32_t> seeds(k);

@@ -239,12 +239,10 @@ __global__ void k_pt_check(const uint64_t *__restrict__ X, uint32_t nx, const ui
 // evaluation count; its key is cleared so that BatchInsert's gather leaves it out
 // (it sorts last).  Full labels: MarkSeed zeroes the size at s*'s label in every
 // sketch.  One wave.
-__global__ void __launch_bounds__(64) k_pt_round_end(SelState *__restrict__ st, uint64_t *__restrict__ key,
-                                                     uint8_t *__restrict__ in_s, uint32_t n, uint32_t kb, uint32_t tot,
-                                                     uint32_t *__restrict__ seeds_out,
-                                                     unsigned long long *__restrict__ gains_out,
-                                                     uint32_t *__restrict__ evals_out, uint2 *__restrict__ E,
-                                                     uint32_t R) {
+__device__ __forceinline__ void pt_round_end_wave(SelState *st, uint64_t *key, uint8_t *in_s, uint32_t n,
+                                                  uint32_t kb, uint32_t tot, uint32_t *seeds_out,
+                                                  unsigned long long *gains_out, uint32_t *evals_out, uint2 *E,
+                                                  uint32_t R) {
     const uint32_t lane = lane_id();
     const uint64_t ks = st->delta;
     const uint64_t mask = (1ull << kb) - 1ull;
@@ -271,6 +269,173 @@ __global__ void __launch_bounds__(64) k_pt_round_end(SelState *__restrict__ st, 
         }
     }
     if (lane == 0) st->round = round + 1;
+}
+
+__global__ void __launch_bounds__(64) k_pt_round_end(SelState *__restrict__ st, uint64_t *__restrict__ key,
+                                                     uint8_t *__restrict__ in_s, uint32_t n, uint32_t kb, uint32_t tot,
+                                                     uint32_t *__restrict__ seeds_out,
+                                                     unsigned long long *__restrict__ gains_out,
+                                                     uint32_t *__restrict__ evals_out, uint2 *__restrict__ E,
+                                                     uint32_t R) {
+    pt_round_end_wave(st, key, in_s, n, kb, tot, seeds_out, gains_out, evals_out, E, R);
+}
+
+// ---- whole rounds on the device (full labels) ------------------------------
+// One workgroup runs round after round while everything stays small: batches of
+// at most kPtDevBatch vertices (one wave per evaluation), BatchInsert sorted in
+// LDS and merged with Y by the workgroup.  It stops, leaving the rest to the host
+// kernels above, inside a round whose next batch is larger (state: off, batch),
+// after a round whose insertion is larger, or after a round whose Y outgrew X's
+// unread part (the host merges them).  Without it every batch is a host round trip.
+constexpr uint32_t kPtRoundBlock = 1024;
+constexpr uint32_t kPtDevBatch = 512;
+constexpr uint32_t kPtDevSort = 2 * kPtDevBatch;  // keys of one round, at most
+constexpr uint32_t kPtDevMerge = 1u << 18;        // largest Y merge done on the device
+
+enum : uint32_t { kPtStopDone = 0, kPtStopMidRound = 1, kPtStopInsert = 2, kPtStopFold = 3 };
+
+struct PtDev {
+    uint64_t *buf[5];
+    int32_t x, y;                // buffers of the runs X and Y
+    uint32_t hx, nx, hy, ny;     // their unread parts [hx, nx), [hy, ny)
+    uint32_t rounds;             // rounds completed by the launch
+    uint32_t stop;               // why it returned (kPtStop*)
+    uint32_t off, batch;         // mid-round: vertices evaluated in the round so far, next batch size;
+                                 // insertion left to the host: the round's evaluation count
+};
+
+__global__ void __launch_bounds__(kPtRoundBlock) k_pt_rounds(PtDev *__restrict__ pd, uint32_t max_rounds,
+                                                             SelState *__restrict__ st, uint64_t *__restrict__ key,
+                                                             uint8_t *__restrict__ in_s, uint32_t n, uint32_t kb,
+                                                             uint32_t *__restrict__ seeds_out,
+                                                             unsigned long long *__restrict__ gains_out,
+                                                             uint32_t *__restrict__ evals_out,
+                                                             uint2 *__restrict__ E, uint32_t R,
+                                                             uint32_t *__restrict__ evl) {
+    constexpr uint32_t kWaves = kPtRoundBlock / kWave;
+    __shared__ uint64_t srt[kPtDevSort];
+    __shared__ unsigned long long sh_best[kWaves];
+    __shared__ uint32_t sh_take;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    uint64_t *b[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) b[i] = pd->buf[i];
+    int32_t x = pd->x, y = pd->y;
+    uint32_t hx = pd->hx, nx = pd->nx, hy = pd->hy, ny = pd->ny;
+    const uint64_t mask = (1ull << kb) - 1ull;
+    uint32_t rounds = 0, stop = kPtStopDone, off = 0;
+    uint64_t batch = 1;
+    while (rounds < max_rounds) {
+        uint64_t best = 0;
+        off = 0;
+        batch = 1;
+        bool mid = false;
+        for (;;) {
+            const uint32_t nxl = nx - hx, nyl = ny - hy;
+            const uint32_t m = (uint32_t)min<uint64_t>(batch, (uint64_t)nxl + nyl);
+            if (m > kPtDevBatch) {
+                mid = true;
+                break;
+            }
+            const uint64_t *X = b[x] + hx, *Y = b[y] + hy;
+            // SplitAndRemove(m): entry t of merge(X, Y) per thread
+            if (tid < m) {
+                const uint32_t i = pt_corank(X, nxl, Y, nyl, tid), j = tid - i;
+                const uint64_t kk = (i < nxl && (j >= nyl || X[i] > Y[j])) ? X[i] : Y[j];
+                evl[off + tid] = (uint32_t)(mask - (kk & mask));
+            }
+            if (tid == 0) sh_take = pt_corank(X, nxl, Y, nyl, m);
+            __syncthreads();
+            // Marginal of every extracted vertex, one wave each
+            uint64_t wb = 0;
+            for (uint32_t e = w; e < m; e += kWaves) {
+                const uint32_t v = evl[off + e];
+                const uint64_t g = marginal_full(E, R, v);
+                const uint64_t nk = in_s[v] ? 0ull : pack_key(g, v, kb);
+                if (lane == 0) key[v] = nk;
+                wb = nk > wb ? nk : wb;
+            }
+            if (lane == 0) sh_best[w] = wb;
+            __syncthreads();
+            for (uint32_t i = 0; i < kWaves; ++i) best = sh_best[i] > best ? sh_best[i] : best;
+            const uint32_t take = sh_take;
+            uint64_t top = 0;
+            if (take < nxl) top = X[take];
+            if (m - take < nyl && Y[m - take] > top) top = Y[m - take];
+            hx += take;
+            hy += m - take;
+            off += m;
+            batch *= 2;
+            __syncthreads();  // sh_take and sh_best are rewritten by the next batch
+            if (best > top) break;
+        }
+        if (tid == 0) st->delta = best;
+        __syncthreads();
+        if (mid) {
+            stop = kPtStopMidRound;
+            break;
+        }
+        if (w == 0) pt_round_end_wave(st, key, in_s, n, kb, off, seeds_out, gains_out, evals_out, E, R);
+        __syncthreads();
+        ++rounds;
+        // BatchInsert of the other evaluated vertices (s*'s key is now 0: it sorts last)
+        const uint32_t tot = off;
+        if (tot > 1) {
+            const uint32_t nyl = ny - hy;
+            if (tot > kPtDevSort || (uint64_t)nyl + tot - 1 > kPtDevMerge) {
+                stop = kPtStopInsert;
+                break;
+            }
+            uint32_t N = 2;
+            while (N < tot) N <<= 1;
+            for (uint32_t t = tid; t < N; t += kPtRoundBlock) srt[t] = t < tot ? key[evl[t]] : 0ull;
+            __syncthreads();
+            for (uint32_t k = 2; k <= N; k <<= 1) {
+                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                    if (tid < N / 2) {
+                        const uint32_t i = ((tid & ~(j - 1)) << 1) | (tid & (j - 1));
+                        const uint64_t p0 = srt[i], p1 = srt[i + j];
+                        const bool dec = (i & k) == 0;
+                        if (dec ? p0 < p1 : p0 > p1) {
+                            srt[i] = p1;
+                            srt[i + j] = p0;
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            int32_t f = 0;
+            while (f == x || f == y) ++f;
+            const uint32_t total = tot - 1 + nyl;
+            const uint32_t per = (total + kPtRoundBlock - 1) / kPtRoundBlock;
+            const uint64_t *Yl = b[y] + hy;
+            uint64_t *out = b[f];
+            const uint32_t d0 = tid * per;
+            if (d0 < total)
+                pt_merge_span(srt, tot - 1, Yl, nyl, d0, min(per, total - d0),
+                              [&](uint32_t p, uint64_t kk) { out[p] = kk; });
+            __syncthreads();
+            y = f;
+            hy = 0;
+            ny = total;
+        }
+        if (ny - hy > nx - hx) {
+            stop = kPtStopFold;
+            break;
+        }
+    }
+    if (tid == 0) {
+        pd->x = x;
+        pd->y = y;
+        pd->hx = hx;
+        pd->nx = nx;
+        pd->hy = hy;
+        pd->ny = ny;
+        pd->rounds = rounds;
+        pd->stop = stop;
+        pd->off = off;
+        pd->batch = (uint32_t)batch;
+    }
 }
 
 // BatchInsert's input: the current keys of the round's evaluated vertices.

@@ -143,3 +143,17 @@ def test_ptree_compact_bulk_evaluation(ctx, bulk, cap, monkeypatch):
         assert st["bulk_resampled"] == 0
     elif bulk == "1":
         assert 1 <= st["bulk_resampled"] <= st["bulk_rounds"]
+
+
+@pytest.mark.parametrize("scale,kind,p,R,k,seed", [(12, TRI, 0.0, 40, 40, 3), (14, U, 0.3, 16, 20, 5)])
+def test_ptree_host_driven_rounds(ctx, scale, kind, p, R, k, seed, monkeypatch):
+    # full labels run whole rounds on the device by default; the host-driven rounds
+    # (every batch a launch and a read-back) must give the same
+    monkeypatch.setenv("PACIM_PTREE_DEVICE", "0")
+    g = inputs.rmat_graph(scale, 8 << scale, seed=seed)
+    _say(f"case ptree host-driven scale={scale}")
+    lab, siz = oracle.sketches(g, kind, p, seed, R, threads=8)
+    ws, wg, wev = oracle.ptree(lab, siz, k)
+    s, gn, ev, _ = _ptree_gpu(ctx, g, kind, p, R, k, seed, 1.0)
+    assert np.array_equal(s, ws) and np.array_equal(gn, wg)
+    assert np.array_equal(ev.astype(np.uint64), wev)
