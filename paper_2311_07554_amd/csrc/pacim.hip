@@ -1528,6 +1528,8 @@ im_status pt_device_rounds(im_sketches *s, uint32_t max_rounds, uint32_t *done) 
         rc = fail(ctx, IM_EINTERNAL, "device prefix-doubling rounds: bad stop state");
     }
     if (rc == IM_OK && rounds == 0) rc = fail(ctx, IM_EINTERNAL, "device prefix-doubling rounds made no progress");
+    if (rc == IM_OK && h.stop == kPtStopDone && rounds < max_rounds)
+        rc = fail(ctx, IM_EINTERNAL, "device prefix-doubling rounds stopped early");
     *done = rounds;
     return rc;
 }

@@ -329,10 +329,14 @@ __global__ void __launch_bounds__(kPtRoundBlock) k_pt_rounds(PtDev *__restrict__
         uint64_t best = 0;
         off = 0;
         batch = 1;
-        bool mid = false;
+        bool mid = false, empty = false;
         for (;;) {
             const uint32_t nxl = nx - hx, nyl = ny - hy;
             const uint32_t m = (uint32_t)min<uint64_t>(batch, (uint64_t)nxl + nyl);
+            if (m == 0) {  // no vertex left before a seed was found: cannot happen for k <= n - |S|
+                empty = true;
+                break;
+            }
             if (m > kPtDevBatch) {
                 mid = true;
                 break;
@@ -368,6 +372,10 @@ __global__ void __launch_bounds__(kPtRoundBlock) k_pt_rounds(PtDev *__restrict__
             batch *= 2;
             __syncthreads();  // sh_take and sh_best are rewritten by the next batch
             if (best > top) break;
+        }
+        if (empty) {
+            if (tid == 0) st->err = 4;
+            break;
         }
         if (tid == 0) st->delta = best;
         __syncthreads();
