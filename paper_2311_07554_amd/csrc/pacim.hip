@@ -439,8 +439,12 @@ extern "C" im_status im_graph_upload(im_ctx *ctx, uint32_t n, uint64_t m_dir, co
     if (device_ptrs) {
         off.resize((size_t)n + 1);
         col.resize(m_dir);
-        HIP_TRY(ctx, hipMemcpy(off.data(), offsets, off.size() * sizeof(uint64_t), hipMemcpyDeviceToHost));
-        if (m_dir) HIP_TRY(ctx, hipMemcpy(col.data(), cols, m_dir * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        // read on the context's stream, after the caller's work that wrote the arrays
+        HIP_TRY(ctx, hipMemcpyAsync(off.data(), offsets, off.size() * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+        if (m_dir)
+            HIP_TRY(ctx, hipMemcpyAsync(col.data(), cols, m_dir * sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     } else {
         off.assign(offsets, offsets + (size_t)n + 1);
         col.assign(cols, cols + m_dir);
@@ -635,6 +639,18 @@ im_status per_edge_thresholds(im_ctx *ctx, const im_graph *g, const double *p_ed
     return IM_OK;
 }
 
+// Workgroups of a sampling pass at most; each thread strides over the edges
+// beyond that.  One edge per thread up to 2^30 edges: short-lived workgroups
+// balance the uneven union work and free compute units often, so that kernels
+// of another stream (a selection running beside the build) get them soon.  A
+// persistent-style grid of 8,192 workgroups made the pass 7% slower at 2^24
+// edges.  PACIM_HOOK_GRID_CAP (tuning) overrides.
+unsigned hook_grid_cap() {
+    const char *e = getenv("PACIM_HOOK_GRID_CAP");
+    const unsigned long v = e ? strtoul(e, nullptr, 10) : 0ul;
+    return v ? (unsigned)std::min<unsigned long>(v, 1ul << 24) : (1u << 22);
+}
+
 // One pass over the edge list for b <= cs.B sketches (keys K[0..b)): union-find
 // labels in parent[b][n] (root = smallest id of the CC), member counts at the
 // roots in cnt, and (if center_rank) the smallest center rank of each CC in minc.
@@ -643,7 +659,7 @@ void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const ui
                      hipStream_t st = nullptr) {
     if (!st) st = ctx->stream;
     const uint32_t n = g->n;
-    const unsigned hook_grid = grid_for(g->m_und, kHookBlock, 256 * 32);
+    const unsigned hook_grid = grid_for(g->m_und, kHookBlock, hook_grid_cap());
     dim3 gi((n + 255) / 256, b);
     k_batch_init<<<gi, 256, 0, st>>>(cs.parent, cs.cnt, minc, n, minc_init, center_rank);
     {
@@ -1033,8 +1049,13 @@ im_status run_persistent_rounds(im_sketches *s, uint32_t max_rounds, unsigned lo
     if (const char *pg = getenv("PACIM_PERSIST_GRID"))  // tuning: workgroups of CompactSketch launches
         if (s->compact) grid = std::max<unsigned>(1u, std::min<unsigned>(ctx->persist_grid, (unsigned)strtoul(pg, nullptr, 10)));
     const char *np = getenv("PACIM_PERSIST");  // "0" (tests): take the path below as if refused
-    const hipError_t le = (np && !strcmp(np, "0"))
-                              ? hipErrorNotSupported
+    // A grid of one workgroup (full labels) never waits on another, so it needs no
+    // cooperative launch; cooperative launches on one device run one at a time,
+    // and a plain one can run beside another query's persistent selection.
+    const hipError_t le = (np && !strcmp(np, "0")) ? hipErrorNotSupported
+                          : grid == 1u
+                              ? hipLaunchKernel(reinterpret_cast<const void *>(k_select_persist), dim3(1),
+                                                dim3(kPersistBlock), args, 0, st)
                               : hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_select_persist),
                                                            dim3(grid), dim3(kPersistBlock), args, 0, st);
     if (le != hipSuccess) {
@@ -1064,7 +1085,8 @@ im_status run_persistent_rounds(im_sketches *s, uint32_t max_rounds, unsigned lo
     *last_gain = 0;
     if (*done) {
         unsigned long long g = 0;
-        HIP_TRY(ctx, hipMemcpy(&g, s->gains_d + h1.round - 1, 8, hipMemcpyDeviceToHost));
+        HIP_TRY(ctx, hipMemcpyAsync(&g, s->gains_d + h1.round - 1, 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(ctx, hipStreamSynchronize(st));
         *last_gain = g;
     }
     return IM_OK;
@@ -1761,7 +1783,9 @@ extern "C" im_status im_sketches_stats(const im_sketches *s, im_sketch_stats *ou
     if (!s || !out) return IM_EINVAL;
     SelState hst{};
     (void)hipSetDevice(s->ctx->device);
-    if (hipMemcpy(&hst, s->st, sizeof(SelState), hipMemcpyDeviceToHost) != hipSuccess) return IM_EDEVICE;
+    if (hipMemcpyAsync(&hst, s->st, sizeof(SelState), hipMemcpyDeviceToHost, s->ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(s->ctx->stream) != hipSuccess)
+        return IM_EDEVICE;
     out->seeds_chosen = s->chosen;
     out->rho = s->rho;
     out->evaluations = hst.evals;
