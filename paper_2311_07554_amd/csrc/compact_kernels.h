@@ -453,7 +453,8 @@ __global__ void __launch_bounds__(kBfsBlock) k_markseed_compact(SelState *__rest
 // flag[b][root of s] = 1 for every seed chosen so far (flag zeroed by k_batch_init).
 __global__ void __launch_bounds__(256) k_bulk_seed_roots(const SelState *__restrict__ st,
                                                          const uint32_t *__restrict__ seeds,
-                                                         const uint32_t *__restrict__ parent, uint32_t n,
+                                                         const uint32_t *__restrict__ parent,
+                                                         const uint32_t *__restrict__ newid, uint32_t n,
                                                          uint32_t B, uint32_t *__restrict__ flag) {
     const uint32_t ns = st->round;
     const uint64_t total = (uint64_t)ns * B;
@@ -461,21 +462,23 @@ __global__ void __launch_bounds__(256) k_bulk_seed_roots(const SelState *__restr
          i += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t b = (uint32_t)(i / ns), j = (uint32_t)(i % ns);
         const size_t base = (size_t)b * sketch_stride(n);
-        flag[base + parent[base + seeds[j]]] = 1u;
+        flag[base + parent[base + newid[seeds[j]]]] = 1u;
     }
 }
 
 // partial[v] += sum over the batch of the uncovered CC size of v.
 __global__ void __launch_bounds__(256) k_bulk_accum(const uint32_t *__restrict__ parent,
                                                     const uint32_t *__restrict__ cnt,
-                                                    const uint32_t *__restrict__ flag, uint32_t n, uint32_t B,
+                                                    const uint32_t *__restrict__ flag,
+                                                    const uint32_t *__restrict__ newid, uint32_t n, uint32_t B,
                                                     unsigned long long *__restrict__ partial) {
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
+    const uint32_t iv = newid[v];
     uint64_t s = 0;
     for (uint32_t b = 0; b < B; ++b) {
         const size_t base = (size_t)b * sketch_stride(n);
-        const uint32_t root = parent[base + v];
+        const uint32_t root = parent[base + iv];
         s += flag[base + root] ? 0u : 1u + cnt[base + root];
     }
     partial[v] += s;

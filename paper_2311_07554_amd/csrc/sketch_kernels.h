@@ -2,19 +2,25 @@
 // B sketches per pass over the edge list.
 //
 //   k_sketch_keys     K(seed, r) for every sketch
-//   k_batch_init      parent[b][v] = v, cnt = 0, minc = v's center rank (or a given value)
+//   k_batch_init      parent[b][x] = x, cnt = 0, minc = x's center rank (or a given value)
 //   k_sample_hook     one thread per undirected edge: B live tests (Sample(e, r),
 //                     fused: sampled graphs are never stored), then union by
 //                     hooking the larger root under the smaller one
-//   k_compress        every vertex points at its root (= smallest id of its CC);
-//                     non-root members counted at the root; centers' smallest
-//                     rank recorded at the root (CompactSketch)
+//   k_compress        every vertex points at its root (the smallest number in its
+//                     CC); non-root members counted at the root; centers'
+//                     smallest rank recorded at the root (CompactSketch)
 //   k_emit_full       (label, size) per (v, r) into E[n][R] and the initial gains
 //   k_giant_sample    per sketch, the largest component among sampled vertices'
 //   k_gain0_emit      CompactSketch: the triple label_c / size_c [R][rho], the
 //                     initial gains and that component's membership bitmap, in
 //                     one pass over the vertices
 //   k_center_*        hashed Bernoulli(alpha) centers, ranked by id
+//
+// The forests of a pass number the vertices in the graph's labelling order
+// (x = newid[v] for vertex v, v = iperm[x]): the highest-degree vertices first,
+// so that the parents that most unions touch share a few cache lines.  The
+// hashes still take the vertices' own ids.  Readers translate with newid; a
+// label written out is a vertex id again (iperm of the root).
 #pragma once
 
 #include "common.h"
@@ -37,12 +43,13 @@ __global__ void k_world_keys(uint64_t seed, uint32_t first, uint32_t count, uint
 // sizes (1 + members counted at the root) summed into *total.  grid (x, B).
 __global__ void __launch_bounds__(256) k_influence_accum(const uint32_t *__restrict__ parent,
                                                          const uint32_t *__restrict__ cnt, uint32_t *__restrict__ flag,
-                                                         uint32_t n, const uint32_t *__restrict__ seeds, uint32_t k,
+                                                         const uint32_t *__restrict__ newid, uint32_t n,
+                                                         const uint32_t *__restrict__ seeds, uint32_t k,
                                                          unsigned long long *__restrict__ total) {
     const size_t base = (size_t)blockIdx.y * sketch_stride(n);
     uint64_t sum = 0;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
-        const uint32_t root = parent[base + seeds[i]];
+        const uint32_t root = parent[base + newid[seeds[i]]];
         if (atomicExch(&flag[base + root], 1u) == 0u) sum += 1u + cnt[base + root];
     }
     sum = wave_sum_u64(sum);
@@ -62,6 +69,13 @@ __global__ void __launch_bounds__(256) k_csr_wic_thr(const uint64_t *__restrict_
             thr[j] = wic_threshold((o1 - o0) + (off[w + 1] - off[w]));
         }
     }
+}
+
+// out[x] = in[iperm[x]]: a per-vertex array in labelling order.
+__global__ void k_to_label_order(const uint32_t *__restrict__ in, const uint32_t *__restrict__ iperm, uint32_t n,
+                                 uint32_t *__restrict__ out) {
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) out[x] = in[iperm[x]];
 }
 
 // minc starts at each vertex's own center rank when center_rank is given (so a
@@ -179,17 +193,19 @@ __device__ __forceinline__ void unite_live(uint32_t *parent, size_t stride, uint
     }
 }
 
-// One thread per undirected edge: its live mask over the pass's sketches, then
-// one union per live sketch.
+// One thread per undirected edge: its live mask over the pass's sketches (from
+// the endpoints' ids, edges[e]), then one union per live sketch (between the
+// endpoints' labelling-order numbers, iedges[e]).
 template <int KIND>
-__global__ void __launch_bounds__(kHookBlock) k_sample_hook(const uint2 *__restrict__ edges, uint64_t m,
+__global__ void __launch_bounds__(kHookBlock) k_sample_hook(const uint2 *__restrict__ edges,
+                                                            const uint2 *__restrict__ iedges, uint64_t m,
                                                             const uint64_t *__restrict__ K, uint32_t B, ProbDev pm,
                                                             uint32_t *__restrict__ parent, uint32_t n) {
     const size_t ns = sketch_stride(n);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
-        const uint2 uv = edges[e];
-        unite_live(parent, ns, live_mask<KIND>(uv.x, uv.y, ((uint64_t)uv.x << 32) | uv.y, e, K, B, pm), uv.x, uv.y);
+        const uint2 uv = edges[e], iuv = iedges[e];
+        unite_live(parent, ns, live_mask<KIND>(uv.x, uv.y, ((uint64_t)uv.x << 32) | uv.y, e, K, B, pm), iuv.x, iuv.y);
     }
 }
 
@@ -265,7 +281,9 @@ __global__ void __launch_bounds__(256) k_compress(uint32_t *__restrict__ parent,
 constexpr int kEmitTile = 32;
 constexpr int kEmitGroups = 256 / kEmitTile;
 __global__ void __launch_bounds__(256) k_emit_full(const uint32_t *__restrict__ parent,
-                                                   const uint32_t *__restrict__ cnt, uint32_t n, uint32_t B,
+                                                   const uint32_t *__restrict__ cnt,
+                                                   const uint32_t *__restrict__ newid,
+                                                   const uint32_t *__restrict__ iperm, uint32_t n, uint32_t B,
                                                    uint32_t R, uint32_t r0, uint2 *__restrict__ E,
                                                    uint64_t *__restrict__ gain0) {
     __shared__ uint2 tile[kEmitTile][65];
@@ -275,12 +293,14 @@ __global__ void __launch_bounds__(256) k_emit_full(const uint32_t *__restrict__ 
     const size_t ns = sketch_stride(n);
     uint64_t acc = 0;
     if (v < n) {
+        const uint32_t iv = newid[v];
 #pragma unroll 4
         for (uint32_t b = grp; b < B; b += kEmitGroups) {
             const size_t base = (size_t)b * ns;
-            const uint32_t root = parent[base + v];
+            const uint32_t root = parent[base + iv];
             const uint32_t sz = 1u + cnt[base + root];
-            tile[vi][b] = make_uint2(root, root == v ? sz : 0u);
+            // the label is the root's vertex id; its own entry carries the size
+            tile[vi][b] = root == iv ? make_uint2(v, sz) : make_uint2(iperm[root], 0u);
             acc += sz;
         }
     }
@@ -344,17 +364,19 @@ __global__ void __launch_bounds__(256) k_gain0_emit(const uint32_t *__restrict__
                                                     uint32_t *__restrict__ label_c, uint32_t *__restrict__ size_c,
                                                     uint64_t *__restrict__ gain0,
                                                     const unsigned long long *__restrict__ gbest,
-                                                    uint64_t *__restrict__ gbits, uint32_t nw) {
+                                                    uint64_t *__restrict__ gbits, uint32_t nw,
+                                                    const uint32_t *__restrict__ newid) {
     constexpr uint32_t U = 4;  // sketches whose root and size loads are issued together (8 was slower)
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = v < n;
     const uint32_t cr = valid ? center_rank[v] : kNone;
+    const uint32_t iv = valid ? newid[v] : 0u;
     const size_t ns = sketch_stride(n);
     uint64_t s = 0;
     for (uint32_t b0 = 0; b0 < B; b0 += U) {
         uint32_t root[U], sz[U], l[U];
 #pragma unroll
-        for (uint32_t i = 0; i < U; ++i) root[i] = (valid && b0 + i < B) ? parent[(b0 + i) * ns + v] : kNone;
+        for (uint32_t i = 0; i < U; ++i) root[i] = (valid && b0 + i < B) ? parent[(b0 + i) * ns + iv] : kNone;
 #pragma unroll
         for (uint32_t i = 0; i < U; ++i) sz[i] = root[i] != kNone ? 1u + cnt[(b0 + i) * ns + root[i]] : 0u;
 #pragma unroll

@@ -250,3 +250,37 @@ def test_module_level_select_from_torch_tensors():
     for alpha in (1.0, 0.25):
         s, gn = pacim.select_seeds(off, cols, TRI, 0.0, 24, 12, 3, alpha=alpha)
         assert np.array_equal(s, ws) and np.array_equal(gn, wg), alpha
+
+
+@pytest.mark.parametrize("hubs", ["0", "1", "300", "1000000"])
+def test_labelling_order_does_not_change_results(ctx, hubs, monkeypatch):
+    # the union-find passes number vertices hubs-first, then linked, then isolated;
+    # labels (smallest id), sizes, triples, seeds and gains must not depend on it:
+    # no hubs, one, some, and every linked vertex a hub
+    monkeypatch.setenv("PACIM_HUBS", hubs)
+    g = inputs.rmat_graph(12, 8 << 12, seed=31)
+    assert (np.diff(g.offsets.astype(np.int64)) == 0).any()  # isolated vertices present
+    R, k, seed, p = 24, 15, 5, 0.08
+    _say(f"case labelling order hubs={hubs}")
+    lab, siz = oracle.sketches(g, U, p, seed, R, threads=8)
+    ws, wg = oracle.greedy(lab, siz, k)
+    gr = upload(ctx, g)
+    try:
+        sk = gr.sketches(U, p, R, seed, 1.0)
+        for r in (0, 11, R - 1):
+            gl, gs = sk.dump(r)
+            assert np.array_equal(gl, lab[r]) and np.array_equal(gs, siz[r]), r
+        s, gn = sk.select(k)
+        sk.close()
+        assert np.array_equal(s, ws) and np.array_equal(gn, wg)
+        cents = oracle.centers(g.n, seed, 0.2)
+        lc, sc = oracle.compact_all(lab, siz, cents)
+        sk = gr.sketches(U, p, R, seed, 0.2)
+        for r in (0, R - 1):
+            cl, cz = sk.dump(r)
+            assert np.array_equal(cl, lc[r]) and np.array_equal(cz, sc[r]), r
+        s, gn = sk.select(k)
+        sk.close()
+        assert np.array_equal(s, ws) and np.array_equal(gn, wg)
+    finally:
+        gr.close()
