@@ -78,6 +78,7 @@ struct im_graph {
     // the edge list's endpoints in it (iedges[e] for edges[e])
     uint32_t *newid = nullptr, *iperm = nullptr;
     uint2 *iedges = nullptr;
+    uint32_t n_linked = 0;  // vertices with an edge: numbers [0, n_linked); isolated ones follow
     uint64_t *csr_thr = nullptr;  // WIC threshold per CSR entry; made by the first CompactSketch
                                   // build under WIC (GetCenter's scans read it with the column)
 };
@@ -372,8 +373,8 @@ void radix_sort_u64(std::vector<uint64_t> &a) {
 // Within a class the order stays monotone, so per-vertex passes that translate
 // v -> newid[v] read their forests in a few sequential runs.  PACIM_HUBS
 // (tuning) overrides the count.
-void labelling_order(uint32_t n, const std::vector<uint64_t> &off, std::vector<uint32_t> &newid,
-                     std::vector<uint32_t> &iperm) {
+uint32_t labelling_order(uint32_t n, const std::vector<uint64_t> &off, std::vector<uint32_t> &newid,
+                         std::vector<uint32_t> &iperm) {
     uint32_t hubs = 4096;
     if (const char *e = getenv("PACIM_HUBS")) hubs = (uint32_t)std::min<unsigned long>(strtoul(e, nullptr, 10), n);
     std::vector<uint8_t> cls(n);
@@ -399,6 +400,7 @@ void labelling_order(uint32_t n, const std::vector<uint64_t> &off, std::vector<u
         newid[v] = next[cls[v]]++;
         iperm[newid[v]] = v;
     }
+    return next[1];  // the vertices with an edge
 }
 
 }  // namespace
@@ -523,7 +525,7 @@ extern "C" im_status im_graph_upload(im_ctx *ctx, uint32_t n, uint64_t m_dir, co
     lo.clear();
     lo.shrink_to_fit();
     std::vector<uint32_t> newid, iperm;
-    labelling_order(n, off, newid, iperm);
+    const uint32_t n_linked = labelling_order(n, off, newid, iperm);
     std::vector<uint2> iedges(m_und);
     for (uint64_t i = 0; i < m_und; ++i) iedges[i] = make_uint2(newid[edges[i].x], newid[edges[i].y]);
 
@@ -533,6 +535,7 @@ extern "C" im_status im_graph_upload(im_ctx *ctx, uint32_t n, uint64_t m_dir, co
     g->n = n;
     g->m_dir = m_dir;
     g->m_und = m_und;
+    g->n_linked = n_linked;
     im_status s;
     if ((s = dev_alloc(ctx, ((size_t)n + 1) * 8, (void **)&g->off)) != IM_OK ||
         (s = dev_alloc(ctx, m_dir * 4, (void **)&g->cols)) != IM_OK ||
@@ -749,7 +752,7 @@ void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const ui
     {
         Prof p(ctx, "compress", st);
         dim3 gc(std::min<unsigned>((n + 255) / 256, 64u), b);
-        k_compress<<<gc, 256, 0, st>>>(cs.parent, cs.cnt, n, center_rank, minc);
+        k_compress<<<gc, 256, 0, st>>>(cs.parent, cs.cnt, n, g->n_linked, center_rank, minc);
     }
 }
 
@@ -763,8 +766,8 @@ void enqueue_full_build(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const
         const uint32_t b = std::min(cs.B, R - r0);
         enqueue_cc_pass(ctx, g, pm, K + r0, b, cs, nullptr, kNone, nullptr, st);
         Prof p(ctx, "emit", st);
-        k_emit_full<<<(n + kEmitTile - 1) / kEmitTile, 256, 0, st>>>(cs.parent, cs.cnt, g->newid, g->iperm, n, b, R,
-                                                                     r0, E, gain0);
+        k_emit_full<<<(n + kEmitTile - 1) / kEmitTile, 256, 0, st>>>(cs.parent, cs.cnt, g->newid, g->iperm, n,
+                                                                     g->n_linked, b, R, r0, E, gain0);
     }
 }
 
@@ -938,11 +941,12 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
             k_giant_sample<<<b, 256, 0, st>>>(parent, cnt, n, s->gbest + r0);
             k_gain0_emit<<<(n + 255) / 256, 256, 0, st>>>(parent, cnt, minc, s->center_rank, s->rho, n, b, r0,
                                                           s->label_c, s->size_c, s->gain0, s->gbest + r0,
-                                                          s->gbits + (size_t)r0 * s->nw, s->nw, g->newid);
+                                                          s->gbits + (size_t)r0 * s->nw, s->nw, g->newid,
+                                                          g->n_linked);
         } else {
             Prof p(ctx, "emit");
-            k_emit_full<<<(n + kEmitTile - 1) / kEmitTile, 256, 0, st>>>(parent, cnt, g->newid, g->iperm, n, b, R,
-                                                                         r0, s->E, s->gain0);
+            k_emit_full<<<(n + kEmitTile - 1) / kEmitTile, 256, 0, st>>>(parent, cnt, g->newid, g->iperm, n,
+                                                                         g->n_linked, b, R, r0, s->E, s->gain0);
         }
         SK_HIP(hipGetLastError());
     }

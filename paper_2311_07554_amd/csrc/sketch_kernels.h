@@ -210,23 +210,25 @@ __global__ void __launch_bounds__(kHookBlock) k_sample_hook(const uint2 *__restr
 }
 
 // grid: (G, B), block 256: the blocks of sketch blockIdx.y stride over its
-// vertices.  In social-like graphs almost every non-root vertex of a sketch lies
+// first n_act numbers (the vertices with an edge; an isolated vertex stays its
+// own root with no members and its own center rank).  In social-like graphs almost every non-root vertex of a sketch lies
 // in one giant component, so per-vertex atomics on its root counter serialise.
 // Each wave therefore keeps the first root it meets as a "hot" root whose member
 // count and smallest center rank it accumulates in registers and flushes once at
 // the end; members of other roots are combined per distinct root in the wave
 // and added with one atomic per root.
 __global__ void __launch_bounds__(256) k_compress(uint32_t *__restrict__ parent, uint32_t *__restrict__ cnt,
-                                                  uint32_t n, const uint32_t *__restrict__ center_rank,
+                                                  uint32_t n, uint32_t n_act,
+                                                  const uint32_t *__restrict__ center_rank,
                                                   uint32_t *__restrict__ minc) {
     const uint32_t lane = lane_id();
     const size_t base = (size_t)blockIdx.y * sketch_stride(n);
     uint32_t *P = parent + base;
     uint32_t hot = kNone, hot_cnt = 0, hot_min = kNone;  // wave-uniform
     const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t v0 = blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); v0 < n; v0 += stride) {
+    for (uint32_t v0 = blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); v0 < n_act; v0 += stride) {
         const uint32_t v = v0 + lane;
-        const bool valid = v < n;
+        const bool valid = v < n_act;
         uint32_t r = v;
         if (valid) {
             uint32_t p = P[v];
@@ -283,17 +285,22 @@ constexpr int kEmitGroups = 256 / kEmitTile;
 __global__ void __launch_bounds__(256) k_emit_full(const uint32_t *__restrict__ parent,
                                                    const uint32_t *__restrict__ cnt,
                                                    const uint32_t *__restrict__ newid,
-                                                   const uint32_t *__restrict__ iperm, uint32_t n, uint32_t B,
-                                                   uint32_t R, uint32_t r0, uint2 *__restrict__ E,
-                                                   uint64_t *__restrict__ gain0) {
+                                                   const uint32_t *__restrict__ iperm, uint32_t n,
+                                                   uint32_t n_linked, uint32_t B, uint32_t R, uint32_t r0,
+                                                   uint2 *__restrict__ E, uint64_t *__restrict__ gain0) {
     __shared__ uint2 tile[kEmitTile][65];
     __shared__ uint64_t part[kEmitGroups][kEmitTile];
     const uint32_t v0 = blockIdx.x * kEmitTile;
     const uint32_t vi = threadIdx.x % kEmitTile, grp = threadIdx.x / kEmitTile, v = v0 + vi;
     const size_t ns = sketch_stride(n);
     uint64_t acc = 0;
-    if (v < n) {
-        const uint32_t iv = newid[v];
+    const uint32_t iv = v < n ? newid[v] : 0u;
+    if (v < n && iv >= n_linked) {  // isolated: its own singleton in every sketch
+        for (uint32_t b = grp; b < B; b += kEmitGroups) {
+            tile[vi][b] = make_uint2(v, 1u);
+            acc += 1u;
+        }
+    } else if (v < n) {
 #pragma unroll 4
         for (uint32_t b = grp; b < B; b += kEmitGroups) {
             const size_t base = (size_t)b * ns;
@@ -365,22 +372,25 @@ __global__ void __launch_bounds__(256) k_gain0_emit(const uint32_t *__restrict__
                                                     uint64_t *__restrict__ gain0,
                                                     const unsigned long long *__restrict__ gbest,
                                                     uint64_t *__restrict__ gbits, uint32_t nw,
-                                                    const uint32_t *__restrict__ newid) {
+                                                    const uint32_t *__restrict__ newid, uint32_t n_linked) {
     constexpr uint32_t U = 4;  // sketches whose root and size loads are issued together (8 was slower)
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = v < n;
     const uint32_t cr = valid ? center_rank[v] : kNone;
     const uint32_t iv = valid ? newid[v] : 0u;
+    const bool alone = valid && iv >= n_linked;  // isolated: root itself, size 1, its own rank
     const size_t ns = sketch_stride(n);
     uint64_t s = 0;
     for (uint32_t b0 = 0; b0 < B; b0 += U) {
         uint32_t root[U], sz[U], l[U];
 #pragma unroll
-        for (uint32_t i = 0; i < U; ++i) root[i] = (valid && b0 + i < B) ? parent[(b0 + i) * ns + iv] : kNone;
+        for (uint32_t i = 0; i < U; ++i)
+            root[i] = (valid && b0 + i < B) ? (alone ? iv : parent[(b0 + i) * ns + iv]) : kNone;
 #pragma unroll
-        for (uint32_t i = 0; i < U; ++i) sz[i] = root[i] != kNone ? 1u + cnt[(b0 + i) * ns + root[i]] : 0u;
+        for (uint32_t i = 0; i < U; ++i) sz[i] = root[i] != kNone ? (alone ? 1u : 1u + cnt[(b0 + i) * ns + root[i]]) : 0u;
 #pragma unroll
-        for (uint32_t i = 0; i < U; ++i) l[i] = (cr != kNone && root[i] != kNone) ? minc[(b0 + i) * ns + root[i]] : kNone;
+        for (uint32_t i = 0; i < U; ++i)
+            l[i] = (cr != kNone && root[i] != kNone) ? (alone ? cr : minc[(b0 + i) * ns + root[i]]) : kNone;
 #pragma unroll
         for (uint32_t i = 0; i < U; ++i) {
             const uint32_t b = b0 + i;
