@@ -123,8 +123,9 @@ im_status im_graph_free(im_graph *g);
 
 /* Builds R sketches of G under model `prob` with sampling seed `seed`.
  * alpha = 1: full labels -- for every vertex v and sketch r the CC label
- *            (smallest vertex id in CC_r(v)) and, at the label's own entry, the
- *            CC size (the InfuserMG-style memoization the paper extends).
+ *            (a vertex of CC_r(v), the same for all its members; im_sketches_dump
+ *            reports the smallest) and, at the label's own entry, the CC size
+ *            (the InfuserMG-style memoization the paper extends).
  * 0 < alpha < 1: CompactSketch (Sec. 3) -- vertex v is a center iff
  *            mix64(v ^ K(seed, 0xC000000000000001)) < T(alpha); centers are
  *            ranked by id; per sketch only label_c[i] (smallest center rank in
