@@ -277,33 +277,45 @@ __global__ void __launch_bounds__(256) k_bulk_full_keys(SelState *__restrict__ s
 #pragma unroll
     for (int i = 0; i < U; ++i) last_l[i] = kNone, last_y[i] = 0;
     const uint32_t lane = lane_id();
-    for (uint32_t v = wave_index(); v < n; v += wave_count()) {
-        const uint2 *row = E + (size_t)v * R;
-        uint64_t g = 0;
-        if (R <= (uint32_t)(U * kWave)) {
-            uint2 e[U];
+    if (R <= (uint32_t)(U * kWave)) {
+        // the wave's next row is loaded while the current one's gathers wait
+        auto load_row = [&](uint32_t v, uint2 *e) {
+            const uint2 *row = E + (size_t)v * R;
 #pragma unroll
             for (int i = 0; i < U; ++i) {
                 const uint32_t r = lane + i * kWave;
                 e[i] = r < R ? row[r] : make_uint2(v, 0u);
             }
+        };
+        uint2 cur[U], nxt[U];
+        uint32_t v = wave_index();
+        if (v < n) load_row(v, cur);
+        for (; v < n; v += wave_count()) {
+            const uint32_t vn = v + wave_count();
+            if (vn < n) load_row(vn, nxt);
+            uint64_t g = 0;
 #pragma unroll
             for (int i = 0; i < U; ++i) {
-                uint32_t y = e[i].y;
-                if (e[i].x != v) {
-                    if (e[i].x != last_l[i]) {
-                        last_l[i] = e[i].x;
-                        last_y[i] = E[(size_t)e[i].x * R + lane + i * kWave].y;
+                uint32_t y = cur[i].y;
+                if (cur[i].x != v) {
+                    if (cur[i].x != last_l[i]) {
+                        last_l[i] = cur[i].x;
+                        last_y[i] = E[(size_t)cur[i].x * R + lane + i * kWave].y;
                     }
                     y = last_y[i];
                 }
                 g += y;
             }
             g = wave_sum_u64(g);
-        } else {
-            g = marginal_full(E, R, v);
+            if (lane == 0) key[v] = in_s[v] ? 0ull : pack_key(g, v, kb);
+#pragma unroll
+            for (int i = 0; i < U; ++i) cur[i] = nxt[i];
         }
-        if (lane == 0) key[v] = in_s[v] ? 0ull : pack_key(g, v, kb);
+    } else {
+        for (uint32_t v = wave_index(); v < n; v += wave_count()) {
+            const uint64_t g = marginal_full(E, R, v);
+            if (lane == 0) key[v] = in_s[v] ? 0ull : pack_key(g, v, kb);
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         for (int l = 0; l <= kMaxLevels; ++l) { st->fr_cnt[l] = 0; st->ev_cnt[l] = 0; }
