@@ -721,12 +721,15 @@ unsigned hook_grid_cap() {
 // in minc.
 void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const uint64_t *K, uint32_t b,
                      const CCScratch &cs, uint32_t *minc, uint32_t minc_init, const uint32_t *center_rank,
-                     hipStream_t st = nullptr) {
+                     bool init_isolated = true, hipStream_t st = nullptr) {
     if (!st) st = ctx->stream;
     const uint32_t n = g->n;
     const unsigned hook_grid = grid_for(g->m_und, kHookBlock, hook_grid_cap());
-    dim3 gi((n + 255) / 256, b);
-    k_batch_init<<<gi, 256, 0, st>>>(cs.parent, cs.cnt, minc, n, minc_init, center_rank);
+    // isolated vertices' entries need setting once per build (nothing writes them
+    // later, unless a caller flags seeds in minc)
+    const uint32_t n_init = init_isolated ? n : g->n_linked;
+    dim3 gi(std::max<uint32_t>((n_init + 255) / 256, 1u), b);
+    k_batch_init<<<gi, 256, 0, st>>>(cs.parent, cs.cnt, minc, n, n_init, minc_init, center_rank);
     {
         Prof p(ctx, "sample_hook", st);
         switch (pm.kind) {
@@ -764,7 +767,7 @@ void enqueue_full_build(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const
     (void)hipMemsetAsync(gain0, 0, (size_t)n * 8, st);
     for (uint32_t r0 = 0; r0 < R; r0 += cs.B) {
         const uint32_t b = std::min(cs.B, R - r0);
-        enqueue_cc_pass(ctx, g, pm, K + r0, b, cs, nullptr, kNone, nullptr, st);
+        enqueue_cc_pass(ctx, g, pm, K + r0, b, cs, nullptr, kNone, nullptr, r0 == 0, st);
         Prof p(ctx, "emit", st);
         k_emit_full<<<(n + kEmitTile - 1) / kEmitTile, 256, 0, st>>>(cs.parent, cs.cnt, g->newid, g->iperm, n,
                                                                      g->n_linked, b, R, r0, E, gain0);
@@ -935,7 +938,7 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
     if (s->compact) k_to_label_order<<<(n + 255) / 256, 256, 0, st>>>(s->center_rank, g->iperm, n, cs.crank);
     for (uint32_t r0 = 0; r0 < R; r0 += B) {
         const uint32_t b = std::min(B, R - r0);
-        enqueue_cc_pass(ctx, g, s->pm, s->K + r0, b, cs, minc, kNone, s->compact ? cs.crank : nullptr);
+        enqueue_cc_pass(ctx, g, s->pm, s->K + r0, b, cs, minc, kNone, s->compact ? cs.crank : nullptr, r0 == 0);
         if (s->compact) {
             Prof p(ctx, "emit");
             k_giant_sample<<<b, 256, 0, st>>>(parent, cnt, n, s->gbest + r0);

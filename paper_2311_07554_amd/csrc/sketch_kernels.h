@@ -79,12 +79,15 @@ __global__ void k_to_label_order(const uint32_t *__restrict__ in, const uint32_t
 }
 
 // minc starts at each vertex's own center rank when center_rank is given (so a
-// root's own rank needs no atomic), else at minc_init.
+// root's own rank needs no atomic), else at minc_init.  Numbers [0, n_init):
+// isolated vertices (numbered last) keep their entries from an earlier pass of
+// the same build, as no pass writes them.
 __global__ void k_batch_init(uint32_t *__restrict__ parent, uint32_t *__restrict__ cnt, uint32_t *__restrict__ minc,
-                             uint32_t n, uint32_t minc_init, const uint32_t *__restrict__ center_rank) {
+                             uint32_t n, uint32_t n_init, uint32_t minc_init,
+                             const uint32_t *__restrict__ center_rank) {
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     const size_t at = (size_t)blockIdx.y * sketch_stride(n) + v;
-    if (v < n) {
+    if (v < n_init) {
         parent[at] = v;
         cnt[at] = 0;
         if (minc) minc[at] = center_rank ? center_rank[v] : minc_init;
@@ -123,7 +126,7 @@ __device__ __forceinline__ uint32_t uf_find_from(uint32_t *P, uint32_t x, uint32
 }
 
 // Union by hooking the larger root under the smaller, so the last root of every
-// component is its smallest vertex id whatever the schedule.  A failed CAS
+// component is its smallest number whatever the schedule.  A failed CAS
 // returns the root's fresh parent, strictly smaller, so a+b strictly decreases
 // on every retry: the loop ends even when uf_find read old values.  pa / pb:
 // the parents of a and b, already loaded.

@@ -159,6 +159,17 @@ def test_tiny_graphs(ctx):
         assert np.array_equal(s, ws) and np.array_equal(gn, wg), n
 
 
+def test_edgeless_graph(ctx):
+    # every vertex isolated: no linked vertex, every component a singleton
+    g = inputs.csr_from_pairs(70, [])
+    lab, siz = oracle.sketches(g, U, 0.5, 2, 6)
+    ws, wg = oracle.greedy(lab, siz, 10)
+    for alpha in (1.0, 0.3):
+        s, gn, _ = run_select(ctx, g, U, 0.5, 6, 10, 2, alpha=alpha)
+        assert np.array_equal(s, ws) and np.array_equal(gn, wg), alpha
+    assert list(ws) == list(range(10)) and set(wg.tolist()) == {6}
+
+
 def test_resume_equals_one_shot(ctx):
     g = inputs.rmat_graph(12, 16 << 12, seed=5)
     a = run_select(ctx, g, TRI, 0.0, 24, 30, 11)
@@ -257,17 +268,19 @@ def test_labelling_order_does_not_change_results(ctx, hubs, monkeypatch):
     # the union-find passes number vertices hubs-first, then linked, then isolated;
     # labels (smallest id), sizes, triples, seeds and gains must not depend on it:
     # no hubs, one, some, and every linked vertex a hub
+    # three passes of 32, 32 and 6 sketches: isolated vertices are set up by the first only
     monkeypatch.setenv("PACIM_HUBS", hubs)
+    monkeypatch.setenv("PACIM_SKETCHES_PER_PASS", "32")
     g = inputs.rmat_graph(12, 8 << 12, seed=31)
     assert (np.diff(g.offsets.astype(np.int64)) == 0).any()  # isolated vertices present
-    R, k, seed, p = 24, 15, 5, 0.08
+    R, k, seed, p = 70, 15, 5, 0.08
     _say(f"case labelling order hubs={hubs}")
     lab, siz = oracle.sketches(g, U, p, seed, R, threads=8)
     ws, wg = oracle.greedy(lab, siz, k)
     gr = upload(ctx, g)
     try:
         sk = gr.sketches(U, p, R, seed, 1.0)
-        for r in (0, 11, R - 1):
+        for r in (0, 11, 40, R - 1):
             gl, gs = sk.dump(r)
             assert np.array_equal(gl, lab[r]) and np.array_equal(gs, siz[r]), r
         s, gn = sk.select(k)
@@ -276,7 +289,7 @@ def test_labelling_order_does_not_change_results(ctx, hubs, monkeypatch):
         cents = oracle.centers(g.n, seed, 0.2)
         lc, sc = oracle.compact_all(lab, siz, cents)
         sk = gr.sketches(U, p, R, seed, 0.2)
-        for r in (0, R - 1):
+        for r in (0, 33, R - 1):
             cl, cz = sk.dump(r)
             assert np.array_equal(cl, lc[r]) and np.array_equal(cz, sc[r]), r
         s, gn = sk.select(k)
