@@ -98,6 +98,10 @@ struct im_sketches {
     unsigned long long *covmin = nullptr;  // [R][nw]: centerless components holding a seed, by smallest vertex
     uint32_t memo_mask = 0;
     uint32_t B = 1;
+    // the device selection state as the last selection call left it (read once at
+    // its end), so that counters need no device read; false while a call runs
+    SelState st_host{};
+    bool st_host_valid = true;
     // arrays
     uint64_t *K = nullptr;
     uint2 *E = nullptr;
@@ -1154,13 +1158,7 @@ im_status run_persistent_rounds(im_sketches *s, uint32_t max_rounds, unsigned lo
         return fail(ctx, IM_EINTERNAL, "persistent selection: round counter mismatch");
     *done = h1.round - h0.round;
     *stop_level = h1.stop_level;
-    *last_gain = 0;
-    if (*done) {
-        unsigned long long g = 0;
-        HIP_TRY(ctx, hipMemcpyAsync(&g, s->gains_d + h1.round - 1, 8, hipMemcpyDeviceToHost, st));
-        HIP_TRY(ctx, hipStreamSynchronize(st));
-        *last_gain = g;
-    }
+    *last_gain = *done ? h1.last_gain : 0;
     return IM_OK;
 }
 
@@ -1285,6 +1283,7 @@ extern "C" im_status im_select_seeds_from(im_ctx *ctx, im_sketches *s, uint32_t 
     HIP_TRY(ctx, hipEventCreate(&t1));
     (void)hipEventRecord(t0, st);
     im_status rc = IM_OK;
+    s->st_host_valid = false;
     {
         Prof p(ctx, "select");
         if (!s->tree_valid) {  // rounds by prefix doubling moved keys: rebuild the tree from them
@@ -1359,6 +1358,10 @@ extern "C" im_status im_select_seeds_from(im_ctx *ctx, im_sketches *s, uint32_t 
         hipError_t e4 = hipStreamSynchronize(st);
         if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess)
             rc = fail(ctx, IM_EDEVICE, std::string("select: ") + hipGetErrorString(e4 != hipSuccess ? e4 : e1));
+        else {
+            s->st_host = hst;
+            s->st_host_valid = true;
+        }
     }
     float ms = 0.f;
     if (rc == IM_OK && hipEventElapsedTime(&ms, t0, t1) == hipSuccess) s->select_ms += ms;
@@ -1649,6 +1652,7 @@ extern "C" im_status im_select_seeds_ptree(im_ctx *ctx, im_sketches *s, uint32_t
     HIP_TRY(ctx, hipEventCreate(&t1));
     (void)hipEventRecord(t0, st);
     im_status rc = IM_OK;
+    s->st_host_valid = false;
     {
         Prof p(ctx, "select_ptree");
         if (!s->pt_valid) rc = pt_build(s);
@@ -1675,6 +1679,10 @@ extern "C" im_status im_select_seeds_ptree(im_ctx *ctx, im_sketches *s, uint32_t
         hipError_t e4 = hipStreamSynchronize(st);
         if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess)
             rc = fail(ctx, IM_EDEVICE, std::string("select: ") + hipGetErrorString(e4 != hipSuccess ? e4 : e1));
+        else {
+            s->st_host = hst;
+            s->st_host_valid = true;
+        }
     }
     float ms = 0.f;
     if (rc == IM_OK && hipEventElapsedTime(&ms, t0, t1) == hipSuccess) s->select_ms += ms;
@@ -1861,10 +1869,11 @@ extern "C" im_status im_select_trace(im_ctx *ctx, const im_sketches *s, uint32_t
 
 extern "C" im_status im_sketches_stats(const im_sketches *s, im_sketch_stats *out) {
     if (!s || !out) return IM_EINVAL;
-    SelState hst{};
+    SelState hst = s->st_host;
     (void)hipSetDevice(s->ctx->device);
-    if (hipMemcpyAsync(&hst, s->st, sizeof(SelState), hipMemcpyDeviceToHost, s->ctx->stream) != hipSuccess ||
-        hipStreamSynchronize(s->ctx->stream) != hipSuccess)
+    if (!s->st_host_valid &&
+        (hipMemcpyAsync(&hst, s->st, sizeof(SelState), hipMemcpyDeviceToHost, s->ctx->stream) != hipSuccess ||
+         hipStreamSynchronize(s->ctx->stream) != hipSuccess))
         return IM_EDEVICE;
     out->seeds_chosen = s->chosen;
     out->rho = s->rho;

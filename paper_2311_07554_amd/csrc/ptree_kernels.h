@@ -259,6 +259,7 @@ __device__ __forceinline__ void pt_round_end_wave(SelState *st, uint64_t *key, u
         in_s[s] = 1;
         key[s] = 0;
         st->last_seed = s;
+        st->last_gain = key_gain(ks, kb);
         st->evals += tot;
     }
     if (E) {

@@ -46,6 +46,7 @@ struct SelState {
     uint32_t err;
     uint32_t stop_level;             // persistent rounds: level whose evaluation was left to the
                                      // per-level kernels (kNone: stopped at a round boundary)
+    unsigned long long last_gain;    // gain of the last round ended
 };
 
 // ---- Marginal on full labels ------------------------------------------------
@@ -214,6 +215,7 @@ __device__ __forceinline__ void round_end_wave(const TreeDesc &td, SelState *st,
         in_s[s] = 1;
         key[s] = 0;
         st->last_seed = s;
+        st->last_gain = key_gain(ks, kb);
         st->evals += evs;
         st->overflow += ovs;
     }
