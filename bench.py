@@ -588,9 +588,11 @@ def main():
                     "measured_ceiling": probe_hash / 1e9,
                     "frac_of_measured_ceiling": achieved / (probe_hash / 1e9)}
         if tr:
-            # the union-find's random parent accesses, not the hashes, move these bytes
+            # the union-find's random parent accesses, not the hashes, move these bytes;
+            # algorithmic: the two endpoint ids of every edge once per pass (the kernel
+            # also reads their labelling-order numbers, another 8 B per edge)
             roofline["traffic_detail"] = dict(tr, achieved_GB_s=tr["bytes"] / (hk["avg_ms"] / 1e3) / 1e9,
-                                              algorithmic_bytes=8.0 * m_und)
+                                              algorithmic_bytes=8.0 * m_und, edge_bytes_read=16.0 * m_und)
 
     # NextSeed by prefix doubling (Algorithm 4) on the same sketches, outside the
     # timed steps: its selection time and evaluations beside the winning tree's
