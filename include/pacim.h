@@ -111,8 +111,10 @@ im_status im_kernel_time(im_ctx *ctx, const char *name, uint64_t *launches, doub
  * (uint64, offsets[0] = 0, non-decreasing, offsets[n] = m_dir) and cols[m_dir]
  * (uint32 neighbour ids).  Every undirected edge {u,v} appears as v in u's row
  * and u in v's row, exactly once each (Sec. 5, Table 2: |E| counts these directed
- * entries).  device_ptrs = 1 if offsets/cols are device pointers, 0 for host.
- * The library copies the graph into memory it owns.
+ * entries).  device_ptrs = 1 if offsets/cols are device pointers (read on the
+ * context's stream, after the work already queued there), 0 for host.
+ * The library copies the graph into memory it owns, with the numbering its
+ * union-find passes use (highest degrees first); results use vertex ids.
  * Errors: EINVAL if n == 0, offsets are not monotone, a column is >= n, a row
  * holds a self-loop or a duplicate, or the CSR is not symmetric; ENOMEM. */
 im_status im_graph_upload(im_ctx *ctx, uint32_t n, uint64_t m_dir, const uint64_t *offsets,
