@@ -3,8 +3,10 @@
 //
 // Device memory layout (all library-owned, one hipMalloc per array):
 //   graph     offsets u64[n+1], cols u32[m_dir] (symmetric CSR, for GetCenter),
-//             edges uint2[m_und] (u < v, for the sampling pass)
-//   full      E uint2[n][R]: (CC label, CC size if v is the label else 0);
+//             edges uint2[m_und] (u < v, for the sampling pass), and the union-find
+//             passes' labelling order: newid u32[n], iperm u32[n], iedges uint2[m_und]
+//   full      E uint2[n][R]: (CC label = one of its vertices, CC size if v is the
+//             label else 0);
 //             R consecutive entries per vertex so one evaluation reads 8R bytes
 //             in one contiguous run, and the size lookup of a singleton CC is the
 //             entry itself
