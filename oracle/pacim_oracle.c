@@ -40,8 +40,10 @@
  * Pins: every function here is pinned by tests that do not reuse this code
  * (published SplitMix64 outputs, exact rational thresholds, library connected
  * components, brute-force reachability and exact IC spread on tiny graphs,
- * closed forms).  orc_celf_evaluations is a measurement aid whose count is not
- * unique (it depends on the queue's tie handling): parity unpinned.
+ * closed forms).  orc_celf_evaluations (Algorithm 2) keeps its queue in a total
+ * order (stale score, then smaller id), so every pop and each round's evaluation
+ * count are determined; the counts are pinned by rounds of Algorithm 2 worked by
+ * hand, including a vertex evaluated twice in one round.
  * orc_influence is pinned by the seeds' reach summed over worlds spelled out from
  * the published mixer, by the IC cascade's exact expected spread (enumerated over
  * coin flips) within 5 standard errors, and by the p = 0 / p = 1 closed forms.
@@ -333,8 +335,10 @@ int orc_compact_greedy(uint32_t n, const uint64_t *offsets, const uint32_t *cols
 }
 
 /* Sequential CELF (Algorithm 2) over full labels, counting evaluations: a
- * binary max-heap keyed by (stale score, smaller id first).  Seeds equal
- * orc_greedy's; the evaluation count is a measurement aid only. */
+ * binary max-heap keyed by (stale score, smaller id first).  Every pop is one
+ * evaluation, as Algorithm 2 states (a vertex popped again in the same round is
+ * evaluated again).  Seeds equal orc_greedy's; under the total order the
+ * per-round counts are unique. */
 static int orc_heap_less(const uint64_t *key, const uint32_t *h, uint32_t a, uint32_t b) {
     /* true if element at a ranks below element at b */
     uint64_t ka = key[h[a]], kb = key[h[b]];

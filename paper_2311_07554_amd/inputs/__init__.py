@@ -247,3 +247,30 @@ def poisson_arrivals(count: int, qps: float, seed: int = 5):
         t += -math.log(1.0 - u) / qps
         out.append(t)
     return out
+
+
+# The served mix of the serving parity test: the first seven graphs of the serving
+# workload (R-MAT scales 16, 16, 17, 17, 18, 18, 18), requests with their own
+# sampling seeds and label kinds.  Seeds repeat across requests so that sketch sets
+# are shared, and two requests differ only in their Uniform-model interval.
+SERVING_MIX_GRAPHS = 7
+
+
+def serving_mix(count: int = 24, seed: int = 55):
+    """(graph index, model kind, p, p_hi, R, k, sampling seed, alpha) per request."""
+    s = _Stream(seed)
+    out = []
+    for i in range(count):
+        gi = s.next() % SERVING_MIX_GRAPHS
+        p = (0.01, 0.02, 0.05)[s.next() % 3]
+        R = (64, 256)[s.next() % 2]
+        k = (10, 50, 100)[s.next() % 3]
+        sseed = (5, 6, 7 + i)[s.next() % 3]
+        alpha = (1.0, 0.1)[s.next() % 2]
+        out.append((int(gi), PROB_UNIFORM, p, 0.0, R, k, sseed, alpha))
+    # the same graph, R and seed under two Uniform U(lo, hi) intervals, and again under the first
+    out.append((4, PROB_RANGE, 0.0, 0.05, 64, 50, 9, 1.0))
+    out.append((4, PROB_RANGE, 0.02, 0.1, 64, 50, 9, 1.0))
+    out.append((4, PROB_RANGE, 0.0, 0.05, 64, 10, 9, 0.1))
+    out.append((4, PROB_UNIFORM, 0.05, 0.0, 64, 50, 9, 1.0))
+    return out

@@ -339,6 +339,23 @@ def test_celf_equals_plain_greedy():
     assert ev.min() >= 1
 
 
+def _celf_cases():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "celf_worked_examples.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _celf_cases(), ids=lambda c: c["name"])
+def test_celf_worked_examples(case):
+    # Algorithm 2 run by hand: with the queue in a total order (score, then smaller id)
+    # every pop is determined, so each round's evaluation count is unique
+    lab = np.array(case["labels"], dtype=np.uint32)
+    siz = np.array(case["sizes"], dtype=np.uint32)
+    s, g, ev = oracle.celf(lab, siz, case["k"])
+    assert list(s) == case["seeds"] and list(g) == case["gains"] and list(ev) == case["evals"]
+    s1, g1 = oracle.greedy(lab, siz, case["k"])
+    assert list(s1) == case["seeds"] and list(g1) == case["gains"]
+
+
 # ---------------------------------------------------------------- CompactSketch
 
 def test_centers_are_hashed_bernoulli():
