@@ -238,8 +238,7 @@ def run_serving(args):
           file=sys.stderr, flush=True)
     arrivals = inputs.poisson_arrivals(len(reqs), qps, seed=5)
     tickets = [None] * len(reqs)
-    srv = pacim.Server(ctx, grs, hbm_budget=int(args.budget_gib * (1 << 30)), max_active=32, rounds_per_step=16,
-                       sample_seed=sample_seed)
+    srv = pacim.Server(ctx, grs, hbm_budget=int(args.budget_gib * (1 << 30)), max_active=32, rounds_per_step=16)
 
     def submitter():
         t_start = time.perf_counter()
@@ -247,7 +246,7 @@ def run_serving(args):
             d = t_start + at - time.perf_counter()
             if d > 0:
                 time.sleep(d)
-            tickets[i] = srv.submit(gi, U, p, R, k)
+            tickets[i] = srv.submit(gi, U, p, R, k, sample_seed)
 
     t0 = time.perf_counter()
     th = threading.Thread(target=submitter)
@@ -271,8 +270,8 @@ def run_serving(args):
     same = True
     for i in range(0, len(reqs), max(1, len(reqs) // 8)):
         gi, p, R, k, _s = reqs[i]
-        srv1 = pacim.Server(ctx, [grs[gi]], max_active=1, sample_seed=sample_seed)
-        tk = srv1.submit(0, U, p, R, k)
+        srv1 = pacim.Server(ctx, [grs[gi]], max_active=1)
+        tk = srv1.submit(0, U, p, R, k, sample_seed)
         s1, g1, _ = srv1.wait(tk)
         srv1.close()
         s2, g2 = grs[gi].select_seeds(U, p, R, k, sample_seed)

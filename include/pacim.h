@@ -101,8 +101,10 @@ im_status im_ctx_set_profiling(im_ctx *ctx, int on);
 /* Accumulated launches and milliseconds of one kernel family since profiling was
  * turned on: "sample_hook" (sampling and hooking pass), "compress" (pointer
  * jumping and counting), "emit" (full labels, or the compact triple and initial
- * gains), "select" (a whole im_select_seeds_from call).  Unknown names give
- * count 0. */
+ * gains), "select" (a whole im_select_seeds_from call); and the batched path's
+ * graph reuse: "batch_capture" (launches = graphs captured and instantiated) and
+ * "batch_replay" (launches = batches that replayed the kept graph).  Unknown
+ * names give count 0. */
 im_status im_kernel_time(im_ctx *ctx, const char *name, uint64_t *launches, double *ms);
 
 /* ---- graph ---------------------------------------------------------------- */
@@ -227,13 +229,18 @@ im_status im_sketches_stats(const im_sketches *s, im_sketch_stats *out);
 
 /* ---- batched selection ------------------------------------------------------ */
 
-/* One request: graph, probability model, R sketches (full labels), k seeds, seed. */
+/* One request: graph, probability model, R sketches, k seeds, sampling seed, and
+ * the label kind: alpha = 1 (or 0, so that a zeroed struct asks for full labels)
+ * for full labels, 0 < alpha < 1 for CompactSketch with that center fraction.
+ * Its seeds and gains equal im_build_sketches(graph, prob, R, seed, alpha)
+ * followed by im_select_seeds_from(k) -- the same for both label kinds. */
 typedef struct {
     const im_graph *graph;
     im_prob prob;
     uint32_t R;
     uint32_t k;
     uint64_t seed;
+    double alpha;
 } im_query;
 
 /* Launch shapes of the batched kernels (0 = library default).  hook_block and
@@ -246,16 +253,20 @@ typedef struct {
     uint32_t select_grid;   /* selection workgroups (taking queries from a counter)  */
 } im_batch_config;
 
-/* Answers nq independent requests together (Algorithm 1 for each, full-label
- * sketches): all sketch builds run as flattened persistent kernels over every
+/* Answers nq independent requests together (Algorithm 1 for each).  Full-label
+ * queries: all sketch builds run as flattened persistent kernels over every
  * (query, pass, edge) and (query, sketch, vertex), and every query's selection
- * runs in one workgroup of a persistent kernel; the five kernels are captured
- * in one hipGraph and launched once.  Each query's seeds and gains equal what
- * im_select_seeds returns for it alone.
- * seeds_out[q] / gains_out[q]: caller-owned host arrays of queries[q].k entries.
- * cfg may be NULL.  *device_ms (may be NULL) gets the graph launch's device time.
- * Errors: EINVAL (a query's k > n, R = 0, bad prob, bad cfg), ENOMEM, EDEVICE,
- * EINTERNAL. */
+ * runs in one workgroup of a persistent kernel; these kernels are captured in
+ * one hipGraph, kept by the context for the next batch of the same shape, and
+ * launched once.  CompactSketch queries (0 < alpha < 1) then run one after
+ * another through the single-query build and selection (GetCenter needs the
+ * whole GPU per evaluation step).  Each query's seeds and gains equal what it
+ * gets alone (see im_query).
+ * seeds_out[q] / gains_out[q]: caller-owned host arrays of queries[q].k entries,
+ * written only if every query succeeded.  cfg may be NULL.  *device_ms (may be
+ * NULL) gets the device time of the whole batch.
+ * Errors: EINVAL (a query's k > n, R = 0, bad prob or alpha, per-edge model, bad
+ * cfg), ENOMEM, EDEVICE, EINTERNAL. */
 im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_query *queries, const im_batch_config *cfg,
                                   uint32_t *const *seeds_out, uint64_t *const *gains_out, double *device_ms);
 
@@ -264,17 +275,20 @@ im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_query *quer
 typedef struct im_server im_server;
 
 typedef struct {
-    size_t hbm_budget;         /* bytes for query slots, build scratch and cached sketch
-                                  sets together (0: 64 GiB)                              */
-    uint32_t max_active;       /* requests selected concurrently (0: 16, at most 256)    */
+    size_t hbm_budget;         /* bytes for query slots, build scratch, cached sketch sets
+                                  and the CompactSketch lane together (0: 64 GiB)        */
+    uint32_t max_active;       /* full-label requests selected concurrently
+                                  (0: 16, at most 256)                                   */
     uint32_t rounds_per_step;  /* rounds each active request advances per step (0: 16)   */
     uint32_t max_R;            /* largest R accepted (0: 256)                            */
     uint32_t max_k;            /* largest k accepted (0: 1000)                           */
-    uint64_t sample_seed;      /* sampling seed of every sketch set                      */
+    size_t compact_budget;     /* part of hbm_budget for CompactSketch requests
+                                  (0: a quarter of it)                                   */
 } im_server_config;
 
 typedef struct {
     uint64_t submitted, completed, steps, builds, cache_hits, evictions;
+    uint64_t compact_completed;  /* CompactSketch requests answered by the compact lane */
     size_t bytes_in_use, peak_bytes;
     uint32_t cached_sets;
     double admit_ms;       /* worker time in admission (sketch-set allocation, eviction, build launch) */
@@ -283,28 +297,31 @@ typedef struct {
     double busy_steps_ms;  /* device time of the selection steps (HIP events)                         */
 } im_server_counters;
 
-/* A request server over resident graphs (Algorithm 1 per request, full-label
- * sketches), with continuous batching: a worker thread admits requests as query
- * slots and HBM free up (sketch sets cached per graph, model and R, least
- * recently used unreferenced sets evicted under hbm_budget), builds missing
- * sketch sets on its own stream, and advances every admitted request by
- * rounds_per_step rounds per step in one batched launch (requests join and leave
- * between steps).  Each request's seeds and gains equal
- * im_select_seeds(graph, prob, R, k, sample_seed) alone.  The graphs must stay
- * alive until im_server_destroy.  While a server exists its worker thread issues
- * work on the context's device; other calls may use the same context. */
+/* A request server over resident graphs (Algorithm 1 per request), with
+ * continuous batching.  Full-label requests: a worker thread admits them as
+ * query slots and HBM free up (sketch sets cached per graph, model thresholds,
+ * R and sampling seed; least recently used unreferenced sets evicted under
+ * hbm_budget), builds missing sketch sets on its own stream, and advances every
+ * admitted request by rounds_per_step rounds per step in one batched launch
+ * (requests join and leave between steps).  CompactSketch requests (a query's
+ * 0 < alpha < 1): a second worker builds and selects them one at a time on a
+ * stream of its own, within compact_budget, while the full-label steps go on
+ * (their selection modifies the sketch triple, so their sets are not cached).
+ * Each request's seeds and gains equal what its im_query gets alone.  The graphs
+ * must stay alive until im_server_destroy.  While a server exists its workers
+ * issue work on the context's device; other calls may use the same context. */
 im_status im_server_create(im_ctx *ctx, const im_graph *const *graphs, uint32_t ngraphs,
                            const im_server_config *cfg, im_server **out);
-/* Queues a request on graphs[graph]; *ticket identifies it.  EINVAL: bad
- * arguments (R > max_R, k > max_k or > n, bad prob); EBUSY: its sketch set can
- * never fit hbm_budget. */
-im_status im_server_submit(im_server *srv, uint32_t graph, im_prob prob, uint32_t R, uint32_t k,
-                           uint64_t *ticket);
+/* Queues a request (q->graph one of the server's graphs); *ticket identifies it.
+ * EINVAL: bad arguments (unknown graph, R > max_R, k > max_k or > n, bad prob or
+ * alpha, per-edge model); EBUSY: its sketch set can never fit the budget. */
+im_status im_server_submit(im_server *srv, const im_query *q, uint64_t *ticket);
 /* *done = 1 once the request finished (EINVAL for an unknown ticket). */
 im_status im_server_poll(im_server *srv, uint64_t ticket, int *done);
 /* Blocks until the request finishes, writes its k seeds and gains (caller-owned
  * host arrays) and the time from submit to completion, and retires the ticket.
- * Returns the request's own status. */
+ * Returns the request's own status (EDEVICE if its sketch build failed on the
+ * device; every request waiting on that build fails the same way). */
 im_status im_server_wait(im_server *srv, uint64_t ticket, uint32_t *seeds, uint64_t *gains, double *latency_ms);
 im_status im_server_stats(im_server *srv, im_server_counters *out);
 /* Finishes every queued request, then frees the server. */

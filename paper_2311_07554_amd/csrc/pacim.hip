@@ -67,6 +67,10 @@ struct im_ctx {
     std::multimap<size_t, void *> cache;
     size_t cached = 0;
     uint64_t clock_hz = 0;      // wall_clock64() rate
+    // the batched path's instantiated graph and the signature of its launches
+    void *batch_exec = nullptr;
+    std::vector<uint64_t> batch_sig;
+    uint64_t batch_captures = 0, batch_replays = 0;
 };
 
 struct im_graph {
@@ -446,6 +450,7 @@ extern "C" im_status im_ctx_destroy(im_ctx *ctx) {
         release_cache_locked(ctx);
     }
     for (hipEvent_t e : ctx->spare_events) (void)hipEventDestroy(e);
+    if (ctx->batch_exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(ctx->batch_exec));
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return IM_OK;
@@ -473,6 +478,11 @@ extern "C" im_status im_kernel_time(im_ctx *ctx, const char *name, uint64_t *lau
     if (!ctx || !name) return IM_EINVAL;
     (void)hipStreamSynchronize(ctx->stream);
     drain_timers(ctx);
+    if (!strcmp(name, "batch_capture") || !strcmp(name, "batch_replay")) {
+        if (launches) *launches = name[6] == 'c' ? ctx->batch_captures : ctx->batch_replays;
+        if (ms) *ms = 0.0;
+        return IM_OK;
+    }
     auto it = ctx->timers.find(name);
     if (launches) *launches = it == ctx->timers.end() ? 0 : it->second.launches;
     if (ms) *ms = it == ctx->timers.end() ? 0.0 : it->second.ms;
@@ -639,7 +649,15 @@ struct CCScratch {
 im_status cc_scratch_alloc(im_ctx *ctx, const im_graph *g, uint32_t R, bool with_minc, CCScratch *cs) {
     const uint32_t n = g->n;
     const size_t per_sketch = sketch_stride(n) * 4 * (with_minc ? 3 : 2);
-    uint32_t B = (uint32_t)std::min<size_t>({(size_t)R, (size_t)64, std::max<size_t>(1, g_scratch_budget() / per_sketch)});
+    size_t budget = g_scratch_budget();
+    if (ctx->cap) {
+        // under a cap, leave room for the selection state a build allocates next
+        // (about 48 bytes per vertex, the GetCenter queues and overflow list)
+        const size_t avail = ctx->cap > ctx->used ? ctx->cap - ctx->used : 0;
+        const size_t reserve = (size_t)n * 48 + ((size_t)320 << 20);
+        budget = std::min(budget, avail > reserve ? avail - reserve : 0);
+    }
+    uint32_t B = (uint32_t)std::min<size_t>({(size_t)R, (size_t)64, std::max<size_t>(1, budget / per_sketch)});
     if (uint32_t ov = g_batch_override()) B = std::min<uint32_t>({ov, R, 64u});
     cs->B = B;
     cs->bytes = per_sketch * B + (with_minc ? sketch_stride(n) * 4 : 0);
@@ -835,7 +853,19 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
     s->kb = kb;
     s->pm = prob_dev(prob, g->off);
     s->kc = sketch_key(seed, kSaltCenter);
-    if (prob.kind == IM_PROB_WIC && alpha < 1.0 && g->m_dir) {
+    if (prob.kind == IM_PROB_WIC && alpha < 1.0 && g->m_dir && !g->csr_thr && g->ctx != ctx) {
+        // a graph of another context (a server's CompactSketch lane): the thresholds
+        // live with these sketches instead of being kept on the graph
+        uint64_t *thr = nullptr;
+        const im_status a = sk_alloc(s, g->m_dir, &thr);
+        if (a != IM_OK) {
+            free_sketches(s);
+            delete s;
+            return a;
+        }
+        k_csr_wic_thr<<<wave_grid(g->n, 1u << 18), 256, 0, ctx->stream>>>(g->off, g->cols, g->n, thr);
+        s->pm.csr_thr = thr;
+    } else if (prob.kind == IM_PROB_WIC && alpha < 1.0 && g->m_dir) {
         if (!g->csr_thr) {
             im_graph *gm = const_cast<im_graph *>(g);
             uint64_t *thr = nullptr;
@@ -1977,49 +2007,30 @@ void enqueue_prepare(BatchQuery *dq, uint32_t nq, const uint64_t *pre_prep, uint
     }
 }
 
-// K(0, SALT_TRIV), computed on the device once per context.
-
 }  // namespace
 
-extern "C" im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_query *queries,
-                                             const im_batch_config *cfg, uint32_t *const *seeds_out,
-                                             uint64_t *const *gains_out, double *device_ms) {
-    if (!ctx || (nq && (!queries || !seeds_out || !gains_out))) return IM_EINVAL;
-    if (nq == 0) return IM_OK;
-    im_batch_config c{256, 0, 1024, 0};
-    if (cfg) {
-        if (cfg->hook_block) c.hook_block = cfg->hook_block;
-        if (cfg->hook_grid) c.hook_grid = cfg->hook_grid;
-        if (cfg->select_block) c.select_block = cfg->select_block;
-        if (cfg->select_grid) c.select_grid = cfg->select_grid;
-    }
-    if (c.hook_block % 64 || c.hook_block > 1024 || c.select_block % 64 || c.select_block > 1024)
-        return fail(ctx, IM_EINVAL, "block sizes must be multiples of 64 and at most 1024");
-    for (uint32_t q = 0; q < nq; ++q) {
-        const im_query &Q = queries[q];
-        if (!Q.graph || Q.graph->ctx != ctx) return fail(ctx, IM_EINVAL, "query graph belongs to another context");
-        if (Q.R == 0) return fail(ctx, IM_EINVAL, "R must be >= 1");
-        if (Q.k > Q.graph->n) return fail(ctx, IM_EINVAL, "k exceeds n");
-        if (!seeds_out[q] || !gains_out[q]) return fail(ctx, IM_EINVAL, "null output array");
-        if (const char *why = prob_problem(Q.prob)) return fail(ctx, IM_EINVAL, why);
-        if (Q.prob.kind == IM_PROB_PER_EDGE)
-            return fail(ctx, IM_EINVAL, "per-edge probabilities are not supported in batched queries");
-        const uint32_t kb = std::max<uint32_t>(1, bit_length((uint64_t)Q.graph->n - 1));
-        if (kb + bit_length((uint64_t)Q.R * Q.graph->n + 1) > 64) return fail(ctx, IM_EINVAL, "R*n too large");
-    }
-    HIP_TRY(ctx, hipSetDevice(ctx->device));
+namespace {
+
+// Full-label queries of a batch: one arena, the build and selection kernels in one
+// hipGraph.  The instantiated graph is kept by the context together with the
+// signature of its launches (arena address, grid sizes, configuration); a later
+// batch whose launches have the same signature replays it without capturing
+// again.  Results go to seeds[q] / gains[q]; *ms gets the launch's device time.
+im_status run_full_batch(im_ctx *ctx, const std::vector<const im_query *> &queries, const im_batch_config &c,
+                         std::vector<std::vector<uint32_t>> &seeds, std::vector<std::vector<uint64_t>> &gains,
+                         float *ms_out) {
+    const uint32_t nq = (uint32_t)queries.size();
     hipStream_t st = ctx->stream;
     im_status rc = IM_OK;
 
     // one arena for every query's arrays
     std::vector<BatchQuery> hq(nq);
-    std::vector<size_t> at(nq);
     size_t total = 0;
     auto take = [&](size_t bytes) { size_t o = total; total += align256(bytes); return o; };
     struct Off { size_t K, E, gain0, parent, cnt, key, in_s, ids, fr, evl, cov, seeds, gains, evals; };
     std::vector<Off> off(nq);
     for (uint32_t q = 0; q < nq; ++q) {
-        const im_query &Q = queries[q];
+        const im_query &Q = *queries[q];
         const uint32_t n = Q.graph->n, R = Q.R, k = std::max<uint32_t>(Q.k, 1);
         TreeDesc td = make_tree(n);
         const uint64_t tn = tree_nodes(td);
@@ -2087,7 +2098,7 @@ extern "C" im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_
             const uint64_t nodes = j < B.td.D ? B.td.lvl_n[B.td.D - 1 - j] : 0;
             pre[(4 + j) * (nq + 1) + q + 1] = pre[(4 + j) * (nq + 1) + q] + nodes;
         }
-        k_sketch_keys<<<grid_for(key_slots(B.R), 256, 1u << 20), 256, 0, st>>>(queries[q].seed, key_slots(B.R),
+        k_sketch_keys<<<grid_for(key_slots(B.R), 256, 1u << 20), 256, 0, st>>>(queries[q]->seed, key_slots(B.R),
                                                                               const_cast<uint64_t *>(B.K));
     }
     BatchQuery *dq = reinterpret_cast<BatchQuery *>(arena + desc_at);
@@ -2116,29 +2127,45 @@ extern "C" im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_
     const unsigned g_emit = (unsigned)std::min<uint64_t>(std::max<uint64_t>(tot_tiles, 1), 256 * 32);
     const unsigned g_sel = c.select_grid ? c.select_grid : std::min<uint32_t>(nq, 256);
 
-    // the five kernels, captured once and launched as one graph
-    hipGraph_t graph = nullptr;
+    // signature of every launch the graph holds: the arena address fixes every
+    // pointer argument, the rest fixes the grids
+    std::vector<uint64_t> sig = {(uint64_t)(uintptr_t)arena, total, nq, Dmax, g_init, g_hook, g_comp, g_emit, g_sel,
+                                 c.hook_block, c.select_block, tot_prep};
+    for (uint32_t j = 0; j < Dmax; ++j) sig.push_back(pre[(size_t)(4 + j) * (nq + 1) + nq]);
     hipGraphExec_t exec = nullptr;
-    rc = IM_OK;
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeGlobal) != hipSuccess) {
-        rc = fail(ctx, IM_EDEVICE, "hipStreamBeginCapture failed");
+    if (ctx->batch_exec && ctx->batch_sig == sig) {
+        exec = static_cast<hipGraphExec_t>(ctx->batch_exec);
+        ++ctx->batch_replays;
     } else {
-        k_bat_init<<<g_init, 256, 0, st>>>(dq, nq, dpre, next_q);
-        k_bat_hook<<<g_hook, c.hook_block, 0, st>>>(dq, nq, dpre + (nq + 1));
-        k_bat_compress<<<g_comp, 256, 0, st>>>(dq, nq, dpre);
-        k_bat_emit<<<g_emit, 256, 0, st>>>(dq, nq, dpre + 2 * (nq + 1));
-        // selection phases: the whole GPU prepares keys and trees (new queries; queries
-        // paused before a round predicted to re-evaluate nearly every vertex), then one
-        // workgroup per query runs rounds until done or until the next such round
-        for (int phase = 0; phase < 3; ++phase) {
-            enqueue_prepare(dq, nq, dpre + 3 * (nq + 1), tot_prep, dpre + 4 * (nq + 1), pre.data() + 4 * (nq + 1),
-                            Dmax, nq + 1, next_q, st);
-            k_bat_select<<<g_sel, c.select_block, 0, st>>>(dq, nq, dorder, next_q, 0xFFFFFFFFu, phase < 2 ? 1u : 0u);
+        hipGraph_t graph = nullptr;
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeGlobal) != hipSuccess) {
+            rc = fail(ctx, IM_EDEVICE, "hipStreamBeginCapture failed");
+        } else {
+            k_bat_init<<<g_init, 256, 0, st>>>(dq, nq, dpre, next_q);
+            k_bat_hook<<<g_hook, c.hook_block, 0, st>>>(dq, nq, dpre + (nq + 1));
+            k_bat_compress<<<g_comp, 256, 0, st>>>(dq, nq, dpre);
+            k_bat_emit<<<g_emit, 256, 0, st>>>(dq, nq, dpre + 2 * (nq + 1));
+            // selection phases: the whole GPU prepares keys and trees (new queries; queries
+            // paused before a round predicted to re-evaluate nearly every vertex), then one
+            // workgroup per query runs rounds until done or until the next such round
+            for (int phase = 0; phase < 3; ++phase) {
+                enqueue_prepare(dq, nq, dpre + 3 * (nq + 1), tot_prep, dpre + 4 * (nq + 1),
+                                pre.data() + 4 * (nq + 1), Dmax, nq + 1, next_q, st);
+                k_bat_select<<<g_sel, c.select_block, 0, st>>>(dq, nq, dorder, next_q, 0xFFFFFFFFu,
+                                                                phase < 2 ? 1u : 0u);
+            }
+            hipError_t ec = hipStreamEndCapture(st, &graph);
+            if (ec != hipSuccess || !graph) rc = fail(ctx, IM_EDEVICE, std::string("capture: ") + hipGetErrorString(ec));
+            else if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+                rc = fail(ctx, IM_EDEVICE, "hipGraphInstantiate failed");
         }
-        hipError_t ec = hipStreamEndCapture(st, &graph);
-        if (ec != hipSuccess || !graph) rc = fail(ctx, IM_EDEVICE, std::string("capture: ") + hipGetErrorString(ec));
-        else if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
-            rc = fail(ctx, IM_EDEVICE, "hipGraphInstantiate failed");
+        if (graph) (void)hipGraphDestroy(graph);
+        if (rc == IM_OK) {
+            if (ctx->batch_exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(ctx->batch_exec));
+            ctx->batch_exec = exec;
+            ctx->batch_sig = sig;
+            ++ctx->batch_captures;
+        }
     }
     hipEvent_t t0 = nullptr, t1 = nullptr;
     float ms = 0.f;
@@ -2155,41 +2182,114 @@ extern "C" im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_
     }
     if (t0) (void)hipEventDestroy(t0);
     if (t1) (void)hipEventDestroy(t1);
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
     // results
     if (rc == IM_OK) {
         std::vector<BatchQuery> back(nq);
         if (hipMemcpy(back.data(), dq, sizeof(BatchQuery) * nq, hipMemcpyDeviceToHost) != hipSuccess)
             rc = fail(ctx, IM_EDEVICE, "batched result copy failed");
         for (uint32_t q = 0; q < nq && rc == IM_OK; ++q) {
-            if (back[q].err || back[q].rounds_done != queries[q].k) {
+            if (back[q].err || back[q].rounds_done != queries[q]->k) {
                 rc = fail(ctx, IM_EINTERNAL, "batched selection consistency check failed for query " + std::to_string(q));
                 break;
             }
         }
-        std::vector<std::vector<unsigned long long>> gtmp(nq);
-        std::vector<std::vector<uint32_t>> stmp(nq);
+        std::vector<unsigned long long> gtmp;
         for (uint32_t q = 0; q < nq && rc == IM_OK; ++q) {
-            const uint32_t k = queries[q].k;
-            stmp[q].resize(k);
-            gtmp[q].resize(k);
+            const uint32_t k = queries[q]->k;
+            seeds[q].resize(k);
+            gains[q].resize(k);
+            gtmp.resize(k);
             if (!k) continue;
-            if (hipMemcpy(stmp[q].data(), hq[q].seeds, (size_t)k * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-                hipMemcpy(gtmp[q].data(), hq[q].gains, (size_t)k * 8, hipMemcpyDeviceToHost) != hipSuccess)
+            if (hipMemcpy(seeds[q].data(), hq[q].seeds, (size_t)k * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(gtmp.data(), hq[q].gains, (size_t)k * 8, hipMemcpyDeviceToHost) != hipSuccess)
                 rc = fail(ctx, IM_EDEVICE, "batched result copy failed");
-        }
-        if (rc == IM_OK) {
-            for (uint32_t q = 0; q < nq; ++q)
-                for (uint32_t i = 0; i < queries[q].k; ++i) {
-                    seeds_out[q][i] = stmp[q][i];
-                    gains_out[q][i] = gtmp[q][i];
-                }
-            if (device_ms) *device_ms = ms;
+            for (uint32_t i = 0; i < k; ++i) gains[q][i] = gtmp[i];
         }
     }
     dev_free(ctx, arena, total);
+    if (rc == IM_OK && ms_out) *ms_out = ms;
     return rc;
+}
+
+bool query_is_compact(const im_query &q) { return q.alpha > 0.0 && q.alpha < 1.0; }
+
+}  // namespace
+
+extern "C" im_status im_select_seeds_batched(im_ctx *ctx, uint32_t nq, const im_query *queries,
+                                             const im_batch_config *cfg, uint32_t *const *seeds_out,
+                                             uint64_t *const *gains_out, double *device_ms) {
+    if (!ctx || (nq && (!queries || !seeds_out || !gains_out))) return IM_EINVAL;
+    if (nq == 0) return IM_OK;
+    im_batch_config c{256, 0, 1024, 0};
+    if (cfg) {
+        if (cfg->hook_block) c.hook_block = cfg->hook_block;
+        if (cfg->hook_grid) c.hook_grid = cfg->hook_grid;
+        if (cfg->select_block) c.select_block = cfg->select_block;
+        if (cfg->select_grid) c.select_grid = cfg->select_grid;
+    }
+    if (c.hook_block % 64 || c.hook_block > 1024 || c.select_block % 64 || c.select_block > 1024)
+        return fail(ctx, IM_EINVAL, "block sizes must be multiples of 64 and at most 1024");
+    std::vector<const im_query *> full, compact;
+    std::vector<uint32_t> full_idx, compact_idx;
+    for (uint32_t q = 0; q < nq; ++q) {
+        const im_query &Q = queries[q];
+        if (!Q.graph || Q.graph->ctx != ctx) return fail(ctx, IM_EINVAL, "query graph belongs to another context");
+        if (Q.R == 0) return fail(ctx, IM_EINVAL, "R must be >= 1");
+        if (Q.k > Q.graph->n) return fail(ctx, IM_EINVAL, "k exceeds n");
+        if (!seeds_out[q] || !gains_out[q]) return fail(ctx, IM_EINVAL, "null output array");
+        if (const char *why = prob_problem(Q.prob)) return fail(ctx, IM_EINVAL, why);
+        if (Q.prob.kind == IM_PROB_PER_EDGE)
+            return fail(ctx, IM_EINVAL, "per-edge probabilities are not supported in batched queries");
+        if (!(Q.alpha >= 0.0 && Q.alpha <= 1.0)) return fail(ctx, IM_EINVAL, "alpha must lie in [0, 1]");
+        const uint32_t kb = std::max<uint32_t>(1, bit_length((uint64_t)Q.graph->n - 1));
+        if (kb + bit_length((uint64_t)Q.R * Q.graph->n + 1) > 64) return fail(ctx, IM_EINVAL, "R*n too large");
+        if (query_is_compact(Q)) {
+            if ((uint64_t)Q.R * Q.graph->n >= (1ull << kPartialShift) || Q.R >= (1u << (64 - kPartialShift)))
+                return fail(ctx, IM_EINVAL, "CompactSketch needs R*n < 2^40 and R < 2^24");
+            compact.push_back(&Q);
+            compact_idx.push_back(q);
+        } else {
+            full.push_back(&Q);
+            full_idx.push_back(q);
+        }
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    std::vector<std::vector<uint32_t>> seeds(nq);
+    std::vector<std::vector<uint64_t>> gains(nq);
+    double total_ms = 0.0;
+    if (!full.empty()) {
+        std::vector<std::vector<uint32_t>> fs(full.size());
+        std::vector<std::vector<uint64_t>> fg(full.size());
+        float ms = 0.f;
+        const im_status rc = run_full_batch(ctx, full, c, fs, fg, &ms);
+        if (rc != IM_OK) return rc;
+        for (size_t i = 0; i < full.size(); ++i) {
+            seeds[full_idx[i]].swap(fs[i]);
+            gains[full_idx[i]].swap(fg[i]);
+        }
+        total_ms += ms;
+    }
+    for (size_t i = 0; i < compact.size(); ++i) {
+        const im_query &Q = *compact[i];
+        im_sketches *sk = nullptr;
+        im_status rc = im_build_sketches(ctx, Q.graph, Q.prob, Q.R, Q.seed, Q.alpha, &sk);
+        if (rc != IM_OK) return rc;
+        std::vector<uint32_t> &s = seeds[compact_idx[i]];
+        std::vector<uint64_t> &g = gains[compact_idx[i]];
+        s.resize(std::max<uint32_t>(Q.k, 1));
+        g.resize(std::max<uint32_t>(Q.k, 1));
+        rc = Q.k ? im_select_seeds_from(ctx, sk, Q.k, s.data(), g.data()) : IM_OK;
+        total_ms += sk->build_ms + sk->select_ms;
+        im_sketches_free(sk);
+        if (rc != IM_OK) return rc;
+    }
+    for (uint32_t q = 0; q < nq; ++q)
+        for (uint32_t i = 0; i < queries[q].k; ++i) {
+            seeds_out[q][i] = seeds[q][i];
+            gains_out[q][i] = gains[q][i];
+        }
+    if (device_ms) *device_ms = total_ms;
+    return IM_OK;
 }
 
 // ---------------------------------------------------------------- serving

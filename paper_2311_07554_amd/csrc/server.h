@@ -1,22 +1,34 @@
 // Serving: a request loop over resident graphs with continuous batching.
 //
-// Requests (graph, model, R, k) arrive at any time (im_server_submit).  A worker
-// thread owns the device work:
+// Requests (an im_query: graph, model, R, k, sampling seed, label kind) arrive at
+// any time (im_server_submit).  Two worker threads own the device work.
+//
+// The full-label worker:
 //   - admission: a request takes a free query slot when the sketch set it needs
 //     is cached or fits the HBM budget (least recently used unreferenced sets are
 //     evicted first); requests wait in arrival order otherwise;
-//   - sketch sets (full labels, keyed by graph, model and R, one sampling seed per
-//     server) are built on a build stream and stay resident, shared by every
-//     request that uses them: selection never modifies them (covered components
-//     live in each request's own set of (sketch, label) pairs);
+//   - sketch sets (full labels, keyed by graph, the model's device thresholds, R
+//     and the sampling seed) are built on a build stream and stay resident,
+//     shared by every request that uses them: selection never modifies them
+//     (covered components live in each request's own set of (sketch, label)
+//     pairs);
 //   - steps: one launch of the batched selection kernel advances every admitted
 //     request whose sketches are ready by up to rounds_per_step rounds, one
 //     workgroup per request; a request whose next round would re-evaluate nearly
 //     every vertex pauses, and the next step first evaluates all its vertices
 //     over the whole GPU.  Requests join and leave between steps, so requests
 //     that arrive while others run are admitted as slots and memory free up, and
-//     builds overlap the selection steps on the device.
-// Each result equals im_select_seeds(graph, model, R, k, sample_seed) alone.
+//     builds overlap the selection steps on the device;
+//   - a build that fails on the device fails every request waiting on its set
+//     (IM_EDEVICE), and the set leaves the cache.
+//
+// The CompactSketch worker answers requests with 0 < alpha < 1 one at a time
+// through the single-query build and selection on a context and stream of its
+// own, capped at compact_budget, while the full-label steps go on.  Their
+// selection modifies the sketch triple (MarkSeed), so their sets are built per
+// request and freed after it.
+//
+// Each result equals what the request's im_query gets alone.
 #pragma once
 
 #include <chrono>
@@ -32,8 +44,9 @@ using srv_clock = std::chrono::steady_clock;
 
 struct SrvSet {
     uint32_t g = 0, R = 0;
-    int kind = 0;
-    double p = 0;
+    uint64_t seed = 0;
+    ProbDev pm{};           // the model as the kernels see it (thresholds), the cache key with g, R, seed
+    bool failed = false;    // its build failed on the device: no longer shared, freed once unreferenced
     uint64_t *K = nullptr;
     uint2 *E = nullptr;
     uint64_t *gain0 = nullptr;
@@ -47,6 +60,9 @@ struct SrvSet {
 struct SrvTicket {
     uint64_t id = 0;
     uint32_t g = 0, R = 0, k = 0;
+    uint64_t seed = 0;
+    double alpha = 1.0;
+    bool compact = false;
     im_prob prob{};
     srv_clock::time_point t0, t1;
     bool done = false;
@@ -113,6 +129,35 @@ size_t set_bytes(uint32_t n, uint32_t R) {
     return align256((size_t)key_slots(R) * 8) + align256((size_t)n * R * 8) + align256((size_t)n * 8);
 }
 
+// Device bytes a CompactSketch request needs at most (im_build_sketches and its
+// selection with one sketch per labelling pass), with rho taken 6 standard
+// deviations above alpha * n.
+size_t compact_need_bytes(uint32_t n, uint32_t R, double alpha) {
+    const double mean = alpha * n;
+    const size_t rho = std::min<size_t>(n, (size_t)(mean + 6.0 * std::sqrt(mean * (1.0 - alpha) + 1.0) + 64.0));
+    const size_t nw = (n + 63) / 64;
+    uint32_t memo = 64;
+    while (memo < n && memo < 4096) memo <<= 1;
+    const uint64_t tn = tree_nodes(make_tree(n));
+    const size_t per_slot = (size_t)n * 4 + (size_t)((n + 31) / 32) * 4;
+    const size_t slots = std::max<size_t>(1, std::min<size_t>(64, ((size_t)256 << 20) / per_slot));
+    const size_t one_pass = sketch_stride(n) * 4 * 4;
+    return (size_t)R * rho * 8 + (size_t)R * nw * 16 + (size_t)memo * R * 16 + (size_t)R * 16 +
+           (size_t)key_slots(R) * 8 + (size_t)n * 57 + rho * 4 + tn * 8 + ((size_t)1 << 25) + slots * per_slot +
+           2 * one_pass + ((size_t)1 << 20);
+}
+
+bool same_model(const ProbDev &a, const ProbDev &b) {
+    return a.kind == b.kind && a.t0 == b.t0 && a.t1 == b.t1 && a.t2 == b.t2 && a.ktriv == b.ktriv;
+}
+
+// Set by the tests to make the worker treat the n-th sketch-set build as failed
+// on the device (PACIM_TEST_FAIL_BUILD=n); the build itself runs normally.
+uint64_t forced_build_failure() {
+    const char *e = getenv("PACIM_TEST_FAIL_BUILD");
+    return e ? strtoull(e, nullptr, 10) : 0;
+}
+
 }  // namespace
 
 struct im_server {
@@ -143,6 +188,13 @@ struct im_server {
     bool stop = false;
     std::thread worker;
     im_server_counters stats{};
+    uint64_t fail_build = 0;   // forced failure of the n-th build (tests), 0: none
+    // CompactSketch lane
+    im_ctx *cctx = nullptr;
+    size_t compact_budget = 0;
+    std::deque<SrvTicket *> cpending;
+    std::condition_variable cv_compact;
+    std::thread cworker;
 };
 
 namespace {
@@ -157,14 +209,15 @@ void srv_free_set(im_server *sv, SrvSet *set) {
 // Finds or creates the sketch set of a request; nullptr if it cannot fit now.
 // Called with sv->mu held.
 SrvSet *srv_acquire_set(im_server *sv, const SrvTicket *t) {
+    const im_graph *g = sv->graphs[t->g];
+    const ProbDev pm = prob_dev(t->prob, g->off);
     for (SrvSet *s : sv->sets)
-        if (s->g == t->g && s->R == t->R && s->kind == t->prob.kind && (t->prob.kind != 0 || s->p == t->prob.p)) {
+        if (!s->failed && s->g == t->g && s->R == t->R && s->seed == t->seed && same_model(s->pm, pm)) {
             ++s->refs;
             s->stamp = ++sv->stamp;
             ++sv->stats.cache_hits;
             return s;
         }
-    const im_graph *g = sv->graphs[t->g];
     const size_t need = set_bytes(g->n, t->R);
     void *mem = sv->pool.alloc(need);
     while (!mem) {  // evict least recently used unreferenced sets until a block fits
@@ -185,8 +238,8 @@ SrvSet *srv_acquire_set(im_server *sv, const SrvTicket *t) {
     s->block = mem;
     s->g = t->g;
     s->R = t->R;
-    s->kind = t->prob.kind;
-    s->p = t->prob.p;
+    s->seed = t->seed;
+    s->pm = pm;
     s->bytes = need;
     char *b = static_cast<char *>(s->block);
     s->K = reinterpret_cast<uint64_t *>(b);
@@ -197,13 +250,22 @@ SrvSet *srv_acquire_set(im_server *sv, const SrvTicket *t) {
     sv->sets_bytes += need;
     sv->peak = std::max(sv->peak, sv->sets_bytes + sv->slab_bytes);
     // build on the build stream; selection steps wait for `ready`
-    k_sketch_keys<<<grid_for(key_slots(t->R), 256, 1u << 20), 256, 0, sv->bld>>>(sv->cfg.sample_seed, key_slots(t->R), s->K);
-    enqueue_full_build(sv->ctx, g, prob_dev(t->prob, g->off), s->K, t->R, sv->cs, s->E, s->gain0, sv->bld);
+    k_sketch_keys<<<grid_for(key_slots(t->R), 256, 1u << 20), 256, 0, sv->bld>>>(t->seed, key_slots(t->R), s->K);
+    enqueue_full_build(sv->ctx, g, pm, s->K, t->R, sv->cs, s->E, s->gain0, sv->bld);
     (void)hipEventCreateWithFlags(&s->ready, hipEventDisableTiming);
     (void)hipEventRecord(s->ready, sv->bld);
     sv->sets.push_back(s);
     ++sv->stats.builds;
+    if (sv->fail_build && sv->stats.builds == sv->fail_build) s->failed = true;  // checked once it is ready
     return s;
+}
+
+// Readiness of a set's build: hipSuccess when built, hipErrorNotReady while it
+// runs, any other code when it failed (or the tests forced a failure).
+hipError_t srv_set_state(const SrvSet *set) {
+    const hipError_t e = hipEventQuery(set->ready);
+    if (e == hipSuccess && set->failed) return hipErrorLaunchFailure;
+    return e;
 }
 
 void srv_complete(im_server *sv, SrvSlot &sl, im_status st) {
@@ -226,6 +288,12 @@ void srv_complete(im_server *sv, SrvSlot &sl, im_status st) {
     if (sl.set) {
         --sl.set->refs;
         sl.set->stamp = ++sv->stamp;
+        if (sl.set->failed && sl.set->refs == 0) {
+            // nothing may still write the block: wait for the build stream first
+            (void)hipStreamSynchronize(sv->bld);
+            sv->sets.remove(sl.set);
+            srv_free_set(sv, sl.set);
+        }
     }
     sl.t = nullptr;
     sl.set = nullptr;
@@ -309,18 +377,37 @@ void srv_worker(im_server *sv) {
         // one step over the requests whose sketch set is built
         desc.clear();
         idx.clear();
+        bool failed_any = false;
         for (uint32_t i = 0; i < sv->slots.size(); ++i) {
             SrvSlot &sl = sv->slots[i];
             if (!sl.t || sl.t->k == 0) continue;
-            if (hipEventQuery(sl.set->ready) != hipSuccess) continue;
+            const hipError_t e = srv_set_state(sl.set);
+            if (e == hipErrorNotReady) continue;
+            if (e != hipSuccess) {
+                // the build failed: every request on this set fails, and the set is dropped
+                {
+                    std::lock_guard<std::mutex> lk(sv->mu);
+                    sl.set->failed = true;
+                }
+                (void)hipGetLastError();
+                srv_complete(sv, sl, IM_EDEVICE);
+                failed_any = true;
+                continue;
+            }
             desc.push_back(sl.q);
             idx.push_back(i);
         }
+        if (failed_any) continue;
         if (desc.empty()) {
             const auto tw = srv_clock::now();
             bool any_built = false;
             for (auto &sl : sv->slots)
-                if (sl.t && sl.set) { (void)hipEventSynchronize(sl.set->ready); any_built = true; break; }
+                if (sl.t && sl.set) {
+                    // a failed build returns at once and is handled on the next pass
+                    (void)hipEventSynchronize(sl.set->ready);
+                    any_built = true;
+                    break;
+                }
             if (!any_built) std::this_thread::sleep_for(std::chrono::microseconds(50));
             std::lock_guard<std::mutex> lk(sv->mu);
             sv->stats.build_wait_ms += ms_since(tw);
@@ -379,6 +466,44 @@ void srv_worker(im_server *sv) {
     }
 }
 
+// The CompactSketch lane: one request at a time, build + selection + free on the
+// lane's own context and stream.
+void srv_compact_worker(im_server *sv) {
+    (void)hipSetDevice(sv->ctx->device);
+    for (;;) {
+        SrvTicket *t = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->cv_compact.wait(lk, [&] { return sv->stop || !sv->cpending.empty(); });
+            if (sv->cpending.empty()) return;  // stopped and drained
+            t = sv->cpending.front();
+            sv->cpending.pop_front();
+        }
+        im_status st = IM_OK;
+        std::vector<uint32_t> seeds(std::max<uint32_t>(t->k, 1));
+        std::vector<uint64_t> gains(std::max<uint32_t>(t->k, 1));
+        if (t->k) {
+            im_sketches *sk = nullptr;
+            st = im_build_sketches(sv->cctx, sv->graphs[t->g], t->prob, t->R, t->seed, t->alpha, &sk);
+            if (st == IM_OK) {
+                st = im_select_seeds_from(sv->cctx, sk, t->k, seeds.data(), gains.data());
+                im_sketches_free(sk);
+            }
+        }
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (st == IM_OK) {
+            t->seeds.assign(seeds.begin(), seeds.begin() + t->k);
+            t->gains.assign(gains.begin(), gains.begin() + t->k);
+        }
+        t->status = st;
+        t->t1 = srv_clock::now();
+        t->done = true;
+        ++sv->stats.completed;
+        ++sv->stats.compact_completed;
+        sv->cv_done.notify_all();
+    }
+}
+
 }  // namespace
 
 extern "C" im_status im_server_create(im_ctx *ctx, const im_graph *const *graphs, uint32_t ngraphs,
@@ -399,11 +524,19 @@ extern "C" im_status im_server_create(im_ctx *ctx, const im_graph *const *graphs
     if (!c.rounds_per_step) c.rounds_per_step = 16;
     if (!c.max_R) c.max_R = 256;
     if (!c.max_k) c.max_k = 1000;
+    if (!c.compact_budget) c.compact_budget = c.hbm_budget / 4;
     c.max_active = std::min<uint32_t>(c.max_active, 256);
+    if (c.compact_budget >= c.hbm_budget) {
+        delete sv;
+        return fail(ctx, IM_EINVAL, "compact_budget must be smaller than hbm_budget");
+    }
     sv->cfg = c;
+    sv->compact_budget = c.compact_budget;
+    sv->fail_build = forced_build_failure();
     for (auto *g : sv->graphs) sv->nmax = std::max(sv->nmax, g->n);
     im_status rc = IM_OK;
     auto bail = [&](im_status code) {
+        if (sv->cctx) im_ctx_destroy(sv->cctx);
         if (sv->sel) (void)hipStreamDestroy(sv->sel);
         if (sv->bld) (void)hipStreamDestroy(sv->bld);
         cc_scratch_free(ctx, &sv->cs);
@@ -428,9 +561,11 @@ extern "C" im_status im_server_create(im_ctx *ctx, const im_graph *const *graphs
                             align256((size_t)sv->nmax * 4) + align256((size_t)cov_slots(c.max_R, c.max_k) * 8) +
                             align256((size_t)c.max_k * 4) * 2 + align256((size_t)c.max_k * 8);
     sv->slab_bytes = per_slot * c.max_active;
-    if (sv->slab_bytes + sv->cs.bytes >= c.hbm_budget)
-        return bail(fail(ctx, IM_EINVAL, "hbm_budget is smaller than the query slots"));
-    sv->sets_budget = c.hbm_budget - sv->slab_bytes - sv->cs.bytes;
+    if (sv->slab_bytes + sv->cs.bytes + c.compact_budget >= c.hbm_budget)
+        return bail(fail(ctx, IM_EINVAL, "hbm_budget is smaller than the query slots and the compact lane"));
+    sv->sets_budget = c.hbm_budget - sv->slab_bytes - sv->cs.bytes - c.compact_budget;
+    if (im_ctx_create(ctx->device, nullptr, c.compact_budget, &sv->cctx) != IM_OK)
+        return bail(fail(ctx, IM_EDEVICE, "compact lane context creation failed"));
     if ((rc = dev_alloc(ctx, sv->slab_bytes, &sv->slab)) != IM_OK) return bail(rc);
     if ((rc = dev_alloc(ctx, sv->sets_budget, &sv->pool_mem)) != IM_OK) return bail(rc);
     sv->pool.init(sv->pool_mem, sv->sets_budget);
@@ -461,26 +596,39 @@ extern "C" im_status im_server_create(im_ctx *ctx, const im_graph *const *graphs
     b += align256(8 * (c.max_active + 1) * (1 + kMaxLevels));
     sv->d_next = reinterpret_cast<uint32_t *>(b);
     sv->worker = std::thread(srv_worker, sv);
+    sv->cworker = std::thread(srv_compact_worker, sv);
     *out = sv;
     return IM_OK;
 }
 
-extern "C" im_status im_server_submit(im_server *sv, uint32_t graph, im_prob prob, uint32_t R, uint32_t k,
-                                      uint64_t *ticket) {
-    if (!sv || !ticket) return IM_EINVAL;
-    if (graph >= sv->graphs.size() || R == 0 || R > sv->cfg.max_R || k > sv->cfg.max_k || k > sv->graphs[graph]->n)
-        return IM_EINVAL;
-    if (prob_problem(prob) || prob.kind == IM_PROB_PER_EDGE) return IM_EINVAL;
-    const uint32_t n = sv->graphs[graph]->n;
+extern "C" im_status im_server_submit(im_server *sv, const im_query *q, uint64_t *ticket) {
+    if (!sv || !q || !ticket) return IM_EINVAL;
+    uint32_t graph = (uint32_t)sv->graphs.size();
+    for (uint32_t i = 0; i < sv->graphs.size(); ++i)
+        if (sv->graphs[i] == q->graph) { graph = i; break; }
+    if (graph >= sv->graphs.size()) return IM_EINVAL;
+    const uint32_t R = q->R, k = q->k, n = sv->graphs[graph]->n;
+    if (R == 0 || R > sv->cfg.max_R || k > sv->cfg.max_k || k > n) return IM_EINVAL;
+    if (prob_problem(q->prob) || q->prob.kind == IM_PROB_PER_EDGE) return IM_EINVAL;
+    if (!(q->alpha >= 0.0 && q->alpha <= 1.0)) return IM_EINVAL;
+    const bool compact = q->alpha > 0.0 && q->alpha < 1.0;
     const uint32_t kb = std::max<uint32_t>(1, bit_length((uint64_t)n - 1));
     if (kb + bit_length((uint64_t)R * n + 1) > 64) return IM_EINVAL;
-    if (set_bytes(n, R) > sv->sets_budget) return IM_EBUSY;  // can never fit the budget
+    if (compact) {
+        if ((uint64_t)R * n >= (1ull << kPartialShift)) return IM_EINVAL;
+        if (compact_need_bytes(n, R, q->alpha) > sv->compact_budget) return IM_EBUSY;
+    } else if (set_bytes(n, R) > sv->sets_budget) {
+        return IM_EBUSY;  // can never fit the budget
+    }
     SrvTicket *t = new (std::nothrow) SrvTicket();
     if (!t) return IM_ENOMEM;
     t->g = graph;
     t->R = R;
     t->k = k;
-    t->prob = prob;
+    t->seed = q->seed;
+    t->alpha = compact ? q->alpha : 1.0;
+    t->compact = compact;
+    t->prob = q->prob;
     t->t0 = srv_clock::now();
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->stop) {
@@ -489,10 +637,15 @@ extern "C" im_status im_server_submit(im_server *sv, uint32_t graph, im_prob pro
     }
     t->id = sv->next_id++;
     sv->tickets[t->id] = t;
-    sv->pending.push_back(t);
     ++sv->stats.submitted;
     *ticket = t->id;
-    sv->cv_work.notify_all();
+    if (compact) {
+        sv->cpending.push_back(t);
+        sv->cv_compact.notify_all();
+    } else {
+        sv->pending.push_back(t);
+        sv->cv_work.notify_all();
+    }
     return IM_OK;
 }
 
@@ -547,8 +700,11 @@ extern "C" im_status im_server_destroy(im_server *sv) {
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->stop = true;
         sv->cv_work.notify_all();
+        sv->cv_compact.notify_all();
     }
     if (sv->worker.joinable()) sv->worker.join();
+    if (sv->cworker.joinable()) sv->cworker.join();
+    if (sv->cctx) im_ctx_destroy(sv->cctx);
     im_ctx *ctx = sv->ctx;
     (void)hipStreamSynchronize(sv->bld);
     (void)hipStreamSynchronize(sv->sel);

@@ -49,18 +49,18 @@ _u64p = ctypes.POINTER(ctypes.c_uint64)
 
 class im_query(ctypes.Structure):
     _fields_ = [("graph", _vp), ("prob", im_prob), ("R", ctypes.c_uint32), ("k", ctypes.c_uint32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("alpha", ctypes.c_double)]
 
 
 class im_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_active", ctypes.c_uint32), ("rounds_per_step", ctypes.c_uint32),
-                ("max_R", ctypes.c_uint32), ("max_k", ctypes.c_uint32), ("sample_seed", ctypes.c_uint64)]
+                ("max_R", ctypes.c_uint32), ("max_k", ctypes.c_uint32), ("compact_budget", ctypes.c_size_t)]
 
 
 class im_server_counters(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("steps", ctypes.c_uint64),
                 ("builds", ctypes.c_uint64), ("cache_hits", ctypes.c_uint64), ("evictions", ctypes.c_uint64),
-                ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t), ("cached_sets", ctypes.c_uint32),
+                ("compact_completed", ctypes.c_uint64), ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t), ("cached_sets", ctypes.c_uint32),
                 ("admit_ms", ctypes.c_double), ("build_wait_ms", ctypes.c_double), ("step_ms", ctypes.c_double),
                 ("busy_steps_ms", ctypes.c_double)]
 
@@ -97,8 +97,7 @@ _SIGS = {
     "im_probe_device": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "im_server_create": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_uint32, ctypes.POINTER(im_server_config),
                                         ctypes.POINTER(_vp)]),
-    "im_server_submit": (ctypes.c_int, [_vp, ctypes.c_uint32, im_prob, ctypes.c_uint32, ctypes.c_uint32,
-                                        ctypes.POINTER(ctypes.c_uint64)]),
+    "im_server_submit": (ctypes.c_int, [_vp, ctypes.POINTER(im_query), ctypes.POINTER(ctypes.c_uint64)]),
     "im_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]),
     "im_server_wait": (ctypes.c_int, [_vp, ctypes.c_uint64, _u32p, _u64p, ctypes.POINTER(ctypes.c_double)]),
     "im_server_stats": (ctypes.c_int, [_vp, ctypes.POINTER(im_server_counters)]),
@@ -295,14 +294,14 @@ def im_probe_device(ctx):
 
 
 def im_select_seeds_batched(ctx, queries, cfg=None):
-    """queries: iterable of (graph handle, kind, p, R, k, seed).  cfg: dict with any of
-    hook_block, hook_grid, select_block, select_grid.  Returns ([(seeds, gains)], device_ms)."""
-    queries = list(queries)
+    """queries: iterable of (graph handle, kind, p, R, k, seed[, alpha]).  cfg: dict with any
+    of hook_block, hook_grid, select_block, select_grid.  Returns ([(seeds, gains)], device_ms)."""
+    queries = [tuple(q) + ((1.0,) if len(q) == 6 else ()) for q in queries]
     nq = len(queries)
     arr = (im_query * max(nq, 1))()
     outs = []
-    for i, (g, kind, p, R, k, seed) in enumerate(queries):
-        arr[i] = im_query(g, _prob(kind, p), R, k, seed & ((1 << 64) - 1))
+    for i, (g, kind, p, R, k, seed, alpha) in enumerate(queries):
+        arr[i] = im_query(g, _prob(kind, p), R, k, seed & ((1 << 64) - 1), float(alpha))
         outs.append((np.empty(max(k, 1), dtype=np.uint32), np.empty(max(k, 1), dtype=np.uint64)))
     sp = (_u32p * max(nq, 1))(*[_u32(a) for a, _ in outs])
     gp = (_u64p * max(nq, 1))(*[_u64(b) for _, b in outs])
@@ -317,9 +316,9 @@ def im_select_seeds_batched(ctx, queries, cfg=None):
 
 
 def im_server_create(ctx, graph_handles, hbm_budget=0, max_active=0, rounds_per_step=0, max_R=0, max_k=0,
-                     sample_seed=1):
+                     compact_budget=0):
     arr = (_vp * len(graph_handles))(*graph_handles)
-    cfg = im_server_config(hbm_budget, max_active, rounds_per_step, max_R, max_k, sample_seed)
+    cfg = im_server_config(hbm_budget, max_active, rounds_per_step, max_R, max_k, compact_budget)
     h = _vp()
     _check(ctx, load().im_server_create(ctx, arr, len(graph_handles), ctypes.byref(cfg), ctypes.byref(h)))
     return h.value
@@ -330,9 +329,11 @@ def _srv_check(rc, what):
         raise ImError(rc, what)
 
 
-def im_server_submit(srv, graph: int, kind: int, p: float, R: int, k: int) -> int:
+def im_server_submit(srv, graph, kind: int, p, R: int, k: int, seed: int, alpha: float = 1.0) -> int:
+    """graph: the handle of one of the server's graphs."""
     t = ctypes.c_uint64()
-    _srv_check(load().im_server_submit(srv, graph, _prob(kind, p), R, k, ctypes.byref(t)), "im_server_submit")
+    q = im_query(graph, _prob(kind, p), R, k, seed & ((1 << 64) - 1), float(alpha))
+    _srv_check(load().im_server_submit(srv, ctypes.byref(q), ctypes.byref(t)), "im_server_submit")
     return t.value
 
 
@@ -406,8 +407,8 @@ class Context:
         return im_probe_device(self.h)
 
     def select_batched(self, queries, cfg=None):
-        """queries: list of (Graph, kind, p, R, k, seed)."""
-        return im_select_seeds_batched(self.h, [(g.h, kd, p, R, k, sd) for (g, kd, p, R, k, sd) in queries], cfg)
+        """queries: list of (Graph, kind, p, R, k, seed[, alpha])."""
+        return im_select_seeds_batched(self.h, [(q[0].h,) + tuple(q[1:]) for q in queries], cfg)
 
 
 class Graph:
@@ -477,8 +478,10 @@ class Server:
         self.h = im_server_create(ctx.h, [g.h for g in self.graphs], **cfg)
         self._k = {}
 
-    def submit(self, graph: int, kind: int, p: float, R: int, k: int) -> int:
-        t = im_server_submit(self.h, graph, kind, p, R, k)
+    def submit(self, graph: int, kind: int, p, R: int, k: int, seed: int, alpha: float = 1.0) -> int:
+        """graph: index into the server's graphs; seed: the request's sampling seed;
+        alpha: 1 for full labels, below 1 for CompactSketch."""
+        t = im_server_submit(self.h, self.graphs[graph].h, kind, p, R, k, seed, alpha)
         self._k[t] = k
         return t
 

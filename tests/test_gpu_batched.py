@@ -1,12 +1,15 @@
 """Batched selection (one hipGraph of persistent kernels) against each query
 alone and against the oracle: bit-exact seeds and gains for every query, under
-several launch shapes."""
+several launch shapes, with CompactSketch queries in the batch, and at the
+workload's own scale (64 Chung-Lu graphs of 2^12-2^18 vertices, R = 128, k = 50)
+against stored oracle results (tests/golden/batched_chunglu64_R128_k50.json,
+written by tests/golden/make_golden.py from the oracle alone)."""
 import numpy as np
 import pytest
 
 import oracle
 from paper_2311_07554_amd import inputs, pacim
-from tests.gpu_util import run_select
+from tests.golden import make_golden
 
 pytestmark = pytest.mark.gpu
 U, TRI = pacim.IM_PROB_UNIFORM, pacim.IM_PROB_TRIVALENCY
@@ -79,3 +82,49 @@ def test_batched_rejects_bad_queries(ctx):
         assert len(set(res[0][0].tolist())) == 50
     finally:
         gr.close()
+
+
+def test_batched_with_compact_queries(ctx, batch):
+    # every other query as CompactSketch (alpha 0.3 or 0.1): the same seeds and gains
+    graphs = [ctx.graph(g.n, g.offsets, g.cols) for (g, *_rest) in batch]
+    try:
+        qs = [(gr, kind, p, R, k, seed, (0.3, 1.0, 0.1, 0.0)[i % 4])
+              for i, (gr, (g, kind, p, R, k, seed, ws, wg)) in enumerate(zip(graphs, batch))]
+        res, ms = ctx.select_batched(qs)
+        assert ms > 0
+        for (s, gn), (g, kind, p, R, k, seed, ws, wg) in zip(res, batch):
+            assert np.array_equal(s, ws) and np.array_equal(gn, wg), (g.n, R, k)
+        with pytest.raises(pacim.ImError):
+            ctx.select_batched([qs[0][:6] + (1.5,)])
+    finally:
+        for gr in graphs:
+            gr.close()
+
+
+def test_batched_workload_scale_matches_oracle_and_replays_its_graph(ctx):
+    w = inputs.batched()
+    want = make_golden.load("batched")
+    print("case batched workload:", len(w.queries), "Chung-Lu graphs, n up to",
+          max(q.graph.n for q in w.queries), flush=True)
+    graphs = [ctx.graph(q.graph.n, q.graph.offsets, q.graph.cols) for q in w.queries]
+    try:
+        ids = [make_golden.query_id(make_golden.graph_digest(q.graph), q.prob_kind, q.p, 0.0, q.R, q.seed)
+               for q in w.queries]
+        qs = [(gr, q.prob_kind, q.p, q.R, q.k, q.seed) for gr, q in zip(graphs, w.queries)]
+        cap0, rep0 = ctx.kernel_time("batch_capture")[0], ctx.kernel_time("batch_replay")[0]
+        for rnd in range(2):
+            res, ms = ctx.select_batched(qs)
+            print(f"  batched launch {rnd}: {ms:.1f} ms", flush=True)
+            for (s, gn), q, i in zip(res, w.queries, ids):
+                assert s.tolist() == want[i]["seeds"] and gn.tolist() == want[i]["gains"], (q.graph.n, q.seed)
+        # the second batch had the same launches: the kept graph was replayed
+        assert ctx.kernel_time("batch_capture")[0] - cap0 == 1
+        assert ctx.kernel_time("batch_replay")[0] - rep0 == 1
+        # with every eighth query as CompactSketch, alpha 0.1
+        qs2 = [qq + ((0.1,) if j % 8 == 3 else (1.0,)) for j, qq in enumerate(qs)]
+        res, _ = ctx.select_batched(qs2)
+        for (s, gn), q, i in zip(res, w.queries, ids):
+            assert s.tolist() == want[i]["seeds"] and gn.tolist() == want[i]["gains"], (q.graph.n, q.seed)
+    finally:
+        for gr in graphs:
+            gr.close()

@@ -1,7 +1,15 @@
 """Serving loop (continuous batching inside the library): every request's result
-equals the same request alone (im_select_seeds with the server's sampling seed)
-and, for small ones, the oracle; admission under a small HBM budget evicts
-cached sketch sets without changing any result."""
+equals the same request alone (its im_query through im_build_sketches and
+im_select_seeds_from) and the oracle; admission under a small HBM budget evicts
+cached sketch sets without changing any result; sketch sets are shared only by
+requests with the same graph, model thresholds, R and sampling seed; a failed
+build fails exactly the requests that wait on it.
+
+The config-scale mix (R-MAT graphs of 2^16 to 2^18 vertices, R in {64, 256},
+k in {10, 50, 100}, per-request seeds, full labels and CompactSketch) is checked
+against stored oracle results (tests/golden/serving_mix.json, written by
+tests/golden/make_golden.py from the oracle alone)."""
+import os
 import threading
 
 import numpy as np
@@ -9,9 +17,10 @@ import pytest
 
 import oracle
 from paper_2311_07554_amd import inputs, pacim
+from tests.golden import make_golden
 
 pytestmark = pytest.mark.gpu
-U, TRI = pacim.IM_PROB_UNIFORM, pacim.IM_PROB_TRIVALENCY
+U, TRI, RANGE = pacim.IM_PROB_UNIFORM, pacim.IM_PROB_TRIVALENCY, pacim.IM_PROB_RANGE
 
 
 @pytest.fixture(scope="module")
@@ -28,7 +37,7 @@ def env():
     ctx.close()
 
 
-def _requests(ngraphs, count, seed):
+def _requests(ngraphs, count, seed, alphas=(1.0,)):
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(count):
@@ -37,36 +46,65 @@ def _requests(ngraphs, count, seed):
         p = float(rng.choice([0.01, 0.05, 0.2]))
         R = int(rng.choice([8, 64, 100]))
         k = int(rng.choice([1, 10, 30]))
-        out.append((gi, kind, p if kind == U else 0.0, R, k))
+        sseed = int(rng.choice([3, 9, 1000 + len(out)]))
+        alpha = float(rng.choice(alphas))
+        out.append((gi, kind, p if kind == U else 0.0, R, k, sseed, alpha))
     return out
+
+
+def _alone(gr, kind, p, R, k, seed, alpha):
+    sk = gr.sketches(kind, p, R, seed, alpha)
+    try:
+        return sk.select(k)
+    finally:
+        sk.close()
 
 
 def test_server_results_equal_alone_and_oracle(env):
     ctx, gs, grs = env
-    reqs = _requests(len(gs), 40, 7)
-    with pacim.Server(ctx, grs, max_active=8, rounds_per_step=4, sample_seed=9) as srv:
+    reqs = _requests(len(gs), 40, 7, alphas=(1.0, 1.0, 0.3))
+    print("case server mix of", len(reqs), "requests", flush=True)
+    with pacim.Server(ctx, grs, max_active=8, rounds_per_step=4) as srv:
         tickets = [srv.submit(*r) for r in reqs]          # all in flight together
         res = [srv.wait(t) for t in tickets]
         st = srv.stats()
     assert st["completed"] == len(reqs) and st["cache_hits"] > 0 and st["steps"] > 0
-    for (gi, kind, p, R, k), (s, gn, lat) in zip(reqs, res):
-        s1, g1 = grs[gi].select_seeds(kind, p, R, k, 9)
-        assert np.array_equal(s, s1) and np.array_equal(gn, g1), (gi, kind, p, R, k)
+    assert st["compact_completed"] == sum(1 for r in reqs if r[6] < 1.0) > 0
+    for (gi, kind, p, R, k, sseed, alpha), (s, gn, lat) in zip(reqs, res):
+        s1, g1 = _alone(grs[gi], kind, p, R, k, sseed, alpha)
+        assert np.array_equal(s, s1) and np.array_equal(gn, g1), (gi, kind, p, R, k, sseed, alpha)
         assert lat > 0
-    for (gi, kind, p, R, k), (s, gn, _) in list(zip(reqs, res))[:6]:
-        lab, siz = oracle.sketches(gs[gi], kind, p, 9, R, threads=8)
+    for (gi, kind, p, R, k, sseed, alpha), (s, gn, _) in list(zip(reqs, res))[:8]:
+        lab, siz = oracle.sketches(gs[gi], kind, p, sseed, R, threads=8)
         ws, wg = oracle.greedy(lab, siz, k)
         assert np.array_equal(s, ws) and np.array_equal(gn, wg)
+
+
+def test_server_keys_sets_by_seed_and_model_thresholds(env):
+    # same graph and R: two sampling seeds, and Uniform U(lo, hi) under two intervals
+    # (the model's kind alone does not identify a set); each request equals the oracle
+    ctx, gs, grs = env
+    reqs = [(1, RANGE, (0.0, 0.05), 32, 10, 4), (1, RANGE, (0.05, 0.3), 32, 10, 4),
+            (1, RANGE, (0.0, 0.05), 32, 10, 5), (1, U, 0.05, 32, 10, 4), (1, RANGE, (0.05, 0.3), 32, 12, 4)]
+    with pacim.Server(ctx, grs, max_active=4, rounds_per_step=3) as srv:
+        res = [srv.wait(srv.submit(gi, kind, p, R, k, sd)) for (gi, kind, p, R, k, sd) in reqs]
+        st = srv.stats()
+    assert st["builds"] == 4 and st["cache_hits"] == 1, st
+    for (gi, kind, p, R, k, sd), (s, gn, _) in zip(reqs, res):
+        lab, siz = oracle.sketches(gs[gi], kind, p, sd, R, threads=8)
+        ws, wg = oracle.greedy(lab, siz, k)
+        assert np.array_equal(s, ws) and np.array_equal(gn, wg), (kind, p, sd, k)
 
 
 def test_server_arrivals_while_running_and_small_budget(env):
     ctx, gs, grs = env
     reqs = _requests(len(gs), 30, 11)
-    # budget for the slots, the build scratch and only a few sketch sets: forces eviction
-    budget = 12 << 20
+    # budget for the slots, the build scratch, the compact lane and only a few sketch
+    # sets: forces eviction
+    budget = 16 << 20
     out = {}
     with pacim.Server(ctx, grs, hbm_budget=budget, max_active=4, rounds_per_step=2, max_R=100, max_k=30,
-                      sample_seed=3) as srv:
+                      compact_budget=4 << 20) as srv:
         def submitter():
             for i, r in enumerate(reqs):
                 out[i] = srv.submit(*r)
@@ -76,8 +114,8 @@ def test_server_arrivals_while_running_and_small_budget(env):
         res = {i: srv.wait(t) for i, t in out.items()}
         st = srv.stats()
     assert st["completed"] == len(reqs)
-    for i, (gi, kind, p, R, k) in enumerate(reqs):
-        s1, g1 = grs[gi].select_seeds(kind, p, R, k, 3)
+    for i, (gi, kind, p, R, k, sseed, alpha) in enumerate(reqs):
+        s1, g1 = grs[gi].select_seeds(kind, p, R, k, sseed)
         assert np.array_equal(res[i][0], s1) and np.array_equal(res[i][1], g1)
     assert st["peak_bytes"] <= budget
     assert st["evictions"] > 0
@@ -85,13 +123,80 @@ def test_server_arrivals_while_running_and_small_budget(env):
 
 def test_server_rejects(env):
     ctx, gs, grs = env
-    with pacim.Server(ctx, grs, hbm_budget=6 << 20, max_active=2, max_R=256, max_k=50) as srv:
+    with pacim.Server(ctx, grs, hbm_budget=12 << 20, max_active=2, max_R=256, max_k=50,
+                      compact_budget=4 << 20) as srv:
         with pytest.raises(pacim.ImError) as e:
-            srv.submit(0, U, 0.1, 300, 5)          # R above max_R
+            srv.submit(0, U, 0.1, 300, 5, 1)          # R above max_R
         assert e.value.status == pacim.IM_EINVAL
         with pytest.raises(pacim.ImError) as e:
-            srv.submit(2, U, 0.1, 256, 5)          # 3000 x 256 x 8 B cannot fit the budget left
+            srv.submit(0, U, 0.1, 4, 5, 1, alpha=1.5)  # alpha outside [0, 1]
+        assert e.value.status == pacim.IM_EINVAL
+        with pytest.raises(pacim.ImError) as e:
+            srv.submit(2, U, 0.1, 256, 5, 1)          # 3000 x 256 x 8 B cannot fit the budget left
         assert e.value.status == pacim.IM_EBUSY
-        t = srv.submit(0, U, 0.1, 4, 0)            # k = 0 completes at once
+        with pytest.raises(pacim.ImError) as e:
+            srv.submit(1, U, 0.1, 256, 5, 1, alpha=0.5)  # nor its compact triple the compact lane
+        assert e.value.status == pacim.IM_EBUSY
+        t = srv.submit(0, U, 0.1, 4, 0, 1)            # k = 0 completes at once
         s, g, _ = srv.wait(t)
         assert s.size == 0
+
+
+def test_server_failed_build_fails_its_requests(env, monkeypatch):
+    # the host marks the second sketch-set build as failed (the build itself runs
+    # normally): the requests waiting on that set end with IM_EDEVICE, every other
+    # request completes, a later request with the same key builds the set again,
+    # and the server shuts down
+    ctx, gs, grs = env
+    monkeypatch.setenv("PACIM_TEST_FAIL_BUILD", "2")
+    reqs = [(0, U, 0.05, 16, 5, 1), (1, U, 0.05, 16, 5, 1), (1, U, 0.05, 16, 7, 1), (2, U, 0.05, 16, 5, 1)]
+    srv = pacim.Server(ctx, grs, max_active=8, rounds_per_step=2)
+    monkeypatch.delenv("PACIM_TEST_FAIL_BUILD")
+    try:
+        tickets = [srv.submit(*r) for r in reqs]
+        status = []
+        for t in tickets:
+            try:
+                srv.wait(t)
+                status.append(pacim.IM_OK)
+            except pacim.ImError as e:
+                status.append(e.status)
+        assert status == [pacim.IM_OK, pacim.IM_EDEVICE, pacim.IM_EDEVICE, pacim.IM_OK], status
+        s, g, _ = srv.wait(srv.submit(1, U, 0.05, 16, 5, 1))
+        s1, g1 = grs[1].select_seeds(U, 0.05, 16, 5, 1)
+        assert np.array_equal(s, s1) and np.array_equal(g, g1)
+    finally:
+        srv.close()
+
+
+def test_server_config_scale_mix_matches_oracle(env):
+    # R-MAT graphs of 2^16-2^18 vertices (the serving workload's first seven),
+    # per-request sampling seeds, full labels and CompactSketch, all submitted at
+    # once: each result equals the stored oracle result of its sketch set (the first
+    # k seeds of the longest run on that set) and the same request alone
+    ctx = env[0]
+    graphs = inputs.serving_graphs(scales=inputs.SERVING_SCALES[:inputs.SERVING_MIX_GRAPHS])
+    digests = [make_golden.graph_digest(g) for g in graphs]
+    want = make_golden.load("serving")
+    mix = inputs.serving_mix()
+    print("case serving config-scale mix:", len(mix), "requests over", len(graphs), "graphs", flush=True)
+    grs = [ctx.graph(g.n, g.offsets, g.cols) for g in graphs]
+    try:
+        with pacim.Server(ctx, grs, hbm_budget=48 << 30, max_active=16, rounds_per_step=16) as srv:
+            tickets = [srv.submit(gi, kind, (p, ph) if kind == RANGE else p, R, k, sd, alpha)
+                       for (gi, kind, p, ph, R, k, sd, alpha) in mix]
+            res = [srv.wait(t) for t in tickets]
+            st = srv.stats()
+        print("  server stats", st, flush=True)
+        assert st["compact_completed"] == sum(1 for m in mix if m[7] < 1.0)
+        for (gi, kind, p, ph, R, k, sd, alpha), (s, gn, _) in zip(mix, res):
+            e = want[make_golden.query_id(digests[gi], kind, p, ph, R, sd)]
+            assert e["graph"] == digests[gi]
+            assert s.tolist() == e["seeds"][:k] and gn.tolist() == e["gains"][:k], (gi, kind, p, ph, R, k, sd, alpha)
+        for i in (0, 4, 12, 25):  # alone, outside the server
+            gi, kind, p, ph, R, k, sd, alpha = mix[i]
+            s1, g1 = _alone(grs[gi], kind, (p, ph) if kind == RANGE else p, R, k, sd, alpha)
+            assert np.array_equal(res[i][0], s1) and np.array_equal(res[i][1], g1)
+    finally:
+        for gr in grs:
+            gr.close()
