@@ -53,21 +53,28 @@ struct SelState {
 // E[v][r] = (label, size-at-label).  Uncovered size of v in sketch r is the
 // size field of the label's own entry, zeroed by MarkSeed.
 // Four row entries per lane are loaded before their label gathers, so a wave has
-// all of them in flight at once.
+// all of them in flight at once.  Entries are read as 64-bit words (label in the
+// low half) so they stay in registers: with uint2 locals the compiler turns the
+// "own entry or gathered entry" choice into a load through a selected address
+// and spills the row to per-lane scratch.
 __device__ __forceinline__ uint64_t marginal_full(const uint2 *__restrict__ E, uint32_t R, uint32_t v) {
     constexpr int U = 4;
-    const uint2 *row = E + (size_t)v * R;
+    const unsigned long long *row = reinterpret_cast<const unsigned long long *>(E + (size_t)v * R);
     uint64_t s = 0;
     for (uint32_t r0 = lane_id(); r0 < R; r0 += U * kWave) {
-        uint2 e[U];
+        unsigned long long e[U];
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             const uint32_t r = r0 + i * kWave;
-            e[i] = r < R ? row[r] : make_uint2(v, 0u);
+            e[i] = r < R ? row[r] : (unsigned long long)v;  // past R: own label, size 0
         }
         uint32_t y[U];
 #pragma unroll
-        for (int i = 0; i < U; ++i) y[i] = (e[i].x == v) ? e[i].y : E[(size_t)e[i].x * R + r0 + i * kWave].y;
+        for (int i = 0; i < U; ++i) {
+            const uint32_t lab = (uint32_t)e[i];
+            y[i] = (uint32_t)(e[i] >> 32);
+            if (lab != v) y[i] = E[(size_t)lab * R + r0 + i * kWave].y;
+        }
 #pragma unroll
         for (int i = 0; i < U; ++i) s += y[i];
     }
