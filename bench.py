@@ -648,5 +648,18 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def teardown():
+    """Leave nothing for exit handlers to release: the library's handles are closed by
+    the runs above; here torch's cached device blocks are returned and the device is
+    idle before the interpreter (and any profiler attached to it) shuts down."""
+    import gc
+    gc.collect()
+    torch = sys.modules.get("torch")
+    if torch is not None and torch.cuda.is_available():
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
+
 if __name__ == "__main__":
     main()
+    teardown()
