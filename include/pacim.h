@@ -187,6 +187,25 @@ im_status im_select_seeds(im_ctx *ctx, const im_graph *g, im_prob prob, uint32_t
 im_status im_influence(im_ctx *ctx, const im_graph *g, im_prob prob, const uint32_t *seeds, uint32_t k,
                        uint64_t sim_seed, uint32_t w0, uint32_t sims, uint64_t *total_out);
 
+/* im_influence for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * arguments, result and errors, but the call allocates nothing.  Its scratch
+ * (world keys, the seed list, the running total and the labelling forests of up
+ * to 64 worlds per pass) lives in one static device array of
+ * im_influence_static_scratch() bytes (64 MiB), held by every device the library
+ * runs on until the process ends; its device address is resolved once per device
+ * by im_ctx_create.  Limits: one world takes 12 bytes per vertex (rounded up to
+ * the sketch stride), so n is at most about 5.5 million, and 12 * n + 4 * k must
+ * fit the array; larger inputs, and IM_PROB_PER_EDGE (whose thresholds would need
+ * device memory), are rejected with EINVAL before any device work.  Every call
+ * on one device shares that device's array: calls that overlap on one device
+ * (two contexts or threads) race and must be serialised by the caller.  Each
+ * call initialises every part of the array it reads.  No profiling timers. */
+im_status im_influence_noalloc(im_ctx *ctx, const im_graph *g, im_prob prob, const uint32_t *seeds, uint32_t k,
+                               uint64_t sim_seed, uint32_t w0, uint32_t sims, uint64_t *total_out);
+/* Size in bytes of im_influence_noalloc's static device scratch. */
+im_status im_influence_static_scratch(size_t *max_bytes);
+
 /* ---- inspection (tests, measurement) -------------------------------------- */
 
 /* Sketch r as it was built (MarkSeed's zeroing not applied):

@@ -312,8 +312,8 @@ struct Prof {
     im_ctx *ctx;
     const char *name;
     hipEvent_t a = nullptr;
-    Prof(im_ctx *c, const char *nm, hipStream_t on = nullptr) : ctx(c), name(nm) {
-        if (ctx->profiling && (!on || on == ctx->stream)) {
+    Prof(im_ctx *c, const char *nm, hipStream_t on = nullptr, bool enabled = true) : ctx(c), name(nm) {
+        if (enabled && ctx->profiling && (!on || on == ctx->stream)) {
             a = take_event(ctx);
             if (a) (void)hipEventRecord(a, ctx->stream);
         }
@@ -415,6 +415,10 @@ uint32_t labelling_order(uint32_t n, const std::vector<uint64_t> &off, std::vect
 
 }  // namespace
 
+namespace {
+hipError_t static_scratch_on(int device, void **ptr);
+}  // namespace
+
 // ---------------------------------------------------------------- context
 extern "C" im_status im_ctx_create(int device, void *hip_stream, size_t hbm_cap, im_ctx **out) {
     if (!out) return IM_EINVAL;
@@ -427,6 +431,13 @@ extern "C" im_status im_ctx_create(int device, void *hip_stream, size_t hbm_cap,
     if (!ctx) return IM_ENOMEM;
     ctx->device = device;
     ctx->cap = hbm_cap;
+    {
+        // device address of the static scratch of im_influence_noalloc, resolved once
+        // per device here with the device current (a failure is kept and reported by
+        // that call)
+        void *sp = nullptr;
+        (void)static_scratch_on(device, &sp);
+    }
     if (hip_stream) {
         ctx->stream = static_cast<hipStream_t>(hip_stream);
     } else {
@@ -745,7 +756,7 @@ unsigned hook_grid_cap() {
 // in minc.
 void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const uint64_t *K, uint32_t b,
                      const CCScratch &cs, uint32_t *minc, uint32_t minc_init, const uint32_t *center_rank,
-                     bool init_isolated = true, hipStream_t st = nullptr) {
+                     bool init_isolated = true, hipStream_t st = nullptr, bool timed = true) {
     if (!st) st = ctx->stream;
     const uint32_t n = g->n;
     const unsigned hook_grid = grid_for(g->m_und, kHookBlock, hook_grid_cap());
@@ -755,7 +766,7 @@ void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const ui
     dim3 gi(std::max<uint32_t>((n_init + 255) / 256, 1u), b);
     k_batch_init<<<gi, 256, 0, st>>>(cs.parent, cs.cnt, minc, n, n_init, minc_init, center_rank);
     {
-        Prof p(ctx, "sample_hook", st);
+        Prof p(ctx, "sample_hook", st, timed);
         switch (pm.kind) {
         case kProbConstant:
             k_sample_hook<kProbConstant><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->iedges, g->m_und, K, b, pm, cs.parent, n);
@@ -777,7 +788,7 @@ void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const ui
         }
     }
     {
-        Prof p(ctx, "compress", st);
+        Prof p(ctx, "compress", st, timed);
         dim3 gc(std::min<unsigned>((n + 255) / 256, 64u), b);
         k_compress<<<gc, 256, 0, st>>>(cs.parent, cs.cnt, n, g->n_linked, center_rank, minc);
     }
@@ -1813,6 +1824,114 @@ extern "C" im_status im_influence(im_ctx *ctx, const im_graph *g, im_prob prob, 
     }
     cc_scratch_free(ctx, &cs);
     dev_free(ctx, blk, small);
+    if (e != hipSuccess) return fail(ctx, IM_EDEVICE, std::string("influence: ") + hipGetErrorString(e));
+    *total_out = host_total;
+    return IM_OK;
+}
+
+// ---------------------------------------------------------------- influence without allocation
+// im_influence's scratch (world keys, the seed list, the total and the labelling
+// forests parent/cnt/flag of B worlds) taken from one static device array instead
+// of the context's allocator.  Each device holds its own copy of the array, at its
+// own address, from when the code object is loaded there until the process ends;
+// the host-side name of the array is not a device address, so host code only ever
+// uses the per-device address that hipGetSymbolAddress returns.
+namespace {
+
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr int kStaticScratchDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kStaticScratchDevices] = {};
+hipError_t g_scratch_err[kStaticScratchDevices] = {};
+bool g_scratch_done[kStaticScratchDevices] = {};
+
+// Resolves the device address of `scratch` on `device` once (the device must be
+// current); later calls return the kept result.
+hipError_t static_scratch_on(int device, void **ptr) {
+    *ptr = nullptr;
+    if (device < 0 || device >= kStaticScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_err[device] = e;
+        g_scratch_ptr[device] = e == hipSuccess ? p : nullptr;
+        g_scratch_done[device] = true;
+        if (e != hipSuccess) (void)hipGetLastError();
+    }
+    *ptr = g_scratch_ptr[device];
+    return g_scratch_err[device];
+}
+
+__global__ void k_zero_u64(unsigned long long *p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
+}
+
+}  // namespace
+
+extern "C" im_status im_influence_static_scratch(size_t *max_bytes) {
+    if (!max_bytes) return IM_EINVAL;
+    *max_bytes = kStaticScratchBytes;
+    return IM_OK;
+}
+
+extern "C" im_status im_influence_noalloc(im_ctx *ctx, const im_graph *g, im_prob prob, const uint32_t *seeds,
+                                          uint32_t k, uint64_t sim_seed, uint32_t w0, uint32_t sims,
+                                          uint64_t *total_out) {
+    if (!ctx || !g || !total_out || (k && !seeds)) return IM_EINVAL;
+    if (g->ctx != ctx) return fail(ctx, IM_EINVAL, "graph belongs to another context");
+    if (const char *why = prob_problem(prob)) return fail(ctx, IM_EINVAL, why);
+    if (prob.kind == IM_PROB_PER_EDGE)
+        return fail(ctx, IM_EINVAL, "the per-edge model needs its thresholds on the device: use im_influence");
+    for (uint32_t i = 0; i < k; ++i)
+        if (seeds[i] >= g->n) return fail(ctx, IM_EINVAL, "seed vertex out of range");
+    if ((uint64_t)w0 + sims > 0xFFFFFFFFull) return fail(ctx, IM_EINVAL, "world range exceeds 2^32");
+    // layout: keys of one pass's worlds | seeds | total | parent, cnt, flag of B worlds
+    auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t head = a256((size_t)key_slots(64) * 8) + a256((size_t)k * 4) + 256;
+    const size_t per_world = sketch_stride(g->n) * 4 * 3;
+    if (head + per_world > kStaticScratchBytes)
+        return fail(ctx, IM_EINVAL, "n = " + std::to_string(g->n) + ", k = " + std::to_string(k) +
+                                        " need more than the " + std::to_string(kStaticScratchBytes >> 20) +
+                                        " MiB static scratch holds (one world takes 12 bytes per vertex)");
+    *total_out = 0;
+    if (k == 0 || sims == 0) return IM_OK;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    void *base = nullptr;
+    if (const hipError_t e = static_scratch_on(ctx->device, &base); e != hipSuccess)
+        return fail(ctx, IM_EDEVICE, std::string("static scratch address: ") + hipGetErrorString(e));
+    const uint32_t B = (uint32_t)std::min<size_t>({(size_t)64, (size_t)sims, (kStaticScratchBytes - head) / per_world});
+    char *b8 = static_cast<char *>(base);
+    uint64_t *K = reinterpret_cast<uint64_t *>(b8);
+    uint32_t *sd = reinterpret_cast<uint32_t *>(b8 + a256((size_t)key_slots(64) * 8));
+    unsigned long long *tot = reinterpret_cast<unsigned long long *>(b8 + a256((size_t)key_slots(64) * 8) +
+                                                                     a256((size_t)k * 4));
+    CCScratch cs;
+    cs.B = B;
+    cs.parent = reinterpret_cast<uint32_t *>(b8 + head);
+    cs.cnt = cs.parent + (size_t)B * sketch_stride(g->n);
+    cs.minc = cs.cnt + (size_t)B * sketch_stride(g->n);
+    hipStream_t st = ctx->stream;
+    const ProbDev pm = prob_dev(prob, g->off);
+    unsigned long long host_total = 0;
+    hipError_t e = hipMemcpyAsync(sd, seeds, (size_t)k * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        k_zero_u64<<<1, 64, 0, st>>>(tot);
+        for (uint32_t a = 0; a < sims; a += B) {
+            const uint32_t b = std::min(B, sims - a);
+            // keys of worlds w0 + a .. w0 + a + key_slots(b) - 1 (the sampling pass reads 8 at a time)
+            k_world_keys<<<1, 128, 0, st>>>(sim_seed, w0 + a, key_slots(b), K);
+            enqueue_cc_pass(ctx, g, pm, K, b, cs, cs.minc, 0u, nullptr, true, st, false);
+            k_influence_accum<<<dim3(grid_for(k, 256, 64), b), 256, 0, st>>>(cs.parent, cs.cnt, cs.minc, g->newid,
+                                                                            g->n, sd, k, tot);
+        }
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(&host_total, tot, 8, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
     if (e != hipSuccess) return fail(ctx, IM_EDEVICE, std::string("influence: ") + hipGetErrorString(e));
     *total_out = host_total;
     return IM_OK;

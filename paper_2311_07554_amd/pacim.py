@@ -87,6 +87,9 @@ _SIGS = {
     "im_select_seeds_ptree": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _u32p, _u64p]),
     "im_influence": (ctypes.c_int, [_vp, _vp, im_prob, _u32p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
                                     ctypes.c_uint32, _u64p]),
+    "im_influence_noalloc": (ctypes.c_int, [_vp, _vp, im_prob, _u32p, ctypes.c_uint32, ctypes.c_uint64,
+                                            ctypes.c_uint32, ctypes.c_uint32, _u64p]),
+    "im_influence_static_scratch": (ctypes.c_int, [ctypes.POINTER(ctypes.c_size_t)]),
     "im_select_seeds": (ctypes.c_int, [_vp, _vp, im_prob, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
                                        _u32p, _u64p]),
     "im_sketches_dump": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _u32p, _u32p]),
@@ -249,6 +252,23 @@ def im_influence(ctx, g, kind: int, p, seeds, sim_seed: int, w0: int, sims: int)
     _check(ctx, load().im_influence(ctx, g, _prob(kind, p), _u32(sd if sd.size else np.zeros(1, np.uint32)),
                                     int(sd.size), sim_seed & ((1 << 64) - 1), int(w0), int(sims), _u64(tot)))
     return int(tot[0])
+
+
+def im_influence_noalloc(ctx, g, kind: int, p, seeds, sim_seed: int, w0: int, sims: int) -> int:
+    sd = np.ascontiguousarray(seeds, dtype=np.uint32)
+    tot = np.zeros(1, dtype=np.uint64)
+    _check(ctx, load().im_influence_noalloc(ctx, g, _prob(kind, p), _u32(sd if sd.size else np.zeros(1, np.uint32)),
+                                            int(sd.size), sim_seed & ((1 << 64) - 1), int(w0), int(sims),
+                                            _u64(tot)))
+    return int(tot[0])
+
+
+def im_influence_static_scratch() -> int:
+    v = ctypes.c_size_t(0)
+    rc = load().im_influence_static_scratch(ctypes.byref(v))
+    if rc != IM_OK:
+        raise ImError(rc, "im_influence_static_scratch")
+    return int(v.value)
 
 
 def im_select_seeds(ctx, g, kind: int, p: float, R: int, k: int, seed: int):
@@ -431,6 +451,10 @@ class Graph:
     def influence(self, kind, p, seeds, sim_seed, w0=0, sims=20000):
         """Sum over simulated worlds [w0, w0 + sims) of the seeds' activated vertices."""
         return im_influence(self.ctx.h, self.h, kind, p, seeds, sim_seed, w0, sims)
+
+    def influence_noalloc(self, kind, p, seeds, sim_seed, w0=0, sims=20000):
+        """influence() through the allocation-free entry point (static device scratch)."""
+        return im_influence_noalloc(self.ctx.h, self.h, kind, p, seeds, sim_seed, w0, sims)
 
 
 class Sketches:
