@@ -99,9 +99,11 @@ im_status im_ctx_memory(const im_ctx *ctx, size_t *used, size_t *cap);
 /* Turns per-kernel HIP-event timing on (1) or off (0); see im_kernel_time. */
 im_status im_ctx_set_profiling(im_ctx *ctx, int on);
 /* Accumulated launches and milliseconds of one kernel family since profiling was
- * turned on: "sample_hook" (sampling and hooking pass), "compress" (pointer
- * jumping and counting), "emit" (full labels, or the compact triple and initial
- * gains), "select" (a whole im_select_seeds_from call); and the batched path's
+ * turned on: "init" (a labelling pass's forest set-up), "sample_hook" (sampling
+ * and hooking pass), "compress" (pointer jumping and counting), "emit" (full
+ * labels, or the compact triple and initial gains), "bulk_keys" (Marginal of every
+ * unselected vertex in a bulk round: from E, or from the largest-component
+ * bitmaps), "select" (a whole im_select_seeds_from call); and the batched path's
  * graph reuse: "batch_capture" (launches = graphs captured and instantiated) and
  * "batch_replay" (launches = batches that replayed the kept graph).  Unknown
  * names give count 0. */
@@ -355,6 +357,11 @@ im_status im_server_destroy(im_server *srv);
  * written, in bytes per second.  Allocates 2 GiB for the duration of the call.
  * Errors: ENOMEM, EDEVICE. */
 im_status im_probe_device(im_ctx *ctx, double *hash_per_s, double *copy_bytes_per_s);
+/* Measures the rate of independent 4-byte reads at pseudo-random places of a
+ * 4 GiB buffer (the access pattern of the union-find's parent lookups), in reads
+ * per second.  Allocates 4 GiB for the duration of the call.  Errors: ENOMEM,
+ * EDEVICE. */
+im_status im_probe_random(im_ctx *ctx, double *reads_per_s);
 
 #ifdef __cplusplus
 }

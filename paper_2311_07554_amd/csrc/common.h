@@ -38,6 +38,35 @@ __host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
+// mix64(x ^ k) for many keys k of one word x: its first step, z ^= z >> 30, is
+// linear over xor, so (x ^ k) ^ ((x ^ k) >> 30) = xs30(x) ^ xs30(k).  A sampling
+// loop takes xs30(x) once per edge and xs30(k) once per sketch key (wave-uniform:
+// scalar instructions), and each hash starts at the multiply.
+__host__ __device__ __forceinline__ uint64_t xs30(uint64_t z) { return z ^ (z >> 30); }
+// xs30 of a wave-uniform key, kept in scalar registers and hidden from the
+// compiler's algebra (it would otherwise fold xs30(x) ^ xs30(k) back into
+// xs30(x ^ k), one vector shift per hash again).
+__device__ __forceinline__ uint64_t xs30_key(uint64_t k) {
+    uint64_t z = xs30(k);
+    asm volatile("" : "+s"(z));
+    return z;
+}
+__host__ __device__ __forceinline__ uint64_t mix64_from_xs30(uint64_t z) {
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// A loaded value made opaque to the compiler, so that a load issued
+// unconditionally (inactive lanes reading a harmless entry) stays unconditional:
+// otherwise the compiler turns "load, then select" back into a branch around the
+// load and waits for each load inside its branch.
+__device__ __forceinline__ uint32_t pin_vgpr(uint32_t x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // K(seed, x): per-sketch (or per-salt) key of the live-edge hash.
 __host__ __device__ __forceinline__ uint64_t sketch_key(uint64_t seed, uint64_t x) { return mix64(seed * kPhi + x); }
 

@@ -1,5 +1,5 @@
 // CompactSketch evaluation (Sec. 3): Marginal(S, v) = sum_r delta_r with
-// <delta_r, l> = GetCenter(Phi_r, v, S), and MarkSeed zeroing size_c[r][l].
+// <delta_r, l> = GetCenter(Phi_r, v, S), and MarkSeed zeroing size_c of (r, l).
 //
 // GetCenter is a BFS from v over the live edges of sketch r that stops at the
 // first center it reaches (delta = size_c[label_c[center]], the CC's size or 0
@@ -32,10 +32,13 @@ struct GraphDev {
     const uint32_t *cols;
 };
 
+struct CompactDev;
+__device__ __forceinline__ size_t tri_at(const CompactDev &cd, uint32_t r, uint32_t i);
+
 struct CompactDev {
     const uint32_t *center_rank;   // [n], rank or kNone
-    const uint32_t *label_c;       // [R][rho]
-    uint32_t *size_c;              // [R][rho]
+    const uint32_t *label_c;       // [rho][R] (center-major: a center's R entries are contiguous)
+    uint32_t *size_c;              // [rho][R]
     uint32_t rho;
     uint64_t kc, Ta;               // center test: mix64(v ^ kc) < Ta (a hash, no memory access)
     unsigned long long *memo;      // [slots][R][2] kept GetCenter results (below), ~0 if empty
@@ -45,6 +48,9 @@ struct CompactDev {
                                    // vertex is m holds a seed (set by MarkSeed)
     uint32_t nw;                   // 64-bit words per sketch, ceil(n / 64)
 };
+
+// Entry of sketch r and center rank i in label_c / size_c.
+__device__ __forceinline__ size_t tri_at(const CompactDev &cd, uint32_t r, uint32_t i) { return (size_t)i * cd.R + r; }
 
 // What GetCenter finds from (v, r) never changes (a sketch's components are
 // fixed; only their compact sizes are zeroed and seeds are added), so results are
@@ -88,9 +94,8 @@ __device__ __forceinline__ uint32_t hs_slot(uint32_t w) { return (w * 0x9E3779B1
 static_assert(kHCap == 1024, "hs_slot assumes 2^10 slots");
 
 __device__ __forceinline__ BfsOut center_hit(const CompactDev &cd, uint32_t r, uint32_t rank) {
-    const size_t row = (size_t)r * cd.rho;
-    const uint32_t l = cd.label_c[row + rank];
-    return BfsOut{cd.size_c[row + l], l, false, 0};
+    const uint32_t l = cd.label_c[tri_at(cd, r, rank)];
+    return BfsOut{cd.size_c[tri_at(cd, r, l)], l, false, 0};
 }
 
 // GetCenter with the queue and visited set in LDS (q: kQCap, hs: kHCap words).
@@ -227,7 +232,7 @@ __device__ __forceinline__ bool memo_read(const CompactDev &cd, uint32_t v, uint
     if ((uint32_t)(x >> 32) != v) return false;
     const uint32_t p = (uint32_t)x;
     if (!(p & kMemoNoCenter)) {
-        *o = BfsOut{cd.size_c[(size_t)r * cd.rho + p], p, false, 0, 0, 0};
+        *o = BfsOut{cd.size_c[tri_at(cd, r, p)], p, false, 0, 0, 0};
         return true;
     }
     const unsigned long long y = __hip_atomic_load(&e[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -342,7 +347,7 @@ __device__ __forceinline__ void overflow_level(int mode, uint32_t slot, SelState
         if (lane_id() == 0) {
             if (o.visits) atomicAdd(&st->visits, (unsigned long long)o.visits);
             if (mode == 0) add_delta(st, partial, t.x, o.delta, evl, kb, in_s, key);
-            else if (o.label != kNone) cd.size_c[(size_t)r * cd.rho + o.label] = 0;
+            else if (o.label != kNone) cd.size_c[tri_at(cd, r, o.label)] = 0;
             else covmin_mark(cd, r, o.ccmin);
         }
     }
@@ -359,7 +364,7 @@ __device__ __forceinline__ void markseed_compact_level(SelState *st, const Graph
         if (lane_id() == 0) {
             if (o.visits) atomicAdd(&st->visits, (unsigned long long)o.visits);
             if (o.overflow) push_overflow(st, &st->ov_cnt[kMaxLevels + 1], mark_list(ov, ov_cap), ov_cap / 2, s, r);
-            else if (o.label != kNone) cd.size_c[(size_t)r * cd.rho + o.label] = 0;
+            else if (o.label != kNone) cd.size_c[tri_at(cd, r, o.label)] = 0;
             else covmin_mark(cd, r, o.ccmin);
         }
     }
@@ -389,7 +394,7 @@ __device__ __forceinline__ void markseed_eval_root_level(SelState *st, const uin
             continue;
         }
         if (lane_id() == 0) {
-            if (m.label != kNone) cd.size_c[(size_t)r * cd.rho + m.label] = 0;
+            if (m.label != kNone) cd.size_c[tri_at(cd, r, m.label)] = 0;
             else covmin_mark(cd, r, m.ccmin);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -551,7 +556,8 @@ __device__ uint32_t component_global(const GraphDev &g, const ProbDev &pm, uint6
 // One 64-thread block per queue/bitmap slot, sketches r = slot, slot + grid, ...:
 // covered[r] = [some seed lies in r's largest component]; sub[w] += |C| for every
 // vertex w of every other covered component C.  *abort = 1 if a sketch's
-// searches passed cap vertices.
+// searches passed cap vertices.  Bitmaps are word-major: bit v of sketch r is bit
+// v % 64 of gbits[(v / 64) * R + r].
 __global__ void __launch_bounds__(64) k_bulk_bits_search(const SelState *__restrict__ st,
                                                          const uint32_t *__restrict__ seeds, GraphDev g, ProbDev pm,
                                                          const uint64_t *__restrict__ K, uint32_t R, uint32_t n,
@@ -565,12 +571,11 @@ __global__ void __launch_bounds__(64) k_bulk_bits_search(const SelState *__restr
     uint32_t *gq = slot_q + (size_t)blockIdx.x * n;
     uint32_t *gvis = slot_vis + (size_t)blockIdx.x * ((n + 31) / 32);
     for (uint32_t r = blockIdx.x; r < R; r += gridDim.x) {
-        const uint64_t *bits = gbits + (size_t)r * nw;
         bool giant = false;
         uint32_t tail = 0;
         for (uint32_t j = 0; j < ns && tail <= cap; ++j) {
             const uint32_t s = seeds[j];
-            if ((bits[s >> 6] >> (s & 63)) & 1ull) {
+            if ((gbits[(size_t)(s >> 6) * R + r] >> (s & 63)) & 1ull) {
                 giant = true;
                 continue;
             }
@@ -596,12 +601,17 @@ __global__ void __launch_bounds__(64) k_bulk_bits_search(const SelState *__restr
 }
 
 // Fresh keys of every vertex from the bitmaps (nothing if *abort_flag); the
-// round's evaluation count is every unselected vertex.  One wave per 64-vertex
-// bitmap word: lane l loads the word and covered size of sketches r0 + l, and
-// every lane then walks them with lane reads (no memory latency per sketch).
+// round's evaluation count is every unselected vertex.  c(v) = sum over sketches r
+// whose largest component is covered (covered[r]) of [v in it] * its size.  One
+// wave per 64-vertex bitmap word.  gsum[v] holds the same sum over every sketch,
+// so when most largest components are covered the wave subtracts the uncovered
+// ones from it, else it adds the covered ones: lane l loads the word of sketch
+// r0 + l (the R words of one vertex word are contiguous), and the wave walks only
+// the sketches of the smaller set with lane reads.
 __global__ void __launch_bounds__(256) k_bulk_bits_keys(SelState *__restrict__ st, const uint64_t *__restrict__ gain0,
                                                         const unsigned long long *__restrict__ sub,
                                                         const uint64_t *__restrict__ gbits, uint32_t nw,
+                                                        const uint64_t *__restrict__ gsum,
                                                         const uint8_t *__restrict__ covered,
                                                         const unsigned long long *__restrict__ gbest, uint32_t R,
                                                         uint32_t n, uint32_t kb, const uint8_t *__restrict__ in_s,
@@ -611,27 +621,37 @@ __global__ void __launch_bounds__(256) k_bulk_bits_keys(SelState *__restrict__ s
     const uint32_t lane = lane_id();
     const uint32_t w = wave_index();
     if (w >= nw) return;
+    uint32_t ncov = 0;
+    for (uint32_t r0 = 0; r0 < R; r0 += kWave) {
+        const uint32_t r = r0 + lane;
+        ncov += (uint32_t)__popcll(__ballot(r < R && covered[r]));
+    }
+    const bool subtract = 2 * ncov >= R;  // wave-uniform
+    const uint32_t v = w * kWave + lane;
     uint64_t c = 0;
     for (uint32_t r0 = 0; r0 < R; r0 += kWave) {
         const uint32_t r = r0 + lane;
+        const bool cov = r < R && covered[r];
+        const bool walk = r < R && (subtract ? !cov : cov);
         uint32_t lo = 0, hi = 0, mult = 0;
-        if (r < R && covered[r]) {
-            const uint64_t word = gbits[(size_t)r * nw + w];
+        if (walk) {
+            const uint64_t word = gbits[(size_t)w * R + r];
             lo = (uint32_t)word;
             hi = (uint32_t)(word >> 32);
             mult = giant_size_of(gbest[r]);
         }
-        const uint32_t cntr = min((uint32_t)kWave, R - r0);
-        for (uint32_t i = 0; i < cntr; ++i) {
-            const uint32_t m = (uint32_t)__builtin_amdgcn_readlane((int)mult, (int)i);
-            if (m == 0) continue;
-            const uint32_t wlo = (uint32_t)__builtin_amdgcn_readlane((int)lo, (int)i);
-            const uint32_t whi = (uint32_t)__builtin_amdgcn_readlane((int)hi, (int)i);
-            if ((((lane < 32) ? wlo : whi) >> (lane & 31)) & 1u) c += m;
+        for (uint64_t m = __ballot(walk && mult != 0); m; m &= m - 1ull) {
+            const int i = (int)__builtin_ctzll(m);
+            const uint32_t mu = (uint32_t)__builtin_amdgcn_readlane((int)mult, i);
+            const uint32_t wlo = (uint32_t)__builtin_amdgcn_readlane((int)lo, i);
+            const uint32_t whi = (uint32_t)__builtin_amdgcn_readlane((int)hi, i);
+            if ((((lane < 32) ? wlo : whi) >> (lane & 31)) & 1u) c += mu;
         }
     }
-    const uint32_t v = w * kWave + lane;
-    if (v < n) key[v] = in_s[v] ? 0ull : pack_key(gain0[v] - sub[v] - c, v, kb);
+    if (v < n) {
+        const uint64_t cv = subtract ? gsum[v] - c : c;
+        key[v] = in_s[v] ? 0ull : pack_key(gain0[v] - sub[v] - cv, v, kb);
+    }
     if (v == 0) {
         for (int l = 0; l <= kMaxLevels; ++l) { st->fr_cnt[l] = 0; st->ev_cnt[l] = 0; }
         for (int l = 0; l < kMaxLevels + 2; ++l) st->ov_cnt[l] = 0;

@@ -10,7 +10,10 @@
 //             R consecutive entries per vertex so one evaluation reads 8R bytes
 //             in one contiguous run, and the size lookup of a singleton CC is the
 //             entry itself
-//   compact   center_rank u32[n], centers u32[rho], label_c u32[R][rho], size_c u32[R][rho]
+//   compact   center_rank u32[n], centers u32[rho], label_c u32[rho][R], size_c u32[rho][R]
+//             (center-major);
+//             each sketch's largest component: gbits u64[n/64][R] membership bitmaps
+//             (word-major), gsum u64[n] the sizes of those holding each vertex
 //   selection key u64[n], in_s u8[n], gain0 u64[n], tree ids u32[~n/63],
 //             frontier u32[~n/63], eval list u32[n], partial sums u64[n]
 //   scratch   parent/cnt(/minc) u32[B][n] for B sketches per pass, freed after the build
@@ -114,6 +117,7 @@ struct im_sketches {
     uint32_t *center_rank = nullptr, *centers = nullptr, *label_c = nullptr, *size_c = nullptr;
     uint32_t *size_c0 = nullptr;  // size_c as built (dump); only kept for small sketches
     uint64_t *gain0 = nullptr, *key = nullptr;
+    uint64_t *gsum = nullptr;  // CompactSketch: per vertex, the sizes of the largest components holding it
     uint8_t *in_s = nullptr;
     TreeDesc td{};
     uint32_t *ids = nullptr, *fr = nullptr, *evl = nullptr;
@@ -131,7 +135,7 @@ struct im_sketches {
     uint32_t bulk_rounds = 0;
     PersistCtl *ctl = nullptr;         // step hand-off of the persistent selection kernel
     // CompactSketch: each sketch's largest component (bulk rounds without re-sampling)
-    uint64_t *gbits = nullptr;         // [R][nw] membership bitmaps
+    uint64_t *gbits = nullptr;         // [nw][R] membership bitmaps (word-major)
     uint32_t nw = 0;                   // 64-bit words per bitmap
     unsigned long long *gbest = nullptr;  // [R] (size << 32) | (2^32 - 1 - root) of the largest
     uint8_t *gcov = nullptr;           // [R] largest component covered by a seed
@@ -764,7 +768,10 @@ void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const ui
     // later, unless a caller flags seeds in minc)
     const uint32_t n_init = init_isolated ? n : g->n_linked;
     dim3 gi(std::max<uint32_t>((n_init + 255) / 256, 1u), b);
-    k_batch_init<<<gi, 256, 0, st>>>(cs.parent, cs.cnt, minc, n, n_init, minc_init, center_rank);
+    {
+        Prof p(ctx, "init", st, timed);
+        k_batch_init<<<gi, 256, 0, st>>>(cs.parent, cs.cnt, minc, n, n_init, minc_init, center_rank);
+    }
     {
         Prof p(ctx, "sample_hook", st, timed);
         switch (pm.kind) {
@@ -789,7 +796,7 @@ void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const ui
     }
     {
         Prof p(ctx, "compress", st, timed);
-        dim3 gc(std::min<unsigned>((n + 255) / 256, 64u), b);
+        dim3 gc(std::min<unsigned>((n + 256 * kCompressIlp - 1) / (256 * kCompressIlp), 64u), b);
         k_compress<<<gc, 256, 0, st>>>(cs.parent, cs.cnt, n, g->n_linked, center_rank, minc);
     }
 }
@@ -959,6 +966,8 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
         SK_TRY(sk_alloc(s, (size_t)R * std::max<uint32_t>(rho, 1), &s->size_c));
         s->nw = (n + 63) / 64;
         SK_TRY(sk_alloc(s, (size_t)R * s->nw, &s->gbits));
+        SK_TRY(sk_alloc(s, n, &s->gsum));
+        SK_HIP(hipMemsetAsync(s->gsum, 0, (size_t)n * 8, st));
         SK_TRY(sk_alloc(s, R, &s->gbest));
         SK_HIP(hipMemsetAsync(s->gbest, 0, (size_t)R * 8, st));
         SK_TRY(sk_alloc(s, R, &s->gcov));
@@ -987,11 +996,11 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
         const uint32_t b = std::min(B, R - r0);
         enqueue_cc_pass(ctx, g, s->pm, s->K + r0, b, cs, minc, kNone, s->compact ? cs.crank : nullptr, r0 == 0);
         if (s->compact) {
-            Prof p(ctx, "emit");
             k_giant_sample<<<b, 256, 0, st>>>(parent, cnt, n, s->gbest + r0);
-            k_gain0_emit<<<(n + 255) / 256, 256, 0, st>>>(parent, cnt, minc, s->center_rank, s->rho, n, b, r0,
-                                                          s->label_c, s->size_c, s->gain0, s->gbest + r0,
-                                                          s->gbits + (size_t)r0 * s->nw, s->nw, g->newid,
+            Prof p(ctx, "emit");
+            k_gain0_emit<<<(n + kWave - 1) / kWave, 256, 0, st>>>(parent, cnt, minc, s->center_rank, s->rho, n, b, r0,
+                                                          R, s->label_c, s->size_c, s->gain0, s->gbest + r0,
+                                                          s->gbits, s->nw, s->gsum, g->newid,
                                                           g->n_linked);
         } else {
             Prof p(ctx, "emit");
@@ -1248,7 +1257,9 @@ im_status enqueue_bulk_keys(im_sketches *s) {
         HIP_TRY(ctx, hipMemcpyAsync(&aborted, s->bulk_abort, 4, hipMemcpyDeviceToHost, st));
         HIP_TRY(ctx, hipStreamSynchronize(st));
         if (!aborted) {
-            k_bulk_bits_keys<<<(s->nw + 3) / 4, 256, 0, st>>>(s->st, s->gain0, s->partial, s->gbits, s->nw, s->gcov,
+            Prof p(ctx, "bulk_keys");
+            k_bulk_bits_keys<<<(s->nw + 3) / 4, 256, 0, st>>>(s->st, s->gain0, s->partial, s->gbits, s->nw, s->gsum,
+                                                              s->gcov,
                                                               s->gbest, s->R, n, s->kb, s->in_s, s->key, s->bulk_abort);
             HIP_TRY(ctx, hipGetLastError());
             return IM_OK;
@@ -1289,7 +1300,10 @@ im_status enqueue_bulk_round(im_sketches *s) {
 im_status enqueue_full_bulk_round(im_sketches *s) {
     hipStream_t st = s->ctx->stream;
     const TreeDesc &td = s->td;
-    k_bulk_full_keys<<<wave_grid(s->n, 65536), 256, 0, st>>>(s->st, s->E, s->R, s->n, s->kb, s->in_s, s->key);
+    {
+        Prof p(s->ctx, "bulk_keys");
+        k_bulk_full_keys<<<wave_grid(s->n, 65536), 256, 0, st>>>(s->st, s->E, s->R, s->n, s->kb, s->in_s, s->key);
+    }
     for (int l = (int)td.D - 1; l >= 0; --l)
         k_tree_build_level<<<wave_grid(td.lvl_n[l], 8192), 256, 0, st>>>(td, (uint32_t)l, s->ids, s->key);
     k_round_end<<<1, 64, 0, st>>>(td, s->st, s->ids, s->key, s->in_s, s->kb, s->seeds_d, s->gains_d, s->evals_d,
@@ -1949,6 +1963,16 @@ __global__ void k_dump_full(const uint2 *__restrict__ E, uint32_t n, uint32_t R,
     siz[v] = E[(size_t)e.x * R + r].y;
 }
 
+// Sketch r of a CompactSketch triple (center-major) as two rho-long rows.
+__global__ void k_dump_compact(const uint32_t *__restrict__ label_c, const uint32_t *__restrict__ size_c,
+                               uint32_t rho, uint32_t R, uint32_t r, uint32_t *__restrict__ lab,
+                               uint32_t *__restrict__ siz) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rho) return;
+    lab[i] = label_c[(size_t)i * R + r];
+    siz[i] = size_c[(size_t)i * R + r];
+}
+
 }  // namespace
 
 extern "C" im_status im_sketches_dump(im_ctx *ctx, const im_sketches *s, uint32_t r, uint32_t *labels,
@@ -1978,8 +2002,17 @@ extern "C" im_status im_sketches_dump(im_ctx *ctx, const im_sketches *s, uint32_
         return IM_OK;
     }
     if (s->rho) {
-        HIP_TRY(ctx, hipMemcpyAsync(labels, s->label_c + (size_t)r * s->rho, (size_t)s->rho * 4, hipMemcpyDeviceToHost, st));
-        HIP_TRY(ctx, hipMemcpyAsync(sizes, s->size_c + (size_t)r * s->rho, (size_t)s->rho * 4, hipMemcpyDeviceToHost, st));
+        uint32_t *tmp = nullptr;
+        im_status a = dev_alloc(ctx, (size_t)s->rho * 8, (void **)&tmp);
+        if (a != IM_OK) return a;
+        k_dump_compact<<<(s->rho + 255) / 256, 256, 0, st>>>(s->label_c, s->size_c, s->rho, s->R, r, tmp,
+                                                              tmp + s->rho);
+        hipError_t e1 = hipMemcpyAsync(labels, tmp, (size_t)s->rho * 4, hipMemcpyDeviceToHost, st);
+        hipError_t e2 = hipMemcpyAsync(sizes, tmp + s->rho, (size_t)s->rho * 4, hipMemcpyDeviceToHost, st);
+        hipError_t e3 = hipStreamSynchronize(st);
+        dev_free(ctx, tmp, (size_t)s->rho * 8);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return fail(ctx, IM_EDEVICE, "dump copy failed");
+        return IM_OK;
     }
     HIP_TRY(ctx, hipStreamSynchronize(st));
     return IM_OK;
@@ -2091,6 +2124,45 @@ extern "C" im_status im_probe_device(im_ctx *ctx, double *hash_per_s, double *co
     if (rc != IM_OK) return rc;
     *hash_per_s = best_hash;
     *copy_bytes_per_s = best_copy;
+    return IM_OK;
+}
+
+extern "C" im_status im_probe_random(im_ctx *ctx, double *reads_per_s) {
+    if (!ctx || !reads_per_s) return IM_EINVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const size_t bytes = (size_t)4 << 30;  // far beyond L2 and the 256 MB last-level cache
+    void *a = nullptr, *b = nullptr;
+    im_status rc = dev_alloc(ctx, bytes, &a);
+    if (rc == IM_OK) rc = dev_alloc(ctx, 256, &b);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == IM_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = fail(ctx, IM_EDEVICE, "hipEventCreate failed");
+    double best = 0;
+    if (rc == IM_OK) {
+        (void)hipMemsetAsync(a, 0x01, bytes, st);
+        const unsigned blocks = 256 * 8;
+        const uint32_t per = 256;
+        for (int rep = 0; rep < 4; ++rep) {
+            (void)hipEventRecord(e0, st);
+            k_probe_gather<<<blocks, 256, 0, st>>>(static_cast<const uint32_t *>(a), bytes / 4, per,
+                                                   static_cast<unsigned long long *>(b));
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep && ms > 0) best = std::max(best, (double)blocks * 256 * per / (ms * 1e-3));
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) rc = fail(ctx, IM_EDEVICE, std::string("probe: ") + hipGetErrorString(e));
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(st);
+    dev_free(ctx, a, bytes);
+    dev_free(ctx, b, 256);
+    if (rc != IM_OK) return rc;
+    *reads_per_s = best;
     return IM_OK;
 }
 

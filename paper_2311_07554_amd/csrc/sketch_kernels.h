@@ -11,7 +11,7 @@
 //                     smallest rank recorded at the root (CompactSketch)
 //   k_emit_full       (label, size) per (v, r) into E[n][R] and the initial gains
 //   k_giant_sample    per sketch, the largest component among sampled vertices'
-//   k_gain0_emit      CompactSketch: the triple label_c / size_c [R][rho], the
+//   k_gain0_emit      CompactSketch: the triple label_c / size_c [rho][R], the
 //                     initial gains and that component's membership bitmap, in
 //                     one pass over the vertices
 //   k_center_*        hashed Bernoulli(alpha) centers, ranked by id
@@ -153,11 +153,12 @@ __device__ __forceinline__ uint64_t live_mask(uint32_t u, uint32_t v, uint64_t x
     const uint64_t T = edge_threshold_of<KIND>(pm, u, v, x, e);
     const uint64_t all = B >= 64 ? ~0ull : ((1ull << B) - 1ull);
     if (T == kAllLive) return all;
+    const uint64_t xp = xs30(x);
     uint64_t live = 0;
     for (uint32_t b0 = 0; b0 < B; b0 += 8) {
         uint32_t chunk = 0;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) chunk |= (mix64(x ^ K[b0 + j]) < T) ? (1u << j) : 0u;
+        for (int j = 0; j < 8; ++j) chunk |= (mix64_from_xs30(xp ^ xs30_key(K[b0 + j])) < T) ? (1u << j) : 0u;
         live |= (uint64_t)chunk << b0;
     }
     return live & all;
@@ -214,12 +215,15 @@ __global__ void __launch_bounds__(kHookBlock) k_sample_hook(const uint2 *__restr
 
 // grid: (G, B), block 256: the blocks of sketch blockIdx.y stride over its
 // first n_act numbers (the vertices with an edge; an isolated vertex stays its
-// own root with no members and its own center rank).  In social-like graphs almost every non-root vertex of a sketch lies
-// in one giant component, so per-vertex atomics on its root counter serialise.
-// Each wave therefore keeps the first root it meets as a "hot" root whose member
-// count and smallest center rank it accumulates in registers and flushes once at
-// the end; members of other roots are combined per distinct root in the wave
-// and added with one atomic per root.
+// own root with no members and its own center rank).  A wave takes 4 x 64
+// consecutive numbers per step, issuing the four parent loads (and root walks)
+// together before counting.  In social-like graphs almost every non-root vertex
+// of a sketch lies in one giant component, so per-vertex atomics on its root
+// counter serialise.  Each wave therefore keeps the first root it meets as a
+// "hot" root whose member count and smallest center rank it accumulates in
+// registers and flushes once at the end; members of other roots are combined per
+// distinct root in the wave and added with one atomic per root.
+constexpr uint32_t kCompressIlp = 4;
 __global__ void __launch_bounds__(256) k_compress(uint32_t *__restrict__ parent, uint32_t *__restrict__ cnt,
                                                   uint32_t n, uint32_t n_act,
                                                   const uint32_t *__restrict__ center_rank,
@@ -228,47 +232,62 @@ __global__ void __launch_bounds__(256) k_compress(uint32_t *__restrict__ parent,
     const size_t base = (size_t)blockIdx.y * sketch_stride(n);
     uint32_t *P = parent + base;
     uint32_t hot = kNone, hot_cnt = 0, hot_min = kNone;  // wave-uniform
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t v0 = blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); v0 < n_act; v0 += stride) {
-        const uint32_t v = v0 + lane;
-        const bool valid = v < n_act;
-        uint32_t r = v;
-        if (valid) {
-            uint32_t p = P[v];
+    const uint32_t stride = gridDim.x * blockDim.x * kCompressIlp;
+    const uint32_t wbase = (blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1))) * kCompressIlp;
+    for (uint32_t v0 = wbase; v0 < n_act; v0 += stride) {
+        uint32_t rr[kCompressIlp], pp[kCompressIlp], cc[kCompressIlp];
+#pragma unroll
+        for (uint32_t j = 0; j < kCompressIlp; ++j) {
+            const uint32_t v = v0 + j * kWave + lane;
+            rr[j] = v;
+            pp[j] = v < n_act ? P[v] : v;
+            if (center_rank) cc[j] = center_rank[v < n_act ? v : 0];
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kCompressIlp; ++j) {
+            const uint32_t v = v0 + j * kWave + lane;
+            uint32_t r = rr[j], p = pp[j];
             while (p != r) { r = p; p = P[r]; }
-            if (r != v) P[v] = r;
+            if (r != v && v < n_act) P[v] = r;
+            rr[j] = r;
         }
-        bool need = valid && r != v;
-        if (hot == kNone) {
-            const uint64_t m = __ballot(need);
-            if (m) hot = __shfl(r, (int)__builtin_ctzll(m));
-        }
-        const bool in_hot = need && r == hot;
-        hot_cnt += (uint32_t)__popcll(__ballot(in_hot));
-        if (in_hot) need = false;
-        for (uint64_t m = __ballot(need); m; m = __ballot(need)) {
-            const uint32_t lr = __shfl(r, (int)__builtin_ctzll(m));
-            const bool same = need && r == lr;
-            const uint64_t sm = __ballot(same);
-            if (lane == (uint32_t)__builtin_ctzll(m)) atomicAdd(cnt + base + lr, (uint32_t)__popcll(sm));
-            if (same) need = false;
-        }
-        if (center_rank) {
-            const uint32_t cr = valid ? center_rank[v] : kNone;
-            bool cneed = cr != kNone && r != v;  // a root's own rank is already in minc
-            uint32_t hm = (cneed && r == hot) ? cr : kNone;
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) hm = min(hm, (uint32_t)__shfl_xor(hm, off));
-            hot_min = min(hot_min, hm);
-            if (r == hot) cneed = false;
-            for (uint64_t m = __ballot(cneed); m; m = __ballot(cneed)) {
+        for (uint32_t j = 0; j < kCompressIlp; ++j) {
+            const uint32_t v = v0 + j * kWave + lane;
+            const bool valid = v < n_act;
+            const uint32_t r = rr[j];
+            bool need = valid && r != v;
+            if (hot == kNone) {
+                const uint64_t m = __ballot(need);
+                if (m) hot = __shfl(r, (int)__builtin_ctzll(m));
+            }
+            const bool in_hot = need && r == hot;
+            hot_cnt += (uint32_t)__popcll(__ballot(in_hot));
+            if (in_hot) need = false;
+            for (uint64_t m = __ballot(need); m; m = __ballot(need)) {
                 const uint32_t lr = __shfl(r, (int)__builtin_ctzll(m));
-                const bool same = cneed && r == lr;
-                uint32_t mn = same ? cr : kNone;
+                const bool same = need && r == lr;
+                const uint64_t sm = __ballot(same);
+                if (lane == (uint32_t)__builtin_ctzll(m)) atomicAdd(cnt + base + lr, (uint32_t)__popcll(sm));
+                if (same) need = false;
+            }
+            if (center_rank) {
+                const uint32_t cr = valid ? pin_vgpr(cc[j]) : kNone;
+                bool cneed = cr != kNone && r != v;  // a root's own rank is already in minc
+                uint32_t hm = (cneed && r == hot) ? cr : kNone;
 #pragma unroll
-                for (int off = 32; off > 0; off >>= 1) mn = min(mn, (uint32_t)__shfl_xor(mn, off));
-                if (lane == (uint32_t)__builtin_ctzll(m)) atomicMin(minc + base + lr, mn);
-                if (same) cneed = false;
+                for (int off = 32; off > 0; off >>= 1) hm = min(hm, (uint32_t)__shfl_xor(hm, off));
+                hot_min = min(hot_min, hm);
+                if (r == hot) cneed = false;
+                for (uint64_t m = __ballot(cneed); m; m = __ballot(cneed)) {
+                    const uint32_t lr = __shfl(r, (int)__builtin_ctzll(m));
+                    const bool same = cneed && r == lr;
+                    uint32_t mn = same ? cr : kNone;
+#pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) mn = min(mn, (uint32_t)__shfl_xor(mn, off));
+                    if (lane == (uint32_t)__builtin_ctzll(m)) atomicMin(minc + base + lr, mn);
+                    if (same) cneed = false;
+                }
             }
         }
     }
@@ -361,56 +380,132 @@ __global__ void __launch_bounds__(256) k_giant_sample(const uint32_t *__restrict
 // One pass over every vertex of the pass's B sketches (compressed: parent[b][v] is
 // v's root) for CompactSketch:
 //   - the initial gains, sum over sketches of |CC_b(v)|;
-//   - gbits non-null: bit v of gbits[b][v / 64] = [v lies in the component of
-//     giant_root_of(gbest[b])];
-//   - for a center v of rank cr, its triple entries label_c[r0 + b][cr] = the
+//   - gbits non-null: bit v % 64 of gbits[(v / 64) * R + r0 + b] = [v lies in the
+//     component of giant_root_of(gbest[b])] (word-major: a vertex word's R
+//     sketches are contiguous), and gsum[v] += the sizes of those components over
+//     the pass's sketches (the bulk rounds' sum over covered largest components
+//     starts from it);
+//   - for a center v of rank cr, its triple entries label_c[cr][r0 + b] = the
 //     smallest center rank in its component (minc at the root) and size_c = the
-//     component size if that rank is cr's own, else 0.
+//     component size if that rank is cr's own, else 0 (center-major [rho][R]).
+// A workgroup takes 64 consecutive vertices (one per lane) and its four waves
+// split the sketches (wave w: b = w, w + 4, ...), so a lane issues the root loads
+// of up to 16 sketches before the first size gather; the waves' gain sums meet
+// in LDS.  The block's centers have consecutive ranks, so their triple entries
+// of the pass are runs of B words, one per center: up to 16 centers are staged in
+// LDS and written out with one lane per sketch (a block with more centers, rare
+// for alpha < 1/4, writes them directly); the largest-component bitmap words of
+// the block (B contiguous words) are staged the same way.  B <= 64.
+constexpr uint32_t kG0Waves = 4;
+constexpr uint32_t kG0PerWave = 64 / kG0Waves;
+constexpr uint32_t kG0StageCenters = 16;
 __global__ void __launch_bounds__(256) k_gain0_emit(const uint32_t *__restrict__ parent,
                                                     const uint32_t *__restrict__ cnt,
                                                     const uint32_t *__restrict__ minc,
                                                     const uint32_t *__restrict__ center_rank, uint32_t rho,
-                                                    uint32_t n, uint32_t B, uint32_t r0,
+                                                    uint32_t n, uint32_t B, uint32_t r0, uint32_t R,
                                                     uint32_t *__restrict__ label_c, uint32_t *__restrict__ size_c,
                                                     uint64_t *__restrict__ gain0,
                                                     const unsigned long long *__restrict__ gbest,
                                                     uint64_t *__restrict__ gbits, uint32_t nw,
+                                                    uint64_t *__restrict__ gsum,
                                                     const uint32_t *__restrict__ newid, uint32_t n_linked) {
-    constexpr uint32_t U = 4;  // sketches whose root and size loads are issued together (8 was slower)
-    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ unsigned long long part[kG0Waves][kWave], gpart[kG0Waves][kWave], gword[kWave];
+    __shared__ uint32_t tl[kG0StageCenters][kWave + 1], ts[kG0StageCenters][kWave + 1];
+    const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
+    const uint32_t v = blockIdx.x * kWave + lane;
     const bool valid = v < n;
     const uint32_t cr = valid ? center_rank[v] : kNone;
+    const uint64_t cmask = __ballot(cr != kNone);  // the same in every wave of the block
+    const uint32_t nc = (uint32_t)__popcll(cmask);
+    const bool stage = nc <= kG0StageCenters;
+    const uint32_t cr0 = nc ? (uint32_t)__builtin_amdgcn_readlane((int)cr, (int)__builtin_ctzll(cmask)) : 0u;
     const uint32_t iv = valid ? newid[v] : 0u;
     const bool alone = valid && iv >= n_linked;  // isolated: root itself, size 1, its own rank
     const size_t ns = sketch_stride(n);
-    uint64_t s = 0;
-    for (uint32_t b0 = 0; b0 < B; b0 += U) {
-        uint32_t root[U], sz[U], l[U];
+    // Each group of loads is issued unconditionally (inactive lanes read entry 0)
+    // and back to back, then waited for once.
+    uint32_t root[kG0PerWave], sz[kG0PerWave], l[kG0PerWave], t[kG0PerWave];
 #pragma unroll
-        for (uint32_t i = 0; i < U; ++i)
-            root[i] = (valid && b0 + i < B) ? (alone ? iv : parent[(b0 + i) * ns + iv]) : kNone;
+    for (uint32_t i = 0; i < kG0PerWave; ++i) {
+        const uint32_t b = wv + kG0Waves * i;
+        const bool act = valid && b < B && !alone;
+        t[i] = parent[act ? b * ns + iv : 0];
+    }
 #pragma unroll
-        for (uint32_t i = 0; i < U; ++i) sz[i] = root[i] != kNone ? (alone ? 1u : 1u + cnt[(b0 + i) * ns + root[i]]) : 0u;
+    for (uint32_t i = 0; i < kG0PerWave; ++i) {
+        const uint32_t b = wv + kG0Waves * i;
+        const bool act = valid && b < B && !alone;
+        root[i] = act ? pin_vgpr(t[i]) : ((valid && b < B) ? iv : kNone);
+    }
 #pragma unroll
-        for (uint32_t i = 0; i < U; ++i)
-            l[i] = (cr != kNone && root[i] != kNone) ? (alone ? cr : minc[(b0 + i) * ns + root[i]]) : kNone;
+    for (uint32_t i = 0; i < kG0PerWave; ++i) {
+        const uint32_t b = wv + kG0Waves * i;
+        const bool act = valid && b < B && !alone;
+        t[i] = cnt[act ? b * ns + root[i] : 0];
+    }
 #pragma unroll
-        for (uint32_t i = 0; i < U; ++i) {
-            const uint32_t b = b0 + i;
-            if (b >= B) break;
-            s += sz[i];
-            if (cr != kNone && root[i] != kNone) {
-                const size_t at = (size_t)(r0 + b) * rho + cr;
-                label_c[at] = l[i];
-                size_c[at] = (l[i] == cr) ? sz[i] : 0u;
-            }
-            if (gbits) {
-                const uint64_t m = __ballot(valid && root[i] == giant_root_of(gbest[b]));
-                if (lane_id() == 0 && (v >> 6) < nw) gbits[(size_t)b * nw + (v >> 6)] = m;
-            }
+    for (uint32_t i = 0; i < kG0PerWave; ++i) {
+        const uint32_t c = pin_vgpr(t[i]);
+        sz[i] = root[i] == kNone ? 0u : (alone ? 1u : 1u + c);
+    }
+    if (cr != kNone) {
+#pragma unroll
+        for (uint32_t i = 0; i < kG0PerWave; ++i) {
+            const uint32_t b = wv + kG0Waves * i;
+            const bool act = b < B && !alone;
+            t[i] = minc[act ? b * ns + root[i] : 0];
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < kG0PerWave; ++i) {
+            const uint32_t m = pin_vgpr(t[i]);
+            l[i] = root[i] == kNone ? kNone : (alone ? cr : m);
         }
     }
-    if (valid) gain0[v] += s;
+    uint64_t s = 0, gs = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kG0PerWave; ++i) {
+        const uint32_t b = wv + kG0Waves * i;
+        if (b >= B) break;  // wave-uniform
+        s += sz[i];
+        if (cr != kNone) {
+            const uint32_t lv = l[i], sv = (l[i] == cr) ? sz[i] : 0u;
+            if (stage) {
+                tl[cr - cr0][b] = lv;
+                ts[cr - cr0][b] = sv;
+            } else {
+                const size_t at = (size_t)cr * R + r0 + b;
+                label_c[at] = lv;
+                size_c[at] = sv;
+            }
+        }
+        if (gbits) {
+            const unsigned long long gb = gbest[b];
+            const bool in_giant = valid && root[i] == giant_root_of(gb);
+            const uint64_t m = __ballot(in_giant);
+            if (lane == 0) gword[b] = m;
+            gs += in_giant ? giant_size_of(gb) : 0u;
+        }
+    }
+    part[wv][lane] = s;
+    gpart[wv][lane] = gs;
+    __syncthreads();
+    if (stage) {
+        for (uint32_t j = wv; j < nc; j += kG0Waves)
+            if (lane < B) {
+                const size_t at = (size_t)(cr0 + j) * R + r0 + lane;
+                label_c[at] = tl[j][lane];
+                size_c[at] = ts[j][lane];
+            }
+    }
+    if (gbits && wv == 1 && lane < B && blockIdx.x < nw) gbits[(size_t)blockIdx.x * R + r0 + lane] = gword[lane];
+    if (wv == 0 && valid) {
+        uint64_t t = 0, tg = 0;
+#pragma unroll
+        for (uint32_t w = 0; w < kG0Waves; ++w) t += part[w][lane], tg += gpart[w][lane];
+        gain0[v] += t;
+        if (gbits) gsum[v] += tg;
+    }
 }
 
 // ---- centers: flag, per-chunk counts, scan, ranks --------------------------

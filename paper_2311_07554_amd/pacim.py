@@ -98,6 +98,7 @@ _SIGS = {
     "im_sketches_stats": (ctypes.c_int, [_vp, ctypes.POINTER(im_sketch_stats)]),
     "im_select_trace": (ctypes.c_int, [_vp, _vp, _u32p, ctypes.c_uint32]),
     "im_probe_device": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "im_probe_random": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
     "im_server_create": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_uint32, ctypes.POINTER(im_server_config),
                                         ctypes.POINTER(_vp)]),
     "im_server_submit": (ctypes.c_int, [_vp, ctypes.POINTER(im_query), ctypes.POINTER(ctypes.c_uint64)]),
@@ -425,6 +426,12 @@ class Context:
 
     def probe(self):
         return im_probe_device(self.h)
+
+    def probe_random(self):
+        """Independent random 4-byte reads per second (4 GiB buffer)."""
+        v = ctypes.c_double(0)
+        _check(self.h, load().im_probe_random(self.h, ctypes.byref(v)))
+        return v.value
 
     def select_batched(self, queries, cfg=None):
         """queries: list of (Graph, kind, p, R, k, seed[, alpha])."""
