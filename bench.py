@@ -1,18 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark of the sketch-based greedy influence-maximization hot path on one MI355X.
 
-Workload (default): R-MAT scale 20 (2^20 vertices, 2^24 undirected pairs,
-a=0.57 b=c=0.19), trivalency IC probabilities, R = 256 sketches, k = 100 seeds.
-One step = the whole path twice on the resident graph: full labels (alpha = 1)
-and CompactSketch (alpha = 0.1), each = build R sketches + select k seeds.  The
-two queries are independent; the CompactSketch one runs on a second stream,
-built first, and its selection overlaps the full-label build (--no-overlap runs
-them one after another).
+Default workload (the headline): R-MAT scale 24 (2^24 vertices, 2^28 undirected
+pairs, a=0.57 b=c=0.19), uniform IC p = 0.02, R = 256 sketches, k = 200 seeds,
+CompactSketch labels (alpha = 0.1).  One step = one query on the resident graph:
+build the R sketches + select the k seeds.  value = R * m_und sampled edges per
+second of step time.
 
-Prints one JSON line.  value = sampled edges per second over the step
-(2 * R * m_und sampled edges / step time); the breakdown gives the sketch-only
-sampled-edge rate, seeds/s of selection, and the per-kernel roofline of the
-dominant kernel measured with HIP events on the library's stream.
+The JSON line also carries:
+  roofline        the dominant kernel (the sampling pass) against its algorithmic
+                  ceiling (integer ALU of the hash), with its measured HBM traffic;
+  hbm_phases      every build kernel and the Marginal pass against 8 TB/s on their
+                  algorithmic bytes per launch (HIP events on the library's stream);
+  cpu_baseline    the oracle, single-threaded, on a bounded sample of the query;
+  evaluations     NextSeed's re-evaluations beside CELF's count on the same sketches;
+  extra           (unless --headline-only) the R-MAT 2^20 trivalency step (full
+                  labels + CompactSketch), the 64-graph batched launch against one
+                  query per launch, and the served request stream (p50/p99) against
+                  one request at a time.
+Other workloads (--workload): rmat20, rmat24 (the headline alone), batched,
+serving, sweep, quality.
 """
 from __future__ import annotations
 
@@ -38,19 +45,24 @@ VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 VALU_PER_HASH = 175.0 / 8.0
 HASH_PEAK_G = VALU_LANE_OPS / VALU_PER_HASH / 1e9
 
+# committed counter profiles of the sampling kernel, by workload
+TRAFFIC_PROFILES = {
+    "rmat24": os.path.join(ROOT, "profiles", "k_sample_hook_rmat24_traffic.txt"),
+    "rmat20": os.path.join(ROOT, "profiles", "k_sample_hook_rmat20_traffic.txt"),
+}
+TRAFFIC_PROFILE = TRAFFIC_PROFILES["rmat20"]
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_sample_hook_rmat20_traffic.txt")
 
-
-def sampling_kernel_traffic():
+def sampling_kernel_traffic(path=None):
     """HBM bytes per launch of the sampling kernel from its committed counter
     profile (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for
     a copy kernel of known size), or None when the profile is missing or the
     kernel sources changed since it was taken."""
     import hashlib
+    path = path or TRAFFIC_PROFILE
     try:
         fields = {}
-        with open(TRAFFIC_PROFILE) as f:
+        with open(path) as f:
             for line in f:
                 if ":" in line and not line.startswith(" "):
                     k, v = line.split(":", 1)
@@ -63,7 +75,7 @@ def sampling_kernel_traffic():
             return None
         return {"bytes": float(fields["traffic_bytes"]), "fetch_bytes": float(fields["traffic_fetch_bytes"]),
                 "write_bytes": float(fields["traffic_write_bytes"]),
-                "profile": os.path.relpath(TRAFFIC_PROFILE, ROOT)}
+                "profile": os.path.relpath(path, ROOT)}
     except (OSError, KeyError, ValueError):
         return None
 
@@ -73,19 +85,24 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--scale", type=int, default=20)
-    ap.add_argument("--R", type=int, default=256)
-    ap.add_argument("--k", type=int, default=100)
-    ap.add_argument("--alpha", type=float, default=0.1, help="CompactSketch alpha of the second query")
-    ap.add_argument("--modes", default="full,compact")
+    ap.add_argument("--scale", type=int, default=20, help="rmat20 workload: R-MAT scale")
+    ap.add_argument("--R", type=int, default=256, help="rmat20 workload: sketches")
+    ap.add_argument("--k", type=int, default=100, help="rmat20 workload: seeds")
+    ap.add_argument("--alpha", type=float, default=0.1, help="rmat20 workload: CompactSketch alpha of its second query")
+    ap.add_argument("--modes", default="full,compact", help="rmat20 workload: label kinds of a step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-overlap", action="store_true",
-                    help="run the step's two queries one after another on one stream")
+                    help="rmat20: run the step's two queries one after another on one stream")
     ap.add_argument("--no-ptree", action="store_true",
                     help="skip the untimed comparison with NextSeed by prefix doubling")
-    ap.add_argument("--cpu-sketches", type=int, default=16)
-    ap.add_argument("--workload", default="rmat20", choices=("rmat20", "rmat24", "batched", "serving", "sweep", "quality"),
-                    help="rmat20: the headline workload; rmat24: the 2^24-vertex CompactSketch configuration; batched: 64 Chung-Lu graphs in one launch; "
+    ap.add_argument("--headline-only", action="store_true",
+                    help="default workload: leave out the rmat20, batched and serving extras")
+    ap.add_argument("--cpu-sketches", type=int, default=0,
+                    help="sketches in the oracle's timed sample (0: 2 at 2^24 vertices, 16 at 2^20)")
+    ap.add_argument("--workload", default="headline",
+                    choices=("headline", "rmat20", "rmat24", "batched", "serving", "sweep", "quality"),
+                    help="headline: R-MAT 2^24 CompactSketch query plus the extras; rmat24: that query alone; "
+                         "rmat20: the 2^20-vertex trivalency step; batched: 64 Chung-Lu graphs in one launch; "
                          "serving: Poisson request stream over 16 resident R-MAT graphs; "
                          "sweep: alpha and edge-probability models on the rmat20 graph; "
                          "quality: spread of the seeds against R by simulation")
@@ -100,17 +117,28 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(g, kind, p, R, k, seed, nsk):
-    """The oracle as it stands (single thread) on nsk of the R sketches plus the plain
-    greedy over them; scaled linearly in R to the full query."""
-    import oracle
+def host_info():
     host = {"logical_cpus": os.cpu_count()}
     try:
         with open("/proc/cpuinfo") as f:
             host["cpu"] = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
     except OSError:
         pass
-    # one thread, pinned to one core while it is timed
+    try:
+        with open("/proc/meminfo") as f:
+            kb = next(int(ln.split()[1]) for ln in f if ln.startswith("MemTotal"))
+        host["ram_gib"] = round(kb / 2**20, 1)
+    except (OSError, StopIteration, ValueError):
+        pass
+    return host
+
+
+def cpu_baseline(g, kind, p, R, k, seed, nsk, rounds):
+    """The oracle as it stands, single-threaded and pinned to one core: BFS labels of
+    nsk of the R sketches, then `rounds` rounds of the plain greedy (full
+    recomputation) over them.  Scaled linearly to the whole query: sketching by
+    R / nsk; a greedy round costs n * R label lookups, so by R / nsk, and k rounds."""
+    import oracle
     old_aff = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
     if old_aff:
         os.sched_setaffinity(0, {min(old_aff)})
@@ -118,27 +146,35 @@ def cpu_baseline(g, kind, p, R, k, seed, nsk):
         t0 = time.perf_counter()
         lab, siz = oracle.sketches(g, kind, p, seed, nsk, threads=1)
         t1 = time.perf_counter()
-        oracle.greedy(lab, siz, k)
+        oracle.greedy(lab, siz, rounds)
         t2 = time.perf_counter()
     finally:
         if old_aff:
             os.sched_setaffinity(0, old_aff)
-    scale = R / nsk
-    t_query = (t1 - t0) * scale + (t2 - t1) * scale
+    del lab, siz
+    t_sketch = (t1 - t0) * R / nsk
+    t_select = (t2 - t1) / rounds * (R / nsk) * k
+    t_query = t_sketch + t_select
     return {
         "value": R * g.m_und / t_query,
         "unit": "sampled edges/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"{nsk} of {R} sketches (BFS labelling) + plain greedy k={k} over them, "
-                  f"{t2 - t0:.1f} s measured, times scaled x{scale:g} to R={R}",
+        "sample": f"{nsk} of {R} sketches labelled by BFS ({t1 - t0:.1f} s) + {rounds} of {k} plain-greedy rounds "
+                  f"over them ({t2 - t1:.1f} s); query time extrapolated: sketching x{R / nsk:g}, each greedy "
+                  f"round x{R / nsk:g} (n*R lookups) and x{k / rounds:g} rounds",
+        "query_s_extrapolated": t_query,
         "sketch_edges_per_s": nsk * g.m_und / (t1 - t0),
-        "greedy_s_measured": t2 - t1,
-        "host": host,
+        "seeds_per_s_extrapolated": k / t_select,
+        "host": host_info(),
     }
 
 
 def run_batched(args):
+    print(json.dumps(batched_measure(args)), flush=True)
+
+
+def batched_measure(args):
     """64 independent power-law graphs answered by one batched launch, against the
     plain path (one im_select_seeds per query, in sequence)."""
     import numpy as np
@@ -203,14 +239,31 @@ def run_batched(args):
     for gr in graphs:
         gr.close()
     ctx.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def run_serving(args):
-    """Poisson request stream over 16 resident R-MAT graphs, served with continuous
-    batching, against the plain path (one request at a time, build + select)."""
-    import threading
+    print(json.dumps(serving_measure(args)), flush=True)
 
+
+def fifo_latencies(arrivals, service):
+    """Latency of each request on a single server taking requests first come first
+    served: wait for the previous request to finish, then its own service time."""
+    out, free = [], 0.0
+    for at, sv in zip(arrivals, service):
+        start = max(at, free)
+        free = start + sv
+        out.append(free - at)
+    return out
+
+
+def serving_measure(args):
+    """Poisson request stream over 16 resident R-MAT graphs, served with continuous
+    batching, against the plain path (one request at a time: build + select, no
+    kept sketches).  Every request is first run on the plain path, timing its
+    service; the plain path's latency under the same arrivals is that of a
+    first-come-first-served queue with those service times.  The server then takes
+    the stream at args.load (and twice that) times the plain path's capacity."""
     import numpy as np
     import torch
 
@@ -225,80 +278,85 @@ def run_serving(args):
     reqs = inputs.serving_queries(len(graphs), args.queries, seed=5)
     sample_seed = 5
     U = pacim.IM_PROB_UNIFORM
-    # plain path capacity on a sample of the same requests
-    ns = min(args.baseline_sample, len(reqs))
-    base = []
-    for (gi, p, R, k, _s) in reqs[:ns]:
+    # plain path: every request, one at a time
+    service, plain_res = [], []
+    for i, (gi, p, R, k, _s) in enumerate(reqs):
         t0 = time.perf_counter()
-        grs[gi].select_seeds(U, p, R, k, sample_seed)
-        base.append((time.perf_counter() - t0) * 1e3)
-    capacity = 1e3 / float(np.mean(base))
-    qps = args.load * capacity
-    print(f"[bench] plain path: {np.mean(base):.1f} ms per request -> {capacity:.1f} req/s; offering {qps:.1f} req/s",
+        plain_res.append(grs[gi].select_seeds(U, p, R, k, sample_seed))
+        service.append(time.perf_counter() - t0)
+        if (i + 1) % 500 == 0:
+            print(f"[bench] plain path {i + 1}/{len(reqs)}", file=sys.stderr, flush=True)
+    capacity = 1.0 / float(np.mean(service))
+    print(f"[bench] plain path: {np.mean(service) * 1e3:.1f} ms per request -> {capacity:.1f} req/s",
           file=sys.stderr, flush=True)
-    arrivals = inputs.poisson_arrivals(len(reqs), qps, seed=5)
-    tickets = [None] * len(reqs)
-    srv = pacim.Server(ctx, grs, hbm_budget=int(args.budget_gib * (1 << 30)), max_active=32, rounds_per_step=16)
+    runs = []
+    for load in (args.load, 2.0 * args.load):
+        qps = load * capacity
+        arrivals = inputs.poisson_arrivals(len(reqs), qps, seed=5)
+        tickets = [None] * len(reqs)
+        srv = pacim.Server(ctx, grs, hbm_budget=int(args.budget_gib * (1 << 30)), max_active=32,
+                           rounds_per_step=16)
 
-    def submitter():
-        t_start = time.perf_counter()
-        for i, ((gi, p, R, k, _s), at) in enumerate(zip(reqs, arrivals)):
-            d = t_start + at - time.perf_counter()
-            if d > 0:
-                time.sleep(d)
-            tickets[i] = srv.submit(gi, U, p, R, k, sample_seed)
+        def submitter():
+            t_start = time.perf_counter()
+            for i, ((gi, p, R, k, _s), at) in enumerate(zip(reqs, arrivals)):
+                d = t_start + at - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = srv.submit(gi, U, p, R, k, sample_seed)
 
-    t0 = time.perf_counter()
-    th = threading.Thread(target=submitter)
-    th.start()
-    lat = []
-    done = 0
-    while done < len(reqs):
-        if tickets[done] is None:
-            time.sleep(0.0005)
-            continue
-        s_, g_, ms = srv.wait(tickets[done])
-        lat.append(ms)
-        done += 1
-        if done % 250 == 0:
-            print(f"[bench] served {done}/{len(reqs)}", file=sys.stderr, flush=True)
-    th.join()
-    t_all = time.perf_counter() - t0
-    st = srv.stats()
-    srv.close()
-    # spot-check: a few served requests against the plain path
-    same = True
-    for i in range(0, len(reqs), max(1, len(reqs) // 8)):
-        gi, p, R, k, _s = reqs[i]
-        srv1 = pacim.Server(ctx, [grs[gi]], max_active=1)
-        tk = srv1.submit(0, U, p, R, k, sample_seed)
-        s1, g1, _ = srv1.wait(tk)
-        srv1.close()
-        s2, g2 = grs[gi].select_seeds(U, p, R, k, sample_seed)
-        same &= bool(np.array_equal(s1, s2) and np.array_equal(g1, g2))
-    lat = np.array(lat)
+        t0 = time.perf_counter()
+        th = threading.Thread(target=submitter)
+        th.start()
+        lat, same = [], True
+        done = 0
+        while done < len(reqs):
+            if tickets[done] is None:
+                time.sleep(0.0005)
+                continue
+            s_, g_, ms = srv.wait(tickets[done])
+            same &= bool(np.array_equal(s_, plain_res[done][0]) and np.array_equal(g_, plain_res[done][1]))
+            lat.append(ms)
+            done += 1
+        th.join()
+        t_all = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        lat = np.array(lat)
+        plain_lat = np.array(fifo_latencies(arrivals, service)) * 1e3
+        runs.append({"offered_load": load, "offered_qps": qps, "throughput_qps": len(reqs) / t_all,
+                     "wall_s": t_all, "p50_ms": float(np.percentile(lat, 50)),
+                     "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+                     "max_ms": float(lat.max()),
+                     "plain_fifo_same_arrivals": {"p50_ms": float(np.percentile(plain_lat, 50)),
+                                                  "p99_ms": float(np.percentile(plain_lat, 99)),
+                                                  "mean_ms": float(plain_lat.mean())},
+                     "identical_to_plain_results": same, "stats": st})
+        print(f"[bench] served at {load:g}x plain capacity: {len(reqs) / t_all:.1f} req/s, p50 "
+              f"{np.percentile(lat, 50):.1f} ms, p99 {np.percentile(lat, 99):.1f} ms (plain path, same arrivals: "
+              f"p50 {np.percentile(plain_lat, 50):.1f} ms, p99 {np.percentile(plain_lat, 99):.1f} ms); "
+              f"identical results: {same}", file=sys.stderr, flush=True)
     sampled = sum(R * graphs[gi].m_und for (gi, p, R, k, _s) in reqs)
+    main_run = runs[-1]
     out = {
         "metric": METRIC,
-        "value": sampled / t_all,
+        "value": sampled / main_run["wall_s"],
         "unit": "sampled edges/s",
-        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": t_all * 1e3,
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": main_run["wall_s"] * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": f"serving_rmat16-22_x16_{len(reqs)}req", "graphs": [g.n for g in graphs],
-                   "p": [0.01, 0.02, 0.05], "R": [64, 256], "k": [10, 50, 100], "parallelism": "single GPU"},
-        "serving": {"offered_qps": qps, "offered_load": args.load, "hbm_budget_gib": args.budget_gib,
-                    "throughput_qps": len(reqs) / t_all,
-                    "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                    "mean_ms": float(lat.mean()), "max_ms": float(lat.max()), "stats": st},
-        "plain_one_request_at_a_time": {"sample": ns, "mean_ms": float(np.mean(base)),
-                                        "p50_ms": float(np.percentile(base, 50)),
-                                        "p99_ms": float(np.percentile(base, 99)), "capacity_qps": capacity},
-        "identical_results_spot_check": same,
+                   "p": [0.01, 0.02, 0.05], "R": [64, 256], "k": [10, 50, 100], "parallelism": "single GPU",
+                   "hbm_budget_gib": args.budget_gib},
+        "serving": runs,
+        "plain_one_request_at_a_time": {"requests": len(reqs), "mean_ms": float(np.mean(service) * 1e3),
+                                        "p50_service_ms": float(np.percentile(service, 50) * 1e3),
+                                        "p99_service_ms": float(np.percentile(service, 99) * 1e3),
+                                        "capacity_qps": capacity},
     }
     for gr in grs:
         gr.close()
     ctx.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 # edge-probability models of the sweep: Sec. 5's trivalency-like workload and the
@@ -426,62 +484,90 @@ def run_quality(args):
     print(json.dumps(out), flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only: the library has no multi-GPU path (asked for {args.gpus}).",
-              file=sys.stderr)
-        sys.exit(2)
-    if args.workload == "batched":
-        return run_batched(args)
-    if args.workload == "serving":
-        return run_serving(args)
-    if args.workload == "sweep":
-        return run_sweep(args)
-    if args.workload == "quality":
-        return run_quality(args)
+def streaming_bytes(name, full, n, n_linked, m_und, B, passes, R, rho):
+    """Bytes a kernel family streams per launch: the scratch forests it sets up, reads
+    or rewrites, the edge words, and the outputs it writes (gathers at component
+    roots and random union-find accesses not counted)."""
+    # the first pass of a build also sets isolated vertices' entries
+    n_init = (n + (passes - 1) * n_linked) / passes
+    if name == "init":
+        return (8.0 if full else 12.0) * B * n_init
+    if name == "sample_hook":
+        return 16.0 * m_und  # the edge list's ids and labelling-order numbers
+    if name == "compress":
+        return 8.0 * B * n_linked  # read each forest entry, write it back pointing at its root
+    if name == "emit":
+        if full:  # forest read, E written, gains read and written, labelling order read
+            return 4.0 * B * n_linked + 8.0 * B * n + 24.0 * n
+        # forest read, triple of the centers, bitmaps, gains, center ranks and order
+        return 4.0 * B * n_linked + 8.0 * B * rho + B * n / 8.0 + 24.0 * n
+    if name == "bulk_keys":
+        if full:  # every row of E read, keys written, selection flags read
+            return 8.0 * R * n + 9.0 * n
+        return R * n / 8.0 + 33.0 * n  # bitmaps, initial gains, partial sums, flags, keys
+    raise KeyError(name)
+
+
+def phase_frames(kern, full, g, n_linked, B, passes, R, rho, build_ms):
+    """HBM frames against the 8 TB/s spec peak.  Per kernel family: the bytes it
+    streams per launch over its mean launch time.  Per phase, on the method's
+    algorithmic bytes: Sketch = passes x (4 m_und + 4 n) of half-CSR plus the
+    sketches written (8 R n full, 8 R rho CompactSketch) over the build time;
+    Marginal = the bulk evaluation of every vertex (every row of E, or the
+    largest-component bitmaps) over its launch time."""
+    rows = {}
+    for name in ("init", "sample_hook", "compress", "emit", "bulk_keys"):
+        t = kern.get(name)
+        if not t or not t["launches"]:
+            continue
+        b = streaming_bytes(name, full, g.n, n_linked, g.m_und, B, passes, R, rho)
+        gbs = b / (t["avg_ms"] / 1e3) / 1e9
+        rows[name] = {"streaming_bytes_per_launch": b, "avg_launch_ms": t["avg_ms"], "launches": t["launches"],
+                      "GB_s": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
+    sk_bytes = passes * (4.0 * g.m_und + 4.0 * g.n) + 8.0 * R * (g.n if full else rho)
+    sk_gbs = sk_bytes / (build_ms / 1e3) / 1e9
+    phases = {"sketch": {"algorithmic_bytes_per_build": sk_bytes, "build_ms": build_ms, "GB_s": sk_gbs,
+                         "frac_of_peak": sk_gbs / HBM_PEAK_GBS,
+                         "note": "bound by the hash ALU and the union-find's random parent accesses, "
+                                 "not by these bytes"}}
+    if "bulk_keys" in rows:
+        phases["marginal_bulk"] = {"algorithmic_bytes_per_launch": rows["bulk_keys"]["streaming_bytes_per_launch"],
+                                   "avg_launch_ms": rows["bulk_keys"]["avg_launch_ms"],
+                                   "GB_s": rows["bulk_keys"]["GB_s"], "frac_of_peak": rows["bulk_keys"]["frac_of_peak"]}
+    return {"kernels": rows, "phases": phases}
+
+
+def measure_sketch_workload(args, w, modes, alphas, overlap, tag, profile_key):
+    """Times steps of the workload's query (one per label kind in `modes`) on the
+    resident graph; returns the result dict (no cpu baseline)."""
     import numpy as np
     import torch
 
     from paper_2311_07554_amd import inputs, pacim
 
-    assert torch.cuda.is_available(), "no GPU visible"
-    torch.cuda.set_device(0)
-    t = time.perf_counter()
-    if args.workload == "rmat24":
-        # the 2^24-vertex configuration: uniform p = 0.02, R = 256, k = 200, CompactSketch only
-        scale = 24
-        w = inputs.rmat24()
-        modes = ["compact"]
-        args.alpha = w.queries[0].alpha
-    else:
-        scale = args.scale
-        w = inputs.rmat20(R=args.R, k=args.k, scale=args.scale)
-        modes = [m for m in args.modes.split(",") if m]
     q = w.queries[0]
     g = q.graph
-    print(f"[bench] graph {g.name}: n={g.n} m_und={g.m_und} generated in {time.perf_counter() - t:.1f}s",
-          file=sys.stderr, flush=True)
-    alphas = {"full": 1.0, "compact": args.alpha}
+    R, m_und, n = q.R, g.m_und, g.n
+    deg = np.diff(g.offsets)
+    n_linked = int((deg > 0).sum())
     prob_name = "trivalency {0.1,0.01,0.001}" if q.prob_kind == inputs.PROB_TRIVALENCY else f"uniform p={q.p}"
-    prob_tag = "trivalency" if q.prob_kind == inputs.PROB_TRIVALENCY else f"p{q.p}"
-
     stream = torch.cuda.Stream()
     ctx = pacim.Context(0, stream)
     gr = ctx.graph(g.n, torch.from_numpy(g.offsets.view(np.int64)).cuda(),
                    torch.from_numpy(g.cols.view(np.int32)).cuda())
-    # The step's two queries are independent: with both modes, the CompactSketch query
-    # runs on a second context and stream, and its selection (latency-bound, one wave
-    # per sketch) overlaps the full-label query's build.
-    overlap = (not args.no_overlap) and modes == ["full", "compact"]
+    # The step's two queries (full labels and CompactSketch) are independent: the
+    # CompactSketch query runs on a second context and stream, and its selection
+    # (latency-bound) overlaps the full-label query's build.
     ctx2 = gr2 = None
     if overlap:
         ctx2 = pacim.Context(0, torch.cuda.Stream())
         gr2 = ctx2.graph(g.n, g.offsets, g.cols)
     torch.cuda.synchronize()
     probe_hash, probe_copy = ctx.probe()
-    print(f"[bench] device probe: {probe_hash / 1e9:.1f} Ghash/s (hash loop alone), "
-          f"{probe_copy / 1e9:.0f} GB/s (stream copy)", file=sys.stderr, flush=True)
+    probe_rand = ctx.probe_random()
+    print(f"[bench] {tag}: device probe {probe_hash / 1e9:.1f} Ghash/s (hash loop alone), "
+          f"{probe_copy / 1e9:.0f} GB/s (stream copy), {probe_rand / 1e9:.1f} G random 4-byte reads/s",
+          file=sys.stderr, flush=True)
 
     def one_query(graph, m, record, per, built=None, wait=None):
         if wait is not None:
@@ -491,11 +577,12 @@ def main():
             built.set()
         s, gn = sk.select(q.k)
         st = sk.stats()
+        ev = sk.trace()
         sk.close()
         if record is not None:
             record.setdefault(m, []).append((st["build_ms"], st["select_ms"], st["evaluations"],
                                              st["sketches_per_pass"], st["bulk_rounds"], st["bulk_resampled"],
-                                             st["bfs_visits"]))
+                                             st["bfs_visits"], ev, st["rho"]))
         per[m] = (s, gn)
 
     def one_step(record, sequential=False):
@@ -504,7 +591,6 @@ def main():
             for m in modes:
                 one_query(gr, m, record, per)
             return per
-        # CompactSketch build, then its selection while the full-label query builds
         built = threading.Event()
         tc = threading.Thread(target=one_query, args=(gr2, "compact", record, per, built, None))
         tf = threading.Thread(target=one_query, args=(gr, "full", record, per, None, built))
@@ -518,7 +604,7 @@ def main():
 
     for i in range(args.warmup):
         one_step(None)
-        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+        print(f"[bench] {tag}: warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     isolated = {}
     if overlap:  # per-query times without the overlap, outside the timed steps
         iso = {}
@@ -532,29 +618,41 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         res = one_step(rec)
-        print(f"[bench] step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+        print(f"[bench] {tag}: step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
 
-    kern = {}
-    for name in ("sample_hook", "compress", "emit", "select"):
-        n_l, ms = ctx.kernel_time(name)
-        if ctx2 is not None:
-            n2, ms2 = ctx2.kernel_time(name)
-            n_l, ms = n_l + n2, ms + ms2
-        kern[name] = {"launches": n_l, "avg_ms": (ms / n_l) if n_l else None, "total_ms": ms}
+    def kernel_times(c_list, names):
+        out = {}
+        for name in names:
+            n_l, ms = 0, 0.0
+            for c in c_list:
+                a, b = c.kernel_time(name)
+                n_l, ms = n_l + a, ms + b
+            out[name] = {"launches": n_l, "avg_ms": (ms / n_l) if n_l else None, "total_ms": ms}
+        return out
+
+    names = ("init", "sample_hook", "compress", "emit", "bulk_keys", "select")
+    kern = kernel_times([c for c in (ctx, ctx2) if c is not None], names)
+    # per label kind: the full query runs on ctx, the CompactSketch one on ctx2 when overlapped
+    kern_by_mode = {}
+    if overlap:
+        kern_by_mode = {"full": kernel_times([ctx], names), "compact": kernel_times([ctx2], names)}
+    else:
+        kern_by_mode = {modes[0]: kern} if len(modes) == 1 else {}
     ctx.profiling(False)
     if ctx2 is not None:
         ctx2.profiling(False)
         gr2.close()
         ctx2.close()
 
-    R, m_und, n = q.R, g.m_und, g.n
     breakdown = {}
     for m, rows in rec.items():
         b = np.array([r[0] for r in rows])
         s = np.array([r[1] for r in rows])
+        ev = rows[-1][7]
+        bulk = int(rows[-1][4])
         breakdown[m] = {
             "alpha": alphas[m],
             "sketch_ms": float(b.mean()),
@@ -562,36 +660,51 @@ def main():
             "sampled_edges_per_s_sketch": R * m_und / (b.mean() / 1e3),
             "seeds_per_s_select": q.k / (s.mean() / 1e3),
             "evaluations": int(rows[-1][2]),
+            "evaluations_per_round_max": int(ev.max()) if ev.size else 0,
             "sketches_per_pass": int(rows[-1][3]),
-            "bulk_rounds": int(rows[-1][4]),
+            "bulk_rounds": bulk,
             "bulk_rounds_resampled": int(rows[-1][5]),
+            "rho": int(rows[-1][8]),
         }
         if alphas[m] < 1.0:
             # GetCenter work of the CompactSketch selection (Marginal, compact)
             breakdown[m]["getcenter_vertices_scanned"] = int(rows[-1][6])
             breakdown[m]["getcenter_vertices_per_s"] = rows[-1][6] / (s.mean() / 1e3)
+        km = kern_by_mode.get(m)
+        if km:
+            B = breakdown[m]["sketches_per_pass"]
+            passes = (R + B - 1) // B
+            breakdown[m]["hbm"] = phase_frames(km, alphas[m] >= 1.0, g, n_linked, B, passes, R,
+                                               breakdown[m]["rho"], breakdown[m]["sketch_ms"])
     # dominant kernel: the sampling + hooking pass over the edge list
     hk = kern["sample_hook"]
-    hk_name = "k_sample_hook"
     B = breakdown[modes[0]]["sketches_per_pass"]
     hashes_per_launch = m_und * B  # one launch samples B sketches of every edge
     roofline = None
     if hk["avg_ms"]:
         achieved = hashes_per_launch / (hk["avg_ms"] / 1e3) / 1e9
-        tr = sampling_kernel_traffic() if (scale == 20 and B == 64 and q.R == 256 and
-                                           q.prob_kind == inputs.PROB_TRIVALENCY) else None
-        roofline = {"bound": "alu", "kernel": hk_name, "achieved": achieved, "peak": HASH_PEAK_G,
+        tr = sampling_kernel_traffic(TRAFFIC_PROFILES[profile_key]) if (profile_key and B == 64) else None
+        alg_bytes = 4.0 * m_und + 4.0 * n
+        roofline = {"bound": "alu", "kernel": "k_sample_hook", "achieved": achieved, "peak": HASH_PEAK_G,
                     "unit": "Ghash/s", "frac": achieved / HASH_PEAK_G,
                     "traffic": tr["bytes"] if tr else None,
                     "per_launch_hashes": hashes_per_launch, "avg_launch_ms": hk["avg_ms"],
                     "measured_ceiling": probe_hash / 1e9,
-                    "frac_of_measured_ceiling": achieved / (probe_hash / 1e9)}
+                    "frac_of_measured_ceiling": achieved / (probe_hash / 1e9),
+                    # the same launches in the HBM frame: the method's bytes (half-CSR,
+                    # one word per undirected edge and per vertex) over the launch time
+                    "hbm_frame": {"algorithmic_bytes_per_launch": alg_bytes,
+                                  "GB_s": alg_bytes / (hk["avg_ms"] / 1e3) / 1e9,
+                                  "frac_of_peak": alg_bytes / (hk["avg_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS}}
         if tr:
-            # the union-find's random parent accesses, not the hashes, move these bytes;
-            # algorithmic: the two endpoint ids of every edge once per pass (the kernel
-            # also reads their labelling-order numbers, another 8 B per edge)
-            roofline["traffic_detail"] = dict(tr, achieved_GB_s=tr["bytes"] / (hk["avg_ms"] / 1e3) / 1e9,
-                                              algorithmic_bytes=8.0 * m_und, edge_bytes_read=16.0 * m_und)
+            # measured HBM traffic of the launch: the union-find's random parent
+            # accesses, not the hashes or the edge words, move these bytes
+            tgbs = tr["bytes"] / (hk["avg_ms"] / 1e3) / 1e9
+            roofline["traffic_detail"] = dict(tr, achieved_GB_s=tgbs, frac_of_peak=tgbs / HBM_PEAK_GBS,
+                                              frac_of_measured_copy=tgbs / (probe_copy / 1e9),
+                                              algorithmic_bytes=alg_bytes, edge_bytes_read=16.0 * m_und,
+                                              limiter="random union-find traffic near the measured copy rate"
+                                              if tgbs > 0.8 * probe_copy / 1e9 else "hash ALU")
 
     # NextSeed by prefix doubling (Algorithm 4) on the same sketches, outside the
     # timed steps: its selection time and evaluations beside the winning tree's
@@ -611,24 +724,14 @@ def main():
                         "winning_tree_select_ms": (isolated[m]["select_ms"] if isolated
                                                    else breakdown[m]["select_ms"]),
                         "winning_tree_evaluations": breakdown[m]["evaluations"]}
-        print(f"[bench] prefix-doubling selection: {trees}", file=sys.stderr, flush=True)
-
-    out = {
-        "metric": METRIC,
+        print(f"[bench] {tag}: prefix-doubling selection: {trees}", file=sys.stderr, flush=True)
+    gr.close()
+    ctx.close()
+    return {
         "value": len(modes) * R * m_und / (ms_step / 1e3),
-        "unit": "sampled edges/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
         "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic",
-        "config": {"workload": f"rmat{scale}_{prob_tag}_R{R}_k{q.k}_" + "+".join(modes),
-                   "n": n, "m_und": m_und, "R": R, "k": q.k, "alpha_compact": args.alpha,
-                   "prob": prob_name, "parallelism": "single GPU"},
+        "config": {"workload": tag, "n": n, "m_und": m_und, "n_linked": n_linked, "R": R, "k": q.k,
+                   "label_kinds": {m: alphas[m] for m in modes}, "prob": prob_name, "parallelism": "single GPU"},
         "breakdown": breakdown,
         "step_schedule": ("CompactSketch query on a second stream; its selection overlaps the full-label build"
                           if overlap else "queries one after another"),
@@ -637,14 +740,123 @@ def main():
         "kernels": kern,
         "roofline": roofline,
         "device_probe": {"hash_loop_Ghash_s": probe_hash / 1e9, "stream_copy_GB_s": probe_copy / 1e9,
-                         "hbm_peak_GB_s": HBM_PEAK_GBS},
-        "seeds_head": [int(x) for x in res[modes[0]][0][:5]],
+                         "random_4B_reads_G_s": probe_rand / 1e9, "hbm_peak_GB_s": HBM_PEAK_GBS},
+        "seeds": {m: [int(x) for x in res[m][0]] for m in modes},
+        "gains": {m: [int(x) for x in res[m][1]] for m in modes},
     }
-    if not args.no_cpu_baseline and args.workload == "rmat20":
-        print("[bench] timing the oracle on a bounded sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(g, q.prob_kind, q.p, R, q.k, q.seed, args.cpu_sketches)
-    gr.close()
-    ctx.close()
+
+
+def stored_evaluations(name, q):
+    """CELF's per-round evaluation count on the query's sketches, from the oracle's
+    stored results (tests/golden, written by tests/golden/make_golden.py), with the
+    seeds and gains they belong to; None when not stored."""
+    try:
+        from tests.golden import make_golden
+        stored = make_golden.load(name)
+    except (OSError, ImportError, ValueError):
+        return None
+    e = stored.get(make_golden.query_id(make_golden.graph_digest(q.graph), q.prob_kind, q.p, 0.0, q.R, q.seed))
+    if not e or "celf_evaluations" not in e:
+        return None
+    return e
+
+
+def evaluations_vs_celf(res, stored):
+    """NextSeed's re-evaluations on the query's sketches against CELF's (Sec. 5's
+    table of evaluation counts), per label kind, with a check of the seeds and
+    gains against the oracle's stored ones."""
+    if stored is None:
+        return None
+    celf = stored["celf_evaluations"]
+    out = {"celf_total": int(sum(celf)), "celf_max_round": int(max(celf)),
+           "prefix_doubling_oracle_total": int(sum(stored["ptree_evaluations"]))}
+    for m, b in res["breakdown"].items():
+        out[m] = {"winning_tree_total": b["evaluations"], "winning_tree_max_round": b["evaluations_per_round_max"],
+                  "bulk_rounds": b["bulk_rounds"],
+                  "oracle_seeds_equal": res["seeds"][m] == stored["seeds"][:len(res["seeds"][m])],
+                  "oracle_gains_equal": res["gains"][m] == stored["gains"][:len(res["gains"][m])]}
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: the library has no multi-GPU path (asked for {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "batched":
+        return run_batched(args)
+    if args.workload == "serving":
+        return run_serving(args)
+    if args.workload == "sweep":
+        return run_sweep(args)
+    if args.workload == "quality":
+        return run_quality(args)
+    import torch
+
+    from paper_2311_07554_amd import inputs
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    torch.cuda.set_device(0)
+    t = time.perf_counter()
+    if args.workload in ("headline", "rmat24"):
+        # R-MAT 2^24, uniform p = 0.02, R = 256, k = 200, CompactSketch alpha = 0.1
+        w = inputs.rmat24()
+        q = w.queries[0]
+        modes, alphas, overlap = ["compact"], {"compact": q.alpha}, False
+        tag = f"rmat24_p{q.p}_R{q.R}_k{q.k}_compact{q.alpha}"
+        profile_key, golden = "rmat24", "rmat24"
+    else:
+        w = inputs.rmat20(R=args.R, k=args.k, scale=args.scale)
+        q = w.queries[0]
+        modes = [m for m in args.modes.split(",") if m]
+        alphas = {"full": 1.0, "compact": args.alpha}
+        overlap = (not args.no_overlap) and modes == ["full", "compact"]
+        tag = f"rmat{args.scale}_trivalency_R{q.R}_k{q.k}_" + "+".join(modes)
+        profile_key = golden = ("rmat20" if (args.scale == 20 and args.R == 256 and args.k == 100) else None)
+    g = q.graph
+    print(f"[bench] graph {g.name}: n={g.n} m_und={g.m_und} generated in {time.perf_counter() - t:.1f}s",
+          file=sys.stderr, flush=True)
+    r = measure_sketch_workload(args, w, modes, alphas, overlap, tag, profile_key)
+    out = {
+        "metric": METRIC, "value": r["value"], "unit": "sampled edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic", "config": r["config"],
+        "roofline": r["roofline"],
+    }
+    for key in ("breakdown", "step_schedule", "breakdown_isolated", "selection_structures", "kernels",
+                "device_probe"):
+        out[key] = r[key]
+    out["hbm_phases"] = {m: b.pop("hbm", None) for m, b in r["breakdown"].items()}
+    out["seeds_head"] = r["seeds"][modes[0]][:5]
+    if golden:
+        out["evaluations"] = evaluations_vs_celf(r, stored_evaluations(golden, q))
+    if not args.no_cpu_baseline and args.workload in ("headline", "rmat24", "rmat20"):
+        nsk = args.cpu_sketches or (2 if g.n >= (1 << 24) else 16)
+        rounds = 2 if g.n >= (1 << 24) else q.k
+        print(f"[bench] timing the oracle on a bounded sample ({nsk} sketches, {rounds} greedy rounds)",
+              file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(g, q.prob_kind, q.p, q.R, q.k, q.seed, nsk, rounds)
+    del w, q, g
+    if args.workload == "headline" and not args.headline_only:
+        extra = {}
+        a2 = argparse.Namespace(**vars(args))
+        w2 = inputs.rmat20()
+        r2 = measure_sketch_workload(a2, w2, ["full", "compact"], {"full": 1.0, "compact": 0.1}, True,
+                                     "rmat20_trivalency_R256_k100_full+compact", "rmat20")
+        r2["evaluations"] = evaluations_vs_celf(r2, stored_evaluations("rmat20", w2.queries[0]))
+        r2["hbm_phases"] = {m: b.pop("hbm", None) for m, b in r2["breakdown"].items()}
+        for key in ("seeds", "gains"):
+            r2.pop(key)
+        extra["rmat20_step"] = r2
+        del w2
+        print("[bench] extra: batched", file=sys.stderr, flush=True)
+        extra["batched"] = batched_measure(argparse.Namespace(**dict(vars(args), steps=3, warmup=1)))
+        print("[bench] extra: serving", file=sys.stderr, flush=True)
+        extra["serving"] = serving_measure(args)
+        for v in extra.values():
+            v.pop("metric", None)
+        out["extra"] = extra
     print(json.dumps(out), flush=True)
 
 

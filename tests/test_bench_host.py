@@ -56,8 +56,31 @@ def test_traffic_dropped_when_sources_changed(tmp_path, monkeypatch):
     assert bench.sampling_kernel_traffic() is None
 
 
-def test_committed_profile_names_its_command_and_calibration():
-    with open(os.path.join(ROOT, "profiles", "k_sample_hook_rmat20_traffic.txt")) as f:
-        text = f.read()
-    assert "rocprofv3 --pmc FETCH_SIZE" in text and "rocprofv3 --pmc WRITE_SIZE" in text
-    assert "k_probe_copy" in text and "factor" in text
+def test_committed_profiles_name_their_command_and_calibration():
+    for name in ("k_sample_hook_rmat20_traffic.txt", "k_sample_hook_rmat24_traffic.txt"):
+        with open(os.path.join(ROOT, "profiles", name)) as f:
+            text = f.read()
+        assert "rocprofv3 --pmc FETCH_SIZE" in text and "rocprofv3 --pmc WRITE_SIZE" in text
+        assert "k_probe_copy" in text and "factor" in text
+
+
+def test_fifo_latencies_of_the_plain_path():
+    # one server, first come first served: a request waits for the one before it
+    lat = bench.fifo_latencies([0.0, 1.0, 1.5, 10.0], [2.0, 2.0, 0.5, 1.0])
+    assert lat == [2.0, 3.0, 3.0, 1.0]
+    assert bench.fifo_latencies([], []) == []
+
+
+def test_phase_frames_on_the_method_bytes():
+    from types import SimpleNamespace
+    g = SimpleNamespace(n=1 << 20, m_und=1 << 24)
+    kern = {"sample_hook": {"launches": 4, "avg_ms": 2.0}, "bulk_keys": {"launches": 1, "avg_ms": 1.0}}
+    f = bench.phase_frames(kern, True, g, 1 << 19, 64, 4, 256, g.n, 10.0)
+    sk = f["phases"]["sketch"]
+    # 4 passes of half-CSR plus E (8 R n bytes), over the 10 ms build
+    want = 4 * (4.0 * g.m_und + 4.0 * g.n) + 8.0 * 256 * g.n
+    assert sk["algorithmic_bytes_per_build"] == want
+    assert abs(sk["GB_s"] - want / 1e-2 / 1e9) < 1e-6
+    assert f["kernels"]["sample_hook"]["streaming_bytes_per_launch"] == 16.0 * g.m_und
+    mb = f["phases"]["marginal_bulk"]
+    assert mb["algorithmic_bytes_per_launch"] == 8.0 * 256 * g.n + 9.0 * g.n
