@@ -2,12 +2,15 @@
 
 The batched path runs every query's sketch build as one flattened pass over
 (query, pass, edge) items and every query's selection in one workgroup.  The
-best block sizes depend on the mix of graph sizes, so they are measured on the
-batch itself: the sampling block size first (selection fixed), then the
-selection workgroup size, each candidate timed by the graph launch's own device
-time (best of `repeats`).  Results are cached in a JSON file keyed by device
-name and a signature of the batch (sizes, R, k), so a repeated batch shape
-costs no tuning.
+best launch shapes depend on the mix of graph sizes, so they are measured on the
+batch itself, one axis at a time with the others at their best so far: the
+sampling pass's block size, then its grid (0: one item per thread; else that
+many workgroups striding over the items), then the selection workgroup size,
+then the number of selection workgroups (0: one per query, at most 256; fewer
+take several queries each from the shared counter).  Each candidate is timed by
+the graph launch's own device time (best of `repeats`); a tie keeps the earlier
+candidate.  Results are cached in a JSON file keyed by device name and a
+signature of the batch (sizes, R, k), so a repeated batch shape costs no tuning.
 """
 from __future__ import annotations
 
@@ -16,7 +19,13 @@ import json
 import os
 
 HOOK_BLOCKS = (128, 256, 512, 1024)
+HOOK_GRIDS = (0, 1024, 4096, 16384)
 SELECT_BLOCKS = (256, 512, 1024)
+SELECT_GRIDS = (0, 16, 32)
+# search order and starting point of every axis
+AXES = (("hook_block", HOOK_BLOCKS), ("hook_grid", HOOK_GRIDS), ("select_block", SELECT_BLOCKS),
+        ("select_grid", SELECT_GRIDS))
+START = {"hook_block": 128, "hook_grid": 0, "select_block": 1024, "select_grid": 0}
 
 
 def _cache_path():
@@ -71,19 +80,17 @@ def tune(ctx, queries, device_name: str = "gpu", repeats: int = 2, use_cache: bo
         table.append({"config": dict(cfg), "device_ms": best})
         return best
 
-    best_hook, best_t = None, None
-    for hb in HOOK_BLOCKS:
-        t = run({"hook_block": hb, "select_block": 1024})
-        if best_t is None or t < best_t:
-            best_hook, best_t = hb, t
-    best_sel, best_t2 = 1024, best_t
-    for sb in SELECT_BLOCKS:
-        if sb == 1024:
-            continue
-        t = run({"hook_block": best_hook, "select_block": sb})
-        if t < best_t2:
-            best_sel, best_t2 = sb, t
-    cfg = {"hook_block": best_hook, "select_block": best_sel}
+    cfg = dict(START)
+    best_t = run(cfg)
+    for axis, cands in AXES:
+        start = cfg[axis]  # measured already, with the other axes as they are now
+        for v in cands:
+            if v == start:
+                continue
+            trial = dict(cfg, **{axis: v})
+            t = run(trial)
+            if t < best_t:
+                cfg, best_t = trial, t
     if use_cache:
         cache = _load()
         cache[key] = {"config": cfg, "table": table}

@@ -1,10 +1,12 @@
 // Batched selection: many independent queries (graph, model, R, k) built and
 // selected by five persistent kernels that a single hipGraph launches.
 //
-//   k_bat_init      parent[b][v] = v, cnt = 0 over every query's R x n scratch
+//   k_bat_init      parent[b][x] = x, cnt = 0 over every query's R x n scratch
 //   k_bat_hook      sample + union-find hooking over every (query, 64-sketch pass, edge)
-//   k_bat_compress  roots and member counts over every (query, sketch, vertex)
+//   k_bat_compress  roots and member counts over every (query, sketch, number)
 //   k_bat_emit      E[n][R] rows and initial gains over every (query, 64-vertex tile)
+// The forests number vertices in each graph's labelling order (hubs first; the
+// hashes take vertex ids), like the single-query build; E holds vertex ids.
 //   k_bat_select    one workgroup per query (work-stealing counter): winning tree
 //                   built from the initial gains, then k rounds of Algorithm 5
 //                   with the frontier levels separated by workgroup barriers
@@ -31,12 +33,14 @@ namespace pacim {
 struct BatchQuery {
     uint32_t n, R, k, kb;
     uint64_t m;                      // undirected edges
-    const uint2 *edges;              // [m], u < v
+    const uint2 *edges;              // [m], u < v (vertex ids: the hash input)
+    const uint2 *iedges;             // [m], the same edges' endpoints in the graph's labelling order
+    const uint32_t *newid, *iperm;   // [n] labelling order: number of vertex v, vertex of number x
     ProbDev pm;
     const uint64_t *K;               // sketch keys, round_up(R, 8) + 8 entries
     uint2 *E;                        // [n][R]: (CC label, CC size if v is the label else 0)
     uint64_t *gain0;                 // [n]
-    uint32_t *parent, *cnt;          // [R][n] scratch of the build
+    uint32_t *parent, *cnt;          // [R][n] scratch of the build, indexed by labelling-order number
     uint64_t *key;                   // [n]
     uint8_t *in_s;                   // [n]
     uint32_t *ids, *fr;              // winning tree levels / frontiers
@@ -175,7 +179,7 @@ __global__ void __launch_bounds__(1024) k_bat_hook(const BatchQuery *__restrict_
         const uint32_t pass = (uint32_t)(local / Q.m);
         const uint64_t e = local - (uint64_t)pass * Q.m;
         const uint32_t b0 = pass * 64, nb = min(64u, Q.R - b0);
-        const uint2 uv = Q.edges[e];
+        const uint2 uv = Q.edges[e], iuv = Q.iedges[e];
         const uint64_t x = ((uint64_t)uv.x << 32) | uv.y;
         const uint64_t T = edge_threshold(Q.pm, uv.x, uv.y, x);
         uint64_t live;
@@ -192,7 +196,7 @@ __global__ void __launch_bounds__(1024) k_bat_hook(const BatchQuery *__restrict_
             }
             live &= nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
         }
-        unite_live(Q.parent + (size_t)b0 * Q.n, Q.n, live, uv.x, uv.y);
+        unite_live(Q.parent + (size_t)b0 * Q.n, Q.n, live, iuv.x, iuv.y);
     }
 }
 
@@ -261,9 +265,11 @@ __global__ void __launch_bounds__(256) k_bat_emit(const BatchQuery *__restrict__
                 const uint32_t b = idx / kEmitTile, vi = idx % kEmitTile, v = v0 + vi;
                 if (v < n) {
                     const size_t base = (size_t)(b0 + b) * n;
-                    const uint32_t root = Q.parent[base + v];
+                    const uint32_t x = Q.newid[v];
+                    const uint32_t root = Q.parent[base + x];
                     const uint32_t s = 1u + Q.cnt[base + root];
-                    tile[vi][b] = make_uint2(root, root == v ? s : 0u);
+                    // the label is the root's vertex id; its own entry carries the size
+                    tile[vi][b] = root == x ? make_uint2(v, s) : make_uint2(Q.iperm[root], 0u);
                     gsz[vi][b] = s;
                 }
             }

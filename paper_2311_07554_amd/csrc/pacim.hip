@@ -2248,6 +2248,9 @@ im_status run_full_batch(im_ctx *ctx, const std::vector<const im_query *> &queri
         B.kb = std::max<uint32_t>(1, bit_length((uint64_t)n - 1));
         B.m = Q.graph->m_und;
         B.edges = Q.graph->edges;
+        B.iedges = Q.graph->iedges;
+        B.newid = Q.graph->newid;
+        B.iperm = Q.graph->iperm;
         B.pm = prob_dev(Q.prob, Q.graph->off);
         B.cov_mask = cov_slots(R, Q.k) - 1;
         B.td = td;

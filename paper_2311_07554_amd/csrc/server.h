@@ -323,6 +323,9 @@ void srv_admit(im_server *sv) {
         B.kb = std::max<uint32_t>(1, bit_length((uint64_t)g->n - 1));
         B.m = g->m_und;
         B.edges = g->edges;
+        B.iedges = g->iedges;
+        B.newid = g->newid;
+        B.iperm = g->iperm;
         B.pm = prob_dev(t->prob, g->off);
         B.K = set->K;
         B.E = set->E;

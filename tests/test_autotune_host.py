@@ -8,8 +8,9 @@ from paper_2311_07554_amd import autotune
 
 
 class FakeCtx:
-    """select_batched returns a device time that is lowest at hook block 512 and
-    selection block 256; records every configuration it was asked for."""
+    """select_batched returns a device time that is lowest at hook block 512,
+    selection block 256 and sampling grid 4096 (the selection grid does not
+    matter); records every configuration it was asked for."""
 
     def __init__(self, forbid=False):
         self.calls = []
@@ -19,8 +20,8 @@ class FakeCtx:
         if self.forbid:
             raise AssertionError("a cached shape must not be measured again")
         self.calls.append(dict(cfg))
-        hb, sb = cfg["hook_block"], cfg["select_block"]
-        return None, abs(hb - 512) / 64.0 + abs(sb - 256) / 256.0 + 1.0
+        hb, sb, hg = cfg["hook_block"], cfg["select_block"], cfg.get("hook_grid", 0)
+        return None, abs(hb - 512) / 64.0 + abs(sb - 256) / 256.0 + (0.0 if hg == 4096 else 0.5) + 1.0
 
 
 def _queries(n=1000):
@@ -31,11 +32,23 @@ def _queries(n=1000):
 def test_search_picks_the_fastest_shape():
     ctx = FakeCtx()
     cfg, table = autotune.tune(ctx, _queries(), repeats=2, use_cache=False)
-    assert cfg == {"hook_block": 512, "select_block": 256}
-    # sampling blocks first with the selection block fixed, then the other selection blocks
+    # the selection grid is a tie everywhere: its first candidate stays
+    assert cfg == {"hook_block": 512, "hook_grid": 4096, "select_block": 256, "select_grid": 0}
+    # one axis at a time, in order, from the starting shape: the sampling blocks first
     firsts = [c["hook_block"] for c in ctx.calls[::2][:len(autotune.HOOK_BLOCKS)]]
     assert firsts == list(autotune.HOOK_BLOCKS)
-    assert len(table) == len(autotune.HOOK_BLOCKS) + len(autotune.SELECT_BLOCKS) - 1
+    assert table[0]["config"] == autotune.START
+    # every candidate differs from the best shape so far in one axis, visited in order
+    axes = [name for name, _ in autotune.AXES]
+    best, best_t, seen = dict(table[0]["config"]), table[0]["device_ms"], []
+    for t in table[1:]:
+        diff = [k for k in axes if t["config"][k] != best[k]]
+        assert len(diff) == 1, (t, best)
+        seen.append(axes.index(diff[0]))
+        if t["device_ms"] < best_t:
+            best, best_t = dict(t["config"]), t["device_ms"]
+    assert seen == sorted(seen) and best == cfg
+    assert len(table) == 1 + sum(len(c) - 1 for _, c in autotune.AXES)
     assert len(ctx.calls) == 2 * len(table)  # best of `repeats` per candidate
 
 
