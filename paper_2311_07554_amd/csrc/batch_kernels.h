@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(1024) k_bat_hook(const BatchQuery *__restrict_
             }
             live &= nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
         }
-        unite_live(Q.parent + (size_t)b0 * Q.n, Q.n, live, iuv.x, iuv.y);
+        unite_live(Q.parent + (size_t)b0 * Q.n, Q.n, 1u, live, iuv.x, iuv.y);
     }
 }
 

@@ -93,15 +93,21 @@ __device__ __forceinline__ void covmin_mark(const CompactDev &cd, uint32_t r, ui
 __device__ __forceinline__ uint32_t hs_slot(uint32_t w) { return (w * 0x9E3779B1u) >> (32 - 10); }
 static_assert(kHCap == 1024, "hs_slot assumes 2^10 slots");
 
+// The center's label and, in the same round trip, its own size entry: when the
+// center labels its component (the usual case) that is the component's size, and
+// only otherwise is the label's entry read.
 __device__ __forceinline__ BfsOut center_hit(const CompactDev &cd, uint32_t r, uint32_t rank) {
-    const uint32_t l = cd.label_c[tri_at(cd, r, rank)];
-    return BfsOut{cd.size_c[tri_at(cd, r, l)], l, false, 0};
+    const size_t at = tri_at(cd, r, rank);
+    const uint32_t l = cd.label_c[at];
+    const uint32_t own = pin_vgpr(cd.size_c[at]);
+    return BfsOut{l == rank ? own : cd.size_c[tri_at(cd, r, l)], l, false, 0};
 }
 
 // GetCenter with the queue and visited set in LDS (q: kQCap, hs: kHCap words).
+// o0v / o1v: v's adjacency range, already loaded by the caller.
 __device__ BfsOut getcenter_lds(const GraphDev &g, const ProbDev &pm, uint64_t kr, const CompactDev &cd,
                                 uint32_t r, const uint8_t *__restrict__ in_s, uint32_t v, uint32_t *q,
-                                uint32_t *hs) {
+                                uint32_t *hs, uint64_t o0v, uint64_t o1v) {
     const uint32_t lane = lane_id();
     if (center_flag(v, cd.kc, cd.Ta)) return center_hit(cd, r, cd.center_rank[v]);
     for (uint32_t i = lane; i < kHCap; i += kWave) hs[i] = kNone;
@@ -115,9 +121,10 @@ __device__ BfsOut getcenter_lds(const GraphDev &g, const ProbDev &pm, uint64_t k
     bool met = in_s[v] != 0;
     while (head < tail && found == kNone) {
         const uint32_t u = q[head];
+        const uint64_t o0 = head == 0 ? o0v : g.off[u];
+        const uint64_t o1 = head == 0 ? o1v : g.off[u + 1];
         ++head;
-        const uint64_t o1 = g.off[u + 1];
-        for (uint64_t base = g.off[u]; base < o1; base += kWave) {
+        for (uint64_t base = o0; base < o1; base += kWave) {
             const uint64_t j = base + lane;
             bool live = false;
             uint32_t w = 0;
@@ -255,12 +262,15 @@ __device__ __forceinline__ void memo_write(const CompactDev &cd, uint32_t v, uin
 }
 
 // GetCenter through the kept results (all lanes take part; lane 0 writes).
+// v's adjacency range is loaded beside the probe of the kept results, so a search
+// that misses them starts one round trip earlier.
 __device__ __forceinline__ BfsOut getcenter_memo_lds(const GraphDev &g, const ProbDev &pm, uint64_t kr,
                                                      const CompactDev &cd, uint32_t r, const uint8_t *in_s, uint32_t v,
                                                      uint32_t *q, uint32_t *hs) {
+    const uint64_t o0v = g.off[v], o1v = g.off[v + 1];
     BfsOut o;
     if (memo_read(cd, v, r, &o)) return o;
-    o = getcenter_lds(g, pm, kr, cd, r, in_s, v, q, hs);
+    o = getcenter_lds(g, pm, kr, cd, r, in_s, v, q, hs, o0v, o1v);
     if (!o.overflow && lane_id() == 0) memo_write(cd, v, r, o);
     return o;
 }
@@ -371,10 +381,13 @@ __device__ __forceinline__ void markseed_compact_level(SelState *st, const Graph
 }
 
 // MarkSeed of the previous round's seed and the evaluation of this round's root
-// (evl[0], the level-0 list) in one step: per sketch, the same wave first zeroes
-// the seed's CC (so the root's search sees it covered) and then searches from the
-// root.  If the MarkSeed search overflows, the root's search in that sketch is
-// deferred to the evaluation overflow list, which runs after the MarkSeed one.
+// (evl[0], the level-0 list) in one step: per sketch, the same wave first searches
+// from the seed and zeroes its CC, then searches from the root without waiting for
+// that write: the root's CC is the seed's exactly when both searches end at the
+// same label (or, without a center, at the same smallest vertex), and then its
+// delta is 0; any other CC is untouched by this MarkSeed.  If the MarkSeed search
+// overflows, the root's search in that sketch is deferred to the evaluation
+// overflow list, which runs after the MarkSeed one.
 __device__ __forceinline__ void markseed_eval_root_level(SelState *st, const uint32_t *evl,
                                                          unsigned long long *partial, const GraphDev &g,
                                                          const ProbDev &pm, const uint64_t *K, uint32_t R,
@@ -397,13 +410,16 @@ __device__ __forceinline__ void markseed_eval_root_level(SelState *st, const uin
             if (m.label != kNone) cd.size_c[tri_at(cd, r, m.label)] = 0;
             else covmin_mark(cd, r, m.ccmin);
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();
         const BfsOut o = getcenter_memo_lds(g, pm, K[r], cd, r, in_s, v, q, hs);
         if (lane_id() == 0) {
             if (o.visits) atomicAdd(&st->visits, (unsigned long long)o.visits);
-            if (o.overflow) push_overflow(st, &st->ov_cnt[0], ov, ov_cap / 2, 0, r);
-            else add_delta(st, partial, 0, o.delta, evl, kb, in_s, key);
+            if (o.overflow) {
+                push_overflow(st, &st->ov_cnt[0], ov, ov_cap / 2, 0, r);
+            } else {
+                const bool same = o.label != kNone ? o.label == m.label : (m.label == kNone && o.ccmin == m.ccmin);
+                add_delta(st, partial, 0, same ? 0ull : o.delta, evl, kb, in_s, key);
+            }
         }
     }
 }
@@ -455,19 +471,19 @@ __global__ void __launch_bounds__(kBfsBlock) k_markseed_compact(SelState *__rest
 // MarkSeed iff a seed lies in it).  The tree is then rebuilt from the fresh
 // keys, so its root is the plain greedy's choice.
 
-// flag[b][root of s] = 1 for every seed chosen so far (flag zeroed by k_batch_init).
+// flag of (sketch b, root of s) = 1 for every seed chosen so far (flag zeroed by
+// k_batch_init); vertex-major forests of width vs.
 __global__ void __launch_bounds__(256) k_bulk_seed_roots(const SelState *__restrict__ st,
                                                          const uint32_t *__restrict__ seeds,
                                                          const uint32_t *__restrict__ parent,
-                                                         const uint32_t *__restrict__ newid, uint32_t n,
+                                                         const uint32_t *__restrict__ newid, uint32_t vs,
                                                          uint32_t B, uint32_t *__restrict__ flag) {
     const uint32_t ns = st->round;
     const uint64_t total = (uint64_t)ns * B;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t b = (uint32_t)(i / ns), j = (uint32_t)(i % ns);
-        const size_t base = (size_t)b * sketch_stride(n);
-        flag[base + parent[base + newid[seeds[j]]]] = 1u;
+        flag[(size_t)parent[(size_t)newid[seeds[j]] * vs + b] * vs + b] = 1u;
     }
 }
 
@@ -475,16 +491,16 @@ __global__ void __launch_bounds__(256) k_bulk_seed_roots(const SelState *__restr
 __global__ void __launch_bounds__(256) k_bulk_accum(const uint32_t *__restrict__ parent,
                                                     const uint32_t *__restrict__ cnt,
                                                     const uint32_t *__restrict__ flag,
-                                                    const uint32_t *__restrict__ newid, uint32_t n, uint32_t B,
-                                                    unsigned long long *__restrict__ partial) {
+                                                    const uint32_t *__restrict__ newid, uint32_t n, uint32_t vs,
+                                                    uint32_t B, unsigned long long *__restrict__ partial) {
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     const uint32_t iv = newid[v];
     uint64_t s = 0;
     for (uint32_t b = 0; b < B; ++b) {
-        const size_t base = (size_t)b * sketch_stride(n);
-        const uint32_t root = parent[base + iv];
-        s += flag[base + root] ? 0u : 1u + cnt[base + root];
+        const uint32_t root = parent[(size_t)iv * vs + b];
+        const size_t at = (size_t)root * vs + b;
+        s += flag[at] ? 0u : 1u + cnt[at];
     }
     partial[v] += s;
 }

@@ -767,37 +767,41 @@ void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const ui
     // isolated vertices' entries need setting once per build (nothing writes them
     // later, unless a caller flags seeds in minc)
     const uint32_t n_init = init_isolated ? n : g->n_linked;
-    dim3 gi(std::max<uint32_t>((n_init + 255) / 256, 1u), b);
+    const unsigned gi = grid_for((uint64_t)n_init * cs.B, 256, 1u << 20);
     {
         Prof p(ctx, "init", st, timed);
-        k_batch_init<<<gi, 256, 0, st>>>(cs.parent, cs.cnt, minc, n, n_init, minc_init, center_rank);
+        k_batch_init<<<gi, 256, 0, st>>>(cs.parent, cs.cnt, minc, cs.B, n_init, minc_init, center_rank);
     }
     {
         Prof p(ctx, "sample_hook", st, timed);
         switch (pm.kind) {
         case kProbConstant:
-            k_sample_hook<kProbConstant><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->iedges, g->m_und, K, b, pm, cs.parent, n);
+            k_sample_hook<kProbConstant><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->iedges, g->m_und, K, b, pm, cs.parent, cs.B);
             break;
         case kProbTrivalency:
             k_sample_hook<kProbTrivalency><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->iedges, g->m_und, K, b, pm, cs.parent,
-                                                                             n);
+                                                                             cs.B);
             break;
         case kProbRange:
-            k_sample_hook<kProbRange><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->iedges, g->m_und, K, b, pm, cs.parent, n);
+            k_sample_hook<kProbRange><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->iedges, g->m_und, K, b, pm, cs.parent, cs.B);
             break;
         case kProbWic:
-            k_sample_hook<kProbWic><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->iedges, g->m_und, K, b, pm, cs.parent, n);
+            k_sample_hook<kProbWic><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->iedges, g->m_und, K, b, pm, cs.parent, cs.B);
             break;
         default:
             k_sample_hook<kProbPerEdge><<<hook_grid, kHookBlock, 0, st>>>(g->edges, g->iedges, g->m_und, K, b, pm, cs.parent,
-                                                                          n);
+                                                                          cs.B);
             break;
         }
     }
     {
         Prof p(ctx, "compress", st, timed);
-        dim3 gc(std::min<unsigned>((n + 256 * kCompressIlp - 1) / (256 * kCompressIlp), 64u), b);
-        k_compress<<<gc, 256, 0, st>>>(cs.parent, cs.cnt, n, g->n_linked, center_rank, minc);
+        // runs of at most 512 numbers, short enough for about 16 waves per SIMD
+        const uint32_t run = (uint32_t)std::min<uint64_t>(
+            kCompressRunMax, std::max<uint64_t>(kCompressIlp, ((uint64_t)g->n_linked / 16384 + 3) & ~3ull));
+        const uint64_t runs = ((uint64_t)g->n_linked + run - 1) / run;  // one wave each
+        k_compress<<<std::max<uint64_t>((runs + 3) / 4, 1), 256, 0, st>>>(cs.parent, cs.cnt, cs.B, b, g->n_linked,
+                                                                          run, center_rank, minc);
     }
 }
 
@@ -811,7 +815,7 @@ void enqueue_full_build(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const
         const uint32_t b = std::min(cs.B, R - r0);
         enqueue_cc_pass(ctx, g, pm, K + r0, b, cs, nullptr, kNone, nullptr, r0 == 0, st);
         Prof p(ctx, "emit", st);
-        k_emit_full<<<(n + kEmitTile - 1) / kEmitTile, 256, 0, st>>>(cs.parent, cs.cnt, g->newid, g->iperm, n,
+        k_emit_full<<<((n + kWave - 1) / kWave + 3) / 4, 256, 0, st>>>(cs.parent, cs.cnt, g->newid, g->iperm, n, cs.B,
                                                                      g->n_linked, b, R, r0, E, gain0);
     }
 }
@@ -996,15 +1000,15 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
         const uint32_t b = std::min(B, R - r0);
         enqueue_cc_pass(ctx, g, s->pm, s->K + r0, b, cs, minc, kNone, s->compact ? cs.crank : nullptr, r0 == 0);
         if (s->compact) {
-            k_giant_sample<<<b, 256, 0, st>>>(parent, cnt, n, s->gbest + r0);
+            k_giant_sample<<<b, 256, 0, st>>>(parent, cnt, n, cs.B, s->gbest + r0);
             Prof p(ctx, "emit");
-            k_gain0_emit<<<(n + kWave - 1) / kWave, 256, 0, st>>>(parent, cnt, minc, s->center_rank, s->rho, n, b, r0,
+            k_gain0_emit<<<(s->nw + 3) / 4, 256, 0, st>>>(parent, cnt, minc, s->center_rank, s->rho, n, cs.B, b, r0,
                                                           R, s->label_c, s->size_c, s->gain0, s->gbest + r0,
                                                           s->gbits, s->nw, s->gsum, g->newid,
                                                           g->n_linked);
         } else {
             Prof p(ctx, "emit");
-            k_emit_full<<<(n + kEmitTile - 1) / kEmitTile, 256, 0, st>>>(parent, cnt, g->newid, g->iperm, n,
+            k_emit_full<<<((n + kWave - 1) / kWave + 3) / 4, 256, 0, st>>>(parent, cnt, g->newid, g->iperm, n, cs.B,
                                                                          g->n_linked, b, R, r0, s->E, s->gain0);
         }
         SK_HIP(hipGetLastError());
@@ -1282,8 +1286,8 @@ im_status enqueue_bulk_keys(im_sketches *s) {
         const uint32_t b = std::min(B, s->R - r0);
         enqueue_cc_pass(ctx, s->g, s->pm, s->K + r0, b, cs, flag, 0u, nullptr);
         k_bulk_seed_roots<<<grid_for((uint64_t)n * b, 256, 1024), 256, 0, st>>>(s->st, s->seeds_d, parent,
-                                                                                 s->g->newid, n, b, flag);
-        k_bulk_accum<<<(n + 255) / 256, 256, 0, st>>>(parent, cnt, flag, s->g->newid, n, b, s->partial);
+                                                                                 s->g->newid, cs.B, b, flag);
+        k_bulk_accum<<<(n + 255) / 256, 256, 0, st>>>(parent, cnt, flag, s->g->newid, n, cs.B, b, s->partial);
     }
     k_bulk_keys<<<(n + 255) / 256, 256, 0, st>>>(s->st, s->partial, n, s->kb, s->in_s, s->key);
     HIP_TRY(ctx, hipGetLastError());
@@ -1830,7 +1834,7 @@ extern "C" im_status im_influence(im_ctx *ctx, const im_graph *g, im_prob prob, 
             const uint32_t b = std::min(cs.B, sims - a);
             enqueue_cc_pass(ctx, g, pm, K + a, b, cs, cs.minc, 0u, nullptr);
             k_influence_accum<<<dim3(grid_for(k, 256, 64), b), 256, 0, st>>>(cs.parent, cs.cnt, cs.minc, g->newid,
-                                                                            g->n, sd, k, tot);
+                                                                            cs.B, sd, k, tot);
         }
         e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(&host_total, tot, 8, hipMemcpyDeviceToHost, st);
@@ -1940,7 +1944,7 @@ extern "C" im_status im_influence_noalloc(im_ctx *ctx, const im_graph *g, im_pro
             k_world_keys<<<1, 128, 0, st>>>(sim_seed, w0 + a, key_slots(b), K);
             enqueue_cc_pass(ctx, g, pm, K, b, cs, cs.minc, 0u, nullptr, true, st, false);
             k_influence_accum<<<dim3(grid_for(k, 256, 64), b), 256, 0, st>>>(cs.parent, cs.cnt, cs.minc, g->newid,
-                                                                            g->n, sd, k, tot);
+                                                                            cs.B, sd, k, tot);
         }
         e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(&host_total, tot, 8, hipMemcpyDeviceToHost, st);

@@ -21,6 +21,13 @@
 // so that the parents that most unions touch share a few cache lines.  The
 // hashes still take the vertices' own ids.  Readers translate with newid; a
 // label written out is a vertex id again (iperm of the root).
+//
+// Scratch layout (parent, cnt, minc) is vertex-major: the entry of sketch b and
+// number x is at x * vs + b, vs = the scratch's sketches per pass, so a vertex's
+// entries in all the pass's sketches share one or two cache lines.  The edges of
+// one vertex are consecutive in the edge list, so the live sketches of one
+// wave's edges mostly read the same lines for their first endpoint; the per-vertex
+// passes read a vertex's sketches together.
 #pragma once
 
 #include "common.h"
@@ -43,14 +50,15 @@ __global__ void k_world_keys(uint64_t seed, uint32_t first, uint32_t count, uint
 // sizes (1 + members counted at the root) summed into *total.  grid (x, B).
 __global__ void __launch_bounds__(256) k_influence_accum(const uint32_t *__restrict__ parent,
                                                          const uint32_t *__restrict__ cnt, uint32_t *__restrict__ flag,
-                                                         const uint32_t *__restrict__ newid, uint32_t n,
+                                                         const uint32_t *__restrict__ newid, uint32_t vs,
                                                          const uint32_t *__restrict__ seeds, uint32_t k,
                                                          unsigned long long *__restrict__ total) {
-    const size_t base = (size_t)blockIdx.y * sketch_stride(n);
+    const uint32_t b = blockIdx.y;
     uint64_t sum = 0;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
-        const uint32_t root = parent[base + newid[seeds[i]]];
-        if (atomicExch(&flag[base + root], 1u) == 0u) sum += 1u + cnt[base + root];
+        const uint32_t root = parent[(size_t)newid[seeds[i]] * vs + b];
+        const size_t at = (size_t)root * vs + b;
+        if (atomicExch(&flag[at], 1u) == 0u) sum += 1u + cnt[at];
     }
     sum = wave_sum_u64(sum);
     if (lane_id() == 0 && sum) atomicAdd(total, (unsigned long long)sum);
@@ -81,16 +89,24 @@ __global__ void k_to_label_order(const uint32_t *__restrict__ in, const uint32_t
 // minc starts at each vertex's own center rank when center_rank is given (so a
 // root's own rank needs no atomic), else at minc_init.  Numbers [0, n_init):
 // isolated vertices (numbered last) keep their entries from an earlier pass of
-// the same build, as no pass writes them.
+// the same build, as no pass writes them.  One thread per (number, sketch) of
+// the first n_init numbers, in layout order.
 __global__ void k_batch_init(uint32_t *__restrict__ parent, uint32_t *__restrict__ cnt, uint32_t *__restrict__ minc,
-                             uint32_t n, uint32_t n_init, uint32_t minc_init,
+                             uint32_t vs, uint32_t n_init, uint32_t minc_init,
                              const uint32_t *__restrict__ center_rank) {
-    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t at = (size_t)blockIdx.y * sketch_stride(n) + v;
-    if (v < n_init) {
-        parent[at] = v;
-        cnt[at] = 0;
-        if (minc) minc[at] = center_rank ? center_rank[v] : minc_init;
+    const uint64_t total = (uint64_t)n_init * vs;
+    const uint64_t step = (uint64_t)gridDim.x * blockDim.x;
+    auto one = [&](uint64_t i, uint32_t x) {
+        parent[i] = x;
+        cnt[i] = 0;
+        if (minc) minc[i] = center_rank ? center_rank[x] : minc_init;
+    };
+    if (total <= 0xFFFFFFFFull) {  // 32-bit division by the width (the common case)
+        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += step)
+            one(i, (uint32_t)i / vs);
+    } else {
+        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += step)
+            one(i, (uint32_t)(i / vs));
     }
 }
 
@@ -101,27 +117,28 @@ __device__ __forceinline__ uint32_t uf_load(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ __forceinline__ uint32_t uf_find(uint32_t *P, uint32_t x) {
+// One sketch's forest: entry of number x at P[x * vs].
+__device__ __forceinline__ uint32_t uf_find(uint32_t *P, uint32_t vs, uint32_t x) {
     for (;;) {
-        uint32_t p = uf_load(P + x);
+        uint32_t p = uf_load(P + (size_t)x * vs);
         if (p == x) return x;
-        uint32_t gp = uf_load(P + p);
+        uint32_t gp = uf_load(P + (size_t)p * vs);
         if (gp == p) return p;
         // path halving; any ancestor is a valid parent
-        __hip_atomic_store(P + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(P + (size_t)x * vs, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         x = gp;
     }
 }
 
 // uf_find continuing from x whose parent p the caller already loaded.
-__device__ __forceinline__ uint32_t uf_find_from(uint32_t *P, uint32_t x, uint32_t p) {
+__device__ __forceinline__ uint32_t uf_find_from(uint32_t *P, uint32_t vs, uint32_t x, uint32_t p) {
     for (;;) {
         if (p == x) return x;
-        const uint32_t gp = uf_load(P + p);
+        const uint32_t gp = uf_load(P + (size_t)p * vs);
         if (gp == p) return p;
-        __hip_atomic_store(P + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(P + (size_t)x * vs, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         x = gp;
-        p = uf_load(P + x);
+        p = uf_load(P + (size_t)x * vs);
     }
 }
 
@@ -130,18 +147,19 @@ __device__ __forceinline__ uint32_t uf_find_from(uint32_t *P, uint32_t x, uint32
 // returns the root's fresh parent, strictly smaller, so a+b strictly decreases
 // on every retry: the loop ends even when uf_find read old values.  pa / pb:
 // the parents of a and b, already loaded.
-__device__ __forceinline__ void uf_unite_from(uint32_t *P, uint32_t a, uint32_t pa, uint32_t b, uint32_t pb) {
-    a = uf_find_from(P, a, pa);
-    b = uf_find_from(P, b, pb);
+__device__ __forceinline__ void uf_unite_from(uint32_t *P, uint32_t vs, uint32_t a, uint32_t pa, uint32_t b,
+                                              uint32_t pb) {
+    a = uf_find_from(P, vs, a, pa);
+    b = uf_find_from(P, vs, b, pb);
     for (;;) {
         if (a == b) return;
         if (a < b) { uint32_t t = a; a = b; b = t; }
         uint32_t expected = a;
-        if (__hip_atomic_compare_exchange_strong(P + a, &expected, b, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT))
+        if (__hip_atomic_compare_exchange_strong(P + (size_t)a * vs, &expected, b, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             return;
-        a = uf_find(P, expected);
-        b = uf_find(P, b);
+        a = uf_find(P, vs, expected);
+        b = uf_find(P, vs, b);
     }
 }
 
@@ -168,10 +186,13 @@ constexpr uint32_t kHookBlock = 256;
 constexpr int kHookIlp = 4;  // live sketches of an edge whose first parent loads are issued together
 
 // Unions of edge (u, v) in every sketch whose bit is set in live (sketch b's
-// forest at parent + b * stride).  The parents of both endpoints in up to
-// kHookIlp sketches are loaded before any of those unions walks on, so a thread
-// keeps several independent memory accesses in flight instead of one chain.
-__device__ __forceinline__ void unite_live(uint32_t *parent, size_t stride, uint64_t live, uint32_t u, uint32_t v) {
+// entry of number x at parent[b * ss + x * vs]: ss = 1, vs = the pass's scratch
+// width for the vertex-major single-query scratch; ss = n, vs = 1 for the batched
+// path's sketch-major rows).  The parents of both endpoints in up to kHookIlp
+// sketches are loaded before any of those unions walks on, so a thread keeps
+// several independent memory accesses in flight instead of one chain.
+__device__ __forceinline__ void unite_live(uint32_t *parent, size_t ss, uint32_t vs, uint64_t live, uint32_t u,
+                                           uint32_t v) {
     while (live) {
         uint32_t bs[kHookIlp], pu[kHookIlp], pv[kHookIlp];
         int c = 0;
@@ -187,163 +208,153 @@ __device__ __forceinline__ void unite_live(uint32_t *parent, size_t stride, uint
 #pragma unroll
         for (int i = 0; i < kHookIlp; ++i)
             if (i < c) {
-                const uint32_t *P = parent + (size_t)bs[i] * stride;
-                pu[i] = uf_load(P + u);
-                pv[i] = uf_load(P + v);
+                const uint32_t *P = parent + (size_t)bs[i] * ss;
+                pu[i] = uf_load(P + (size_t)u * vs);
+                pv[i] = uf_load(P + (size_t)v * vs);
             }
 #pragma unroll
         for (int i = 0; i < kHookIlp; ++i)
-            if (i < c) uf_unite_from(parent + (size_t)bs[i] * stride, u, pu[i], v, pv[i]);
+            if (i < c) uf_unite_from(parent + (size_t)bs[i] * ss, vs, u, pu[i], v, pv[i]);
     }
 }
 
 // One thread per undirected edge: its live mask over the pass's sketches (from
 // the endpoints' ids, edges[e]), then one union per live sketch (between the
-// endpoints' labelling-order numbers, iedges[e]).
+// endpoints' labelling-order numbers, iedges[e]) in the vertex-major forests of
+// width vs.
 template <int KIND>
 __global__ void __launch_bounds__(kHookBlock) k_sample_hook(const uint2 *__restrict__ edges,
                                                             const uint2 *__restrict__ iedges, uint64_t m,
                                                             const uint64_t *__restrict__ K, uint32_t B, ProbDev pm,
-                                                            uint32_t *__restrict__ parent, uint32_t n) {
-    const size_t ns = sketch_stride(n);
+                                                            uint32_t *__restrict__ parent, uint32_t vs) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
         const uint2 uv = edges[e], iuv = iedges[e];
-        unite_live(parent, ns, live_mask<KIND>(uv.x, uv.y, ((uint64_t)uv.x << 32) | uv.y, e, K, B, pm), iuv.x, iuv.y);
+        unite_live(parent, 1, vs, live_mask<KIND>(uv.x, uv.y, ((uint64_t)uv.x << 32) | uv.y, e, K, B, pm), iuv.x,
+                   iuv.y);
     }
 }
 
-// grid: (G, B), block 256: the blocks of sketch blockIdx.y stride over its
-// first n_act numbers (the vertices with an edge; an isolated vertex stays its
-// own root with no members and its own center rank).  A wave takes 4 x 64
-// consecutive numbers per step, issuing the four parent loads (and root walks)
-// together before counting.  In social-like graphs almost every non-root vertex
-// of a sketch lies in one giant component, so per-vertex atomics on its root
-// counter serialise.  Each wave therefore keeps the first root it meets as a
-// "hot" root whose member count and smallest center rank it accumulates in
-// registers and flushes once at the end; members of other roots are combined per
-// distinct root in the wave and added with one atomic per root.
+// Pointer jumping and counting over the first n_act numbers (the vertices with
+// an edge; an isolated vertex stays its own root with no members and its own
+// center rank).  One wave per run of `run` consecutive numbers (a multiple of
+// kCompressIlp, at most kCompressRunMax), lane b =
+// sketch b of the pass (b < nb): for each number x the wave reads x's entries of
+// all sketches in one or two cache lines, each lane walks to its root, points x
+// at it and counts x there.  kCompressIlp numbers are loaded together.  In
+// social-like graphs most non-root vertices of a sketch lie in one giant
+// component, so per-vertex atomics on its root counter would serialise: each lane
+// keeps a "hot" root whose member count and smallest center rank it accumulates
+// in registers (the first root it meets, replaced while it has at most one
+// member) and flushes them with one atomic each; other roots get one atomic per
+// member.
+constexpr uint32_t kCompressRunMax = 512;
 constexpr uint32_t kCompressIlp = 4;
 __global__ void __launch_bounds__(256) k_compress(uint32_t *__restrict__ parent, uint32_t *__restrict__ cnt,
-                                                  uint32_t n, uint32_t n_act,
+                                                  uint32_t vs, uint32_t nb, uint32_t n_act, uint32_t run,
                                                   const uint32_t *__restrict__ center_rank,
                                                   uint32_t *__restrict__ minc) {
-    const uint32_t lane = lane_id();
-    const size_t base = (size_t)blockIdx.y * sketch_stride(n);
-    uint32_t *P = parent + base;
-    uint32_t hot = kNone, hot_cnt = 0, hot_min = kNone;  // wave-uniform
-    const uint32_t stride = gridDim.x * blockDim.x * kCompressIlp;
-    const uint32_t wbase = (blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1))) * kCompressIlp;
-    for (uint32_t v0 = wbase; v0 < n_act; v0 += stride) {
-        uint32_t rr[kCompressIlp], pp[kCompressIlp], cc[kCompressIlp];
+    const uint32_t b = lane_id();
+    const bool act = b < nb;
+    const uint64_t x0 = (uint64_t)wave_index() * run;
+    if (x0 >= n_act) return;
+    const uint32_t x1 = (uint32_t)min<uint64_t>(x0 + run, n_act);
+    uint32_t hot = kNone, hot_cnt = 0, hot_min = kNone;
+    for (uint32_t xb = (uint32_t)x0; xb < x1; xb += kCompressIlp) {
+        uint32_t pp[kCompressIlp], cr[kCompressIlp];
 #pragma unroll
         for (uint32_t j = 0; j < kCompressIlp; ++j) {
-            const uint32_t v = v0 + j * kWave + lane;
-            rr[j] = v;
-            pp[j] = v < n_act ? P[v] : v;
-            if (center_rank) cc[j] = center_rank[v < n_act ? v : 0];
+            const uint32_t x = xb + j;
+            const bool ok = act && x < x1;
+            pp[j] = parent[ok ? (size_t)x * vs + b : 0];
+            cr[j] = center_rank ? center_rank[x < x1 ? x : xb] : kNone;  // the same x in every lane
         }
 #pragma unroll
         for (uint32_t j = 0; j < kCompressIlp; ++j) {
-            const uint32_t v = v0 + j * kWave + lane;
-            uint32_t r = rr[j], p = pp[j];
-            while (p != r) { r = p; p = P[r]; }
-            if (r != v && v < n_act) P[v] = r;
-            rr[j] = r;
-        }
-#pragma unroll
-        for (uint32_t j = 0; j < kCompressIlp; ++j) {
-            const uint32_t v = v0 + j * kWave + lane;
-            const bool valid = v < n_act;
-            const uint32_t r = rr[j];
-            bool need = valid && r != v;
-            if (hot == kNone) {
-                const uint64_t m = __ballot(need);
-                if (m) hot = __shfl(r, (int)__builtin_ctzll(m));
-            }
-            const bool in_hot = need && r == hot;
-            hot_cnt += (uint32_t)__popcll(__ballot(in_hot));
-            if (in_hot) need = false;
-            for (uint64_t m = __ballot(need); m; m = __ballot(need)) {
-                const uint32_t lr = __shfl(r, (int)__builtin_ctzll(m));
-                const bool same = need && r == lr;
-                const uint64_t sm = __ballot(same);
-                if (lane == (uint32_t)__builtin_ctzll(m)) atomicAdd(cnt + base + lr, (uint32_t)__popcll(sm));
-                if (same) need = false;
-            }
-            if (center_rank) {
-                const uint32_t cr = valid ? pin_vgpr(cc[j]) : kNone;
-                bool cneed = cr != kNone && r != v;  // a root's own rank is already in minc
-                uint32_t hm = (cneed && r == hot) ? cr : kNone;
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) hm = min(hm, (uint32_t)__shfl_xor(hm, off));
-                hot_min = min(hot_min, hm);
-                if (r == hot) cneed = false;
-                for (uint64_t m = __ballot(cneed); m; m = __ballot(cneed)) {
-                    const uint32_t lr = __shfl(r, (int)__builtin_ctzll(m));
-                    const bool same = cneed && r == lr;
-                    uint32_t mn = same ? cr : kNone;
-#pragma unroll
-                    for (int off = 32; off > 0; off >>= 1) mn = min(mn, (uint32_t)__shfl_xor(mn, off));
-                    if (lane == (uint32_t)__builtin_ctzll(m)) atomicMin(minc + base + lr, mn);
-                    if (same) cneed = false;
+            const uint32_t x = xb + j;
+            if (!act || x >= x1) continue;
+            uint32_t r = x, p = pin_vgpr(pp[j]);
+            while (p != r) { r = p; p = parent[(size_t)r * vs + b]; }
+            if (r == x) continue;
+            parent[(size_t)x * vs + b] = r;
+            const uint32_t c = cr[j];
+            if (r != hot && hot_cnt <= 1) {  // take r as the hot root, giving back a weak one
+                if (hot != kNone) {
+                    if (hot_cnt) atomicAdd(cnt + (size_t)hot * vs + b, hot_cnt);
+                    if (hot_min != kNone) atomicMin(minc + (size_t)hot * vs + b, hot_min);
                 }
+                hot = r;
+                hot_cnt = 0;
+                hot_min = kNone;
+            }
+            if (r == hot) {
+                ++hot_cnt;
+                hot_min = min(hot_min, c);  // a root's own rank is already in minc
+            } else {
+                atomicAdd(cnt + (size_t)r * vs + b, 1u);
+                if (c != kNone) atomicMin(minc + (size_t)r * vs + b, c);
             }
         }
     }
-    if (lane == 0 && hot != kNone) {
-        if (hot_cnt) atomicAdd(cnt + base + hot, hot_cnt);
-        if (center_rank && hot_min != kNone) atomicMin(minc + base + hot, hot_min);
+    if (hot != kNone) {
+        if (hot_cnt) atomicAdd(cnt + (size_t)hot * vs + b, hot_cnt);
+        if (hot_min != kNone) atomicMin(minc + (size_t)hot * vs + b, hot_min);
     }
 }
 
-// One block of 256 threads per tile of 32 vertices; B <= 64.  The (label, size)
-// entries of the tile are staged in LDS (17 KB, so that many blocks share a CU)
-// and each E row segment E[v][r0 .. r0+B) is written by consecutive lanes.
-// Thread t reads the entries of vertex t % 32 in sketches t / 32, t / 32 + 8, ...
-// and keeps their sizes' sum for the initial gains.
-constexpr int kEmitTile = 32;
-constexpr int kEmitGroups = 256 / kEmitTile;
+// The vertex-major passes below take one wave per 64 consecutive vertices, lane b
+// = sketch b of the pass (b < nb): per vertex the wave reads the vertex's nb
+// forest entries in one or two cache lines, gathers the root sizes, and sums the
+// initial gain across the lanes; kEmitIlp vertices are in flight together.  The
+// per-vertex values (labelling-order number, center rank) are the same in every
+// lane.  Isolated vertices (numbers >= n_linked) are their own singletons and read
+// nothing.
+constexpr int kEmitTile = 32;  // vertices per tile of the batched emit
+constexpr uint32_t kEmitIlp = 4;
+
+// Sum over the wave of x, carried in 64 bits.
+__device__ __forceinline__ uint64_t wave_sum_lanes(uint64_t x) { return wave_sum_u64(x); }
+
+// Full labels: E[v][r0 + b] = (label, size at the label's own entry) with the
+// label the root's vertex id, and the initial gains.
 __global__ void __launch_bounds__(256) k_emit_full(const uint32_t *__restrict__ parent,
                                                    const uint32_t *__restrict__ cnt,
                                                    const uint32_t *__restrict__ newid,
-                                                   const uint32_t *__restrict__ iperm, uint32_t n,
-                                                   uint32_t n_linked, uint32_t B, uint32_t R, uint32_t r0,
+                                                   const uint32_t *__restrict__ iperm, uint32_t n, uint32_t vs,
+                                                   uint32_t n_linked, uint32_t nb, uint32_t R, uint32_t r0,
                                                    uint2 *__restrict__ E, uint64_t *__restrict__ gain0) {
-    __shared__ uint2 tile[kEmitTile][65];
-    __shared__ uint64_t part[kEmitGroups][kEmitTile];
-    const uint32_t v0 = blockIdx.x * kEmitTile;
-    const uint32_t vi = threadIdx.x % kEmitTile, grp = threadIdx.x / kEmitTile, v = v0 + vi;
-    const size_t ns = sketch_stride(n);
-    uint64_t acc = 0;
-    const uint32_t iv = v < n ? newid[v] : 0u;
-    if (v < n && iv >= n_linked) {  // isolated: its own singleton in every sketch
-        for (uint32_t b = grp; b < B; b += kEmitGroups) {
-            tile[vi][b] = make_uint2(v, 1u);
-            acc += 1u;
-        }
-    } else if (v < n) {
-#pragma unroll 4
-        for (uint32_t b = grp; b < B; b += kEmitGroups) {
-            const size_t base = (size_t)b * ns;
-            const uint32_t root = parent[base + iv];
-            const uint32_t sz = 1u + cnt[base + root];
-            // the label is the root's vertex id; its own entry carries the size
-            tile[vi][b] = root == iv ? make_uint2(v, sz) : make_uint2(iperm[root], 0u);
-            acc += sz;
-        }
-    }
-    part[grp][vi] = acc;
-    __syncthreads();
-    for (uint32_t idx = threadIdx.x; idx < kEmitTile * B; idx += blockDim.x) {
-        const uint32_t ti = idx / B, b = idx % B, tv = v0 + ti;
-        if (tv < n) E[(size_t)tv * R + r0 + b] = tile[ti][b];
-    }
-    if (threadIdx.x < kEmitTile && v0 + threadIdx.x < n) {
-        uint64_t s = 0;
+    const uint32_t b = lane_id();
+    const bool act = b < nb;
+    const uint32_t v0 = wave_index() * kWave;
+    if (v0 >= n) return;
+    for (uint32_t j0 = 0; j0 < kWave; j0 += kEmitIlp) {
+        uint32_t iv[kEmitIlp], t[kEmitIlp], root[kEmitIlp], c[kEmitIlp], lab[kEmitIlp];
 #pragma unroll
-        for (int g = 0; g < kEmitGroups; ++g) s += part[g][threadIdx.x];
-        gain0[v0 + threadIdx.x] += s;
+        for (uint32_t u = 0; u < kEmitIlp; ++u) {
+            const uint32_t v = v0 + j0 + u;
+            iv[u] = v < n ? newid[v] : 0u;
+            const bool rd = act && v < n && iv[u] < n_linked;
+            t[u] = parent[rd ? (size_t)iv[u] * vs + b : 0];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kEmitIlp; ++u) {
+            const uint32_t v = v0 + j0 + u;
+            const bool rd = act && v < n && iv[u] < n_linked;
+            root[u] = rd ? pin_vgpr(t[u]) : iv[u];
+            c[u] = cnt[rd ? (size_t)root[u] * vs + b : 0];
+            lab[u] = iperm[rd ? root[u] : 0];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kEmitIlp; ++u) {
+            const uint32_t v = v0 + j0 + u;
+            if (v >= n) break;  // wave-uniform
+            const bool rd = act && iv[u] < n_linked;
+            const uint32_t sz = !act ? 0u : (rd ? 1u + pin_vgpr(c[u]) : 1u);
+            const bool own = root[u] == iv[u];
+            if (act) E[(size_t)v * R + r0 + b] = own ? make_uint2(v, sz) : make_uint2(pin_vgpr(lab[u]), 0u);
+            const uint64_t g = wave_sum_lanes(sz);
+            if (b == 0) gain0[v] += g;
+        }
     }
 }
 
@@ -357,15 +368,16 @@ __device__ __forceinline__ uint32_t giant_size_of(uint64_t gbest) { return (uint
 // the bulk rounds that use it; a small one only makes them search more.
 constexpr uint32_t kGiantSamples = 1024;
 __global__ void __launch_bounds__(256) k_giant_sample(const uint32_t *__restrict__ parent,
-                                                      const uint32_t *__restrict__ cnt, uint32_t n,
+                                                      const uint32_t *__restrict__ cnt, uint32_t n, uint32_t vs,
                                                       unsigned long long *__restrict__ gbest) {
     __shared__ unsigned long long best_w[256 / kWave];
-    const size_t base = (size_t)blockIdx.x * sketch_stride(n);
+    const uint32_t b = blockIdx.x;
     unsigned long long best = 0;
     for (uint32_t j = threadIdx.x; j < kGiantSamples; j += blockDim.x) {
         const uint32_t v = (uint32_t)((uint64_t)j * n / kGiantSamples);
-        const uint32_t root = parent[base + v];
-        const unsigned long long c = ((unsigned long long)(1u + cnt[base + root]) << 32) | (0xFFFFFFFFull - root);
+        const uint32_t root = parent[(size_t)v * vs + b];
+        const unsigned long long c = ((unsigned long long)(1u + cnt[(size_t)root * vs + b]) << 32) |
+                                     (0xFFFFFFFFull - root);
         best = c > best ? c : best;
     }
     best = wave_max_u64(best);
@@ -377,135 +389,89 @@ __global__ void __launch_bounds__(256) k_giant_sample(const uint32_t *__restrict
     }
 }
 
-// One pass over every vertex of the pass's B sketches (compressed: parent[b][v] is
-// v's root) for CompactSketch:
+// One pass over every vertex of the pass's nb sketches (compressed: every entry
+// points at its root) for CompactSketch, one wave per 64-vertex word as above:
 //   - the initial gains, sum over sketches of |CC_b(v)|;
 //   - gbits non-null: bit v % 64 of gbits[(v / 64) * R + r0 + b] = [v lies in the
 //     component of giant_root_of(gbest[b])] (word-major: a vertex word's R
-//     sketches are contiguous), and gsum[v] += the sizes of those components over
-//     the pass's sketches (the bulk rounds' sum over covered largest components
-//     starts from it);
+//     sketches are contiguous, and here lane b writes its word once), and
+//     gsum[v] += the sizes of those components over the pass's sketches (the bulk
+//     rounds' sum over covered largest components starts from it);
 //   - for a center v of rank cr, its triple entries label_c[cr][r0 + b] = the
 //     smallest center rank in its component (minc at the root) and size_c = the
-//     component size if that rank is cr's own, else 0 (center-major [rho][R]).
-// A workgroup takes 64 consecutive vertices (one per lane) and its four waves
-// split the sketches (wave w: b = w, w + 4, ...), so a lane issues the root loads
-// of up to 16 sketches before the first size gather; the waves' gain sums meet
-// in LDS.  The block's centers have consecutive ranks, so their triple entries
-// of the pass are runs of B words, one per center: up to 16 centers are staged in
-// LDS and written out with one lane per sketch (a block with more centers, rare
-// for alpha < 1/4, writes them directly); the largest-component bitmap words of
-// the block (B contiguous words) are staged the same way.  B <= 64.
-constexpr uint32_t kG0Waves = 4;
-constexpr uint32_t kG0PerWave = 64 / kG0Waves;
-constexpr uint32_t kG0StageCenters = 16;
+//     component size if that rank is cr's own, else 0 (center-major [rho][R], so
+//     the wave writes a center's entries as one run).
 __global__ void __launch_bounds__(256) k_gain0_emit(const uint32_t *__restrict__ parent,
                                                     const uint32_t *__restrict__ cnt,
                                                     const uint32_t *__restrict__ minc,
                                                     const uint32_t *__restrict__ center_rank, uint32_t rho,
-                                                    uint32_t n, uint32_t B, uint32_t r0, uint32_t R,
+                                                    uint32_t n, uint32_t vs, uint32_t nb, uint32_t r0, uint32_t R,
                                                     uint32_t *__restrict__ label_c, uint32_t *__restrict__ size_c,
                                                     uint64_t *__restrict__ gain0,
                                                     const unsigned long long *__restrict__ gbest,
                                                     uint64_t *__restrict__ gbits, uint32_t nw,
                                                     uint64_t *__restrict__ gsum,
                                                     const uint32_t *__restrict__ newid, uint32_t n_linked) {
-    __shared__ unsigned long long part[kG0Waves][kWave], gpart[kG0Waves][kWave], gword[kWave];
-    __shared__ uint32_t tl[kG0StageCenters][kWave + 1], ts[kG0StageCenters][kWave + 1];
-    const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
-    const uint32_t v = blockIdx.x * kWave + lane;
-    const bool valid = v < n;
-    const uint32_t cr = valid ? center_rank[v] : kNone;
-    const uint64_t cmask = __ballot(cr != kNone);  // the same in every wave of the block
-    const uint32_t nc = (uint32_t)__popcll(cmask);
-    const bool stage = nc <= kG0StageCenters;
-    const uint32_t cr0 = nc ? (uint32_t)__builtin_amdgcn_readlane((int)cr, (int)__builtin_ctzll(cmask)) : 0u;
-    const uint32_t iv = valid ? newid[v] : 0u;
-    const bool alone = valid && iv >= n_linked;  // isolated: root itself, size 1, its own rank
-    const size_t ns = sketch_stride(n);
-    // Each group of loads is issued unconditionally (inactive lanes read entry 0)
-    // and back to back, then waited for once.
-    uint32_t root[kG0PerWave], sz[kG0PerWave], l[kG0PerWave], t[kG0PerWave];
+    const uint32_t b = lane_id();
+    const bool act = b < nb;
+    const uint32_t w = wave_index();
+    if (w >= nw) return;
+    const uint32_t v0 = w * kWave;
+    const unsigned long long gb = (act && gbits) ? gbest[b] : 0ull;
+    const uint32_t groot = giant_root_of(gb), gsize = giant_size_of(gb);
+    // the gain and the largest-component sum of a vertex travel in one 64-bit sum
+    // while 64 n < 2^32
+    const bool packed = (uint64_t)n * kWave < (1ull << 32);
+    uint64_t gmask = 0;
+    for (uint32_t j0 = 0; j0 < kWave; j0 += kEmitIlp) {
+        uint32_t iv[kEmitIlp], cr[kEmitIlp], t[kEmitIlp], root[kEmitIlp], c[kEmitIlp], m[kEmitIlp];
 #pragma unroll
-    for (uint32_t i = 0; i < kG0PerWave; ++i) {
-        const uint32_t b = wv + kG0Waves * i;
-        const bool act = valid && b < B && !alone;
-        t[i] = parent[act ? b * ns + iv : 0];
-    }
-#pragma unroll
-    for (uint32_t i = 0; i < kG0PerWave; ++i) {
-        const uint32_t b = wv + kG0Waves * i;
-        const bool act = valid && b < B && !alone;
-        root[i] = act ? pin_vgpr(t[i]) : ((valid && b < B) ? iv : kNone);
-    }
-#pragma unroll
-    for (uint32_t i = 0; i < kG0PerWave; ++i) {
-        const uint32_t b = wv + kG0Waves * i;
-        const bool act = valid && b < B && !alone;
-        t[i] = cnt[act ? b * ns + root[i] : 0];
-    }
-#pragma unroll
-    for (uint32_t i = 0; i < kG0PerWave; ++i) {
-        const uint32_t c = pin_vgpr(t[i]);
-        sz[i] = root[i] == kNone ? 0u : (alone ? 1u : 1u + c);
-    }
-    if (cr != kNone) {
-#pragma unroll
-        for (uint32_t i = 0; i < kG0PerWave; ++i) {
-            const uint32_t b = wv + kG0Waves * i;
-            const bool act = b < B && !alone;
-            t[i] = minc[act ? b * ns + root[i] : 0];
+        for (uint32_t u = 0; u < kEmitIlp; ++u) {
+            const uint32_t v = v0 + j0 + u;
+            iv[u] = v < n ? newid[v] : 0u;
+            cr[u] = v < n ? center_rank[v] : kNone;
+            const bool rd = act && v < n && iv[u] < n_linked;
+            t[u] = parent[rd ? (size_t)iv[u] * vs + b : 0];
         }
 #pragma unroll
-        for (uint32_t i = 0; i < kG0PerWave; ++i) {
-            const uint32_t m = pin_vgpr(t[i]);
-            l[i] = root[i] == kNone ? kNone : (alone ? cr : m);
+        for (uint32_t u = 0; u < kEmitIlp; ++u) {
+            const uint32_t v = v0 + j0 + u;
+            const bool rd = act && v < n && iv[u] < n_linked;
+            root[u] = rd ? pin_vgpr(t[u]) : iv[u];
+            c[u] = cnt[rd ? (size_t)root[u] * vs + b : 0];
+            m[u] = minc[(rd && cr[u] != kNone) ? (size_t)root[u] * vs + b : 0];
         }
-    }
-    uint64_t s = 0, gs = 0;
 #pragma unroll
-    for (uint32_t i = 0; i < kG0PerWave; ++i) {
-        const uint32_t b = wv + kG0Waves * i;
-        if (b >= B) break;  // wave-uniform
-        s += sz[i];
-        if (cr != kNone) {
-            const uint32_t lv = l[i], sv = (l[i] == cr) ? sz[i] : 0u;
-            if (stage) {
-                tl[cr - cr0][b] = lv;
-                ts[cr - cr0][b] = sv;
+        for (uint32_t u = 0; u < kEmitIlp; ++u) {
+            const uint32_t v = v0 + j0 + u;
+            if (v >= n) break;  // wave-uniform
+            const bool rd = act && iv[u] < n_linked;
+            const uint32_t sz = !act ? 0u : (rd ? 1u + pin_vgpr(c[u]) : 1u);
+            if (cr[u] != kNone && act) {  // a center: its triple entry in this sketch
+                const uint32_t l = rd ? pin_vgpr(m[u]) : cr[u];
+                const size_t at = (size_t)cr[u] * R + r0 + b;
+                label_c[at] = l;
+                size_c[at] = l == cr[u] ? sz : 0u;
+            }
+            const bool in_giant = act && gbits && root[u] == groot;
+            gmask |= (uint64_t)in_giant << (j0 + u);
+            const uint32_t gs = in_giant ? gsize : 0u;
+            if (packed) {
+                const uint64_t tot = wave_sum_lanes((uint64_t)sz | ((uint64_t)gs << 32));
+                if (b == 0) {
+                    gain0[v] += (uint32_t)tot;
+                    if (gbits) gsum[v] += tot >> 32;
+                }
             } else {
-                const size_t at = (size_t)cr * R + r0 + b;
-                label_c[at] = lv;
-                size_c[at] = sv;
+                const uint64_t g = wave_sum_lanes(sz), h = wave_sum_lanes(gs);
+                if (b == 0) {
+                    gain0[v] += g;
+                    if (gbits) gsum[v] += h;
+                }
             }
         }
-        if (gbits) {
-            const unsigned long long gb = gbest[b];
-            const bool in_giant = valid && root[i] == giant_root_of(gb);
-            const uint64_t m = __ballot(in_giant);
-            if (lane == 0) gword[b] = m;
-            gs += in_giant ? giant_size_of(gb) : 0u;
-        }
     }
-    part[wv][lane] = s;
-    gpart[wv][lane] = gs;
-    __syncthreads();
-    if (stage) {
-        for (uint32_t j = wv; j < nc; j += kG0Waves)
-            if (lane < B) {
-                const size_t at = (size_t)(cr0 + j) * R + r0 + lane;
-                label_c[at] = tl[j][lane];
-                size_c[at] = ts[j][lane];
-            }
-    }
-    if (gbits && wv == 1 && lane < B && blockIdx.x < nw) gbits[(size_t)blockIdx.x * R + r0 + lane] = gword[lane];
-    if (wv == 0 && valid) {
-        uint64_t t = 0, tg = 0;
-#pragma unroll
-        for (uint32_t w = 0; w < kG0Waves; ++w) t += part[w][lane], tg += gpart[w][lane];
-        gain0[v] += t;
-        if (gbits) gsum[v] += tg;
-    }
+    if (gbits && act) gbits[(size_t)w * R + r0 + b] = gmask;
 }
 
 // ---- centers: flag, per-chunk counts, scan, ranks --------------------------
