@@ -767,10 +767,12 @@ void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const ui
     // isolated vertices' entries need setting once per build (nothing writes them
     // later, unless a caller flags seeds in minc)
     const uint32_t n_init = init_isolated ? n : g->n_linked;
-    const unsigned gi = grid_for((uint64_t)n_init * cs.B, 256, 1u << 20);
+    uint32_t lw = 0;  // threads per number of the set-up: the width rounded up to a power of two
+    while ((1u << lw) < cs.B) ++lw;
+    const unsigned gi = grid_for((uint64_t)n_init << lw, 256, 1u << 20);
     {
         Prof p(ctx, "init", st, timed);
-        k_batch_init<<<gi, 256, 0, st>>>(cs.parent, cs.cnt, minc, cs.B, n_init, minc_init, center_rank);
+        k_batch_init<<<gi, 256, 0, st>>>(cs.parent, cs.cnt, minc, cs.B, lw, n_init, minc_init, center_rank);
     }
     {
         Prof p(ctx, "sample_hook", st, timed);
@@ -800,8 +802,9 @@ void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const ui
         const uint32_t run = (uint32_t)std::min<uint64_t>(
             kCompressRunMax, std::max<uint64_t>(kCompressIlp, ((uint64_t)g->n_linked / 16384 + 3) & ~3ull));
         const uint64_t runs = ((uint64_t)g->n_linked + run - 1) / run;  // one wave each
-        k_compress<<<std::max<uint64_t>((runs + 3) / 4, 1), 256, 0, st>>>(cs.parent, cs.cnt, cs.B, b, g->n_linked,
-                                                                          run, center_rank, minc);
+        const uint64_t wpb = kCompressBlock / kWave;
+        k_compress<<<std::max<uint64_t>((runs + wpb - 1) / wpb, 1), kCompressBlock, 0, st>>>(
+            cs.parent, cs.cnt, cs.B, b, g->n_linked, run, center_rank, minc);
     }
 }
 

@@ -89,24 +89,21 @@ __global__ void k_to_label_order(const uint32_t *__restrict__ in, const uint32_t
 // minc starts at each vertex's own center rank when center_rank is given (so a
 // root's own rank needs no atomic), else at minc_init.  Numbers [0, n_init):
 // isolated vertices (numbered last) keep their entries from an earlier pass of
-// the same build, as no pass writes them.  One thread per (number, sketch) of
-// the first n_init numbers, in layout order.
+// the same build, as no pass writes them.  2^lw threads per number (2^lw >= vs),
+// thread t of a number writing its sketch t < vs: rows in layout order, and the
+// number and sketch of a thread by shifts.
 __global__ void k_batch_init(uint32_t *__restrict__ parent, uint32_t *__restrict__ cnt, uint32_t *__restrict__ minc,
-                             uint32_t vs, uint32_t n_init, uint32_t minc_init,
+                             uint32_t vs, uint32_t lw, uint32_t n_init, uint32_t minc_init,
                              const uint32_t *__restrict__ center_rank) {
-    const uint64_t total = (uint64_t)n_init * vs;
+    const uint64_t total = (uint64_t)n_init << lw;
     const uint64_t step = (uint64_t)gridDim.x * blockDim.x;
-    auto one = [&](uint64_t i, uint32_t x) {
-        parent[i] = x;
-        cnt[i] = 0;
-        if (minc) minc[i] = center_rank ? center_rank[x] : minc_init;
-    };
-    if (total <= 0xFFFFFFFFull) {  // 32-bit division by the width (the common case)
-        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += step)
-            one(i, (uint32_t)i / vs);
-    } else {
-        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += step)
-            one(i, (uint32_t)(i / vs));
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += step) {
+        const uint32_t x = (uint32_t)(i >> lw), b = (uint32_t)i & ((1u << lw) - 1u);
+        if (b >= vs) continue;
+        const size_t at = (size_t)x * vs + b;
+        parent[at] = x;
+        cnt[at] = 0;
+        if (minc) minc[at] = center_rank ? center_rank[x] : minc_init;
     }
 }
 
@@ -238,67 +235,91 @@ __global__ void __launch_bounds__(kHookBlock) k_sample_hook(const uint2 *__restr
 // Pointer jumping and counting over the first n_act numbers (the vertices with
 // an edge; an isolated vertex stays its own root with no members and its own
 // center rank).  One wave per run of `run` consecutive numbers (a multiple of
-// kCompressIlp, at most kCompressRunMax), lane b =
-// sketch b of the pass (b < nb): for each number x the wave reads x's entries of
-// all sketches in one or two cache lines, each lane walks to its root, points x
-// at it and counts x there.  kCompressIlp numbers are loaded together.  In
-// social-like graphs most non-root vertices of a sketch lie in one giant
-// component, so per-vertex atomics on its root counter would serialise: each lane
-// keeps a "hot" root whose member count and smallest center rank it accumulates
-// in registers (the first root it meets, replaced while it has at most one
-// member) and flushes them with one atomic each; other roots get one atomic per
-// member.
+// kCompressIlp, at most kCompressRunMax), lane b = sketch b of the pass (b < nb):
+// for each number x the wave reads x's entries of all sketches in one or two
+// cache lines, each lane walks to its root, points x at it and counts x there.
+// kCompressIlp numbers are loaded together.  In social-like graphs most non-root
+// vertices of a sketch lie in one giant component, so per-vertex atomics on its
+// root counter would serialise: each lane keeps a "hot" root whose member count
+// and smallest center rank it accumulates in registers (the first root it meets,
+// replaced while it has at most one member); other roots get one atomic per
+// member.  At the end the workgroup's waves combine their hot roots per sketch in
+// LDS, so a giant root gets one atomic per workgroup rather than per wave.
 constexpr uint32_t kCompressRunMax = 512;
 constexpr uint32_t kCompressIlp = 4;
-__global__ void __launch_bounds__(256) k_compress(uint32_t *__restrict__ parent, uint32_t *__restrict__ cnt,
-                                                  uint32_t vs, uint32_t nb, uint32_t n_act, uint32_t run,
-                                                  const uint32_t *__restrict__ center_rank,
-                                                  uint32_t *__restrict__ minc) {
-    const uint32_t b = lane_id();
+constexpr uint32_t kCompressBlock = 1024;
+__global__ void __launch_bounds__(kCompressBlock) k_compress(uint32_t *__restrict__ parent,
+                                                             uint32_t *__restrict__ cnt, uint32_t vs, uint32_t nb,
+                                                             uint32_t n_act, uint32_t run,
+                                                             const uint32_t *__restrict__ center_rank,
+                                                             uint32_t *__restrict__ minc) {
+    constexpr uint32_t kW = kCompressBlock / kWave;
+    __shared__ uint32_t sh_root[kW][kWave], sh_cnt[kW][kWave], sh_min[kW][kWave];
+    const uint32_t b = lane_id(), wl = threadIdx.x / kWave;
     const bool act = b < nb;
     const uint64_t x0 = (uint64_t)wave_index() * run;
-    if (x0 >= n_act) return;
-    const uint32_t x1 = (uint32_t)min<uint64_t>(x0 + run, n_act);
     uint32_t hot = kNone, hot_cnt = 0, hot_min = kNone;
-    for (uint32_t xb = (uint32_t)x0; xb < x1; xb += kCompressIlp) {
-        uint32_t pp[kCompressIlp], cr[kCompressIlp];
+    if (x0 < n_act) {
+        const uint32_t x1 = (uint32_t)min<uint64_t>(x0 + run, n_act);
+        for (uint32_t xb = (uint32_t)x0; xb < x1; xb += kCompressIlp) {
+            uint32_t pp[kCompressIlp], cr[kCompressIlp];
 #pragma unroll
-        for (uint32_t j = 0; j < kCompressIlp; ++j) {
-            const uint32_t x = xb + j;
-            const bool ok = act && x < x1;
-            pp[j] = parent[ok ? (size_t)x * vs + b : 0];
-            cr[j] = center_rank ? center_rank[x < x1 ? x : xb] : kNone;  // the same x in every lane
-        }
-#pragma unroll
-        for (uint32_t j = 0; j < kCompressIlp; ++j) {
-            const uint32_t x = xb + j;
-            if (!act || x >= x1) continue;
-            uint32_t r = x, p = pin_vgpr(pp[j]);
-            while (p != r) { r = p; p = parent[(size_t)r * vs + b]; }
-            if (r == x) continue;
-            parent[(size_t)x * vs + b] = r;
-            const uint32_t c = cr[j];
-            if (r != hot && hot_cnt <= 1) {  // take r as the hot root, giving back a weak one
-                if (hot != kNone) {
-                    if (hot_cnt) atomicAdd(cnt + (size_t)hot * vs + b, hot_cnt);
-                    if (hot_min != kNone) atomicMin(minc + (size_t)hot * vs + b, hot_min);
-                }
-                hot = r;
-                hot_cnt = 0;
-                hot_min = kNone;
+            for (uint32_t j = 0; j < kCompressIlp; ++j) {
+                const uint32_t x = xb + j;
+                const bool ok = act && x < x1;
+                pp[j] = parent[ok ? (size_t)x * vs + b : 0];
+                cr[j] = center_rank ? center_rank[x < x1 ? x : xb] : kNone;  // the same x in every lane
             }
-            if (r == hot) {
-                ++hot_cnt;
-                hot_min = min(hot_min, c);  // a root's own rank is already in minc
-            } else {
-                atomicAdd(cnt + (size_t)r * vs + b, 1u);
-                if (c != kNone) atomicMin(minc + (size_t)r * vs + b, c);
+#pragma unroll
+            for (uint32_t j = 0; j < kCompressIlp; ++j) {
+                const uint32_t x = xb + j;
+                if (!act || x >= x1) continue;
+                uint32_t r = x, p = pin_vgpr(pp[j]);
+                while (p != r) { r = p; p = parent[(size_t)r * vs + b]; }
+                if (r == x) continue;
+                parent[(size_t)x * vs + b] = r;
+                const uint32_t c = cr[j];
+                if (r != hot && hot_cnt <= 1) {  // take r as the hot root, giving back a weak one
+                    if (hot != kNone) {
+                        if (hot_cnt) atomicAdd(cnt + (size_t)hot * vs + b, hot_cnt);
+                        if (hot_min != kNone) atomicMin(minc + (size_t)hot * vs + b, hot_min);
+                    }
+                    hot = r;
+                    hot_cnt = 0;
+                    hot_min = kNone;
+                }
+                if (r == hot) {
+                    ++hot_cnt;
+                    hot_min = min(hot_min, c);  // a root's own rank is already in minc
+                } else {
+                    atomicAdd(cnt + (size_t)r * vs + b, 1u);
+                    if (c != kNone) atomicMin(minc + (size_t)r * vs + b, c);
+                }
             }
         }
     }
-    if (hot != kNone) {
-        if (hot_cnt) atomicAdd(cnt + (size_t)hot * vs + b, hot_cnt);
-        if (hot_min != kNone) atomicMin(minc + (size_t)hot * vs + b, hot_min);
+    sh_root[wl][b] = hot;
+    sh_cnt[wl][b] = hot_cnt;
+    sh_min[wl][b] = hot_min;
+    __syncthreads();
+    if (wl == 0 && act) {  // lane b combines the waves' hot roots of sketch b
+        uint32_t r0 = kNone, c0 = 0, m0 = kNone;
+        for (uint32_t k = 0; k < kW; ++k) {
+            const uint32_t r = sh_root[k][b], c = sh_cnt[k][b], mn = sh_min[k][b];
+            if (r == kNone) continue;
+            if (r0 == kNone) r0 = r;
+            if (r == r0) {
+                c0 += c;
+                m0 = min(m0, mn);
+            } else {
+                if (c) atomicAdd(cnt + (size_t)r * vs + b, c);
+                if (mn != kNone) atomicMin(minc + (size_t)r * vs + b, mn);
+            }
+        }
+        if (r0 != kNone) {
+            if (c0) atomicAdd(cnt + (size_t)r0 * vs + b, c0);
+            if (m0 != kNone) atomicMin(minc + (size_t)r0 * vs + b, m0);
+        }
     }
 }
 
