@@ -141,6 +141,19 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
     return x;
 }
 
+// Sum over the 64 lanes of a 32-bit value whose total fits in 32 bits, returned
+// wave-uniform: two quad permutations and two row rotations (DPP, no LDS) leave
+// every lane of a 16-lane row holding the row's sum, then the four row sums are
+// read out.  All 64 lanes must be active.
+__device__ __forceinline__ uint32_t wave_sum_u32_rows(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x124, 0xF, 0xF, false);  // row_ror 4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xF, 0xF, false);  // row_ror 8
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 0) + (uint32_t)__builtin_amdgcn_readlane((int)x, 16) +
+           (uint32_t)__builtin_amdgcn_readlane((int)x, 32) + (uint32_t)__builtin_amdgcn_readlane((int)x, 48);
+}
+
 __device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {

@@ -764,8 +764,10 @@ void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const ui
     if (!st) st = ctx->stream;
     const uint32_t n = g->n;
     const unsigned hook_grid = grid_for(g->m_und, kHookBlock, hook_grid_cap());
-    // isolated vertices' entries need setting once per build (nothing writes them
-    // later, unless a caller flags seeds in minc)
+    // isolated numbers' entries are set only for callers that read them (the
+    // influence passes read the seeds'); nothing else writes them, so they keep
+    // their values from an earlier pass of the same build unless a caller flags
+    // seeds in minc
     const uint32_t n_init = init_isolated ? n : g->n_linked;
     uint32_t lw = 0;  // threads per number of the set-up: the width rounded up to a power of two
     while ((1u << lw) < cs.B) ++lw;
@@ -816,7 +818,7 @@ void enqueue_full_build(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const
     (void)hipMemsetAsync(gain0, 0, (size_t)n * 8, st);
     for (uint32_t r0 = 0; r0 < R; r0 += cs.B) {
         const uint32_t b = std::min(cs.B, R - r0);
-        enqueue_cc_pass(ctx, g, pm, K + r0, b, cs, nullptr, kNone, nullptr, r0 == 0, st);
+        enqueue_cc_pass(ctx, g, pm, K + r0, b, cs, nullptr, kNone, nullptr, false, st);  // the emit skips isolated numbers
         Prof p(ctx, "emit", st);
         k_emit_full<<<((n + kWave - 1) / kWave + 3) / 4, 256, 0, st>>>(cs.parent, cs.cnt, g->newid, g->iperm, n, cs.B,
                                                                      g->n_linked, b, R, r0, E, gain0);
@@ -1001,9 +1003,10 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
     if (s->compact) k_to_label_order<<<(n + 255) / 256, 256, 0, st>>>(s->center_rank, g->iperm, n, cs.crank);
     for (uint32_t r0 = 0; r0 < R; r0 += B) {
         const uint32_t b = std::min(B, R - r0);
-        enqueue_cc_pass(ctx, g, s->pm, s->K + r0, b, cs, minc, kNone, s->compact ? cs.crank : nullptr, r0 == 0);
+        // the emits and the giant sample read no entry of an isolated number
+        enqueue_cc_pass(ctx, g, s->pm, s->K + r0, b, cs, minc, kNone, s->compact ? cs.crank : nullptr, false);
         if (s->compact) {
-            k_giant_sample<<<b, 256, 0, st>>>(parent, cnt, n, cs.B, s->gbest + r0);
+            k_giant_sample<<<b, 256, 0, st>>>(parent, cnt, n, cs.B, g->n_linked, s->gbest + r0);
             Prof p(ctx, "emit");
             k_gain0_emit<<<(s->nw + 3) / 4, 256, 0, st>>>(parent, cnt, minc, s->center_rank, s->rho, n, cs.B, b, r0,
                                                           R, s->label_c, s->size_c, s->gain0, s->gbest + r0,

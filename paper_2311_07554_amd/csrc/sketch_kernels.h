@@ -348,12 +348,19 @@ __global__ void __launch_bounds__(256) k_emit_full(const uint32_t *__restrict__ 
     const bool act = b < nb;
     const uint32_t v0 = wave_index() * kWave;
     if (v0 >= n) return;
+    // lane j holds vertex v0 + j's number and its gain sum, written once at the end
+    const uint32_t vl = v0 + b;
+    const bool vok = vl < n;
+    const uint32_t my_iv = vok ? newid[vl] : 0u;
+    const uint64_t g_old = vok ? gain0[vl] : 0ull;
+    const bool small = (uint64_t)n * kWave < (1ull << 32);  // a vertex's sum over 64 sketches fits 32 bits
+    uint64_t g_add = 0;
     for (uint32_t j0 = 0; j0 < kWave; j0 += kEmitIlp) {
         uint32_t iv[kEmitIlp], t[kEmitIlp], root[kEmitIlp], c[kEmitIlp], lab[kEmitIlp];
 #pragma unroll
         for (uint32_t u = 0; u < kEmitIlp; ++u) {
             const uint32_t v = v0 + j0 + u;
-            iv[u] = v < n ? newid[v] : 0u;
+            iv[u] = (uint32_t)__builtin_amdgcn_readlane((int)my_iv, (int)(j0 + u));
             const bool rd = act && v < n && iv[u] < n_linked;
             t[u] = parent[rd ? (size_t)iv[u] * vs + b : 0];
         }
@@ -373,10 +380,11 @@ __global__ void __launch_bounds__(256) k_emit_full(const uint32_t *__restrict__ 
             const uint32_t sz = !act ? 0u : (rd ? 1u + pin_vgpr(c[u]) : 1u);
             const bool own = root[u] == iv[u];
             if (act) E[(size_t)v * R + r0 + b] = own ? make_uint2(v, sz) : make_uint2(pin_vgpr(lab[u]), 0u);
-            const uint64_t g = wave_sum_lanes(sz);
-            if (b == 0) gain0[v] += g;
+            const uint64_t g = small ? (uint64_t)wave_sum_u32_rows(sz) : wave_sum_lanes(sz);
+            if (b == j0 + u) g_add = g;
         }
     }
+    if (vok) gain0[vl] = g_old + g_add;
 }
 
 // The largest component packed as (size << 32) | (2^32 - 1 - root).
@@ -390,15 +398,16 @@ __device__ __forceinline__ uint32_t giant_size_of(uint64_t gbest) { return (uint
 constexpr uint32_t kGiantSamples = 1024;
 __global__ void __launch_bounds__(256) k_giant_sample(const uint32_t *__restrict__ parent,
                                                       const uint32_t *__restrict__ cnt, uint32_t n, uint32_t vs,
-                                                      unsigned long long *__restrict__ gbest) {
+                                                      uint32_t n_linked, unsigned long long *__restrict__ gbest) {
     __shared__ unsigned long long best_w[256 / kWave];
     const uint32_t b = blockIdx.x;
     unsigned long long best = 0;
     for (uint32_t j = threadIdx.x; j < kGiantSamples; j += blockDim.x) {
         const uint32_t v = (uint32_t)((uint64_t)j * n / kGiantSamples);
-        const uint32_t root = parent[(size_t)v * vs + b];
-        const unsigned long long c = ((unsigned long long)(1u + cnt[(size_t)root * vs + b]) << 32) |
-                                     (0xFFFFFFFFull - root);
+        const bool linked = v < n_linked;  // an isolated number is its own singleton and reads nothing
+        const uint32_t root = linked ? parent[(size_t)v * vs + b] : v;
+        const uint32_t members = linked ? cnt[(size_t)root * vs + b] : 0u;
+        const unsigned long long c = ((unsigned long long)(1u + members) << 32) | (0xFFFFFFFFull - root);
         best = c > best ? c : best;
     }
     best = wave_max_u64(best);
@@ -440,17 +449,23 @@ __global__ void __launch_bounds__(256) k_gain0_emit(const uint32_t *__restrict__
     const uint32_t v0 = w * kWave;
     const unsigned long long gb = (act && gbits) ? gbest[b] : 0ull;
     const uint32_t groot = giant_root_of(gb), gsize = giant_size_of(gb);
-    // the gain and the largest-component sum of a vertex travel in one 64-bit sum
-    // while 64 n < 2^32
-    const bool packed = (uint64_t)n * kWave < (1ull << 32);
-    uint64_t gmask = 0;
+    // lane j holds vertex v0 + j's number, center rank and sums, the sums written
+    // once at the end
+    const uint32_t vl = v0 + b;
+    const bool vok = vl < n;
+    const uint32_t my_iv = vok ? newid[vl] : 0u;
+    const uint32_t my_cr = vok ? center_rank[vl] : kNone;
+    const uint64_t g_old = vok ? gain0[vl] : 0ull;
+    const uint64_t s_old = (vok && gbits) ? gsum[vl] : 0ull;
+    const bool small = (uint64_t)n * kWave < (1ull << 32);  // a vertex's sums over 64 sketches fit 32 bits
+    uint64_t g_add = 0, s_add = 0, gmask = 0;
     for (uint32_t j0 = 0; j0 < kWave; j0 += kEmitIlp) {
         uint32_t iv[kEmitIlp], cr[kEmitIlp], t[kEmitIlp], root[kEmitIlp], c[kEmitIlp], m[kEmitIlp];
 #pragma unroll
         for (uint32_t u = 0; u < kEmitIlp; ++u) {
             const uint32_t v = v0 + j0 + u;
-            iv[u] = v < n ? newid[v] : 0u;
-            cr[u] = v < n ? center_rank[v] : kNone;
+            iv[u] = (uint32_t)__builtin_amdgcn_readlane((int)my_iv, (int)(j0 + u));
+            cr[u] = (uint32_t)__builtin_amdgcn_readlane((int)my_cr, (int)(j0 + u));
             const bool rd = act && v < n && iv[u] < n_linked;
             t[u] = parent[rd ? (size_t)iv[u] * vs + b : 0];
         }
@@ -477,20 +492,23 @@ __global__ void __launch_bounds__(256) k_gain0_emit(const uint32_t *__restrict__
             const bool in_giant = act && gbits && root[u] == groot;
             gmask |= (uint64_t)in_giant << (j0 + u);
             const uint32_t gs = in_giant ? gsize : 0u;
-            if (packed) {
-                const uint64_t tot = wave_sum_lanes((uint64_t)sz | ((uint64_t)gs << 32));
-                if (b == 0) {
-                    gain0[v] += (uint32_t)tot;
-                    if (gbits) gsum[v] += tot >> 32;
-                }
+            uint64_t g, h;
+            if (small) {
+                g = wave_sum_u32_rows(sz);
+                h = gbits ? wave_sum_u32_rows(gs) : 0u;
             } else {
-                const uint64_t g = wave_sum_lanes(sz), h = wave_sum_lanes(gs);
-                if (b == 0) {
-                    gain0[v] += g;
-                    if (gbits) gsum[v] += h;
-                }
+                g = wave_sum_lanes(sz);
+                h = gbits ? wave_sum_lanes(gs) : 0u;
+            }
+            if (b == j0 + u) {
+                g_add = g;
+                s_add = h;
             }
         }
+    }
+    if (vok) {
+        gain0[vl] = g_old + g_add;
+        if (gbits) gsum[vl] = s_old + s_add;
     }
     if (gbits && act) gbits[(size_t)w * R + r0 + b] = gmask;
 }
