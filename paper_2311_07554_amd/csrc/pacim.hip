@@ -801,8 +801,8 @@ void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const ui
     {
         Prof p(ctx, "compress", st, timed);
         // runs of at most 512 numbers, short enough for about 16 waves per SIMD
-        const uint32_t run = (uint32_t)std::min<uint64_t>(
-            kCompressRunMax, std::max<uint64_t>(kCompressIlp, ((uint64_t)g->n_linked / 16384 + 3) & ~3ull));
+        const uint64_t want = ((uint64_t)g->n_linked / 16384 + kCompressIlp - 1) / kCompressIlp * kCompressIlp;
+        const uint32_t run = (uint32_t)std::min<uint64_t>(kCompressRunMax, std::max<uint64_t>(kCompressIlp, want));
         const uint64_t runs = ((uint64_t)g->n_linked + run - 1) / run;  // one wave each
         const uint64_t wpb = kCompressBlock / kWave;
         k_compress<<<std::max<uint64_t>((runs + wpb - 1) / wpb, 1), kCompressBlock, 0, st>>>(

@@ -246,7 +246,7 @@ __global__ void __launch_bounds__(kHookBlock) k_sample_hook(const uint2 *__restr
 // member.  At the end the workgroup's waves combine their hot roots per sketch in
 // LDS, so a giant root gets one atomic per workgroup rather than per wave.
 constexpr uint32_t kCompressRunMax = 512;
-constexpr uint32_t kCompressIlp = 4;
+constexpr uint32_t kCompressIlp = 8;
 constexpr uint32_t kCompressBlock = 1024;
 __global__ void __launch_bounds__(kCompressBlock) k_compress(uint32_t *__restrict__ parent,
                                                              uint32_t *__restrict__ cnt, uint32_t vs, uint32_t nb,
@@ -262,7 +262,7 @@ __global__ void __launch_bounds__(kCompressBlock) k_compress(uint32_t *__restric
     if (x0 < n_act) {
         const uint32_t x1 = (uint32_t)min<uint64_t>(x0 + run, n_act);
         for (uint32_t xb = (uint32_t)x0; xb < x1; xb += kCompressIlp) {
-            uint32_t pp[kCompressIlp], cr[kCompressIlp];
+            uint32_t pp[kCompressIlp], cr[kCompressIlp], rt[kCompressIlp];
 #pragma unroll
             for (uint32_t j = 0; j < kCompressIlp; ++j) {
                 const uint32_t x = xb + j;
@@ -270,12 +270,35 @@ __global__ void __launch_bounds__(kCompressBlock) k_compress(uint32_t *__restric
                 pp[j] = parent[ok ? (size_t)x * vs + b : 0];
                 cr[j] = center_rank ? center_rank[x < x1 ? x : xb] : kNone;  // the same x in every lane
             }
+            // the numbers' walks to their roots in lock step, one load per unfinished
+            // walk per step (after the hook most entries point at their root, so one
+            // step confirms all of them)
+#pragma unroll
+            for (uint32_t j = 0; j < kCompressIlp; ++j) {
+                rt[j] = xb + j;
+                if (act && xb + j < x1) pp[j] = pin_vgpr(pp[j]);
+                else pp[j] = rt[j];
+            }
+            for (;;) {
+                bool more = false;
+#pragma unroll
+                for (uint32_t j = 0; j < kCompressIlp; ++j) more |= pp[j] != rt[j];
+                if (!more) break;
+                uint32_t nx[kCompressIlp];
+#pragma unroll
+                for (uint32_t j = 0; j < kCompressIlp; ++j) nx[j] = parent[pp[j] != rt[j] ? (size_t)pp[j] * vs + b : 0];
+#pragma unroll
+                for (uint32_t j = 0; j < kCompressIlp; ++j)
+                    if (pp[j] != rt[j]) {
+                        rt[j] = pp[j];
+                        pp[j] = pin_vgpr(nx[j]);
+                    }
+            }
 #pragma unroll
             for (uint32_t j = 0; j < kCompressIlp; ++j) {
                 const uint32_t x = xb + j;
                 if (!act || x >= x1) continue;
-                uint32_t r = x, p = pin_vgpr(pp[j]);
-                while (p != r) { r = p; p = parent[(size_t)r * vs + b]; }
+                const uint32_t r = rt[j];
                 if (r == x) continue;
                 parent[(size_t)x * vs + b] = r;
                 const uint32_t c = cr[j];
