@@ -757,10 +757,12 @@ unsigned hook_grid_cap() {
 // forests in parent[b][n] over the graph's labelling order (x = newid[v]; the
 // root of a CC is its smallest number), member counts at the roots in cnt, and
 // (if center_rank, given in labelling order) the smallest center rank of each CC
-// in minc.
+// in minc.  parent_fresh: the linked numbers' entries already hold their own
+// numbers (the previous pass's emit reset them; with init_isolated false).
 void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const uint64_t *K, uint32_t b,
                      const CCScratch &cs, uint32_t *minc, uint32_t minc_init, const uint32_t *center_rank,
-                     bool init_isolated = true, hipStream_t st = nullptr, bool timed = true) {
+                     bool init_isolated = true, hipStream_t st = nullptr, bool timed = true,
+                     bool parent_fresh = false) {
     if (!st) st = ctx->stream;
     const uint32_t n = g->n;
     const unsigned hook_grid = grid_for(g->m_und, kHookBlock, hook_grid_cap());
@@ -774,7 +776,8 @@ void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const ui
     const unsigned gi = grid_for((uint64_t)n_init << lw, 256, 1u << 20);
     {
         Prof p(ctx, "init", st, timed);
-        k_batch_init<<<gi, 256, 0, st>>>(cs.parent, cs.cnt, minc, cs.B, lw, n_init, minc_init, center_rank);
+        k_batch_init<<<gi, 256, 0, st>>>(parent_fresh ? nullptr : cs.parent, cs.cnt, minc, cs.B, lw, n_init,
+                                         minc_init, center_rank);
     }
     {
         Prof p(ctx, "sample_hook", st, timed);
@@ -818,10 +821,12 @@ void enqueue_full_build(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const
     (void)hipMemsetAsync(gain0, 0, (size_t)n * 8, st);
     for (uint32_t r0 = 0; r0 < R; r0 += cs.B) {
         const uint32_t b = std::min(cs.B, R - r0);
-        enqueue_cc_pass(ctx, g, pm, K + r0, b, cs, nullptr, kNone, nullptr, false, st);  // the emit skips isolated numbers
+        const bool last = r0 + cs.B >= R;
+        // the emit skips isolated numbers, and resets the forest for the next pass
+        enqueue_cc_pass(ctx, g, pm, K + r0, b, cs, nullptr, kNone, nullptr, false, st, true, r0 > 0);
         Prof p(ctx, "emit", st);
         k_emit_full<<<((n + kWave - 1) / kWave + 3) / 4, 256, 0, st>>>(cs.parent, cs.cnt, g->newid, g->iperm, n, cs.B,
-                                                                     g->n_linked, b, R, r0, E, gain0);
+                                                                     g->n_linked, b, R, r0, E, gain0, !last);
     }
 }
 
@@ -1003,19 +1008,23 @@ extern "C" im_status im_build_sketches(im_ctx *ctx, const im_graph *g, im_prob p
     if (s->compact) k_to_label_order<<<(n + 255) / 256, 256, 0, st>>>(s->center_rank, g->iperm, n, cs.crank);
     for (uint32_t r0 = 0; r0 < R; r0 += B) {
         const uint32_t b = std::min(B, R - r0);
-        // the emits and the giant sample read no entry of an isolated number
-        enqueue_cc_pass(ctx, g, s->pm, s->K + r0, b, cs, minc, kNone, s->compact ? cs.crank : nullptr, false);
+        // the emits and the giant sample read no entry of an isolated number; an
+        // emit resets the forest for the next pass
+        const bool last = r0 + B >= R;
+        enqueue_cc_pass(ctx, g, s->pm, s->K + r0, b, cs, minc, kNone, s->compact ? cs.crank : nullptr, false, st, true,
+                        r0 > 0);
         if (s->compact) {
             k_giant_sample<<<b, 256, 0, st>>>(parent, cnt, n, cs.B, g->n_linked, s->gbest + r0);
             Prof p(ctx, "emit");
             k_gain0_emit<<<(s->nw + 3) / 4, 256, 0, st>>>(parent, cnt, minc, s->center_rank, s->rho, n, cs.B, b, r0,
                                                           R, s->label_c, s->size_c, s->gain0, s->gbest + r0,
                                                           s->gbits, s->nw, s->gsum, g->newid,
-                                                          g->n_linked);
+                                                          g->n_linked, !last);
         } else {
             Prof p(ctx, "emit");
             k_emit_full<<<((n + kWave - 1) / kWave + 3) / 4, 256, 0, st>>>(parent, cnt, g->newid, g->iperm, n, cs.B,
-                                                                         g->n_linked, b, R, r0, s->E, s->gain0);
+                                                                         g->n_linked, b, R, r0, s->E, s->gain0,
+                                                                         !last);
         }
         SK_HIP(hipGetLastError());
     }

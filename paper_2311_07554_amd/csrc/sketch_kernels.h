@@ -87,7 +87,8 @@ __global__ void k_to_label_order(const uint32_t *__restrict__ in, const uint32_t
 }
 
 // minc starts at each vertex's own center rank when center_rank is given (so a
-// root's own rank needs no atomic), else at minc_init.  Numbers [0, n_init):
+// root's own rank needs no atomic), else at minc_init.  parent null: the entries
+// already hold their own numbers (an emit that reset them).  Numbers [0, n_init):
 // isolated vertices (numbered last) keep their entries from an earlier pass of
 // the same build, as no pass writes them.  2^lw threads per number (2^lw >= vs),
 // thread t of a number writing its sketch t < vs: rows in layout order, and the
@@ -101,7 +102,7 @@ __global__ void k_batch_init(uint32_t *__restrict__ parent, uint32_t *__restrict
         const uint32_t x = (uint32_t)(i >> lw), b = (uint32_t)i & ((1u << lw) - 1u);
         if (b >= vs) continue;
         const size_t at = (size_t)x * vs + b;
-        parent[at] = x;
+        if (parent) parent[at] = x;
         cnt[at] = 0;
         if (minc) minc[at] = center_rank ? center_rank[x] : minc_init;
     }
@@ -360,13 +361,16 @@ constexpr uint32_t kEmitIlp = 4;
 __device__ __forceinline__ uint64_t wave_sum_lanes(uint64_t x) { return wave_sum_u64(x); }
 
 // Full labels: E[v][r0 + b] = (label, size at the label's own entry) with the
-// label the root's vertex id, and the initial gains.
-__global__ void __launch_bounds__(256) k_emit_full(const uint32_t *__restrict__ parent,
+// label the root's vertex id, and the initial gains.  reset: each linked entry is
+// set back to its own number once read (no other vertex reads it), so the next
+// pass's set-up leaves the forest alone.
+__global__ void __launch_bounds__(256) k_emit_full(uint32_t *__restrict__ parent,
                                                    const uint32_t *__restrict__ cnt,
                                                    const uint32_t *__restrict__ newid,
                                                    const uint32_t *__restrict__ iperm, uint32_t n, uint32_t vs,
                                                    uint32_t n_linked, uint32_t nb, uint32_t R, uint32_t r0,
-                                                   uint2 *__restrict__ E, uint64_t *__restrict__ gain0) {
+                                                   uint2 *__restrict__ E, uint64_t *__restrict__ gain0,
+                                                   bool reset) {
     const uint32_t b = lane_id();
     const bool act = b < nb;
     const uint32_t v0 = wave_index() * kWave;
@@ -392,6 +396,7 @@ __global__ void __launch_bounds__(256) k_emit_full(const uint32_t *__restrict__ 
             const uint32_t v = v0 + j0 + u;
             const bool rd = act && v < n && iv[u] < n_linked;
             root[u] = rd ? pin_vgpr(t[u]) : iv[u];
+            if (reset && rd) parent[(size_t)iv[u] * vs + b] = iv[u];
             c[u] = cnt[rd ? (size_t)root[u] * vs + b : 0];
             lab[u] = iperm[rd ? root[u] : 0];
         }
@@ -453,8 +458,10 @@ __global__ void __launch_bounds__(256) k_giant_sample(const uint32_t *__restrict
 //   - for a center v of rank cr, its triple entries label_c[cr][r0 + b] = the
 //     smallest center rank in its component (minc at the root) and size_c = the
 //     component size if that rank is cr's own, else 0 (center-major [rho][R], so
-//     the wave writes a center's entries as one run).
-__global__ void __launch_bounds__(256) k_gain0_emit(const uint32_t *__restrict__ parent,
+//     the wave writes a center's entries as one run);
+//   - reset: each linked entry set back to its own number once read, as in
+//     k_emit_full.
+__global__ void __launch_bounds__(256) k_gain0_emit(uint32_t *__restrict__ parent,
                                                     const uint32_t *__restrict__ cnt,
                                                     const uint32_t *__restrict__ minc,
                                                     const uint32_t *__restrict__ center_rank, uint32_t rho,
@@ -464,7 +471,8 @@ __global__ void __launch_bounds__(256) k_gain0_emit(const uint32_t *__restrict__
                                                     const unsigned long long *__restrict__ gbest,
                                                     uint64_t *__restrict__ gbits, uint32_t nw,
                                                     uint64_t *__restrict__ gsum,
-                                                    const uint32_t *__restrict__ newid, uint32_t n_linked) {
+                                                    const uint32_t *__restrict__ newid, uint32_t n_linked,
+                                                    bool reset) {
     const uint32_t b = lane_id();
     const bool act = b < nb;
     const uint32_t w = wave_index();
@@ -497,6 +505,7 @@ __global__ void __launch_bounds__(256) k_gain0_emit(const uint32_t *__restrict__
             const uint32_t v = v0 + j0 + u;
             const bool rd = act && v < n && iv[u] < n_linked;
             root[u] = rd ? pin_vgpr(t[u]) : iv[u];
+            if (reset && rd) parent[(size_t)iv[u] * vs + b] = iv[u];
             c[u] = cnt[rd ? (size_t)root[u] * vs + b : 0];
             m[u] = minc[(rd && cr[u] != kNone) ? (size_t)root[u] * vs + b : 0];
         }
