@@ -37,12 +37,12 @@ METRIC = "sampled edges/s for Sketch; seeds/s for k-seed select; HBM GB/s vs pea
 HBM_PEAK_GBS = 8000.0
 # Integer VALU ceiling of the live-edge test: 256 CUs x 4 SIMDs x 16 lanes at
 # 2.4 GHz issue 39.3e12 lane-instructions/s, and the compiled test loop of the
-# sampling kernel spends 175 VALU instructions per 8 tests (64 v_xor_b32,
-# 32 v_mul_lo_u32, 24 v_lshrrev_b64, 16 v_mad_u64_u32, 16 v_add3_u32, 8 v_cmp_lt_u64
+# sampling kernel spends 151 VALU instructions per 8 tests (48 v_xor_b32,
+# 32 v_mul_lo_u32, 16 v_mad_u64_u32, 16 v_add3_u32, 16 v_lshrrev_b64, 8 v_cmp_gt_u64
 # and 15 to build the mask), each taken as one issue; the device probe's hash
 # loop, the same instructions with no memory traffic, reaches about 90% of this.
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
-VALU_PER_HASH = 175.0 / 8.0
+VALU_PER_HASH = 151.0 / 8.0
 HASH_PEAK_G = VALU_LANE_OPS / VALU_PER_HASH / 1e9
 
 # committed counter profiles of the sampling kernel, by workload
@@ -73,9 +73,12 @@ def sampling_kernel_traffic(path=None):
                 h.update(f.read())
         if h.hexdigest() != fields["kernel_sources_sha256"]:
             return None
-        return {"bytes": float(fields["traffic_bytes"]), "fetch_bytes": float(fields["traffic_fetch_bytes"]),
-                "write_bytes": float(fields["traffic_write_bytes"]),
-                "profile": os.path.relpath(path, ROOT)}
+        out = {"bytes": float(fields["traffic_bytes"]), "fetch_bytes": float(fields["traffic_fetch_bytes"]),
+               "write_bytes": float(fields["traffic_write_bytes"]),
+               "profile": os.path.relpath(path, ROOT)}
+        if "traffic_fetch_counted_bytes" in fields:
+            out["fetch_counted_bytes"] = float(fields["traffic_fetch_counted_bytes"])
+        return out
     except (OSError, KeyError, ValueError):
         return None
 
@@ -488,19 +491,22 @@ def streaming_bytes(name, full, n, n_linked, m_und, B, passes, R, rho):
     """Bytes a kernel family streams per launch: the scratch forests it sets up, reads
     or rewrites, the edge words, and the outputs it writes (gathers at component
     roots and random union-find accesses not counted)."""
-    # the first pass of a build also sets isolated vertices' entries
-    n_init = (n + (passes - 1) * n_linked) / passes
+    # a build sets up the linked vertices' entries only; after the first pass the
+    # forest is already reset (by the previous emit) and only the counters are set
+    reset = (passes - 1) / passes  # share of the passes whose emit resets the forest
     if name == "init":
-        return (8.0 if full else 12.0) * B * n_init
+        first, later = (8.0, 4.0) if full else (12.0, 8.0)
+        return (first + (passes - 1) * later) / passes * B * n_linked
     if name == "sample_hook":
         return 16.0 * m_und  # the edge list's ids and labelling-order numbers
     if name == "compress":
         return 8.0 * B * n_linked  # read each forest entry, write it back pointing at its root
     if name == "emit":
-        if full:  # forest read, E written, gains read and written, labelling order read
-            return 4.0 * B * n_linked + 8.0 * B * n + 24.0 * n
-        # forest read, triple of the centers, bitmaps, gains, center ranks and order
-        return 4.0 * B * n_linked + 8.0 * B * rho + B * n / 8.0 + 24.0 * n
+        forest = (4.0 + 4.0 * reset) * B * n_linked  # read, and reset on all but the last pass
+        if full:  # E written, gains read and written, labelling order read
+            return forest + 8.0 * B * n + 24.0 * n
+        # triple of the centers, bitmaps, gains, center ranks and order
+        return forest + 8.0 * B * rho + B * n / 8.0 + 24.0 * n
     if name == "bulk_keys":
         if full:  # every row of E read, keys written, selection flags read
             return 8.0 * R * n + 9.0 * n
@@ -700,11 +706,18 @@ def measure_sketch_workload(args, w, modes, alphas, overlap, tag, profile_key):
             # measured HBM traffic of the launch: the union-find's random parent
             # accesses, not the hashes or the edge words, move these bytes
             tgbs = tr["bytes"] / (hk["avg_ms"] / 1e3) / 1e9
-            roofline["traffic_detail"] = dict(tr, achieved_GB_s=tgbs, frac_of_peak=tgbs / HBM_PEAK_GBS,
-                                              frac_of_measured_copy=tgbs / (probe_copy / 1e9),
-                                              algorithmic_bytes=alg_bytes, edge_bytes_read=16.0 * m_und,
-                                              limiter="random union-find traffic near the measured copy rate"
-                                              if tgbs > 0.8 * probe_copy / 1e9 else "hash ALU")
+            detail = dict(tr, achieved_GB_s=tgbs, frac_of_peak=tgbs / HBM_PEAK_GBS,
+                          frac_of_measured_copy=tgbs / (probe_copy / 1e9),
+                          algorithmic_bytes=alg_bytes, edge_bytes_read=16.0 * m_und,
+                          limiter="random union-find traffic near the measured copy rate"
+                          if tgbs > 0.8 * probe_copy / 1e9 else "hash ALU")
+            if "fetch_counted_bytes" in tr and probe_rand:
+                # the same fetches as counted (a random read counts one 64-byte
+                # sector) against the random-read probe's sectors per second
+                cgbs = tr["fetch_counted_bytes"] / (hk["avg_ms"] / 1e3) / 1e9
+                detail["counted_fetch_GB_s"] = cgbs
+                detail["frac_of_random_read_probe"] = cgbs / (probe_rand * 64.0 / 1e9)
+            roofline["traffic_detail"] = detail
 
     # NextSeed by prefix doubling (Algorithm 4) on the same sketches, outside the
     # timed steps: its selection time and evaluations beside the winning tree's

@@ -38,7 +38,7 @@ def _sha(sources):
 
 
 def test_traffic_read_while_sources_match(tmp_path, monkeypatch):
-    src = ["paper_2311_07554_amd/csrc/common.h", "paper_2311_07554_amd/csrc/sketch_kernels.h"]
+    src = ["paper_2311_07554_amd/csrc/common.h", "paper_2311_07554_amd/csrc/hook_kernels.h"]
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", _profile(tmp_path, src, _sha(src)))
     t = bench.sampling_kernel_traffic()
     assert t is not None
@@ -46,7 +46,7 @@ def test_traffic_read_while_sources_match(tmp_path, monkeypatch):
 
 
 def test_traffic_dropped_when_sources_changed(tmp_path, monkeypatch):
-    src = ["paper_2311_07554_amd/csrc/common.h", "paper_2311_07554_amd/csrc/sketch_kernels.h"]
+    src = ["paper_2311_07554_amd/csrc/common.h", "paper_2311_07554_amd/csrc/hook_kernels.h"]
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", _profile(tmp_path, src, "0" * 64))
     assert bench.sampling_kernel_traffic() is None
     # a source list that no longer exists, and a missing profile
