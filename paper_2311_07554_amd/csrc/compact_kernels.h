@@ -118,7 +118,6 @@ __device__ BfsOut getcenter_lds(const GraphDev &g, const ProbDev &pm, uint64_t k
     }
     __builtin_amdgcn_wave_barrier();
     uint32_t head = 0, tail = 1, found = kNone;
-    bool met = in_s[v] != 0;
     while (head < tail && found == kNone) {
         const uint32_t u = q[head];
         const uint64_t o0 = head == 0 ? o0v : g.off[u];
@@ -152,7 +151,6 @@ __device__ BfsOut getcenter_lds(const GraphDev &g, const ProbDev &pm, uint64_t k
             const uint32_t ni = (uint32_t)__popcll(im);
             if (tail + ni > kQCap) return BfsOut{0, kNone, true, head};
             if (ins) q[tail + (uint32_t)__popcll(im & ((1ull << lane) - 1ull))] = w;
-            if (__ballot(ins && in_s[w] != 0)) met = true;
             tail += ni;
             __builtin_amdgcn_wave_barrier();
         }
@@ -162,10 +160,18 @@ __device__ BfsOut getcenter_lds(const GraphDev &g, const ProbDev &pm, uint64_t k
         o.visits = head;
         return o;
     }
+    // the component has no center: its smallest vertex, and whether a seed lies in
+    // it (read once for the whole queue, off the search's chain of loads)
     uint32_t mn = kNone;
-    for (uint32_t i = lane; i < tail; i += kWave) mn = min(mn, q[i]);
+    bool seed = false;
+    for (uint32_t i = lane; i < tail; i += kWave) {
+        const uint32_t w = q[i];
+        mn = min(mn, w);
+        seed = seed || in_s[w] != 0;
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mn = min(mn, (uint32_t)__shfl_xor(mn, off));
+    const bool met = __ballot(seed) != 0;
     return BfsOut{met ? 0ull : (uint64_t)tail, kNone, false, head, tail, mn};
 }
 
@@ -183,7 +189,6 @@ __device__ BfsOut getcenter_global(const GraphDev &g, const ProbDev &pm, uint64_
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
     uint32_t head = 0, tail = 1, found = kNone;
-    bool met = in_s[v] != 0;
     while (head < tail && found == kNone) {
         const uint32_t u = __hip_atomic_load(&gq[head], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         ++head;
@@ -209,18 +214,22 @@ __device__ BfsOut getcenter_global(const GraphDev &g, const ProbDev &pm, uint64_
             }
             const uint64_t im = __ballot(ins);
             if (ins) gq[tail + (uint32_t)__popcll(im & ((1ull << lane) - 1ull))] = w;
-            if (__ballot(ins && in_s[w] != 0)) met = true;
             tail += (uint32_t)__popcll(im);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             __builtin_amdgcn_wave_barrier();
         }
     }
+    // clear the visited bits; for a component without a center, its smallest vertex
+    // and whether a seed lies in it
     uint32_t mn = kNone;
+    bool seed = false;
     for (uint32_t i = lane; i < tail; i += kWave) {
         const uint32_t w = __hip_atomic_load(&gq[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         atomicAnd(&gvis[w >> 5], ~(1u << (w & 31)));
         mn = min(mn, w);
+        if (found == kNone) seed = seed || in_s[w] != 0;
     }
+    const bool met = __ballot(seed) != 0;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     if (found != kNone) {
         BfsOut o = center_hit(cd, r, found);
