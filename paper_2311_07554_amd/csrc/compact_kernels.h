@@ -118,11 +118,26 @@ __device__ BfsOut getcenter_lds(const GraphDev &g, const ProbDev &pm, uint64_t k
     }
     __builtin_amdgcn_wave_barrier();
     uint32_t head = 0, tail = 1, found = kNone;
+    // the adjacency range of the next queued vertex is loaded together with the
+    // current vertex's neighbours when that vertex is already queued (pre = its
+    // queue index), so a scanned vertex usually costs one round trip, not two
+    uint32_t pre = 0;
+    uint64_t p0 = o0v, p1 = o1v;
     while (head < tail && found == kNone) {
         const uint32_t u = q[head];
-        const uint64_t o0 = head == 0 ? o0v : g.off[u];
-        const uint64_t o1 = head == 0 ? o1v : g.off[u + 1];
+        uint64_t o0 = p0, o1 = p1;
+        if (pre != head) {
+            o0 = g.off[u];
+            o1 = g.off[u + 1];
+        }
         ++head;
+        pre = kNone;
+        if (head < tail) {
+            const uint32_t un = q[head];
+            pre = head;
+            p0 = g.off[un];
+            p1 = g.off[un + 1];
+        }
         for (uint64_t base = o0; base < o1; base += kWave) {
             const uint64_t j = base + lane;
             bool live = false;
