@@ -203,10 +203,11 @@ __device__ __forceinline__ void relink_level(const TreeDesc &td, uint32_t l, con
 // relink its leaf-to-root path so the next round starts from the best stale
 // key; with full labels also MarkSeed: zero the size at the seed's label in
 // every sketch.
+// relink false: the caller relinks the path itself (from values it holds).
 __device__ __forceinline__ void round_end_wave(const TreeDesc &td, SelState *st, uint32_t *ids, uint64_t *key,
                                                uint8_t *in_s, uint32_t kb, uint32_t *seeds_out,
                                                unsigned long long *gains_out, uint32_t *evals_out, uint2 *E,
-                                               uint32_t R) {
+                                               uint32_t R, bool relink = true) {
     const uint32_t lane = lane_id();
     const uint32_t s = ids[td.lvl_off[0]];
     const uint64_t ks = key[s];
@@ -229,7 +230,7 @@ __device__ __forceinline__ void round_end_wave(const TreeDesc &td, SelState *st,
     // relink the path of leaf s, bottom-up, using the values this wave just wrote
     uint32_t child = s, child_id = s;
     uint64_t child_key = 0;
-    for (int l = (int)td.D - 1; l >= 0; --l) {
+    for (int l = relink ? (int)td.D - 1 : -1; l >= 0; --l) {
         const uint32_t t = child >> kFanLog;
         const uint32_t w = relink_node(td, ids, key, (uint32_t)l, t, child, child_id, child_key, true);
         const uint64_t wk = (w == s) ? 0ull : key[w];
