@@ -803,7 +803,10 @@ void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const ui
     }
     {
         Prof p(ctx, "compress", st, timed);
-        // runs of at most 512 numbers, short enough for about 16 waves per SIMD
+        // about 16,384 runs (one wave each), fewer and longer ones keeping the
+        // per-wave hot roots of a giant component few; at most 128 numbers a run
+        // (R-MAT 2^24: 1.47 ms per pass at 512, 1.33 ms at 128; 2^20 takes runs of 40,
+        // and 4x as many runs there doubled the time)
         const uint64_t want = ((uint64_t)g->n_linked / 16384 + kCompressIlp - 1) / kCompressIlp * kCompressIlp;
         const uint32_t run = (uint32_t)std::min<uint64_t>(kCompressRunMax, std::max<uint64_t>(kCompressIlp, want));
         const uint64_t runs = ((uint64_t)g->n_linked + run - 1) / run;  // one wave each

@@ -122,7 +122,7 @@ __global__ void k_batch_init(uint32_t *__restrict__ parent, uint32_t *__restrict
 // replaced while it has at most one member); other roots get one atomic per
 // member.  At the end the workgroup's waves combine their hot roots per sketch in
 // LDS, so a giant root gets one atomic per workgroup rather than per wave.
-constexpr uint32_t kCompressRunMax = 512;
+constexpr uint32_t kCompressRunMax = 128;
 constexpr uint32_t kCompressIlp = 8;
 constexpr uint32_t kCompressBlock = 1024;
 __global__ void __launch_bounds__(kCompressBlock) k_compress(uint32_t *__restrict__ parent,
