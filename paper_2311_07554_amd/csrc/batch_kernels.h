@@ -1,12 +1,14 @@
 // Batched selection: many independent queries (graph, model, R, k) built and
 // selected by five persistent kernels that a single hipGraph launches.
 //
-//   k_bat_init      parent[b][x] = x, cnt = 0 over every query's R x n scratch
+//   k_bat_init      every query's forests to identity and counters to 0
 //   k_bat_hook      sample + union-find hooking over every (query, 64-sketch pass, edge)
-//   k_bat_compress  roots and member counts over every (query, sketch, number)
+//   k_bat_compress  roots and member counts over every (query, 64-number tile)
 //   k_bat_emit      E[n][R] rows and initial gains over every (query, 64-vertex tile)
 // The forests number vertices in each graph's labelling order (hubs first; the
-// hashes take vertex ids), like the single-query build; E holds vertex ids.
+// hashes take vertex ids), like the single-query build, and are vertex-major: the
+// entry of number x in sketch b at x * R + b, so a vertex's entries in all R
+// sketches are one contiguous row; E holds vertex ids.
 //   k_bat_select    one workgroup per query (work-stealing counter): winning tree
 //                   built from the initial gains, then k rounds of Algorithm 5
 //                   with the frontier levels separated by workgroup barriers
@@ -40,7 +42,7 @@ struct BatchQuery {
     const uint64_t *K;               // sketch keys, round_up(R, 8) + 8 entries
     uint2 *E;                        // [n][R]: (CC label, CC size if v is the label else 0)
     uint64_t *gain0;                 // [n]
-    uint32_t *parent, *cnt;          // [R][n] scratch of the build, indexed by labelling-order number
+    uint32_t *parent, *cnt;          // [n][R] scratch of the build, indexed by labelling-order number
     uint64_t *key;                   // [n]
     uint8_t *in_s;                   // [n]
     uint32_t *ids, *fr;              // winning tree levels / frontiers
@@ -140,9 +142,9 @@ __device__ __forceinline__ uint64_t marginal_cov(const uint2 *__restrict__ E, ui
     return wave_sum_u64(s);
 }
 
-// (sketch, vertex) items: each query's R rows of n vertices are padded to whole
-// waves (npad = n rounded up to 64), so a wave never straddles two rows and finds
-// its query and sketch once.
+// (number, sketch) items: each query's npad x R entries (n rounded up to 64, so a
+// query's item count is a multiple of 64 and a wave never straddles two queries),
+// item i of a query being entry (i / R, i % R).
 __device__ __forceinline__ uint32_t row_pad(uint32_t n) { return (n + 63u) & ~63u; }
 
 __global__ void __launch_bounds__(256) k_bat_init(const BatchQuery *__restrict__ qs, uint32_t nq,
@@ -151,16 +153,13 @@ __global__ void __launch_bounds__(256) k_bat_init(const BatchQuery *__restrict__
     if (blockIdx.x == 0 && threadIdx.x == 0) *next_q = 0;
     const uint64_t total = pre_vn[nq], stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-        const uint64_t i0 = i & ~63ull;
-        const uint32_t q = (uint32_t)__builtin_amdgcn_readfirstlane((int)find_query(pre_vn, nq, i0));
+        const uint32_t q = (uint32_t)__builtin_amdgcn_readfirstlane((int)find_query(pre_vn, nq, i & ~63ull));
         const BatchQuery &Q = qs[q];
-        const uint32_t npad = row_pad(Q.n);
-        const uint64_t wl = i0 - pre_vn[q];
-        const uint32_t b = (uint32_t)(wl / npad);
-        const uint32_t v = (uint32_t)(wl - (uint64_t)b * npad) + lane_id();
-        if (v < Q.n) {
-            Q.parent[(size_t)b * Q.n + v] = v;
-            Q.cnt[(size_t)b * Q.n + v] = 0;
+        const uint64_t wl = i - pre_vn[q];
+        const uint32_t x = (uint32_t)(wl / Q.R);
+        if (x < Q.n) {
+            Q.parent[wl] = x;
+            Q.cnt[wl] = 0;
         }
     }
 }
@@ -196,93 +195,137 @@ __global__ void __launch_bounds__(1024) k_bat_hook(const BatchQuery *__restrict_
             }
             live &= nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
         }
-        unite_live(Q.parent + (size_t)b0 * Q.n, Q.n, 1u, live, iuv.x, iuv.y);
+        unite_live(Q.parent + b0, 1, Q.R, live, iuv.x, iuv.y);
     }
 }
 
-// Roots and member counts, one wave per 64 vertices of one (query, sketch) row.
-// Each wave keeps one hot counter (in practice a giant component's root) in a
-// register, across rows (it is an address); members of other roots are
-// combined per distinct root in the wave and added with one atomic per root.
+// Tiles of the per-vertex passes: 64 consecutive numbers (compress) or vertices
+// (emit) of one query, one wave each; lane b of a wave is sketch p0 + b of the
+// 64-sketch group p0 the wave is on, the groups taken one after another.
+constexpr uint32_t kBatTile = 64;
+constexpr uint32_t kBatIlp = 8;
+
+// Roots and member counts: each lane walks every number of the tile to its root in
+// its sketch (kBatIlp numbers' walks in lock step), points the number at it and
+// counts it there.  A lane keeps one "hot" root per group in a register (the first
+// root it meets, replaced while it has at most one member), since most members of
+// a sketch often share one giant component's root.
 __global__ void __launch_bounds__(256) k_bat_compress(const BatchQuery *__restrict__ qs, uint32_t nq,
-                                                      const uint64_t *__restrict__ pre_vn) {
+                                                      const uint64_t *__restrict__ pre_tiles) {
     const uint32_t lane = lane_id();
-    const uint64_t total = pre_vn[nq], stride = (uint64_t)gridDim.x * blockDim.x;
-    unsigned long long hot = 0;
-    uint32_t hot_cnt = 0;
-    for (uint64_t wb = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~63ull; wb < total; wb += stride) {
-        const uint32_t q = (uint32_t)__builtin_amdgcn_readfirstlane((int)find_query(pre_vn, nq, wb));
-        const BatchQuery &Q = qs[q];
-        const uint32_t n = Q.n, npad = row_pad(n);
-        const uint64_t wl = wb - pre_vn[q];
-        const uint32_t b = (uint32_t)(wl / npad);
-        const uint32_t v = (uint32_t)(wl - (uint64_t)b * npad) + lane;
-        uint32_t *P = Q.parent + (size_t)b * n;
-        unsigned long long target = 0;
-        if (v < n) {
-            uint32_t r = v, p = P[v];
-            while (p != r) { r = p; p = P[r]; }
-            if (r != v) {
-                P[v] = r;
-                target = (unsigned long long)(Q.cnt + (size_t)b * n + r);
-            }
-        }
-        bool need = target != 0;
-        if (hot == 0) {
-            const uint64_t m = __ballot(need);
-            if (m) hot = __shfl(target, (int)__builtin_ctzll(m));
-        }
-        const bool in_hot = need && target == hot;
-        hot_cnt += (uint32_t)__popcll(__ballot(in_hot));
-        if (in_hot) need = false;
-        for (uint64_t m = __ballot(need); m; m = __ballot(need)) {
-            const unsigned long long lt = __shfl(target, (int)__builtin_ctzll(m));
-            const bool same = need && target == lt;
-            const uint64_t sm = __ballot(same);
-            if (lane == (uint32_t)__builtin_ctzll(m)) atomicAdd(reinterpret_cast<uint32_t *>(lt), (uint32_t)__popcll(sm));
-            if (same) need = false;
-        }
-    }
-    if (lane == 0 && hot && hot_cnt) atomicAdd(reinterpret_cast<uint32_t *>(hot), hot_cnt);
-}
-
-// One block of 256 threads per (query, kEmitTile-vertex tile); the R sketches are
-// staged 64 at a time in LDS so E row segments are written by consecutive lanes.
-__global__ void __launch_bounds__(256) k_bat_emit(const BatchQuery *__restrict__ qs, uint32_t nq,
-                                                  const uint64_t *__restrict__ pre_tiles) {
-    __shared__ uint2 tile[kEmitTile][65];
-    __shared__ uint32_t gsz[kEmitTile][65];
     const uint64_t total = pre_tiles[nq];
-    for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
-        const uint32_t q = find_query(pre_tiles, nq, it);
+    for (uint64_t t = wave_index(); t < total; t += wave_count()) {
+        const uint32_t q = (uint32_t)__builtin_amdgcn_readfirstlane((int)find_query(pre_tiles, nq, t));
         const BatchQuery &Q = qs[q];
         const uint32_t n = Q.n, R = Q.R;
-        const uint32_t v0 = (uint32_t)(it - pre_tiles[q]) * kEmitTile;
-        uint64_t gsum = 0;
-        for (uint32_t b0 = 0; b0 < R; b0 += 64) {
-            const uint32_t nb = min(64u, R - b0);
-            for (uint32_t idx = threadIdx.x; idx < kEmitTile * nb; idx += blockDim.x) {
-                const uint32_t b = idx / kEmitTile, vi = idx % kEmitTile, v = v0 + vi;
-                if (v < n) {
-                    const size_t base = (size_t)(b0 + b) * n;
-                    const uint32_t x = Q.newid[v];
-                    const uint32_t root = Q.parent[base + x];
-                    const uint32_t s = 1u + Q.cnt[base + root];
-                    // the label is the root's vertex id; its own entry carries the size
-                    tile[vi][b] = root == x ? make_uint2(v, s) : make_uint2(Q.iperm[root], 0u);
-                    gsz[vi][b] = s;
+        uint32_t *P = Q.parent;
+        uint32_t *C = Q.cnt;
+        const uint32_t x0 = (uint32_t)(t - pre_tiles[q]) * kBatTile, x1 = min(x0 + kBatTile, n);
+        for (uint32_t p0 = 0; p0 < R; p0 += kWave) {
+            const uint32_t b = p0 + lane;
+            const bool act = b < R;
+            uint32_t hot = kNone, hot_cnt = 0;
+            for (uint32_t xb = x0; xb < x1; xb += kBatIlp) {
+                uint32_t pp[kBatIlp], rt[kBatIlp];
+#pragma unroll
+                for (uint32_t j = 0; j < kBatIlp; ++j) {
+                    const bool ok = act && xb + j < x1;
+                    pp[j] = P[ok ? (size_t)(xb + j) * R + b : 0];
+                }
+#pragma unroll
+                for (uint32_t j = 0; j < kBatIlp; ++j) {
+                    rt[j] = xb + j;
+                    if (act && xb + j < x1) pp[j] = pin_vgpr(pp[j]);
+                    else pp[j] = rt[j];
+                }
+                for (;;) {
+                    bool more = false;
+#pragma unroll
+                    for (uint32_t j = 0; j < kBatIlp; ++j) more |= pp[j] != rt[j];
+                    if (!more) break;
+                    uint32_t nx[kBatIlp];
+#pragma unroll
+                    for (uint32_t j = 0; j < kBatIlp; ++j) nx[j] = P[pp[j] != rt[j] ? (size_t)pp[j] * R + b : 0];
+#pragma unroll
+                    for (uint32_t j = 0; j < kBatIlp; ++j)
+                        if (pp[j] != rt[j]) {
+                            rt[j] = pp[j];
+                            pp[j] = pin_vgpr(nx[j]);
+                        }
+                }
+#pragma unroll
+                for (uint32_t j = 0; j < kBatIlp; ++j) {
+                    const uint32_t x = xb + j;
+                    if (!act || x >= x1) continue;
+                    const uint32_t r = rt[j];
+                    if (r == x) continue;
+                    P[(size_t)x * R + b] = r;
+                    if (r != hot && hot_cnt <= 1) {
+                        if (hot != kNone && hot_cnt) atomicAdd(C + (size_t)hot * R + b, hot_cnt);
+                        hot = r;
+                        hot_cnt = 0;
+                    }
+                    if (r == hot) ++hot_cnt;
+                    else atomicAdd(C + (size_t)r * R + b, 1u);
                 }
             }
-            __syncthreads();
-            for (uint32_t idx = threadIdx.x; idx < kEmitTile * nb; idx += blockDim.x) {
-                const uint32_t vi = idx / nb, b = idx % nb, v = v0 + vi;
-                if (v < n) Q.E[(size_t)v * R + b0 + b] = tile[vi][b];
-            }
-            if (threadIdx.x < kEmitTile)
-                for (uint32_t b = 0; b < nb; ++b) gsum += gsz[threadIdx.x][b];
-            __syncthreads();
+            if (act && hot != kNone && hot_cnt) atomicAdd(C + (size_t)hot * R + b, hot_cnt);
         }
-        if (threadIdx.x < kEmitTile && v0 + threadIdx.x < n) Q.gain0[v0 + threadIdx.x] = gsum;
+    }
+}
+
+// E rows and initial gains: per vertex v of the tile the wave reads the row of its
+// number newid[v] (lane b: sketch p0 + b), gathers the root counts and the roots'
+// vertex ids, and writes E[v][p0 + b] = (v, size) at a root, (the root's vertex id,
+// 0) elsewhere; the vertex's sizes are summed across lanes (DPP) and groups, lane j
+// keeping vertex v0 + j's sum.
+__global__ void __launch_bounds__(256) k_bat_emit(const BatchQuery *__restrict__ qs, uint32_t nq,
+                                                  const uint64_t *__restrict__ pre_tiles) {
+    constexpr uint32_t kIlp = 4;
+    const uint32_t lane = lane_id();
+    const uint64_t total = pre_tiles[nq];
+    for (uint64_t t = wave_index(); t < total; t += wave_count()) {
+        const uint32_t q = (uint32_t)__builtin_amdgcn_readfirstlane((int)find_query(pre_tiles, nq, t));
+        const BatchQuery &Q = qs[q];
+        const uint32_t n = Q.n, R = Q.R;
+        const uint32_t *P = Q.parent;
+        const uint32_t *C = Q.cnt;
+        const uint32_t v0 = (uint32_t)(t - pre_tiles[q]) * kBatTile;
+        const uint32_t vl = v0 + lane;
+        const uint32_t my_iv = vl < n ? Q.newid[vl] : 0u;
+        const bool small = (uint64_t)n * kWave < (1ull << 32);  // a group's sum of one vertex fits 32 bits
+        uint64_t g_sum = 0;
+        for (uint32_t p0 = 0; p0 < R; p0 += kWave) {
+            const uint32_t b = p0 + lane;
+            const bool act = b < R;
+            for (uint32_t j0 = 0; j0 < kBatTile; j0 += kIlp) {
+                uint32_t iv[kIlp], tt[kIlp], root[kIlp], c[kIlp], lab[kIlp];
+#pragma unroll
+                for (uint32_t u = 0; u < kIlp; ++u) {
+                    iv[u] = (uint32_t)__builtin_amdgcn_readlane((int)my_iv, (int)(j0 + u));
+                    const bool rd = act && v0 + j0 + u < n;
+                    tt[u] = P[rd ? (size_t)iv[u] * R + b : 0];
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < kIlp; ++u) {
+                    const bool rd = act && v0 + j0 + u < n;
+                    root[u] = rd ? pin_vgpr(tt[u]) : iv[u];
+                    c[u] = C[rd ? (size_t)root[u] * R + b : 0];
+                    lab[u] = Q.iperm[rd ? root[u] : 0];
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < kIlp; ++u) {
+                    const uint32_t v = v0 + j0 + u;
+                    if (v >= n) break;  // wave-uniform
+                    const uint32_t sz = act ? 1u + pin_vgpr(c[u]) : 0u;
+                    if (act)
+                        Q.E[(size_t)v * R + b] = root[u] == iv[u] ? make_uint2(v, sz) : make_uint2(pin_vgpr(lab[u]), 0u);
+                    const uint64_t g = small ? (uint64_t)wave_sum_u32_rows(sz) : wave_sum_u64(sz);
+                    if (lane == j0 + u) g_sum += g;
+                }
+            }
+        }
+        if (vl < n) Q.gain0[vl] = g_sum;
     }
 }
 

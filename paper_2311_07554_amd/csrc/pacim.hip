@@ -2305,10 +2305,10 @@ im_status run_full_batch(im_ctx *ctx, const std::vector<const im_query *> &queri
         B.seeds = reinterpret_cast<uint32_t *>(arena + o.seeds);
         B.gains = reinterpret_cast<unsigned long long *>(arena + o.gains);
         B.evals = reinterpret_cast<uint32_t *>(arena + o.evals);
-        pre[q + 1] = pre[q] + (uint64_t)B.R * ((B.n + 63) & ~63u);                          // (sketch, vertex), rows wave-padded
+        pre[q + 1] = pre[q] + (uint64_t)B.R * ((B.n + 63) & ~63u);                          // (number, sketch), wave-padded
         const uint64_t hook = (uint64_t)((B.R + 63) / 64) * B.m;
         pre[(nq + 1) + q + 1] = pre[(nq + 1) + q] + ((hook + 63) & ~63ull);                 // (pass, edge), wave-padded
-        pre[2 * (nq + 1) + q + 1] = pre[2 * (nq + 1) + q] + (B.n + kEmitTile - 1) / kEmitTile;  // vertex tiles
+        pre[2 * (nq + 1) + q + 1] = pre[2 * (nq + 1) + q] + (B.n + kBatTile - 1) / kBatTile;    // vertex tiles
         pre[3 * (nq + 1) + q + 1] = pre[3 * (nq + 1) + q] + prep_items(B);                       // prepare items
         for (uint32_t j = 0; j < Dmax; ++j) {                                                        // tree level j
             const uint64_t nodes = j < B.td.D ? B.td.lvl_n[B.td.D - 1 - j] : 0;
@@ -2339,8 +2339,8 @@ im_status run_full_batch(im_ctx *ctx, const std::vector<const im_query *> &queri
     const uint64_t tot_prep = pre[4 * nq + 3];
     const unsigned g_init = grid_for(tot_vn, 256, 256 * 64);
     const unsigned g_hook = c.hook_grid ? c.hook_grid : grid_for(tot_hook, c.hook_block, 256 * 64);
-    const unsigned g_comp = grid_for(tot_vn, 256, 256 * 32);
-    const unsigned g_emit = (unsigned)std::min<uint64_t>(std::max<uint64_t>(tot_tiles, 1), 256 * 32);
+    const unsigned g_comp = grid_for(tot_tiles * kWave, 256, 256 * 32);  // one wave per tile
+    const unsigned g_emit = g_comp;
     const unsigned g_sel = c.select_grid ? c.select_grid : std::min<uint32_t>(nq, 256);
 
     // signature of every launch the graph holds: the arena address fixes every
@@ -2359,7 +2359,7 @@ im_status run_full_batch(im_ctx *ctx, const std::vector<const im_query *> &queri
         } else {
             k_bat_init<<<g_init, 256, 0, st>>>(dq, nq, dpre, next_q);
             k_bat_hook<<<g_hook, c.hook_block, 0, st>>>(dq, nq, dpre + (nq + 1));
-            k_bat_compress<<<g_comp, 256, 0, st>>>(dq, nq, dpre);
+            k_bat_compress<<<g_comp, 256, 0, st>>>(dq, nq, dpre + 2 * (nq + 1));
             k_bat_emit<<<g_emit, 256, 0, st>>>(dq, nq, dpre + 2 * (nq + 1));
             // selection phases: the whole GPU prepares keys and trees (new queries; queries
             // paused before a round predicted to re-evaluate nearly every vertex), then one

@@ -230,7 +230,6 @@ __global__ void __launch_bounds__(kCompressBlock) k_compress(uint32_t *__restric
 // per-vertex values (labelling-order number, center rank) are the same in every
 // lane.  Isolated vertices (numbers >= n_linked) are their own singletons and read
 // nothing.
-constexpr int kEmitTile = 32;  // vertices per tile of the batched emit
 constexpr uint32_t kEmitIlp = 4;
 
 // Sum over the wave of x, carried in 64 bits.
