@@ -164,38 +164,47 @@ __global__ void __launch_bounds__(256) k_bat_init(const BatchQuery *__restrict__
     }
 }
 
-// pre_hook: per-query item counts rounded up to whole waves, so every wave lies in
-// one query and reads its descriptor through scalar loads.  blockDim must be a
-// multiple of 64.
+// The sampling pass over every (query, 64-sketch pass, chunk of kBatHookChunk
+// edges) item, one workgroup per item: the workgroup reads its query once, and
+// every thread of it samples the same 64 sketches.  pre_hook: items per query,
+// passes x chunks.  The batched path takes the four models whose threshold the end
+// points give (a per-edge model is rejected before the launch).
+constexpr uint32_t kBatHookChunk = 1024;
 __global__ void __launch_bounds__(1024) k_bat_hook(const BatchQuery *__restrict__ qs, uint32_t nq,
                                                    const uint64_t *__restrict__ pre_hook) {
-    const uint64_t total = pre_hook[nq], stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-        const uint32_t q = (uint32_t)__builtin_amdgcn_readfirstlane((int)find_query(pre_hook, nq, i & ~63ull));
+    __shared__ uint32_t sh_q;
+    const uint64_t total = pre_hook[nq];
+    for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        __syncthreads();  // the previous item's readers of sh_q are done
+        if (threadIdx.x == 0) sh_q = find_query(pre_hook, nq, it);
+        __syncthreads();
+        const uint32_t q = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh_q);  // uniform: scalar loads
         const BatchQuery &Q = qs[q];
-        const uint64_t local = i - pre_hook[q];
-        if (local >= (uint64_t)((Q.R + 63) / 64) * Q.m) continue;
-        const uint32_t pass = (uint32_t)(local / Q.m);
-        const uint64_t e = local - (uint64_t)pass * Q.m;
+        const uint64_t chunks = (Q.m + kBatHookChunk - 1) / kBatHookChunk;
+        const uint64_t local = it - pre_hook[q];
+        const uint32_t pass = (uint32_t)(local / chunks);
+        const uint64_t e0 = (local - (uint64_t)pass * chunks) * kBatHookChunk;
+        const uint64_t e1 = min(e0 + kBatHookChunk, Q.m);
         const uint32_t b0 = pass * 64, nb = min(64u, Q.R - b0);
-        const uint2 uv = Q.edges[e], iuv = Q.iedges[e];
-        const uint64_t x = ((uint64_t)uv.x << 32) | uv.y;
-        const uint64_t T = edge_threshold(Q.pm, uv.x, uv.y, x);
-        uint64_t live;
-        if (T == kAllLive) {
-            live = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
-        } else {
-            live = 0;
-            const uint64_t *K = Q.K + b0;
-            for (uint32_t c0 = 0; c0 < nb; c0 += 8) {
-                uint32_t chunk = 0;
+        const uint64_t *K = Q.K + b0;
+        const uint64_t all = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
+        for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+            const uint2 uv = Q.edges[e], iuv = Q.iedges[e];
+            const uint64_t x = ((uint64_t)uv.x << 32) | uv.y;
+            const uint64_t T = edge_threshold(Q.pm, uv.x, uv.y, x);
+            uint64_t live = all;
+            if (T != kAllLive) {
+                live = 0;
+                for (uint32_t c0 = 0; c0 < nb; c0 += 8) {
+                    uint32_t chunk = 0;
 #pragma unroll
-                for (int j = 0; j < 8; ++j) chunk |= (mix64(x ^ K[c0 + j]) < T) ? (1u << j) : 0u;
-                live |= (uint64_t)chunk << c0;
+                    for (int j = 0; j < 8; ++j) chunk |= (mix64(x ^ K[c0 + j]) < T) ? (1u << j) : 0u;
+                    live |= (uint64_t)chunk << c0;
+                }
+                live &= all;
             }
-            live &= nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
+            unite_live(Q.parent + b0, 1, Q.R, live, iuv.x, iuv.y);
         }
-        unite_live(Q.parent + b0, 1, Q.R, live, iuv.x, iuv.y);
     }
 }
 

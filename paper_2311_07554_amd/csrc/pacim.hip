@@ -2306,8 +2306,8 @@ im_status run_full_batch(im_ctx *ctx, const std::vector<const im_query *> &queri
         B.gains = reinterpret_cast<unsigned long long *>(arena + o.gains);
         B.evals = reinterpret_cast<uint32_t *>(arena + o.evals);
         pre[q + 1] = pre[q] + (uint64_t)B.R * ((B.n + 63) & ~63u);                          // (number, sketch), wave-padded
-        const uint64_t hook = (uint64_t)((B.R + 63) / 64) * B.m;
-        pre[(nq + 1) + q + 1] = pre[(nq + 1) + q] + ((hook + 63) & ~63ull);                 // (pass, edge), wave-padded
+        const uint64_t hook = (uint64_t)((B.R + 63) / 64) * ((B.m + kBatHookChunk - 1) / kBatHookChunk);
+        pre[(nq + 1) + q + 1] = pre[(nq + 1) + q] + hook;                                   // (pass, edge chunk)
         pre[2 * (nq + 1) + q + 1] = pre[2 * (nq + 1) + q] + (B.n + kBatTile - 1) / kBatTile;    // vertex tiles
         pre[3 * (nq + 1) + q + 1] = pre[3 * (nq + 1) + q] + prep_items(B);                       // prepare items
         for (uint32_t j = 0; j < Dmax; ++j) {                                                        // tree level j
@@ -2338,7 +2338,7 @@ im_status run_full_batch(im_ctx *ctx, const std::vector<const im_query *> &queri
     const uint64_t tot_vn = pre[nq], tot_hook = pre[2 * nq + 1], tot_tiles = pre[3 * nq + 2];
     const uint64_t tot_prep = pre[4 * nq + 3];
     const unsigned g_init = grid_for(tot_vn, 256, 256 * 64);
-    const unsigned g_hook = c.hook_grid ? c.hook_grid : grid_for(tot_hook, c.hook_block, 256 * 64);
+    const unsigned g_hook = c.hook_grid ? c.hook_grid : (unsigned)std::min<uint64_t>(std::max<uint64_t>(tot_hook, 1), 16384);
     const unsigned g_comp = grid_for(tot_tiles * kWave, 256, 256 * 32);  // one wave per tile
     const unsigned g_emit = g_comp;
     const unsigned g_sel = c.select_grid ? c.select_grid : std::min<uint32_t>(nq, 256);
