@@ -126,76 +126,6 @@ __device__ __forceinline__ void persist_step(const PersistArgs &a, uint32_t kind
     }
 }
 
-// The leader's walk of a round while each level's frontier is one node (the usual
-// lazy round: the root's fresh key still beats every other stale key, so each
-// level explores only the child on the previous winner's path and evaluates
-// nothing).  check_level's rules on that node, with its children's ids and keys
-// kept in LDS: it writes the frontier of the next level as check_level would
-// (one node; no evaluations), and stops at the first level whose check needs the
-// general step (an evaluation, or more than one child to explore).  Returns that
-// level (D if none); node[l] = the frontier node of level l.  One wave.
-__device__ __forceinline__ uint32_t leader_walk(const PersistArgs &a, uint32_t (*cid_c)[kWave],
-                                                unsigned long long (*ck_c)[kWave], uint32_t *node) {
-    const uint32_t lane = lane_id();
-    const uint64_t delta = __hip_atomic_load(&a.st->delta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t t = 0;
-    uint32_t pid = a.ids[a.td.lvl_off[0]];
-    for (uint32_t l = 0; l < a.td.D; ++l) {
-        const uint32_t c = t * kFan + lane;
-        const bool valid = c < a.td.lvl_n[l + 1];
-        const bool leaf = l + 1 == a.td.D;
-        uint32_t cid = 0;
-        uint64_t ck = 0;
-        if (valid) {
-            cid = leaf ? c : a.ids[a.td.lvl_off[l + 1] + c];
-            ck = a.key[cid];
-        }
-        const bool stale = valid && cid != pid;
-        const bool need = stale && ck >= delta;
-        const bool explore = valid && !leaf && (!stale || need);
-        const uint64_t ex = __ballot(explore);
-        if (__ballot(need) != 0ull || (!leaf && __popcll(ex) != 1)) return l;
-        cid_c[l][lane] = cid;
-        ck_c[l][lane] = ck;
-        if (!leaf) {  // the explored child keeps the winner's id, so pid carries over
-            const uint32_t nt = t * kFan + (uint32_t)__builtin_ctzll(ex);
-            if (lane == 0) {
-                a.fr[a.td.lvl_off[l + 1]] = nt;
-                a.st->fr_cnt[l + 1] = 1;
-                node[l + 1] = nt;
-            }
-            t = nt;
-        }
-    }
-    return a.td.D;
-}
-
-// relink_level's argmax on the walked nodes of levels lstart, lstart - 1, ..., 0
-// from the kept children, the path child of level l (lane sub_lane) substituted by
-// the winner below it (sub_id, sub_key).  One wave.
-__device__ __forceinline__ void leader_relink(const PersistArgs &a, uint32_t (*cid_c)[kWave],
-                                              unsigned long long (*ck_c)[kWave], const uint32_t *node, int lstart,
-                                              uint32_t sub_lane, uint32_t sub_id, uint64_t sub_key) {
-    const uint32_t lane = lane_id();
-    for (int l = lstart; l >= 0; --l) {
-        const uint32_t t = node[l];
-        const bool valid = t * kFan + lane < a.td.lvl_n[l + 1];
-        uint32_t cid = cid_c[l][lane];
-        uint64_t ck = valid ? ck_c[l][lane] : 0ull;
-        if (lane == sub_lane) {
-            cid = sub_id;
-            ck = sub_key;
-        }
-        const uint64_t best = wave_max_u64(ck);
-        const uint64_t win = __ballot(valid && ck == best);
-        const uint32_t w = __shfl(cid, (int)__builtin_ctzll(win));
-        if (lane == 0) a.ids[a.td.lvl_off[l] + t] = w;
-        sub_lane = t & (kFan - 1);
-        sub_id = w;
-        sub_key = best;
-    }
-}
-
 __global__ void __launch_bounds__(kPersistBlock) k_select_persist(PersistArgs a) {
     __shared__ uint32_t lds[kPersistWaves][kQCap + kHCap];
     __shared__ uint32_t sh_kind, sh_arg, sh_mode, sh_ok, sh_val;
@@ -324,7 +254,9 @@ __global__ void __launch_bounds__(kPersistBlock) k_select_persist(PersistArgs a)
         if (pending == kNone && ok) {
             __syncthreads();
             if (w == 0) {
-                const uint32_t f = leader_walk(a, sh_cid, sh_ck, sh_node);
+                const uint64_t delta = __hip_atomic_load(&a.st->delta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t f = walk_single_frontiers(a.td, a.ids, a.key, delta, a.fr, a.st->fr_cnt, sh_cid, sh_ck,
+                                                         sh_node);
                 if (tid == 0) {
                     sh_node[0] = 0;
                     sh_lf = f;
@@ -352,13 +284,13 @@ __global__ void __launch_bounds__(kPersistBlock) k_select_persist(PersistArgs a)
                 const uint32_t s = a.ids[a.td.lvl_off[0]];
                 round_end_wave(a.td, a.st, a.ids, a.key, a.in_s, a.kb, a.seeds_out, a.gains_out, a.evals_out, a.E,
                                a.R, false);
-                leader_relink(a, sh_cid, sh_ck, sh_node, (int)a.td.D - 1, s & (kFan - 1), s, 0ull);
+                relink_kept(a.td, a.ids, sh_cid, sh_ck, sh_node, (int)a.td.D - 1, s & (kFan - 1), s, 0ull);
             }
         } else {
             if (w == 0 && lf > 0) {  // the walked levels, below them the general steps' winner
                 const uint32_t tn = sh_node[lf];
                 const uint32_t id = a.ids[a.td.lvl_off[lf] + tn];
-                leader_relink(a, sh_cid, sh_ck, sh_node, (int)lf - 1, tn & (kFan - 1), id, a.key[id]);
+                relink_kept(a.td, a.ids, sh_cid, sh_ck, sh_node, (int)lf - 1, tn & (kFan - 1), id, a.key[id]);
             }
             __syncthreads();
             if (w == 0) round_end_wave(a.td, a.st, a.ids, a.key, a.in_s, a.kb, a.seeds_out, a.gains_out, a.evals_out,

@@ -249,6 +249,79 @@ __device__ __forceinline__ void round_end_wave(const TreeDesc &td, SelState *st,
     if (lane == 0) st->round = round + 1;
 }
 
+// A round's walk while each level's frontier is one node (the usual lazy round:
+// the root's fresh key still beats every other stale key, so each level explores
+// only the child on the previous winner's path and evaluates nothing).
+// check_level's rules on that node, with its children's ids and keys kept in LDS
+// (cid_c / ck_c): it writes the frontier of the next level as check_level would
+// (one node in fr, fr_cnt[l + 1] = 1; no evaluations), and stops at the first
+// level whose check needs the general step (an evaluation, or more than one child
+// to explore).  Returns that level (D if none); node[l] = the frontier node of
+// level l for l >= 1 (level 0's is the root, 0).  delta: the round's best fresh
+// key so far.  One wave.
+__device__ __forceinline__ uint32_t walk_single_frontiers(const TreeDesc &td, const uint32_t *ids,
+                                                          const uint64_t *key, uint64_t delta, uint32_t *fr,
+                                                          uint32_t *fr_cnt, uint32_t (*cid_c)[kWave],
+                                                          unsigned long long (*ck_c)[kWave], uint32_t *node) {
+    const uint32_t lane = lane_id();
+    uint32_t t = 0;
+    uint32_t pid = ids[td.lvl_off[0]];
+    for (uint32_t l = 0; l < td.D; ++l) {
+        const uint32_t c = t * kFan + lane;
+        const bool valid = c < td.lvl_n[l + 1];
+        const bool leaf = l + 1 == td.D;
+        uint32_t cid = 0;
+        uint64_t ck = 0;
+        if (valid) {
+            cid = leaf ? c : ids[td.lvl_off[l + 1] + c];
+            ck = key[cid];
+        }
+        const bool stale = valid && cid != pid;
+        const bool need = stale && ck >= delta;
+        const bool explore = valid && !leaf && (!stale || need);
+        const uint64_t ex = __ballot(explore);
+        if (__ballot(need) != 0ull || (!leaf && __popcll(ex) != 1)) return l;
+        cid_c[l][lane] = cid;
+        ck_c[l][lane] = ck;
+        if (!leaf) {  // the explored child keeps the winner's id, so pid carries over
+            const uint32_t nt = t * kFan + (uint32_t)__builtin_ctzll(ex);
+            if (lane == 0) {
+                fr[td.lvl_off[l + 1]] = nt;
+                fr_cnt[l + 1] = 1;
+                node[l + 1] = nt;
+            }
+            t = nt;
+        }
+    }
+    return td.D;
+}
+
+// relink_level's argmax on the walked nodes of levels lstart, lstart - 1, ..., 0
+// from the kept children, the path child of level l (lane sub_lane) substituted by
+// the winner below it (sub_id, sub_key).  node[0] must hold 0.  One wave.
+__device__ __forceinline__ void relink_kept(const TreeDesc &td, uint32_t *ids, uint32_t (*cid_c)[kWave],
+                                            unsigned long long (*ck_c)[kWave], const uint32_t *node, int lstart,
+                                            uint32_t sub_lane, uint32_t sub_id, uint64_t sub_key) {
+    const uint32_t lane = lane_id();
+    for (int l = lstart; l >= 0; --l) {
+        const uint32_t t = node[l];
+        const bool valid = t * kFan + lane < td.lvl_n[l + 1];
+        uint32_t cid = cid_c[l][lane];
+        uint64_t ck = valid ? ck_c[l][lane] : 0ull;
+        if (lane == sub_lane) {
+            cid = sub_id;
+            ck = sub_key;
+        }
+        const uint64_t best = wave_max_u64(ck);
+        const uint64_t win = __ballot(valid && ck == best);
+        const uint32_t w = __shfl(cid, (int)__builtin_ctzll(win));
+        if (lane == 0) ids[td.lvl_off[l] + t] = w;
+        sub_lane = t & (kFan - 1);
+        sub_id = w;
+        sub_key = best;
+    }
+}
+
 __global__ void k_round_begin(TreeDesc td, SelState *__restrict__ st, const uint32_t *__restrict__ ids,
                               uint32_t *__restrict__ fr, uint32_t *__restrict__ evl,
                               unsigned long long *__restrict__ partial, unsigned long long partial_init) {
