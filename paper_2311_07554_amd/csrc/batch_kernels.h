@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(1024) k_bat_hook(const BatchQuery *__restrict_
                 }
                 live &= all;
             }
-            unite_live(Q.parent + b0, 1, Q.R, live, iuv.x, iuv.y);
+            unite_live(Q.parent + b0, Q.R, live, iuv.x, iuv.y);
         }
     }
 }

@@ -3,7 +3,7 @@
 // per undirected edge tests the edge in each of the pass's sketches and unites
 // its endpoints in every sketch where it is live, in union-find forests whose
 // roots are the smallest numbers of their components.  The forest operations are
-// shared with the batched path (sketch-major forests).
+// shared with the batched path, whose forests are vertex-major too.
 #pragma once
 
 #include "common.h"
@@ -86,13 +86,13 @@ constexpr uint32_t kHookBlock = 256;
 constexpr int kHookIlp = 4;  // live sketches of an edge whose first parent loads are issued together
 
 // Unions of edge (u, v) in every sketch whose bit is set in live (sketch b's
-// entry of number x at parent[b * ss + x * vs]: ss = 1, vs = the pass's scratch
-// width for the vertex-major single-query scratch; ss = n, vs = 1 for the batched
-// path's sketch-major rows).  The parents of both endpoints in up to kHookIlp
-// sketches are loaded before any of those unions walks on, so a thread keeps
-// several independent memory accesses in flight instead of one chain.
-__device__ __forceinline__ void unite_live(uint32_t *parent, size_t ss, uint32_t vs, uint64_t live, uint32_t u,
-                                           uint32_t v) {
+// entry of number x at parent[b + x * vs]: vs = the pass's scratch width for the
+// single-query scratch; vs = the query's R for the batched path, whose rows hold
+// all of a query's sketches and whose caller offsets parent to the pass's first
+// sketch).  The parents of both endpoints in up to kHookIlp sketches are loaded
+// before any of those unions walks on, so a thread keeps several independent
+// memory accesses in flight instead of one chain.
+__device__ __forceinline__ void unite_live(uint32_t *parent, uint32_t vs, uint64_t live, uint32_t u, uint32_t v) {
     while (live) {
         uint32_t bs[kHookIlp], pu[kHookIlp], pv[kHookIlp];
         int c = 0;
@@ -108,13 +108,13 @@ __device__ __forceinline__ void unite_live(uint32_t *parent, size_t ss, uint32_t
 #pragma unroll
         for (int i = 0; i < kHookIlp; ++i)
             if (i < c) {
-                const uint32_t *P = parent + (size_t)bs[i] * ss;
+                const uint32_t *P = parent + bs[i];
                 pu[i] = uf_load(P + (size_t)u * vs);
                 pv[i] = uf_load(P + (size_t)v * vs);
             }
 #pragma unroll
         for (int i = 0; i < kHookIlp; ++i)
-            if (i < c) uf_unite_from(parent + (size_t)bs[i] * ss, vs, u, pu[i], v, pv[i]);
+            if (i < c) uf_unite_from(parent + bs[i], vs, u, pu[i], v, pv[i]);
     }
 }
 
@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(kHookBlock) k_sample_hook(const uint2 *__restr
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
         const uint2 uv = edges[e], iuv = iedges[e];
-        unite_live(parent, 1, vs, live_mask<KIND>(uv.x, uv.y, ((uint64_t)uv.x << 32) | uv.y, e, K, B, pm), iuv.x,
+        unite_live(parent, vs, live_mask<KIND>(uv.x, uv.y, ((uint64_t)uv.x << 32) | uv.y, e, K, B, pm), iuv.x,
                    iuv.y);
     }
 }

@@ -754,7 +754,7 @@ unsigned hook_grid_cap() {
 }
 
 // One pass over the edge list for b <= cs.B sketches (keys K[0..b)): union-find
-// forests in parent[b][n] over the graph's labelling order (x = newid[v]; the
+// forests in parent[n][cs.B] over the graph's labelling order (x = newid[v]; the
 // root of a CC is its smallest number), member counts at the roots in cnt, and
 // (if center_rank, given in labelling order) the smallest center rank of each CC
 // in minc.  parent_fresh: the linked numbers' entries already hold their own
