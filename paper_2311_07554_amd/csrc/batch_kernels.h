@@ -142,11 +142,12 @@ __device__ __forceinline__ uint64_t marginal_cov(const uint2 *__restrict__ E, ui
     return wave_sum_u64(s);
 }
 
-// (number, sketch) items: each query's npad x R entries (n rounded up to 64, so a
-// query's item count is a multiple of 64 and a wave never straddles two queries),
-// item i of a query being entry (i / R, i % R).
-__device__ __forceinline__ uint32_t row_pad(uint32_t n) { return (n + 63u) & ~63u; }
-
+// Set-up of the forests and counters, four entries per thread: item i of a query
+// covers its entries 4i .. 4i + 3 of n x R, entry (x, b) at x * R + b.  pre_vn
+// counts items per query, ceil(n R / 4) rounded up to a multiple of 64 so that a
+// wave never straddles two queries.  Four entries that all exist are written with
+// one 16-byte store per array (the arrays start 256-byte aligned), the last few
+// of a query entry by entry.
 __global__ void __launch_bounds__(256) k_bat_init(const BatchQuery *__restrict__ qs, uint32_t nq,
                                                   const uint64_t *__restrict__ pre_vn,
                                                   uint32_t *__restrict__ next_q) {
@@ -155,11 +156,20 @@ __global__ void __launch_bounds__(256) k_bat_init(const BatchQuery *__restrict__
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
         const uint32_t q = (uint32_t)__builtin_amdgcn_readfirstlane((int)find_query(pre_vn, nq, i & ~63ull));
         const BatchQuery &Q = qs[q];
-        const uint64_t wl = i - pre_vn[q];
-        const uint32_t x = (uint32_t)(wl / Q.R);
-        if (x < Q.n) {
-            Q.parent[wl] = x;
-            Q.cnt[wl] = 0;
+        const uint64_t w0 = (i - pre_vn[q]) * 4u, end = (uint64_t)Q.n * Q.R;
+        if (w0 >= end) continue;
+        const uint32_t x0 = (uint32_t)(w0 / Q.R), r0 = (uint32_t)(w0 - (uint64_t)x0 * Q.R);
+        uint32_t x[4];
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) x[k] = x0 + (r0 + k) / Q.R;
+        if (w0 + 4u <= end) {
+            *reinterpret_cast<uint4 *>(Q.parent + w0) = make_uint4(x[0], x[1], x[2], x[3]);
+            *reinterpret_cast<uint4 *>(Q.cnt + w0) = make_uint4(0u, 0u, 0u, 0u);
+        } else {
+            for (uint32_t k = 0; w0 + k < end; ++k) {
+                Q.parent[w0 + k] = x[k];
+                Q.cnt[w0 + k] = 0;
+            }
         }
     }
 }

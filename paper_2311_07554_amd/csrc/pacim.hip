@@ -771,13 +771,20 @@ void enqueue_cc_pass(im_ctx *ctx, const im_graph *g, const ProbDev &pm, const ui
     // their values from an earlier pass of the same build unless a caller flags
     // seeds in minc
     const uint32_t n_init = init_isolated ? n : g->n_linked;
-    uint32_t lw = 0;  // threads per number of the set-up: the width rounded up to a power of two
-    while ((1u << lw) < cs.B) ++lw;
-    const unsigned gi = grid_for((uint64_t)n_init << lw, 256, 1u << 20);
     {
         Prof p(ctx, "init", st, timed);
-        k_batch_init<<<gi, 256, 0, st>>>(parent_fresh ? nullptr : cs.parent, cs.cnt, minc, cs.B, lw, n_init,
-                                         minc_init, center_rank);
+        uint32_t *const par = parent_fresh ? nullptr : cs.parent;
+        const uintptr_t bases = reinterpret_cast<uintptr_t>(cs.parent) | reinterpret_cast<uintptr_t>(cs.cnt) |
+                                reinterpret_cast<uintptr_t>(minc);
+        if (cs.B % 4u == 0u && bases % 16u == 0u) {  // 16-byte stores: rows of whole 16-byte pieces
+            k_batch_init4<<<grid_for((uint64_t)n_init * (cs.B / 4u), 256, 1u << 20), 256, 0, st>>>(
+                par, cs.cnt, minc, cs.B, n_init, minc_init, center_rank);
+        } else {
+            uint32_t lw = 0;  // threads per number: the width rounded up to a power of two
+            while ((1u << lw) < cs.B) ++lw;
+            k_batch_init<<<grid_for((uint64_t)n_init << lw, 256, 1u << 20), 256, 0, st>>>(
+                par, cs.cnt, minc, cs.B, lw, n_init, minc_init, center_rank);
+        }
     }
     {
         Prof p(ctx, "sample_hook", st, timed);
@@ -2305,7 +2312,7 @@ im_status run_full_batch(im_ctx *ctx, const std::vector<const im_query *> &queri
         B.seeds = reinterpret_cast<uint32_t *>(arena + o.seeds);
         B.gains = reinterpret_cast<unsigned long long *>(arena + o.gains);
         B.evals = reinterpret_cast<uint32_t *>(arena + o.evals);
-        pre[q + 1] = pre[q] + (uint64_t)B.R * ((B.n + 63) & ~63u);                          // (number, sketch), wave-padded
+        pre[q + 1] = pre[q] + ((((uint64_t)B.n * B.R + 3) / 4 + 63) & ~63ull);           // 4 entries each, wave-padded
         const uint64_t hook = (uint64_t)((B.R + 63) / 64) * ((B.m + kBatHookChunk - 1) / kBatHookChunk);
         pre[(nq + 1) + q + 1] = pre[(nq + 1) + q] + hook;                                   // (pass, edge chunk)
         pre[2 * (nq + 1) + q + 1] = pre[2 * (nq + 1) + q] + (B.n + kBatTile - 1) / kBatTile;    // vertex tiles
