@@ -92,6 +92,43 @@ def test_rmat_compact_matches_oracle(ctx, alpha):
     gr.close()
 
 
+@pytest.mark.parametrize("width", ["6", "8"])
+def test_pass_width_matches_oracle(ctx, width, monkeypatch):
+    # scratch rows of 6 and 8 entries: the set-up writes a row in 16-byte pieces only
+    # when the width is a multiple of 4 (8), entry by entry otherwise (6); 20
+    # sketches in passes of 6, 6, 6, 2 or 8, 8, 4; full labels, CompactSketch, and
+    # simulated influence over 7 worlds (rows of 6, or of 7 where passes hold 8)
+    monkeypatch.setenv("PACIM_SKETCHES_PER_PASS", width)
+    g = inputs.rmat_graph(11, 8 << 11, seed=41)
+    R, k, seed, p = 20, 10, 9, 0.1
+    _say(f"case pass width {width}")
+    lab, siz = oracle.sketches(g, U, p, seed, R, threads=8)
+    ws, wg = oracle.greedy(lab, siz, k)
+    gr = upload(ctx, g)
+    try:
+        sk = gr.sketches(U, p, R, seed, 1.0)
+        assert sk.stats()["sketches_per_pass"] == int(width)
+        for r in range(R):
+            gl, gs = sk.dump(r)
+            assert np.array_equal(gl, lab[r]) and np.array_equal(gs, siz[r]), r
+        s, gn = sk.select(k)
+        sk.close()
+        assert np.array_equal(s, ws) and np.array_equal(gn, wg)
+        cents = oracle.centers(g.n, seed, 0.3)
+        lc, sc = oracle.compact_all(lab, siz, cents)
+        sk = gr.sketches(U, p, R, seed, 0.3)
+        for r in range(R):
+            cl, cz = sk.dump(r)
+            assert np.array_equal(cl, lc[r]) and np.array_equal(cz, sc[r]), r
+        s, gn = sk.select(k)
+        sk.close()
+        assert np.array_equal(s, ws) and np.array_equal(gn, wg)
+        assert gr.influence(U, p, [int(x) for x in ws[:3]], 3, 5, 7) == \
+            oracle.influence(g, U, p, [int(x) for x in ws[:3]], 3, 5, 7, threads=8)
+    finally:
+        gr.close()
+
+
 @pytest.mark.parametrize("policy,cap", [("always", None), ("never", None), ("auto", None), ("always", "1"),
                                         ("auto", "1")])
 def test_compact_bulk_rounds_match_oracle(ctx, policy, cap, monkeypatch):
