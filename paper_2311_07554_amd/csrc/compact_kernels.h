@@ -496,7 +496,7 @@ __global__ void __launch_bounds__(kBfsBlock) k_markseed_compact(SelState *__rest
 // keys, so its root is the plain greedy's choice.
 
 // flag of (sketch b, root of s) = 1 for every seed chosen so far (flag zeroed by
-// k_batch_init); vertex-major forests of width vs.
+// the set-up, k_batch_init or k_batch_init4); vertex-major forests of width vs.
 __global__ void __launch_bounds__(256) k_bulk_seed_roots(const SelState *__restrict__ st,
                                                          const uint32_t *__restrict__ seeds,
                                                          const uint32_t *__restrict__ parent,

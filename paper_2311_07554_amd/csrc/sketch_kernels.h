@@ -2,7 +2,8 @@
 // B sketches per pass over the edge list.
 //
 //   k_sketch_keys     K(seed, r) for every sketch
-//   k_batch_init      parent[b][x] = x, cnt = 0, minc = x's center rank (or a given value)
+//   k_batch_init(4)   entry (x, b): parent = x, cnt = 0, minc = x's center rank (or a
+//                     given value); the "4" form writes 4 entries per 16-byte store
 //   k_sample_hook     one thread per undirected edge: B live tests (Sample(e, r),
 //                     fused: sampled graphs are never stored), then union by
 //                     hooking the larger root under the smaller one
