@@ -287,6 +287,53 @@ def test_invalid_arguments(ctx):
     assert lib.im_ctx_memory(ctx.h)[0] == 0
 
 
+def test_size_limits_rejected_before_device_work(ctx):
+    # the build's size limits (keys of ceil(log2(R*n+2)) + ceil(log2 n) <= 64 bits;
+    # CompactSketch: R*n < 2^40 and R < 2^24) are refused with EINVAL before any
+    # allocation, on an edgeless graph of 2^20 vertices and a small one
+    big = inputs.csr_from_pairs(1 << 20, [])
+    gr = upload(ctx, big)
+    small = upload(ctx, inputs.er_graph(50, 100, seed=2))
+    try:
+        for g_, R, alpha in [(gr, (1 << 32) - 1, 1.0), (gr, 1 << 20, 0.5), (small, 1 << 24, 0.5)]:
+            with pytest.raises(pacim.ImError) as e:
+                g_.sketches(U, 0.1, R, 1, alpha)
+            assert e.value.status == pacim.IM_EINVAL, (R, alpha)
+        assert pacim.im_ctx_memory(ctx.h)[0] > 0  # the two graphs only
+    finally:
+        gr.close()
+        small.close()
+    assert pacim.im_ctx_memory(ctx.h)[0] == 0
+
+
+def test_zero_seed_requests(ctx):
+    # k = 0 is a valid request on every path: nothing is selected and the handle's
+    # state is unchanged (the next k seeds are the oracle's first k)
+    g = inputs.er_graph(300, 1200, seed=5)
+    R, k, seed, p = 16, 6, 3, 0.2
+    _say("case k = 0 requests")
+    lab, siz = oracle.sketches(g, U, p, seed, R)
+    ws, wg = oracle.greedy(lab, siz, k)
+    gr = upload(ctx, g)
+    try:
+        for alpha in (1.0, 0.3):
+            sk = gr.sketches(U, p, R, seed, alpha)
+            for sel in (sk.select, sk.select_ptree):
+                s0, g0 = sel(0)
+                assert s0.size == 0 and g0.size == 0
+            s, gn = sk.select(k)
+            assert np.array_equal(s, ws) and np.array_equal(gn, wg), alpha
+            s0, g0 = sk.select_ptree(0)
+            assert s0.size == 0 and g0.size == 0
+            sk.close()
+        res, _ = ctx.select_batched([(gr, U, p, R, 0, seed), (gr, U, p, R, k, seed), (gr, U, p, R, 0, seed, 0.3)])
+        assert res[0][0].size == 0 and res[0][1].size == 0 and res[2][0].size == 0
+        assert np.array_equal(res[1][0], ws) and np.array_equal(res[1][1], wg)
+        assert ctx.select_batched([])[0] == []
+    finally:
+        gr.close()
+
+
 def test_module_level_select_from_torch_tensors():
     # CSR handed over as device tensors on torch's current stream; full labels and CompactSketch
     import torch
